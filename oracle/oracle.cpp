@@ -1,0 +1,990 @@
+// CPU FP64 oracle of the hybrid mesh-Gaussian rasterizer.
+//
+// TEST INFRASTRUCTURE ONLY: only tests/, the smoke entry point and the
+// benchmark's CPU-baseline leg may load this library. It shares no code,
+// header or table with the HIP implementation.
+//
+// What it computes, and where the paper defines it:
+//   * Gaussian primitive: centre u, opacity, rotation R, scale S, SH colour;
+//     density exp(-1/2 (x-u)^T Sigma^-1 (x-u))                 (Sec. 3.1, Eq. 1)
+//   * Sigma = R S S^T R^T;  Sigma' = J W Sigma W^T J^T           (Sec. 3.1)
+//   * front-to-back alpha blending over depth-sorted Gaussians (Sec. 3.1, Eq. 2)
+//   * textured mesh rendered by barycentric UV interpolation     (Sec. 3.1 "Textured mesh")
+//   * joint rasterization: mesh gives I_m and D_m; only Gaussians with
+//     D_gs < D_m are blended; the residual transmittance T weights the mesh
+//     colour, else the background colour                         (Sec. 3.4 "Joint rasterization")
+//   * gradients to Gaussians and texture (texture optimisable, no vertex
+//     optimisation)                                              (Sec. 3.4)
+// Conventions the paper leaves to its 3DGS code base (16 px tiles, 3 sigma
+// extent, 0.3 px^2 low-pass, alpha in [1/255, 0.99], T stop 1e-4, 0.2 near
+// plane, 1.3 x FOV clamp of the Jacobian, SH colour + 0.5 clamped at 0) are
+// inputs (or_params), not constants.
+//
+// Everything is FP64 except where the method's definition rounds: the sort key
+// and the depth test use fp32(z); the blend reads the projected record rounded
+// to FP32 (the record precision of the kernel) unless OR_FP64_RECORDS is set,
+// which the finite-difference tests use.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+extern "C" {
+
+typedef struct {
+  int32_t n, sh_degree;
+  const double* means;           // [n,3]
+  const double* log_scales;      // [n,3]
+  const double* quats;           // [n,4] (w,x,y,z)
+  const double* opacity_logits;  // [n]
+  const double* sh;              // [n,(d+1)^2,3]
+  int32_t n_verts, n_faces, n_tex, tex_h, tex_w;
+  const double* verts;     // [V,3]
+  const int32_t* faces;    // [F,3]
+  const double* uvs;       // [F,3,2]
+  const int32_t* face_tex; // [F]
+  const float* tex;        // [n_tex,tex_h,tex_w,3]
+} or_scene;
+
+typedef struct {
+  int32_t width, height;
+  double fx, fy, cx, cy;
+  double R[9];  // world -> camera, row-major
+  double t[3];
+} or_camera;
+
+typedef struct {
+  double bg[3];
+  double low_pass, alpha_min, alpha_max, t_min, near_gs, near_mesh, clamp_fov;
+  int32_t tile, flags;
+  double amb_alpha, amb_t;  // relative slack under which a decision is tagged
+} or_params;
+
+enum { OR_FP64_RECORDS = 1 };
+
+// per-Gaussian record export
+typedef struct {
+  double* mean2d;      // [n,2]
+  double* conic;       // [n,3]
+  double* cov2d;       // [n,3]
+  double* opacity;     // [n]
+  double* rgb;         // [n,3]
+  double* depth;       // [n]
+  uint32_t* depth_bits;// [n]
+  int32_t* radius;     // [n]   0 = culled
+  int32_t* rect;       // [n,4] x0,x1,y0,y1 in tiles (exclusive ends)
+  int32_t* tiles;      // [n]
+  uint8_t* amb;        // [n]
+} or_proj_out;
+
+typedef struct {
+  double* image;        // [3,h,w]  window
+  double* final_T;      // [h,w]
+  int32_t* n_contrib;   // [h,w]
+  int32_t* n_blended;   // [h,w]
+  int32_t* n_processed; // [h,w]
+  uint8_t* amb;         // [h,w]  bit0 alpha slack, bit1 T slack, bit2 projection, bit4 mesh
+  int32_t* tri_id;      // [h,w]
+  float* mesh_depth;    // [h,w]
+  double* mesh_rgb;     // [3,h,w]
+  uint64_t* trace;      // [1] hash of every decision taken
+} or_render_out;
+
+typedef struct {
+  double* means;     // [n,3]
+  double* log_scales;
+  double* quats;     // [n,4]
+  double* opacity_logits;
+  double* sh;        // [n,K,3]
+  double* tex;       // [n_tex,H,W,3]
+} or_grads;
+}
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+struct Rec {
+  bool vis = false, amb = false;
+  double pc[3];
+  double u, v;
+  double cov[3];
+  double con[3];
+  double op, logit;
+  double rgb[3];
+  bool clamped[3];
+  double dir[3], dnorm;
+  int r, x0, x1, y0, y1;
+  uint32_t dbits;
+  double zf;  // fp32(z) as double
+  // values the blend uses (FP32-rounded unless OR_FP64_RECORDS)
+  double bu, bv, bcon[3], bop, brgb[3];
+  // backward intermediates
+  double s[3], qn[4], qnorm, Rq[9], Sc[9], J[6];
+  bool clx, cly;
+  double xc, yc;
+};
+
+inline uint32_t f32bits(float f) {
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  return b;
+}
+
+inline double r32(double x) { return (double)(float)x; }
+
+bool near_int(double x, double rel) {
+  double d = std::fabs(x - std::nearbyint(x));
+  return d <= rel * std::max(1.0, std::fabs(x));
+}
+
+bool f32_boundary(double x) {
+  double e = std::fabs(x) * 1e-12;
+  return (float)(x + e) != (float)(x - e);
+}
+
+// Real spherical harmonics, orthonormal on the unit sphere, without the
+// Condon-Shortley phase; index k = l*l + l + m, m = -l..l.
+void sh_basis(const double d[3], double* Y, int deg) {
+  const double x = d[0], y = d[1], z = d[2];
+  Y[0] = 0.5 * std::sqrt(1.0 / PI);
+  if (deg < 1) return;
+  const double c1 = std::sqrt(3.0 / (4.0 * PI));
+  Y[1] = c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = c1 * x;
+  if (deg < 2) return;
+  const double a2 = 0.5 * std::sqrt(15.0 / PI), b2 = 0.25 * std::sqrt(5.0 / PI),
+               d2 = 0.25 * std::sqrt(15.0 / PI);
+  Y[4] = a2 * x * y;
+  Y[5] = a2 * y * z;
+  Y[6] = b2 * (3.0 * z * z - 1.0);
+  Y[7] = a2 * x * z;
+  Y[8] = d2 * (x * x - y * y);
+  if (deg < 3) return;
+  const double e3 = 0.25 * std::sqrt(35.0 / (2.0 * PI)), f3 = 0.5 * std::sqrt(105.0 / PI),
+               g3 = 0.25 * std::sqrt(21.0 / (2.0 * PI)), h3 = 0.25 * std::sqrt(7.0 / PI),
+               k3 = 0.25 * std::sqrt(105.0 / PI);
+  Y[9] = e3 * y * (3.0 * x * x - y * y);
+  Y[10] = f3 * x * y * z;
+  Y[11] = g3 * y * (5.0 * z * z - 1.0);
+  Y[12] = h3 * z * (5.0 * z * z - 3.0);
+  Y[13] = g3 * x * (5.0 * z * z - 1.0);
+  Y[14] = k3 * z * (x * x - y * y);
+  Y[15] = e3 * x * (x * x - 3.0 * y * y);
+}
+
+// gradient of each basis polynomial above with respect to (x, y, z)
+void sh_basis_grad(const double d[3], double (*G)[3], int deg) {
+  const double x = d[0], y = d[1], z = d[2];
+  for (int k = 0; k < 16; ++k) G[k][0] = G[k][1] = G[k][2] = 0.0;
+  if (deg < 1) return;
+  const double c1 = std::sqrt(3.0 / (4.0 * PI));
+  G[1][1] = c1;
+  G[2][2] = c1;
+  G[3][0] = c1;
+  if (deg < 2) return;
+  const double a2 = 0.5 * std::sqrt(15.0 / PI), b2 = 0.25 * std::sqrt(5.0 / PI),
+               d2 = 0.25 * std::sqrt(15.0 / PI);
+  G[4][0] = a2 * y; G[4][1] = a2 * x;
+  G[5][1] = a2 * z; G[5][2] = a2 * y;
+  G[6][2] = 6.0 * b2 * z;
+  G[7][0] = a2 * z; G[7][2] = a2 * x;
+  G[8][0] = 2.0 * d2 * x; G[8][1] = -2.0 * d2 * y;
+  if (deg < 3) return;
+  const double e3 = 0.25 * std::sqrt(35.0 / (2.0 * PI)), f3 = 0.5 * std::sqrt(105.0 / PI),
+               g3 = 0.25 * std::sqrt(21.0 / (2.0 * PI)), h3 = 0.25 * std::sqrt(7.0 / PI),
+               k3 = 0.25 * std::sqrt(105.0 / PI);
+  G[9][0] = 6.0 * e3 * x * y; G[9][1] = e3 * (3.0 * x * x - 3.0 * y * y);
+  G[10][0] = f3 * y * z; G[10][1] = f3 * x * z; G[10][2] = f3 * x * y;
+  G[11][1] = g3 * (5.0 * z * z - 1.0); G[11][2] = 10.0 * g3 * y * z;
+  G[12][2] = h3 * (15.0 * z * z - 3.0);
+  G[13][0] = g3 * (5.0 * z * z - 1.0); G[13][2] = 10.0 * g3 * x * z;
+  G[14][0] = 2.0 * k3 * x * z; G[14][1] = -2.0 * k3 * y * z; G[14][2] = k3 * (x * x - y * y);
+  G[15][0] = e3 * (3.0 * x * x - 3.0 * y * y); G[15][1] = -6.0 * e3 * x * y;
+}
+
+// unit quaternion (w,x,y,z) -> rotation matrix, row-major
+void quat_to_rot(const double q[4], double* R) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+int tiles_x(const or_camera& c, const or_params& p) { return (c.width + p.tile - 1) / p.tile; }
+int tiles_y(const or_camera& c, const or_params& p) { return (c.height + p.tile - 1) / p.tile; }
+
+// Sec. 3.1: Sigma = R S S^T R^T, Sigma' = J W Sigma W^T J^T (+ low-pass), conic,
+// 3-sigma radius and tile rectangle, SH colour, depth key.
+Rec project(const or_scene& sc, const or_camera& cam, const or_params& p, int g) {
+  Rec r;
+  const int K = (sc.sh_degree + 1) * (sc.sh_degree + 1);
+  const double* mu = sc.means + 3 * (size_t)g;
+  const double* ls = sc.log_scales + 3 * (size_t)g;
+  const double* q = sc.quats + 4 * (size_t)g;
+  const double* shc = sc.sh + (size_t)g * K * 3;
+  bool fin = std::isfinite(sc.opacity_logits[g]);
+  for (int i = 0; i < 3; ++i) fin = fin && std::isfinite(mu[i]) && std::isfinite(ls[i]);
+  for (int i = 0; i < 4; ++i) fin = fin && std::isfinite(q[i]);
+  for (int i = 0; i < K * 3; ++i) fin = fin && std::isfinite(shc[i]);
+  if (!fin) return r;
+
+  const double* W = cam.R;
+  for (int i = 0; i < 3; ++i)
+    r.pc[i] = W[3 * i] * mu[0] + W[3 * i + 1] * mu[1] + W[3 * i + 2] * mu[2] + cam.t[i];
+  const double x = r.pc[0], y = r.pc[1], z = r.pc[2];
+  if (std::fabs(z - p.near_gs) <= 1e-12 * p.near_gs) r.amb = true;
+  if (!(z > p.near_gs)) return r;
+
+  r.logit = sc.opacity_logits[g];
+  r.op = 1.0 / (1.0 + std::exp(-r.logit));
+  for (int i = 0; i < 3; ++i) r.s[i] = std::exp(ls[i]);
+  r.qnorm = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  if (!(r.qnorm > 0)) return r;
+  for (int i = 0; i < 4; ++i) r.qn[i] = q[i] / r.qnorm;
+  quat_to_rot(r.qn, r.Rq);
+  double M[9], Sig[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = r.Rq[3 * i + j] * r.s[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double a = 0;
+      for (int k = 0; k < 3; ++k) a += M[3 * i + k] * M[3 * j + k];
+      Sig[3 * i + j] = a;
+    }
+  double WS[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double a = 0;
+      for (int k = 0; k < 3; ++k) a += W[3 * i + k] * Sig[3 * k + j];
+      WS[3 * i + j] = a;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double a = 0;
+      for (int k = 0; k < 3; ++k) a += WS[3 * i + k] * W[3 * j + k];
+      r.Sc[3 * i + j] = a;
+    }
+  const double limx = p.clamp_fov * cam.width / (2.0 * cam.fx);
+  const double limy = p.clamp_fov * cam.height / (2.0 * cam.fy);
+  const double xz = x / z, yz = y / z;
+  r.xc = std::min(limx, std::max(-limx, xz));
+  r.yc = std::min(limy, std::max(-limy, yz));
+  r.clx = (xz < -limx) || (xz > limx);
+  r.cly = (yz < -limy) || (yz > limy);
+  r.J[0] = cam.fx / z; r.J[1] = 0.0; r.J[2] = -cam.fx * r.xc / z;
+  r.J[3] = 0.0; r.J[4] = cam.fy / z; r.J[5] = -cam.fy * r.yc / z;
+  double JS[6];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double a = 0;
+      for (int k = 0; k < 3; ++k) a += r.J[3 * i + k] * r.Sc[3 * k + j];
+      JS[3 * i + j] = a;
+    }
+  double C2[4];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double a = 0;
+      for (int k = 0; k < 3; ++k) a += JS[3 * i + k] * r.J[3 * j + k];
+      C2[2 * i + j] = a;
+    }
+  r.cov[0] = C2[0] + p.low_pass;
+  r.cov[1] = 0.5 * (C2[1] + C2[2]);
+  r.cov[2] = C2[3] + p.low_pass;
+  const double det = r.cov[0] * r.cov[2] - r.cov[1] * r.cov[1];
+  if (!(det > 0)) return r;
+  r.con[0] = r.cov[2] / det;
+  r.con[1] = -r.cov[1] / det;
+  r.con[2] = r.cov[0] / det;
+  r.u = cam.fx * x / z + cam.cx;
+  r.v = cam.fy * y / z + cam.cy;
+  const double m = 0.5 * (r.cov[0] + r.cov[2]);
+  const double lam = m + std::sqrt(std::max(0.1, m * m - det));
+  const double r3 = 3.0 * std::sqrt(lam);
+  r.r = (int)std::ceil(r3);
+  if (near_int(r3, 1e-11)) r.amb = true;
+  const int TX = tiles_x(cam, p), TY = tiles_y(cam, p);
+  const double T = (double)p.tile;
+  const double ex0 = (r.u - r.r) / T, ex1 = (r.u + r.r) / T;
+  const double ey0 = (r.v - r.r) / T, ey1 = (r.v + r.r) / T;
+  if (near_int(ex0, 1e-11) || near_int(ex1, 1e-11) || near_int(ey0, 1e-11) ||
+      near_int(ey1, 1e-11))
+    r.amb = true;
+  auto clampi = [](double v, int hi) {
+    if (!(v > 0)) return 0;  // also catches NaN
+    if (v > hi) return hi;
+    return (int)v;
+  };
+  r.x0 = clampi(std::floor(ex0), TX);
+  r.x1 = clampi(std::floor(ex1) + 1, TX);
+  r.y0 = clampi(std::floor(ey0), TY);
+  r.y1 = clampi(std::floor(ey1) + 1, TY);
+  if ((r.x1 - r.x0) * (r.y1 - r.y0) <= 0) return r;
+
+  // view-dependent colour from SH toward normalize(u - camera centre)
+  double C[3];
+  for (int i = 0; i < 3; ++i)
+    C[i] = -(W[i] * cam.t[0] + W[3 + i] * cam.t[1] + W[6 + i] * cam.t[2]);
+  double d[3] = {mu[0] - C[0], mu[1] - C[1], mu[2] - C[2]};
+  r.dnorm = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  for (int i = 0; i < 3; ++i) r.dir[i] = d[i] / r.dnorm;
+  double Y[16];
+  sh_basis(r.dir, Y, sc.sh_degree);
+  for (int c = 0; c < 3; ++c) {
+    double a = 0.5;
+    for (int k = 0; k < K; ++k) a += Y[k] * shc[3 * k + c];
+    r.clamped[c] = a < 0.0;
+    r.rgb[c] = r.clamped[c] ? 0.0 : a;
+  }
+  const float zf = (float)z;
+  r.dbits = f32bits(zf);
+  r.zf = zf;
+  if (f32_boundary(z)) r.amb = true;
+  r.vis = true;
+  if (p.flags & OR_FP64_RECORDS) {
+    r.bu = r.u; r.bv = r.v; r.bop = r.op;
+    for (int i = 0; i < 3; ++i) { r.bcon[i] = r.con[i]; r.brgb[i] = r.rgb[i]; }
+  } else {
+    r.bu = r32(r.u); r.bv = r32(r.v); r.bop = r32(r.op);
+    for (int i = 0; i < 3; ++i) { r.bcon[i] = r32(r.con[i]); r.brgb[i] = r32(r.rgb[i]); }
+  }
+  return r;
+}
+
+std::vector<Rec> project_all(const or_scene& sc, const or_camera& cam, const or_params& p) {
+  std::vector<Rec> recs(sc.n);
+#pragma omp parallel for schedule(static)
+  for (int g = 0; g < sc.n; ++g) recs[g] = project(sc, cam, p, g);
+  return recs;
+}
+
+// ------------------------------------------------------------------ mesh --
+struct MeshPix {
+  uint64_t key = ~0ull;  // fp32 depth bits << 32 | (2 * face + sub)
+  double z, uv[2];
+  bool amb = false;
+};
+
+struct CVert {
+  double p[3];
+  double uv[2];
+  double w[3];  // world position, used to order clip edges canonically
+};
+
+// Sutherland-Hodgman against z >= zn. The crossing of an edge is computed
+// from the lexicographically smaller world endpoint so that an edge shared by
+// two faces gives the same clip point in both.
+int clip_near(const CVert in[3], double zn, CVert out[4], bool* amb) {
+  int n = 0;
+  for (int i = 0; i < 3; ++i) {
+    const CVert& a = in[i];
+    const CVert& b = in[(i + 1) % 3];
+    if (std::fabs(a.p[2] - zn) <= 1e-12 * zn) *amb = true;
+    const bool ain = a.p[2] >= zn, bin = b.p[2] >= zn;
+    if (ain) out[n++] = a;
+    if (ain != bin) {
+      bool swap = std::lexicographical_compare(b.w, b.w + 3, a.w, a.w + 3);
+      const CVert& e0 = swap ? b : a;
+      const CVert& e1 = swap ? a : b;
+      const double t = (zn - e0.p[2]) / (e1.p[2] - e0.p[2]);
+      CVert c;
+      for (int k = 0; k < 3; ++k) c.p[k] = e0.p[k] + t * (e1.p[k] - e0.p[k]);
+      c.p[2] = zn;
+      for (int k = 0; k < 2; ++k) c.uv[k] = e0.uv[k] + t * (e1.uv[k] - e0.uv[k]);
+      for (int k = 0; k < 3; ++k) c.w[k] = 0;
+      out[n++] = c;
+    }
+  }
+  return n;
+}
+
+inline int64_t edge_fn(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t px, int64_t py) {
+  return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+}
+
+// an edge a->b owns the samples lying exactly on it when it points down the
+// screen, or exactly left; the reverse edge of a neighbour then does not
+inline bool owns(int64_t ax, int64_t ay, int64_t bx, int64_t by) {
+  const int64_t dx = bx - ax, dy = by - ay;
+  return dy > 0 || (dy == 0 && dx < 0);
+}
+
+constexpr int64_t SUBPIX = 256;
+constexpr int64_t GUARD = (int64_t)1 << 29;
+
+// Z-buffered rasterization of the textured mesh over window [wx0,wx1)x[wy0,wy1).
+void mesh_pass(const or_scene& sc, const or_camera& cam, const or_params& p, int wx0, int wy0,
+               int wx1, int wy1, std::vector<MeshPix>& pix) {
+  const int ww = wx1 - wx0, wh = wy1 - wy0;
+  pix.assign((size_t)ww * wh, MeshPix());
+  const double* W = cam.R;
+  for (int f = 0; f < sc.n_faces; ++f) {
+    CVert cv[3];
+    for (int k = 0; k < 3; ++k) {
+      const int vi = sc.faces[3 * f + k];
+      const double* v = sc.verts + 3 * (size_t)vi;
+      for (int i = 0; i < 3; ++i) {
+        cv[k].p[i] = W[3 * i] * v[0] + W[3 * i + 1] * v[1] + W[3 * i + 2] * v[2] + cam.t[i];
+        cv[k].w[i] = v[i];
+      }
+      cv[k].uv[0] = sc.uvs[6 * (size_t)f + 2 * k];
+      cv[k].uv[1] = sc.uvs[6 * (size_t)f + 2 * k + 1];
+    }
+    bool famb = false;
+    CVert poly[4];
+    const int np = clip_near(cv, p.near_mesh, poly, &famb);
+    if (np < 3) continue;
+    for (int sub = 0; sub < np - 2; ++sub) {
+      CVert tv[3] = {poly[0], poly[sub + 1], poly[sub + 2]};
+      int64_t X[3], Yv[3];
+      bool skip = false, amb = famb;
+      for (int k = 0; k < 3; ++k) {
+        const double u = cam.fx * tv[k].p[0] / tv[k].p[2] + cam.cx;
+        const double v = cam.fy * tv[k].p[1] / tv[k].p[2] + cam.cy;
+        const double su = u * SUBPIX, sv = v * SUBPIX;
+        if (!(std::fabs(su) <= (double)GUARD && std::fabs(sv) <= (double)GUARD)) skip = true;
+        if (std::fabs(std::fabs(su - std::floor(su)) - 0.5) <= 1e-9 * std::max(1.0, std::fabs(su)) ||
+            std::fabs(std::fabs(sv - std::floor(sv)) - 0.5) <= 1e-9 * std::max(1.0, std::fabs(sv)))
+          amb = true;
+        X[k] = skip ? 0 : (int64_t)std::nearbyint(su);
+        Yv[k] = skip ? 0 : (int64_t)std::nearbyint(sv);
+      }
+      if (skip) continue;
+      int64_t A = edge_fn(X[0], Yv[0], X[1], Yv[1], X[2], Yv[2]);
+      if (A == 0) continue;
+      if (A < 0) {
+        std::swap(X[1], X[2]);
+        std::swap(Yv[1], Yv[2]);
+        std::swap(tv[1], tv[2]);
+        A = -A;
+      }
+      const int64_t minx = std::min(X[0], std::min(X[1], X[2]));
+      const int64_t maxx = std::max(X[0], std::max(X[1], X[2]));
+      const int64_t miny = std::min(Yv[0], std::min(Yv[1], Yv[2]));
+      const int64_t maxy = std::max(Yv[0], std::max(Yv[1], Yv[2]));
+      // pixel i samples at 256 i + 128
+      int64_t i0 = (int64_t)std::floor((minx - 128) / 256.0), i1 = (int64_t)std::ceil((maxx - 128) / 256.0);
+      int64_t j0 = (int64_t)std::floor((miny - 128) / 256.0), j1 = (int64_t)std::ceil((maxy - 128) / 256.0);
+      i0 = std::max<int64_t>(i0, wx0); i1 = std::min<int64_t>(i1, wx1 - 1);
+      j0 = std::max<int64_t>(j0, wy0); j1 = std::min<int64_t>(j1, wy1 - 1);
+      const bool o0 = owns(X[1], Yv[1], X[2], Yv[2]);
+      const bool o1 = owns(X[2], Yv[2], X[0], Yv[0]);
+      const bool o2 = owns(X[0], Yv[0], X[1], Yv[1]);
+      const uint64_t uid = 2ull * (uint64_t)f + (uint64_t)sub;
+      for (int64_t j = j0; j <= j1; ++j)
+        for (int64_t i = i0; i <= i1; ++i) {
+          const int64_t px = SUBPIX * i + SUBPIX / 2, py = SUBPIX * j + SUBPIX / 2;
+          const int64_t e0 = edge_fn(X[1], Yv[1], X[2], Yv[2], px, py);
+          const int64_t e1 = edge_fn(X[2], Yv[2], X[0], Yv[0], px, py);
+          const int64_t e2 = edge_fn(X[0], Yv[0], X[1], Yv[1], px, py);
+          const bool in0 = e0 > 0 || (e0 == 0 && o0);
+          const bool in1 = e1 > 0 || (e1 == 0 && o1);
+          const bool in2 = e2 > 0 || (e2 == 0 && o2);
+          if (!(in0 && in1 && in2)) continue;
+          // screen barycentrics, then perspective-correct weights
+          const double b0 = (double)e0 / (double)A, b1 = (double)e1 / (double)A,
+                       b2 = (double)e2 / (double)A;
+          const double q0 = b0 / tv[0].p[2], q1 = b1 / tv[1].p[2], q2 = b2 / tv[2].p[2];
+          const double s = q0 + q1 + q2;
+          const double z = 1.0 / s;
+          const float zf = (float)z;
+          const uint64_t key = ((uint64_t)f32bits(zf) << 32) | uid;
+          MeshPix& mp = pix[(size_t)(j - wy0) * ww + (i - wx0)];
+          if (key < mp.key) {
+            mp.key = key;
+            mp.z = z;
+            const double w0 = q0 * z, w1 = q1 * z, w2 = q2 * z;
+            for (int k = 0; k < 2; ++k) mp.uv[k] = w0 * tv[0].uv[k] + w1 * tv[1].uv[k] + w2 * tv[2].uv[k];
+            mp.amb = amb || f32_boundary(z);
+          }
+        }
+    }
+  }
+}
+
+struct Bilin {
+  int tex, i0, i1, j0, j1;
+  double fx, fy;
+};
+
+// bilinear texel addressing: texel (i, j) centred at ((i+0.5)/W, (j+0.5)/H),
+// row 0 at V = 0, clamp to edge
+Bilin bilinear(const or_scene& sc, int face, const double uv[2]) {
+  Bilin b;
+  b.tex = sc.face_tex[face];
+  const double x = uv[0] * sc.tex_w - 0.5, y = uv[1] * sc.tex_h - 0.5;
+  const double fx0 = std::floor(x), fy0 = std::floor(y);
+  b.fx = x - fx0;
+  b.fy = y - fy0;
+  auto cl = [](double v, int hi) { return (int)std::min<double>(hi, std::max<double>(0.0, v)); };
+  b.i0 = cl(fx0, sc.tex_w - 1);
+  b.i1 = cl(fx0 + 1, sc.tex_w - 1);
+  b.j0 = cl(fy0, sc.tex_h - 1);
+  b.j1 = cl(fy0 + 1, sc.tex_h - 1);
+  return b;
+}
+
+double texel(const or_scene& sc, int t, int j, int i, int c) {
+  return (double)sc.tex[(((size_t)t * sc.tex_h + j) * sc.tex_w + i) * 3 + c];
+}
+
+// --------------------------------------------------------------- binning --
+struct Cand {
+  uint32_t dbits;
+  int32_t g;
+};
+
+// For every tile overlapping the window: all Gaussians whose tile rectangle
+// holds it, ordered by (fp32 depth bits, index).
+std::vector<std::vector<Cand>> tile_lists(const std::vector<Rec>& recs, int tx0, int ty0, int tx1,
+                                          int ty1) {
+  const int ntx = tx1 - tx0, nty = ty1 - ty0;
+  std::vector<std::vector<Cand>> lists((size_t)ntx * nty);
+  for (int g = 0; g < (int)recs.size(); ++g) {
+    const Rec& r = recs[g];
+    if (!r.vis) continue;
+    for (int ty = std::max(r.y0, ty0); ty < std::min(r.y1, ty1); ++ty)
+      for (int tx = std::max(r.x0, tx0); tx < std::min(r.x1, tx1); ++tx)
+        lists[(size_t)(ty - ty0) * ntx + (tx - tx0)].push_back({r.dbits, g});
+  }
+#pragma omp parallel for schedule(dynamic)
+  for (int t = 0; t < ntx * nty; ++t)
+    std::sort(lists[t].begin(), lists[t].end(), [](const Cand& a, const Cand& b) {
+      return a.dbits != b.dbits ? a.dbits < b.dbits : a.g < b.g;
+    });
+  return lists;
+}
+
+inline uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  return h;
+}
+
+struct Step {
+  int g;
+  double alpha, G, T;  // T before this Gaussian
+  bool clamped;
+};
+
+// Sec. 3.1 Eq. 2 with the joint-rasterization depth stop of Sec. 3.4.
+// Returns the steps that blended (the tape) and fills the pixel outputs.
+void blend_pixel(const std::vector<Rec>& recs, const std::vector<Cand>& list, const or_params& p,
+                 double px, double py, float Dm, std::vector<Step>* tape, double C[3], double* Tout,
+                 int* nc, int* nb, int* npro, uint8_t* amb, uint64_t* hash) {
+  double T = 1.0;
+  C[0] = C[1] = C[2] = 0.0;
+  *nc = 0; *nb = 0; *npro = (int)list.size();
+  uint64_t h = 0;
+  for (size_t k = 0; k < list.size(); ++k) {
+    const Rec& r = recs[list[k].g];
+    if (r.amb) *amb |= 4;
+    if ((float)r.zf >= Dm) {
+      *npro = (int)k + 1;
+      h = mix(h, 3);
+      break;
+    }
+    const double dx = px - r.bu, dy = py - r.bv;
+    const double power = -0.5 * (r.bcon[0] * dx * dx + r.bcon[2] * dy * dy) - r.bcon[1] * dx * dy;
+    const double G = std::exp(power);
+    const double a = r.bop * G;
+    const bool clamped = a >= p.alpha_max;
+    const double alpha = clamped ? p.alpha_max : a;
+    if (std::fabs(alpha - p.alpha_min) <= p.amb_alpha * p.alpha_min) *amb |= 1;
+    if (alpha < p.alpha_min) {
+      h = mix(h, 1);
+      continue;
+    }
+    const double Tn = T * (1.0 - alpha);
+    if (std::fabs(Tn - p.t_min) <= p.amb_t * p.t_min) *amb |= 2;
+    if (Tn < p.t_min) {
+      *npro = (int)k + 1;
+      h = mix(h, 2);
+      break;
+    }
+    if (tape) tape->push_back({list[k].g, alpha, G, T, clamped});
+    for (int c = 0; c < 3; ++c) C[c] += r.brgb[c] * alpha * T;
+    T = Tn;
+    *nc = (int)k + 1;
+    *nb += 1;
+    h = mix(h, ((uint64_t)list[k].g << 3) | (clamped ? 5 : 4));
+  }
+  *Tout = T;
+  *hash = h;
+}
+
+struct Frame {
+  std::vector<Rec> recs;
+  std::vector<MeshPix> mesh;
+  std::vector<std::vector<Cand>> lists;
+  int tx0, ty0, tx1, ty1;
+};
+
+Frame prepare(const or_scene& sc, const or_camera& cam, const or_params& p, int wx0, int wy0,
+              int wx1, int wy1) {
+  Frame f;
+  f.recs = project_all(sc, cam, p);
+  mesh_pass(sc, cam, p, wx0, wy0, wx1, wy1, f.mesh);
+  f.tx0 = wx0 / p.tile;
+  f.ty0 = wy0 / p.tile;
+  f.tx1 = (wx1 + p.tile - 1) / p.tile;
+  f.ty1 = (wy1 + p.tile - 1) / p.tile;
+  f.lists = tile_lists(f.recs, f.tx0, f.ty0, f.tx1, f.ty1);
+  return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int or_abi_version(void) { return 1; }
+
+// Per-Gaussian projected records for one camera.
+int or_project(const or_scene* sc, const or_camera* cam, const or_params* p, or_proj_out* o) {
+  if (!sc || !cam || !p || !o || p->tile <= 0) return 1;
+  std::vector<Rec> recs = project_all(*sc, *cam, *p);
+  for (int g = 0; g < sc->n; ++g) {
+    const Rec& r = recs[g];
+    if (o->amb) o->amb[g] = r.amb;
+    if (o->radius) o->radius[g] = r.vis ? r.r : 0;
+    if (o->tiles) o->tiles[g] = r.vis ? (r.x1 - r.x0) * (r.y1 - r.y0) : 0;
+    if (!r.vis) continue;
+    if (o->mean2d) { o->mean2d[2 * g] = r.u; o->mean2d[2 * g + 1] = r.v; }
+    for (int i = 0; i < 3; ++i) {
+      if (o->conic) o->conic[3 * g + i] = r.con[i];
+      if (o->cov2d) o->cov2d[3 * g + i] = r.cov[i];
+      if (o->rgb) o->rgb[3 * g + i] = r.rgb[i];
+    }
+    if (o->opacity) o->opacity[g] = r.op;
+    if (o->depth) o->depth[g] = r.pc[2];
+    if (o->depth_bits) o->depth_bits[g] = r.dbits;
+    if (o->rect) {
+      o->rect[4 * g] = r.x0; o->rect[4 * g + 1] = r.x1;
+      o->rect[4 * g + 2] = r.y0; o->rect[4 * g + 3] = r.y1;
+    }
+  }
+  return 0;
+}
+
+// Sorted (tile << 32 | depth bits, index) pairs and per-tile [start, end).
+// Returns the pair count; arrays are filled when capacity allows.
+int64_t or_keys(const or_scene* sc, const or_camera* cam, const or_params* p, uint64_t* keys,
+                uint32_t* values, uint32_t* ranges, int64_t capacity) {
+  if (!sc || !cam || !p || p->tile <= 0) return -1;
+  std::vector<Rec> recs = project_all(*sc, *cam, *p);
+  const int TX = tiles_x(*cam, *p), TY = tiles_y(*cam, *p);
+  auto lists = tile_lists(recs, 0, 0, TX, TY);
+  int64_t K = 0;
+  for (auto& l : lists) K += (int64_t)l.size();
+  if (keys && values && ranges && capacity >= K) {
+    int64_t o = 0;
+    for (int t = 0; t < TX * TY; ++t) {
+      ranges[2 * t] = (uint32_t)o;
+      for (const Cand& c : lists[t]) {
+        keys[o] = ((uint64_t)t << 32) | c.dbits;
+        values[o] = (uint32_t)c.g;
+        ++o;
+      }
+      ranges[2 * t + 1] = (uint32_t)o;
+    }
+  }
+  return K;
+}
+
+// Forward render of the pixels in window [wx0,wx1) x [wy0,wy1).
+int or_render(const or_scene* sc, const or_camera* cam, const or_params* p, int wx0, int wy0,
+              int wx1, int wy1, or_render_out* o) {
+  if (!sc || !cam || !p || !o || p->tile <= 0) return 1;
+  if (wx0 < 0 || wy0 < 0 || wx1 > cam->width || wy1 > cam->height || wx0 >= wx1 || wy0 >= wy1)
+    return 1;
+  Frame f = prepare(*sc, *cam, *p, wx0, wy0, wx1, wy1);
+  const int ww = wx1 - wx0, wh = wy1 - wy0;
+  const int ntx = f.tx1 - f.tx0;
+  std::vector<uint64_t> hashes((size_t)ww * wh);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int idx = 0; idx < ww * wh; ++idx) {
+    const int i = wx0 + idx % ww, j = wy0 + idx / ww;
+    const MeshPix& mp = f.mesh[idx];
+    const bool has = mp.key != ~0ull;
+    const int face = has ? (int)((mp.key & 0xffffffffull) >> 1) : -1;
+    const float Dm = has ? (float)mp.z : std::numeric_limits<float>::infinity();
+    double Im[3] = {0, 0, 0};
+    if (has) {
+      Bilin b = bilinear(*sc, face, mp.uv);
+      for (int c = 0; c < 3; ++c)
+        Im[c] = (1 - b.fx) * (1 - b.fy) * texel(*sc, b.tex, b.j0, b.i0, c) +
+                b.fx * (1 - b.fy) * texel(*sc, b.tex, b.j0, b.i1, c) +
+                (1 - b.fx) * b.fy * texel(*sc, b.tex, b.j1, b.i0, c) +
+                b.fx * b.fy * texel(*sc, b.tex, b.j1, b.i1, c);
+    }
+    const auto& list = f.lists[(size_t)(j / p->tile - f.ty0) * ntx + (i / p->tile - f.tx0)];
+    double C[3], T;
+    int nc, nb, npro;
+    uint8_t amb = has && mp.amb ? 16 : 0;
+    uint64_t h;
+    blend_pixel(f.recs, list, *p, i + 0.5, j + 0.5, Dm, nullptr, C, &T, &nc, &nb, &npro, &amb, &h);
+    const size_t hw = (size_t)ww * wh;
+    for (int c = 0; c < 3; ++c) {
+      const double B = has ? Im[c] : p->bg[c];
+      if (o->image) o->image[c * hw + idx] = C[c] + T * B;
+      if (o->mesh_rgb) o->mesh_rgb[c * hw + idx] = Im[c];
+    }
+    if (o->final_T) o->final_T[idx] = T;
+    if (o->n_contrib) o->n_contrib[idx] = nc;
+    if (o->n_blended) o->n_blended[idx] = nb;
+    if (o->n_processed) o->n_processed[idx] = npro;
+    if (o->amb) o->amb[idx] = amb;
+    if (o->tri_id) o->tri_id[idx] = face;
+    if (o->mesh_depth) o->mesh_depth[idx] = Dm;
+    hashes[idx] = mix(h, (uint64_t)face + 7);
+  }
+  if (o->trace) {
+    uint64_t h = 0;
+    for (uint64_t v : hashes) h = mix(h, v);
+    for (const Rec& r : f.recs) {
+      h = mix(h, r.vis ? ((uint64_t)r.r << 40 | (uint64_t)r.x0 << 30 | (uint64_t)r.x1 << 20 |
+                          (uint64_t)r.y0 << 10 | (uint64_t)r.y1)
+                       : 1);
+      if (r.vis) h = mix(h, (uint64_t)r.clamped[0] | (uint64_t)r.clamped[1] << 1 |
+                                (uint64_t)r.clamped[2] << 2 | (uint64_t)r.clx << 3 |
+                                (uint64_t)r.cly << 4);
+    }
+    *o->trace = h;
+  }
+  return 0;
+}
+
+// Reverse mode over a stored tape: the gradient of
+//   F = sum(g_image * I_h) + sum(g_T * T) + sum(g_mesh_rgb * I_m)
+// over the window, with respect to all Gaussian parameters and the texture.
+// Gradients are accumulated (+=) into `o` (any pointer may be null).
+int or_backward(const or_scene* sc, const or_camera* cam, const or_params* p, int wx0, int wy0,
+                int wx1, int wy1, const double* g_image, const double* g_T,
+                const double* g_mesh_rgb, or_grads* o) {
+  if (!sc || !cam || !p || !o || p->tile <= 0) return 1;
+  if (wx0 < 0 || wy0 < 0 || wx1 > cam->width || wy1 > cam->height || wx0 >= wx1 || wy0 >= wy1)
+    return 1;
+  Frame f = prepare(*sc, *cam, *p, wx0, wy0, wx1, wy1);
+  const int ww = wx1 - wx0, wh = wy1 - wy0;
+  const int ntx = f.tx1 - f.tx0;
+  const size_t hw = (size_t)ww * wh;
+  const int n = sc->n;
+  // per-Gaussian gradient of the record: u, v, conic[3], opacity, rgb[3]
+  std::vector<double> grec((size_t)n * 9, 0.0);
+  std::vector<double> gtex;
+  if (o->tex) gtex.assign((size_t)sc->n_tex * sc->tex_h * sc->tex_w * 3, 0.0);
+  // pixels are processed sequentially so that the accumulation order is fixed
+  std::vector<Step> tape;
+  for (size_t idx = 0; idx < hw; ++idx) {
+    const int i = wx0 + (int)(idx % ww), j = wy0 + (int)(idx / ww);
+    const MeshPix& mp = f.mesh[idx];
+    const bool has = mp.key != ~0ull;
+    const int face = has ? (int)((mp.key & 0xffffffffull) >> 1) : -1;
+    const float Dm = has ? (float)mp.z : std::numeric_limits<float>::infinity();
+    Bilin b{};
+    double B[3];
+    for (int c = 0; c < 3; ++c) B[c] = p->bg[c];
+    if (has) {
+      b = bilinear(*sc, face, mp.uv);
+      for (int c = 0; c < 3; ++c)
+        B[c] = (1 - b.fx) * (1 - b.fy) * texel(*sc, b.tex, b.j0, b.i0, c) +
+               b.fx * (1 - b.fy) * texel(*sc, b.tex, b.j0, b.i1, c) +
+               (1 - b.fx) * b.fy * texel(*sc, b.tex, b.j1, b.i0, c) +
+               b.fx * b.fy * texel(*sc, b.tex, b.j1, b.i1, c);
+    }
+    const auto& list = f.lists[(size_t)(j / p->tile - f.ty0) * ntx + (i / p->tile - f.tx0)];
+    tape.clear();
+    double C[3], Tf;
+    int nc, nb, npro;
+    uint8_t amb = 0;
+    uint64_t h;
+    blend_pixel(f.recs, list, *p, i + 0.5, j + 0.5, Dm, &tape, C, &Tf, &nc, &nb, &npro, &amb, &h);
+    double gC[3], gT = g_T ? g_T[idx] : 0.0;
+    for (int c = 0; c < 3; ++c) {
+      gC[c] = g_image ? g_image[c * hw + idx] : 0.0;
+      gT += gC[c] * B[c];
+    }
+    if (has && !gtex.empty()) {
+      for (int c = 0; c < 3; ++c) {
+        const double gm = Tf * gC[c] + (g_mesh_rgb ? g_mesh_rgb[c * hw + idx] : 0.0);
+        auto add = [&](int jj, int ii, double w) {
+          gtex[(((size_t)b.tex * sc->tex_h + jj) * sc->tex_w + ii) * 3 + c] += w * gm;
+        };
+        add(b.j0, b.i0, (1 - b.fx) * (1 - b.fy));
+        add(b.j0, b.i1, b.fx * (1 - b.fy));
+        add(b.j1, b.i0, (1 - b.fx) * b.fy);
+        add(b.j1, b.i1, b.fx * b.fy);
+      }
+    }
+    // reverse sweep: S = colour accumulated behind step k (from T = 1 after it),
+    // P = product of (1 - alpha) behind step k
+    double S[3] = {0, 0, 0}, P = 1.0;
+    for (int k = (int)tape.size() - 1; k >= 0; --k) {
+      const Step& st = tape[k];
+      const Rec& r = f.recs[st.g];
+      double* gr = &grec[(size_t)st.g * 9];
+      double galpha = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        gr[6 + c] += st.alpha * st.T * gC[c];
+        galpha += st.T * (r.brgb[c] - S[c]) * gC[c];
+      }
+      galpha += gT * (-st.T * P);  // dT_final / dalpha_k = -T_k * prod_{j>k} (1 - alpha_j)
+      for (int c = 0; c < 3; ++c) S[c] = st.alpha * r.brgb[c] + (1.0 - st.alpha) * S[c];
+      P *= (1.0 - st.alpha);
+      if (st.clamped) continue;
+      gr[5] += galpha * st.G;  // d alpha / d opacity
+      const double gpow = galpha * r.bop * st.G;
+      const double dx = (i + 0.5) - r.bu, dy = (j + 0.5) - r.bv;
+      // power = -1/2 (a dx^2 + c dy^2) - b dx dy,  dx = px - u
+      gr[0] += gpow * (r.bcon[0] * dx + r.bcon[1] * dy);
+      gr[1] += gpow * (r.bcon[2] * dy + r.bcon[1] * dx);
+      gr[2] += gpow * (-0.5 * dx * dx);
+      gr[3] += gpow * (-dx * dy);
+      gr[4] += gpow * (-0.5 * dy * dy);
+    }
+  }
+  if (o->tex)
+    for (size_t k = 0; k < gtex.size(); ++k) o->tex[k] += gtex[k];
+
+  // chain rule from records to parameters
+  const int K = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+  const double* W = cam->R;
+#pragma omp parallel for schedule(static)
+  for (int g = 0; g < n; ++g) {
+    const double* gr = &grec[(size_t)g * 9];
+    bool any = false;
+    for (int k = 0; k < 9; ++k) any = any || gr[k] != 0.0;
+    if (!any) continue;
+    const Rec& r = f.recs[g];
+    double gpc[3] = {0, 0, 0}, gmu[3] = {0, 0, 0};
+    // opacity
+    if (o->opacity_logits) o->opacity_logits[g] += gr[5] * r.op * (1.0 - r.op);
+    // colour
+    {
+      double Y[16], GY[16][3];
+      sh_basis(r.dir, Y, sc->sh_degree);
+      sh_basis_grad(r.dir, GY, sc->sh_degree);
+      const double* shc = sc->sh + (size_t)g * K * 3;
+      double gdir[3] = {0, 0, 0};
+      for (int c = 0; c < 3; ++c) {
+        if (r.clamped[c]) continue;
+        for (int k = 0; k < K; ++k) {
+          if (o->sh) o->sh[((size_t)g * K + k) * 3 + c] += Y[k] * gr[6 + c];
+          for (int a = 0; a < 3; ++a) gdir[a] += GY[k][a] * shc[3 * k + c] * gr[6 + c];
+        }
+      }
+      const double dd = gdir[0] * r.dir[0] + gdir[1] * r.dir[1] + gdir[2] * r.dir[2];
+      for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - r.dir[a] * dd) / r.dnorm;
+    }
+    // conic -> 2D covariance: G = [[ga, gb/2],[gb/2, gc]], H = -Q G Q
+    const double Q[4] = {r.con[0], r.con[1], r.con[1], r.con[2]};
+    const double Gm[4] = {gr[2], 0.5 * gr[3], 0.5 * gr[3], gr[4]};
+    double QG[4], H[4];
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 2; ++c) QG[2 * a + c] = Q[2 * a] * Gm[c] + Q[2 * a + 1] * Gm[2 + c];
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 2; ++c) H[2 * a + c] = -(QG[2 * a] * Q[c] + QG[2 * a + 1] * Q[2 + c]);
+    // Sigma' = J Sc J^T + lp I:  dSc = J^T H J,  dJ = 2 H J Sc
+    double gSc[9], HJ[6], gJ[6];
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 3; ++c) HJ[3 * a + c] = H[2 * a] * r.J[c] + H[2 * a + 1] * r.J[3 + c];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) gSc[3 * a + c] = r.J[a] * HJ[c] + r.J[3 + a] * HJ[3 + c];
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0;
+        for (int k = 0; k < 3; ++k) s += HJ[3 * a + k] * r.Sc[3 * k + c];
+        gJ[3 * a + c] = 2.0 * s;
+      }
+    const double x = r.pc[0], y = r.pc[1], z = r.pc[2];
+    const double fx = cam->fx, fy = cam->fy;
+    // J00 = fx/z, J02 = -fx xc / z (xc = x/z unless clamped), same for row 1
+    gpc[2] += gJ[0] * (-fx / (z * z)) + gJ[4] * (-fy / (z * z));
+    if (r.clx) {
+      gpc[2] += gJ[2] * (fx * r.xc / (z * z));
+    } else {
+      gpc[0] += gJ[2] * (-fx / (z * z));
+      gpc[2] += gJ[2] * (2.0 * fx * x / (z * z * z));
+    }
+    if (r.cly) {
+      gpc[2] += gJ[5] * (fy * r.yc / (z * z));
+    } else {
+      gpc[1] += gJ[5] * (-fy / (z * z));
+      gpc[2] += gJ[5] * (2.0 * fy * y / (z * z * z));
+    }
+    // mean2D
+    gpc[0] += gr[0] * fx / z;
+    gpc[1] += gr[1] * fy / z;
+    gpc[2] += gr[0] * (-fx * x / (z * z)) + gr[1] * (-fy * y / (z * z));
+    for (int a = 0; a < 3; ++a)
+      gmu[a] += W[a] * gpc[0] + W[3 + a] * gpc[1] + W[6 + a] * gpc[2];
+    if (o->means)
+      for (int a = 0; a < 3; ++a) o->means[3 * g + a] += gmu[a];
+    // Sc = W Sig W^T -> gSig = W^T gSc W
+    double tmp[9], gSig[9];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0;
+        for (int k = 0; k < 3; ++k) s += W[3 * k + a] * gSc[3 * k + c];
+        tmp[3 * a + c] = s;
+      }
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0;
+        for (int k = 0; k < 3; ++k) s += tmp[3 * a + k] * W[3 * k + c];
+        gSig[3 * a + c] = s;
+      }
+    // Sig = M M^T, M = Rq diag(s): gM = (gSig + gSig^T) M
+    double M[9], gM[9];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) M[3 * a + c] = r.Rq[3 * a + c] * r.s[c];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0;
+        for (int k = 0; k < 3; ++k) s += (gSig[3 * a + k] + gSig[3 * k + a]) * M[3 * k + c];
+        gM[3 * a + c] = s;
+      }
+    double gR[9];
+    for (int c = 0; c < 3; ++c) {
+      double gs = 0;
+      for (int a = 0; a < 3; ++a) {
+        gs += gM[3 * a + c] * r.Rq[3 * a + c];
+        gR[3 * a + c] = gM[3 * a + c] * r.s[c];
+      }
+      if (o->log_scales) o->log_scales[3 * g + c] += gs * r.s[c];
+    }
+    const double w = r.qn[0], qx = r.qn[1], qy = r.qn[2], qz = r.qn[3];
+    double gq[4];
+    gq[0] = 2 * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+    gq[1] = 2 * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2 * qx * gR[4] - w * gR[5] + qz * gR[6] +
+                 w * gR[7] - 2 * qx * gR[8]);
+    gq[2] = 2 * (-2 * qy * gR[0] + qx * gR[1] + w * gR[2] + qx * gR[3] + qz * gR[5] - w * gR[6] +
+                 qz * gR[7] - 2 * qy * gR[8]);
+    gq[3] = 2 * (-2 * qz * gR[0] - w * gR[1] + qx * gR[2] + w * gR[3] - 2 * qz * gR[4] +
+                 qy * gR[5] + qx * gR[6] + qy * gR[7]);
+    const double dq = gq[0] * r.qn[0] + gq[1] * r.qn[1] + gq[2] * r.qn[2] + gq[3] * r.qn[3];
+    if (o->quats)
+      for (int a = 0; a < 4; ++a) o->quats[4 * g + a] += (gq[a] - r.qn[a] * dq) / r.qnorm;
+  }
+  return 0;
+}
+
+// SH basis at unit directions (used by the orthonormality pins)
+void or_sh_basis(int deg, int n, const double* dirs, double* out) {
+  const int K = (deg + 1) * (deg + 1);
+  for (int i = 0; i < n; ++i) {
+    double Y[16];
+    sh_basis(dirs + 3 * i, Y, deg);
+    for (int k = 0; k < K; ++k) out[(size_t)i * K + k] = Y[k];
+  }
+}
+
+void or_quat_to_rot(const double* q, double* R) {
+  double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  double qn[4] = {q[0] / n, q[1] / n, q[2] / n, q[3] / n};
+  quat_to_rot(qn, R);
+}
+
+}  // extern "C"
