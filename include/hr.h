@@ -1,0 +1,239 @@
+/*
+ * hr.h - C ABI of the MI355X hybrid mesh-Gaussian rasterizer (libhybrid_raster.so).
+ *
+ * The library renders the hybrid representation of "Hybrid Mesh-Gaussian
+ * Representation for Efficient Indoor Scene Reconstruction" (arXiv 2506.06988):
+ *   - 3D Gaussians: centre, opacity, rotation, scale and SH colour, with
+ *     Sigma = R S S^T R^T projected to Sigma' = J W Sigma W^T J^T      (Sec. 3.1, Eq. 1)
+ *   - front-to-back alpha blending over depth-sorted Gaussians        (Sec. 3.1, Eq. 2)
+ *   - an opaque textured mesh rendered with barycentric UVs           (Sec. 3.1 "Textured mesh")
+ *   - joint rasterization: the mesh gives I_m and D_m, only Gaussians
+ *     with D_gs < D_m are blended and the residual transmittance T
+ *     weights I_m (or the background)                                  (Sec. 3.4 "Joint rasterization")
+ *   - gradients to every Gaussian parameter and to the texture map,
+ *     none to mesh vertices                                            (Sec. 3.4)
+ *   - the loss L1 + lambda * M_T * ||I~ - I~_m||^2                     (Sec. 3.4, transmittance-aware supervision)
+ *
+ * Conventions the paper inherits from its 3DGS code base without stating
+ * them are fields of hr_settings: 16x16 pixel tiles, 3-sigma extent, the
+ * 0.3 px^2 low-pass, alpha in [1/255, 0.99], the 1e-4 transmittance stop,
+ * the 0.2 Gaussian near plane, the 1.3 x FOV clamp of the Jacobian and the
+ * SH colour offset of 0.5 clamped at 0.
+ *
+ * Geometry: world and camera axes are x right, y down, z forward;
+ * p_cam = R p_world + t; the pixel (i, j) is sampled at (i + 1/2, j + 1/2).
+ *
+ * Memory and ownership
+ *   - Every array pointer is DEVICE memory owned by the caller, except the
+ *     hr_camera array, which is host memory read during the call.
+ *   - The library never allocates or frees device memory except inside
+ *     hr_batch_create/hr_batch_destroy (documented there), and keeps no state
+ *     between calls. All intermediate state lives in the caller's workspace,
+ *     sized by hr_query_workspace. The forward's workspace contents are the
+ *     saved context of the matching backward call.
+ *   - All work is enqueued on the given stream (hipStream_t passed as void*;
+ *     NULL = the null stream); calls return before the GPU finishes.
+ *   - Several cameras are rendered by one call. Their pixels are packed one
+ *     camera after another: camera c starts at pixel offset
+ *     P_c = sum_{c'<c} W_c' H_c'; images are planar [3, H_c, W_c] at 3 P_c.
+ *
+ * Errors
+ *   - Every entry point returns hr_status and never aborts or throws.
+ *   - Arguments are checked before anything is enqueued; on
+ *     HR_ERR_INVALID_ARGUMENT nothing is written. hr_last_error() returns a
+ *     thread-local description of the last failure.
+ *   - When the pair count exceeds the workspace's key capacity the outputs
+ *     are undefined, hr_stats.overflow is set on the device and, unless
+ *     HR_FLAG_NO_SYNC is given, the call synchronises the stream once and
+ *     returns HR_ERR_CAPACITY with hr_stats.n_keys holding the needed count.
+ *   - Non-finite Gaussian parameters cull that Gaussian; degenerate triangles
+ *     are skipped; n = 0 and n_faces = 0 are legal.
+ */
+#ifndef HR_H_
+#define HR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HR_ABI_VERSION 1
+
+typedef enum {
+  HR_OK = 0,
+  HR_ERR_INVALID_ARGUMENT = 1,
+  HR_ERR_CAPACITY = 2,
+  HR_ERR_HIP = 3,
+  HR_ERR_UNSUPPORTED = 4,
+  HR_ERR_INTERNAL = 5
+} hr_status;
+
+/* Gaussian set (Sec. 3.1): n Gaussians, structure of arrays, FP32. */
+typedef struct {
+  int32_t n;               /* >= 0 */
+  int32_t sh_degree;       /* 0..3; K = (sh_degree + 1)^2 coefficients */
+  const float* means;      /* [n,3] world centre u */
+  const float* log_scales; /* [n,3] S = diag(exp(log_scales)) */
+  const float* quats;      /* [n,4] (w,x,y,z), normalised by the library */
+  const float* opacity_logits; /* [n] opacity = sigmoid(logit) */
+  const float* sh;         /* [n,K,3] real SH coefficients per channel */
+} hr_gaussians;
+
+/* Textured triangle mesh (Sec. 3.1 "Textured mesh"). Each face corner has
+ * its own UV; texel (i, j) of a W x H texture is centred at
+ * ((i + 1/2)/W, (j + 1/2)/H), row 0 at V = 0, clamped at the edges. */
+typedef struct {
+  int32_t n_verts, n_faces; /* n_faces = 0: no mesh (Gaussians over bg) */
+  int32_t n_tex, tex_h, tex_w;
+  const float* verts;      /* [n_verts,3] */
+  const int32_t* faces;    /* [n_faces,3] vertex indices */
+  const float* uvs;        /* [n_faces,3,2] */
+  const int32_t* face_tex; /* [n_faces] texture index in [0, n_tex) */
+  const float* tex;        /* [n_tex,tex_h,tex_w,3] RGB, FP32 */
+} hr_mesh;
+
+/* Pinhole camera, host memory. */
+typedef struct {
+  int32_t width, height;
+  double fx, fy, cx, cy;
+  double R[9]; /* world -> camera rotation, row-major */
+  double t[3];
+} hr_camera;
+
+enum {
+  HR_FLAG_NO_SYNC = 1u << 0,      /* never synchronise to check the capacity */
+  HR_FLAG_DETACH_MASK = 1u << 1,  /* loss: no gradient through M_T */
+  HR_FLAG_EXPORT_KEYS = 1u << 2   /* forward: fill hr_outputs.keys/values/ranges */
+};
+
+typedef struct {
+  float bg[3];        /* I_bg, Sec. 3.4 (default 0) */
+  float low_pass;     /* added to the diagonal of Sigma' (0.3) */
+  float alpha_min;    /* Gaussians with alpha below are skipped (1/255) */
+  float alpha_max;    /* alpha clamp (0.99) */
+  float t_min;        /* a pixel stops before T would drop below (1e-4) */
+  float near_gs;      /* Gaussians with view z <= near_gs are culled (0.2) */
+  float near_mesh;    /* triangles are clipped at view z = near_mesh (0.05) */
+  float clamp_fov;    /* Jacobian direction clamp in units of tan(fov/2) (1.3) */
+  uint32_t flags;     /* HR_FLAG_* */
+  int32_t batch;      /* Gaussians staged in LDS per batch: 32,64,128,256 (0 = tuned default) */
+  int32_t variant;    /* blend kernel variant chosen by hr_autotune (0 = default) */
+} hr_settings;
+
+/* Counters written by the forward (device memory). */
+typedef struct {
+  uint32_t n_visible;  /* visible (camera, Gaussian) pairs */
+  uint32_t n_keys;     /* (tile, Gaussian) pairs, needed key capacity */
+  uint32_t overflow;   /* 1 when n_keys exceeded the capacity */
+  uint32_t n_tris;     /* visible clipped triangles */
+  uint64_t n_processed;/* sum over pixels of list entries examined */
+  uint64_t n_blended;  /* sum over pixels of Gaussians blended */
+} hr_stats;
+
+/* Outputs of the forward; every pointer is device memory, sized over the
+ * packed pixels of all cameras (P = sum W_c H_c) unless stated. */
+typedef struct {
+  float* image;          /* [3P] planar per camera: I_h, Sec. 3.4 */
+  float* final_T;        /* [P]  residual transmittance T */
+  float* mesh_rgb;       /* [3P] I_m (0 where no triangle), nullable */
+  float* mesh_depth;     /* [P]  D_m, view z of the mesh (+inf where none), nullable */
+  int32_t* tri_id;       /* [P]  covering face, -1 where none, nullable */
+  int32_t* n_contrib;    /* [P]  1-based list index of the last blended Gaussian, nullable */
+  int32_t* n_blended;    /* [P]  Gaussians blended, nullable */
+  int32_t* n_processed;  /* [P]  list entries examined incl. the terminating one, nullable */
+  int32_t* radii;        /* [n_cams*n] integer 3-sigma radius, 0 = culled, nullable */
+  uint64_t* keys;        /* [key_capacity] (global tile << 32 | fp32 depth bits), with EXPORT_KEYS */
+  uint32_t* values;      /* [key_capacity] Gaussian index, with EXPORT_KEYS */
+  uint32_t* ranges;      /* [n_tiles,2] [start,end) per global tile, with EXPORT_KEYS */
+  hr_stats* stats;       /* nullable */
+} hr_outputs;
+
+/* Gradients, accumulated (+=) into caller-zeroed device arrays; any may be
+ * NULL to skip it. Shapes match hr_gaussians / hr_mesh.tex. */
+typedef struct {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+  float* tex;
+} hr_grads;
+
+/* hr_settings with the defaults listed above. */
+hr_settings hr_default_settings(void);
+
+/* Bytes of workspace the forward/backward pair needs for these inputs and a
+ * key capacity (maximum number of (tile, Gaussian) pairs); 0 on invalid
+ * arguments. The global tile id of camera c's tile (tx, ty) is
+ * T_c + ty * ceil(W_c/16) + tx with T_c the tiles of the cameras before c. */
+size_t hr_query_workspace(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                          int32_t n_cams, const hr_settings* s, int64_t key_capacity);
+
+/* Forward joint rasterization (Sec. 3.4) of n_cams cameras:
+ * mesh raster -> I_m, D_m; Gaussian projection -> tile binning and depth
+ * sort -> per-pixel blend stopping at D_m; I_h = C + T * (I_m or I_bg).
+ * `workspace` (workspace_bytes >= hr_query_workspace(...)) keeps the
+ * context for hr_render_hybrid_backward. */
+hr_status hr_render_hybrid(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                           int32_t n_cams, const hr_settings* s, int64_t key_capacity,
+                           void* workspace, size_t workspace_bytes, hr_outputs* out,
+                           void* stream);
+
+/* Backward of hr_render_hybrid given upstream gradients of I_h, T and I_m
+ * (grad_final_T and grad_mesh_rgb nullable). Blends in reverse order,
+ * recovering each T from the stored final T by division, and accumulates
+ * gradients to the Gaussian parameters and the texture (Sec. 3.4). Every
+ * argument except the gradients must equal the forward's. */
+hr_status hr_render_hybrid_backward(const hr_gaussians* g, const hr_mesh* mesh,
+                                    const hr_camera* cams, int32_t n_cams, const hr_settings* s,
+                                    int64_t key_capacity, void* workspace, size_t workspace_bytes,
+                                    const float* grad_image, const float* grad_final_T,
+                                    const float* grad_mesh_rgb, hr_grads* grads, void* stream);
+
+/* Loss of Sec. 3.4 over n_pix packed pixels:
+ *   L = mean_{p,c} |I_h - I| + lambda_t * mean_{p,c} M_T(p) (I~ - I~_m)^2,
+ *   M_T = 1 / (1 + exp(-k (T - 1/2))), I~ = I and I~_m = I_m where
+ *   tri_id >= 0, else 0 (the means run over 3 n_pix values).
+ * Writes the loss (device scalar, deterministic reduction) and dL/dI_h,
+ * dL/dT (0 with HR_FLAG_DETACH_MASK) and dL/dI_m. `scratch` holds
+ * hr_loss_scratch_bytes(n_pix) bytes. Images are planar [3, n_pix]. */
+size_t hr_loss_scratch_bytes(int64_t n_pix);
+hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* mesh_rgb,
+                         const int32_t* tri_id, const float* target, int64_t n_pix,
+                         float lambda_t, float k, uint32_t flags, float* loss_out,
+                         float* grad_image, float* grad_final_T, float* grad_mesh_rgb,
+                         void* scratch, void* stream);
+
+/* Autotuner: times the blend variants (LDS batch size and staging depth) on
+ * the inputs of a forward that has just run with this workspace, checks that
+ * every variant's outputs are bit-identical, and writes the fastest choice to
+ * s->batch and s->variant. Synchronises the stream. */
+hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                      int32_t n_cams, hr_settings* s, int64_t key_capacity, void* workspace,
+                      size_t workspace_bytes, hr_outputs* out, int32_t repeats, void* stream);
+
+/* Batched training step captured in a hipGraph: forward of all cameras,
+ * loss against `target` (planar, packed like the image), backward into
+ * `grads`. The graph is recorded once for fixed shapes and pointers; every
+ * hr_batch_launch replays it. hr_batch_create allocates nothing on the
+ * device; the graph object itself is host state freed by hr_batch_destroy. */
+typedef struct hr_batch hr_batch;
+hr_status hr_batch_create(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                          int32_t n_cams, const hr_settings* s, int64_t key_capacity,
+                          void* workspace, size_t workspace_bytes, hr_outputs* out,
+                          const float* target, float lambda_t, float k, float* loss_out,
+                          float* grad_image, float* grad_final_T, float* grad_mesh_rgb,
+                          void* loss_scratch, hr_grads* grads, void* stream, hr_batch** batch);
+hr_status hr_batch_launch(hr_batch* batch, void* stream);
+void hr_batch_destroy(hr_batch* batch);
+
+const char* hr_status_string(hr_status s);
+const char* hr_last_error(void);
+int32_t hr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HR_H_ */

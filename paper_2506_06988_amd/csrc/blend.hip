@@ -1,0 +1,340 @@
+// Per-tile front-to-back blending with the mesh depth stop (Sec. 3.1 Eq. 2,
+// Sec. 3.4 "Joint rasterization") and its reverse-order backward.
+//
+// One 256-thread workgroup (4 waves of 64) per 16x16 tile, one pixel per
+// thread. The tile's depth-ordered list is streamed through LDS in batches of
+// BG records; every pixel walks the batch from LDS (broadcast reads). A pixel
+// stops at the first Gaussian whose depth reaches D_m, or before T would drop
+// under t_min; the workgroup leaves as soon as every pixel has stopped.
+#include "kernels.hpp"
+
+namespace hr {
+namespace {
+
+__device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, int tile) {
+  int lo = 0, hi = n_cams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cams[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// LDS form of a record: conic pre-scaled so that G = exp2(p2)
+struct Staged {
+  float4 a;  // u, v, A2 = -ca/2 log2e, B2 = -cb log2e
+  float4 b;  // C2 = -cc/2 log2e, opacity, depth, unused
+  float4 c;  // r, g, b, unused
+};
+
+__device__ __forceinline__ Staged stage(const GRec& R) {
+  Staged s;
+  s.a = make_float4(R.u, R.v, -0.5f * LOG2E * R.ca, -LOG2E * R.cb);
+  s.b = make_float4(-0.5f * LOG2E * R.cc, R.op, R.depth, 0.f);
+  s.c = make_float4(R.r, R.g, R.b, 0.f);
+  return s;
+}
+
+// exponent (log2 units) of the Gaussian at pixel centre (px, py); the
+// operation order is fixed so the backward reproduces the forward bit for bit
+__device__ __forceinline__ float gauss_p2(const float4& a, const float4& b, float px, float py,
+                                          float& dx, float& dy) {
+  dx = a.x - px;
+  dy = a.y - py;
+  const float dxx = dx * dx, dyy = dy * dy, dxy = dx * dy;
+  return __builtin_fmaf(a.z, dxx, __builtin_fmaf(b.x, dyy, a.w * dxy));
+}
+
+struct TileCtx {
+  int cam, tx, ty, i, j;
+  bool inside;
+  int64_t p;       // packed pixel
+  int64_t s, e;    // list range
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const SetDev& S, const CamDev* cams,
+                                            const uint32_t* tile_start, const uint32_t* tile_total,
+                                            int t) {
+  TileCtx c;
+  c.cam = find_cam_by_tile(cams, S.n_cams, t);
+  const CamDev& C = cams[c.cam];
+  const int lt = t - C.tile_off;
+  c.ty = lt / C.TX;
+  c.tx = lt - c.ty * C.TX;
+  c.i = c.tx * TILE + (threadIdx.x & 15);
+  c.j = c.ty * TILE + (threadIdx.x >> 4);
+  c.inside = c.i < C.W && c.j < C.H;
+  c.p = C.pix_off + (int64_t)c.j * C.W + c.i;
+  c.s = tile_start[t];
+  c.e = c.s + tile_total[t];
+  if (c.e > S.key_cap) c.e = S.key_cap;
+  return c;
+}
+
+template <int BG, bool PREFETCH>
+__global__ __launch_bounds__(256) void k_blend_fwd(
+    SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ tile_start,
+    const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ lists,
+    const GRec* __restrict__ rec_s, const unsigned long long* __restrict__ zbuf,
+    const float* __restrict__ mesh_rgb, float* __restrict__ image, float* __restrict__ T_ws,
+    int32_t* __restrict__ nc_ws, float* __restrict__ T_out, int32_t* __restrict__ nc_out,
+    int32_t* __restrict__ nb_out, int32_t* __restrict__ np_out, uint32_t* __restrict__ counters) {
+  __shared__ Staged sh[BG];
+  __shared__ unsigned long long red[2];
+  const int t = blockIdx.x;
+  const TileCtx tc = tile_ctx(S, cams, tile_start, tile_total, t);
+  const CamDev& C = cams[tc.cam];
+  const float px = (float)tc.i + 0.5f, py = (float)tc.j + 0.5f;
+  unsigned long long key = ~0ull;
+  if (tc.inside) key = zbuf[tc.p];
+  const float Dm = key == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(key >> 32));
+  const float amin = S.alpha_min, amax = S.alpha_max, tmin = S.t_min;
+  float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
+  int nc = 0, nbl = 0, npro = (int)(tc.e - tc.s);
+  bool done = !tc.inside;
+  if (threadIdx.x == 0) red[0] = red[1] = 0;
+  const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
+  GRec pre;
+  if (PREFETCH && threadIdx.x < BG && tc.s + threadIdx.x < tc.e)
+    pre = rec_s[min(lists[tc.s + threadIdx.x], rmax)];
+  for (int64_t b0 = tc.s; b0 < tc.e; b0 += BG) {
+    if (__syncthreads_and(done)) break;
+    const int n = (int)min((int64_t)BG, tc.e - b0);
+    if (threadIdx.x < n) {
+      if (PREFETCH) {
+        sh[threadIdx.x] = stage(pre);
+      } else {
+        sh[threadIdx.x] = stage(rec_s[min(lists[b0 + threadIdx.x], rmax)]);
+      }
+    }
+    __syncthreads();
+    if (PREFETCH && threadIdx.x < BG && b0 + BG + threadIdx.x < tc.e)
+      pre = rec_s[min(lists[b0 + BG + threadIdx.x], rmax)];
+    if (!done) {
+      for (int k = 0; k < n; ++k) {
+        const float4 a = sh[k].a, b = sh[k].b;
+        if (b.z >= Dm) {
+          done = true;
+          npro = (int)(b0 - tc.s) + k + 1;
+          break;
+        }
+        float dx, dy;
+        const float p2 = gauss_p2(a, b, px, py, dx, dy);
+        const float alpha = fminf(amax, b.y * __builtin_amdgcn_exp2f(p2));
+        if (alpha < amin) continue;
+        const float Tn = T * (1.f - alpha);
+        if (Tn < tmin) {
+          done = true;
+          npro = (int)(b0 - tc.s) + k + 1;
+          break;
+        }
+        const float4 c = sh[k].c;
+        const float wgt = alpha * T;
+        cr = __builtin_fmaf(c.x, wgt, cr);
+        cg = __builtin_fmaf(c.y, wgt, cg);
+        cb = __builtin_fmaf(c.z, wgt, cb);
+        T = Tn;
+        nc = (int)(b0 - tc.s) + k + 1;
+        ++nbl;
+      }
+    }
+  }
+  if (tc.inside) {
+    const int64_t hw = (int64_t)C.W * C.H;
+    const int64_t lp = tc.p - C.pix_off;
+    const int64_t pl = 3 * C.pix_off + lp;
+    float br, bgc, bb;
+    if (key != ~0ull) {
+      br = mesh_rgb[pl];
+      bgc = mesh_rgb[pl + hw];
+      bb = mesh_rgb[pl + 2 * hw];
+    } else {
+      br = S.bg[0];
+      bgc = S.bg[1];
+      bb = S.bg[2];
+    }
+    image[pl] = __builtin_fmaf(T, br, cr);
+    image[pl + hw] = __builtin_fmaf(T, bgc, cg);
+    image[pl + 2 * hw] = __builtin_fmaf(T, bb, cb);
+    T_ws[tc.p] = T;
+    nc_ws[tc.p] = nc;
+    if (T_out) T_out[tc.p] = T;
+    if (nc_out) nc_out[tc.p] = nc;
+    if (nb_out) nb_out[tc.p] = nbl;
+    if (np_out) np_out[tc.p] = npro;
+  } else {
+    npro = 0;
+  }
+  // workgroup sums of the counters
+  unsigned long long sp = (unsigned long long)npro, sb = (unsigned long long)nbl;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sp += __shfl_xor(sp, o, 64);
+    sb += __shfl_xor(sb, o, 64);
+  }
+  __syncthreads();
+  if (__lane_id() == 0) {
+    atomicAdd(&red[0], sp);
+    atomicAdd(&red[1], sb);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(counters + 6), red[0]);
+    atomicAdd(reinterpret_cast<unsigned long long*>(counters + 8), red[1]);
+  }
+}
+
+// ------------------------------------------------------------- backward --
+// Gradient of one blended Gaussian at one pixel, written to 9 accumulators:
+// u, v, conic a, b, c, opacity, r, g, b.
+template <int BG>
+__global__ __launch_bounds__(256) void k_blend_bwd(
+    SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ tile_start,
+    const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ lists,
+    const GRec* __restrict__ rec_s, const unsigned long long* __restrict__ zbuf,
+    const float* __restrict__ mesh_rgb, const float* __restrict__ T_ws,
+    const int32_t* __restrict__ nc_ws, const float* __restrict__ grad_image,
+    const float* __restrict__ grad_T, float* __restrict__ gacc) {
+  __shared__ Staged sh[BG];
+  __shared__ float4 raw[BG];     // ca, cb, cc, unused
+  __shared__ uint32_t rank[BG];
+  __shared__ int maxnc;
+  const int t = blockIdx.x;
+  const TileCtx tc = tile_ctx(S, cams, tile_start, tile_total, t);
+  const CamDev& C = cams[tc.cam];
+  const float px = (float)tc.i + 0.5f, py = (float)tc.j + 0.5f;
+  const float amin = S.alpha_min, amax = S.alpha_max;
+  float gr = 0.f, gg = 0.f, gb = 0.f, gT = 0.f, Tf = 1.f;
+  int nc = 0;
+  if (threadIdx.x == 0) maxnc = 0;
+  if (tc.inside) {
+    const int64_t hw = (int64_t)C.W * C.H;
+    const int64_t pl = 3 * C.pix_off + (tc.p - C.pix_off);
+    gr = grad_image[pl];
+    gg = grad_image[pl + hw];
+    gb = grad_image[pl + 2 * hw];
+    Tf = T_ws[tc.p];
+    nc = nc_ws[tc.p];
+    float br, bgc, bb;
+    if (zbuf[tc.p] != ~0ull) {
+      br = mesh_rgb[pl];
+      bgc = mesh_rgb[pl + hw];
+      bb = mesh_rgb[pl + 2 * hw];
+    } else {
+      br = S.bg[0];
+      bgc = S.bg[1];
+      bb = S.bg[2];
+    }
+    // I_h = C + T (I_m or bg): T receives the background's colour gradient
+    gT = (grad_T ? grad_T[tc.p] : 0.f) + gr * br + gg * bgc + gb * bb;
+  }
+  __syncthreads();
+  if (nc > 0) atomicMax(&maxnc, nc);
+  __syncthreads();
+  const int last = maxnc;
+  float T = Tf, Sr = 0.f, Sg = 0.f, Sb = 0.f;
+  const int lane = __lane_id();
+  for (int hi = last; hi > 0; hi -= BG) {
+    const int lo = hi - BG > 0 ? hi - BG : 0;
+    const int n = hi - lo;
+    if (threadIdx.x < n) {
+      const uint32_t r = min(lists[tc.s + lo + threadIdx.x], (uint32_t)((int64_t)S.n * S.n_cams - 1));
+      const GRec R = rec_s[r];
+      sh[threadIdx.x] = stage(R);
+      raw[threadIdx.x] = make_float4(R.ca, R.cb, R.cc, 0.f);
+      rank[threadIdx.x] = r;
+    }
+    __syncthreads();
+    for (int k = n - 1; k >= 0; --k) {
+      const int idx = lo + k + 1;  // 1-based list position
+      float g[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[q] = 0.f;
+      bool contrib = idx <= nc;
+      float alpha = 0.f, G = 0.f, dx = 0.f, dy = 0.f;
+      const float4 a = sh[k].a, b = sh[k].b;
+      if (contrib) {
+        const float p2 = gauss_p2(a, b, px, py, dx, dy);
+        G = __builtin_amdgcn_exp2f(p2);
+        const float ag = b.y * G;
+        alpha = fminf(amax, ag);
+        contrib = alpha >= amin;
+        if (contrib) {
+          const float4 c = sh[k].c;
+          T = T / (1.f - alpha);  // transmittance in front of this Gaussian
+          const float w = alpha * T;
+          g[6] = w * gr;
+          g[7] = w * gg;
+          g[8] = w * gb;
+          const float galpha = T * ((c.x - Sr) * gr + (c.y - Sg) * gg + (c.z - Sb) * gb) -
+                               gT * Tf / (1.f - alpha);
+          Sr = alpha * c.x + (1.f - alpha) * Sr;
+          Sg = alpha * c.y + (1.f - alpha) * Sg;
+          Sb = alpha * c.z + (1.f - alpha) * Sb;
+          if (ag < amax) {
+            g[5] = galpha * G;
+            // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy with dx = u - px
+            const float gp = galpha * b.y * G;
+            const float4 rw = raw[k];
+            g[0] = -gp * (rw.x * dx + rw.y * dy);
+            g[1] = -gp * (rw.z * dy + rw.y * dx);
+            g[2] = -0.5f * gp * dx * dx;
+            g[3] = -gp * dx * dy;
+            g[4] = -0.5f * gp * dy * dy;
+          }
+        }
+      }
+      const unsigned long long any = __ballot(contrib);
+      if (any) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q] = wave_sum(g[q]);
+        if (lane == 0) {
+          float* dst = gacc + (size_t)rank[k] * 9;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) atomicAdd(dst + q, g[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+#define HR_FWD(BG, PF)                                                                          \
+  hipLaunchKernelGGL((k_blend_fwd<BG, PF>), dim3(S.n_tiles), dim3(256), 0, st, S, w.cams,       \
+                     w.tile_start, w.tile_total, w.lists, w.rec_s,                              \
+                     (const unsigned long long*)w.zbuf, w.mesh_rgb, out->image, w.final_T,      \
+                     w.n_contrib, out->final_T, out->n_contrib, out->n_blended, out->n_processed, \
+                     w.counters)
+
+void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int batch, int variant,
+                          hipStream_t st) {
+  if (S.n_tiles == 0) return;
+  const bool pf = variant == 1;
+  switch (batch) {
+    case 32: if (pf) HR_FWD(32, true); else HR_FWD(32, false); break;
+    case 64: if (pf) HR_FWD(64, true); else HR_FWD(64, false); break;
+    case 128: if (pf) HR_FWD(128, true); else HR_FWD(128, false); break;
+    default: if (pf) HR_FWD(256, true); else HR_FWD(256, false); break;
+  }
+}
+
+#define HR_BWD(BG)                                                                              \
+  hipLaunchKernelGGL((k_blend_bwd<BG>), dim3(S.n_tiles), dim3(256), 0, st, S, w.cams,           \
+                     w.tile_start, w.tile_total, w.lists, w.rec_s,                              \
+                     (const unsigned long long*)w.zbuf, w.mesh_rgb, w.final_T, w.n_contrib,     \
+                     grad_image, grad_T, w.gacc)
+
+void launch_blend_backward(const SetDev& S, const Work& w, const float* grad_image,
+                           const float* grad_T, int batch, hipStream_t st) {
+  if (S.n_tiles == 0) return;
+  switch (batch) {
+    case 32: HR_BWD(32); break;
+    case 64: HR_BWD(64); break;
+    case 128: HR_BWD(128); break;
+    default: HR_BWD(256); break;
+  }
+}
+
+}  // namespace hr

@@ -1,0 +1,318 @@
+// Backward of the projection (chain rule from the per-rank record gradients
+// to the Gaussian parameters, summed over cameras in registers), backward of
+// the bilinear texture fetch, and the loss of Sec. 3.4.
+#include "kernels.hpp"
+#include "mesh_math.hpp"
+#include "project_math.hpp"
+
+namespace hr {
+namespace {
+
+// One thread per Gaussian; loops over cameras, recomputes the projection in
+// FP64 and accumulates every parameter gradient before one write per array.
+__global__ __launch_bounds__(128) void k_project_bwd(
+    SetDev S, const CamDev* __restrict__ cams, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ logits, const float* __restrict__ sh,
+    const int32_t* __restrict__ rank_of, const float* __restrict__ gacc,
+    float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
+    float* __restrict__ g_logit, float* __restrict__ g_sh) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= S.n) return;
+  const int K = (S.sh_degree + 1) * (S.sh_degree + 1);
+  double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glg = 0;
+  float gshr[48];
+#pragma unroll
+  for (int k = 0; k < 48; ++k) gshr[k] = 0.f;
+  bool any = false;
+  const float* shg = sh + (size_t)g * K * 3;
+  for (int c = 0; c < S.n_cams; ++c) {
+    const int r = rank_of[(int64_t)c * S.n + g];
+    if (r < 0) continue;
+    const float* ga = gacc + (size_t)r * 9;
+    double G9[9];
+    bool nz = false;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      G9[q] = ga[q];
+      nz = nz || G9[q] != 0.0;
+    }
+    if (!nz) continue;
+    any = true;
+    const CamDev& cam = cams[c];
+    Proj P;
+    project_gaussian(S, cam, means, log_scales, quats, logits, sh, g, P, true);
+    if (!P.vis) continue;
+    // opacity
+    glg += G9[5] * P.op * (1.0 - P.op);
+    // colour: SH coefficients and the view direction
+    double Y[16];
+    sh_eval(P.dir, S.sh_degree, Y);
+    double wdir[16];
+    for (int k = 0; k < K; ++k) wdir[k] = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      if (P.clamped[ch]) continue;
+      const double gc = G9[6 + ch];
+      for (int k = 0; k < K; ++k) {
+        gshr[3 * k + ch] += (float)(Y[k] * gc);
+        wdir[k] += (double)shg[3 * k + ch] * gc;
+      }
+    }
+    double gdir[3] = {0, 0, 0};
+    sh_grad_acc(P.dir, S.sh_degree, wdir, gdir);
+    const double dd = gdir[0] * P.dir[0] + gdir[1] * P.dir[1] + gdir[2] * P.dir[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - P.dir[a] * dd) / P.dnorm;
+    // conic -> Sigma': H = -Q G Q with G the symmetric gradient of the conic
+    const double q00 = P.con[0], q01 = P.con[1], q11 = P.con[2];
+    const double G00 = G9[2], G01 = 0.5 * G9[3], G11 = G9[4];
+    const double a00 = q00 * G00 + q01 * G01, a01 = q00 * G01 + q01 * G11;
+    const double a10 = q01 * G00 + q11 * G01, a11 = q01 * G01 + q11 * G11;
+    const double H00 = -(a00 * q00 + a01 * q01), H01 = -(a00 * q01 + a01 * q11);
+    const double H11 = -(a10 * q01 + a11 * q11);
+    // Sigma' = J Sc J^T + lp:  gSc = J^T H J,  gJ = 2 H J Sc
+    const double j00 = P.J[0], j02 = P.J[1], j11 = P.J[2], j12 = P.J[3];
+    // HJ (2x3): row a = H[a][0] J[0][:] + H[a][1] J[1][:], J rows (j00,0,j02), (0,j11,j12)
+    const double hj00 = H00 * j00, hj01 = H01 * j11, hj02 = H00 * j02 + H01 * j12;
+    const double hj10 = H01 * j00, hj11 = H11 * j11, hj12 = H01 * j02 + H11 * j12;
+    // gSc[k][l] = J[0][k] HJ[0][l] + J[1][k] HJ[1][l]
+    double gSc[9];
+    const double J0[3] = {j00, 0.0, j02}, J1[3] = {0.0, j11, j12};
+    const double HJ0[3] = {hj00, hj01, hj02}, HJ1[3] = {hj10, hj11, hj12};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) gSc[3 * k + l] = J0[k] * HJ0[l] + J1[k] * HJ1[l];
+    const double Sc[9] = {P.Sc[0], P.Sc[1], P.Sc[2], P.Sc[1], P.Sc[3], P.Sc[4],
+                          P.Sc[2], P.Sc[4], P.Sc[5]};
+    auto gJ = [&](const double* HJr, int col) {
+      return 2.0 * (HJr[0] * Sc[col] + HJr[1] * Sc[3 + col] + HJr[2] * Sc[6 + col]);
+    };
+    const double gj00 = gJ(HJ0, 0), gj02 = gJ(HJ0, 2), gj11 = gJ(HJ1, 1), gj12 = gJ(HJ1, 2);
+    const double x = P.pc[0], y = P.pc[1], z = P.pc[2];
+    const double fx = cam.fx, fy = cam.fy, iz = 1.0 / z, iz2 = iz * iz;
+    double gpc[3] = {0, 0, 0};
+    gpc[2] += gj00 * (-fx * iz2) + gj11 * (-fy * iz2);
+    if (P.clx) {
+      gpc[2] += gj02 * (fx * P.xc * iz2);
+    } else {
+      gpc[0] += gj02 * (-fx * iz2);
+      gpc[2] += gj02 * (2.0 * fx * x * iz2 * iz);
+    }
+    if (P.cly) {
+      gpc[2] += gj12 * (fy * P.yc * iz2);
+    } else {
+      gpc[1] += gj12 * (-fy * iz2);
+      gpc[2] += gj12 * (2.0 * fy * y * iz2 * iz);
+    }
+    // mean2D
+    gpc[0] += G9[0] * fx * iz;
+    gpc[1] += G9[1] * fy * iz;
+    gpc[2] += -(G9[0] * fx * x + G9[1] * fy * y) * iz2;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      gmu[a] += cam.R[a] * gpc[0] + cam.R[3 + a] * gpc[1] + cam.R[6 + a] * gpc[2];
+    // Sigma_cam = N N^T, N = W Rq S:  gN = 2 gSc N (gSc symmetric)
+    double gN[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        gN[3 * i + j] = (gSc[3 * i] + gSc[i]) * P.N[j] + (gSc[3 * i + 1] + gSc[3 + i]) * P.N[3 + j] +
+                        (gSc[3 * i + 2] + gSc[6 + i]) * P.N[6 + j];
+    // N[i][j] = (W Rq)[i][j] s_j
+    double gWR[9];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double gs = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double wr = cam.R[3 * i] * P.Rq[j] + cam.R[3 * i + 1] * P.Rq[3 + j] +
+                          cam.R[3 * i + 2] * P.Rq[6 + j];
+        gs += gN[3 * i + j] * wr;
+        gWR[3 * i + j] = gN[3 * i + j] * P.s[j];
+      }
+      gls[j] += gs * P.s[j];
+    }
+    // gRq = W^T gWR
+    double gR[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        gR[3 * i + j] = cam.R[i] * gWR[j] + cam.R[3 + i] * gWR[3 + j] + cam.R[6 + i] * gWR[6 + j];
+    const double w = P.qn[0], qa = P.qn[1], qb = P.qn[2], qc = P.qn[3];
+    double gqn[4];
+    gqn[0] = 2.0 * (-qc * gR[1] + qb * gR[2] + qc * gR[3] - qa * gR[5] - qb * gR[6] + qa * gR[7]);
+    gqn[1] = 2.0 * (qb * gR[1] + qc * gR[2] + qb * gR[3] - 2.0 * qa * gR[4] - w * gR[5] +
+                    qc * gR[6] + w * gR[7] - 2.0 * qa * gR[8]);
+    gqn[2] = 2.0 * (-2.0 * qb * gR[0] + qa * gR[1] + w * gR[2] + qa * gR[3] + qc * gR[5] -
+                    w * gR[6] + qc * gR[7] - 2.0 * qb * gR[8]);
+    gqn[3] = 2.0 * (-2.0 * qc * gR[0] - w * gR[1] + qa * gR[2] + w * gR[3] - 2.0 * qc * gR[4] +
+                    qb * gR[5] + qa * gR[6] + qb * gR[7]);
+    const double dq = gqn[0] * w + gqn[1] * qa + gqn[2] * qb + gqn[3] * qc;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gq[a] += (gqn[a] - P.qn[a] * dq) / P.qnorm;
+  }
+  if (!any) return;
+  if (g_means)
+    for (int a = 0; a < 3; ++a) g_means[3 * g + a] += (float)gmu[a];
+  if (g_ls)
+    for (int a = 0; a < 3; ++a) g_ls[3 * g + a] += (float)gls[a];
+  if (g_q)
+    for (int a = 0; a < 4; ++a) g_q[4 * g + a] += (float)gq[a];
+  if (g_logit) g_logit[g] += (float)glg;
+  if (g_sh)
+    for (int k = 0; k < 3 * K; ++k) g_sh[(size_t)g * K * 3 + k] += gshr[k];
+}
+
+__device__ __forceinline__ int find_cam_by_pix(const CamDev* cams, int n_cams, int64_t p) {
+  int lo = 0, hi = n_cams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cams[mid].pix_off <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights
+__global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restrict__ cams,
+                                                 const unsigned long long* __restrict__ zbuf,
+                                                 const TriRec* __restrict__ tris,
+                                                 const float* __restrict__ T_ws,
+                                                 const float* __restrict__ grad_image,
+                                                 const float* __restrict__ grad_mesh,
+                                                 float* __restrict__ grad_tex) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= S.n_pix) return;
+  const unsigned long long key = zbuf[p];
+  if (key == ~0ull) return;
+  const int c = find_cam_by_pix(cams, S.n_cams, p);
+  const CamDev& C = cams[c];
+  const int64_t lp = p - C.pix_off;
+  const int64_t hw = (int64_t)C.W * C.H;
+  const int i = (int)(lp % C.W), j = (int)(lp / C.W);
+  const float Tf = T_ws[p];
+  const int64_t pl = 3 * C.pix_off + lp;
+  float gm[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    gm[ch] = (grad_image ? Tf * grad_image[pl + ch * hw] : 0.f) +
+             (grad_mesh ? grad_mesh[pl + ch * hw] : 0.f);
+  }
+  if (gm[0] == 0.f && gm[1] == 0.f && gm[2] == 0.f) return;
+  const TriRec& T = tris[(uint32_t)key];
+  int64_t e[3];
+  tri_cover(T, i, j, e);
+  double uv[2];
+  tri_interp(T, e, uv);
+  const Taps tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
+  const float wx = tp.fx, wy = tp.fy;
+  const float w00 = (1.f - wx) * (1.f - wy), w10 = wx * (1.f - wy), w01 = (1.f - wx) * wy,
+              w11 = wx * wy;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    atomicAdd(grad_tex + tp.o00 + ch, w00 * gm[ch]);
+    atomicAdd(grad_tex + tp.o10 + ch, w10 * gm[ch]);
+    atomicAdd(grad_tex + tp.o01 + ch, w01 * gm[ch]);
+    atomicAdd(grad_tex + tp.o11 + ch, w11 * gm[ch]);
+  }
+}
+
+// ------------------------------------------------------------------ loss --
+constexpr int LB = 256;
+
+__global__ __launch_bounds__(LB) void k_loss(const float* __restrict__ image,
+                                             const float* __restrict__ T,
+                                             const float* __restrict__ mesh,
+                                             const int32_t* __restrict__ tri,
+                                             const float* __restrict__ target, int64_t n_pix,
+                                             float lambda_t, float k, int detach,
+                                             float* __restrict__ g_image, float* __restrict__ g_T,
+                                             float* __restrict__ g_mesh,
+                                             double* __restrict__ partial) {
+  __shared__ double red[LB / 64];
+  const int64_t p = (int64_t)blockIdx.x * LB + threadIdx.x;
+  double acc = 0.0;
+  if (p < n_pix) {
+    const float inv = 1.0f / (3.0f * (float)n_pix);
+    const bool has = tri[p] >= 0;
+    const float t = T[p];
+    const float mt = 1.f / (1.f + __expf(-k * (t - 0.5f)));
+    float sq = 0.f;
+    for (int ch = 0; ch < 3; ++ch) {
+      const int64_t q = ch * n_pix + p;
+      const float d = image[q] - target[q];
+      acc += fabs((double)d);
+      g_image[q] = (d > 0.f ? inv : (d < 0.f ? -inv : 0.f));
+      if (has) {
+        const float dm = mesh[q] - target[q];
+        sq += dm * dm;
+        g_mesh[q] = lambda_t * mt * 2.f * dm * inv;
+      } else {
+        g_mesh[q] = 0.f;
+      }
+    }
+    acc += (double)lambda_t * (double)mt * (double)sq;
+    g_T[p] = (detach || !has) ? 0.f : lambda_t * sq * mt * (1.f - mt) * k * inv;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (__lane_id() == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < LB / 64; ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(LB) void k_loss_final(const double* __restrict__ partial, int64_t nb,
+                                                   int64_t n_pix, float* __restrict__ out) {
+  __shared__ double red[LB / 64];
+  double acc = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += LB) acc += partial[b];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (__lane_id() == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < LB / 64; ++w) s += red[w];
+    *out = (float)(s / (3.0 * (double)n_pix));
+  }
+}
+
+}  // namespace
+
+void launch_project_backward(const SetDev& S, const CamDev* cams, const hr_gaussians& g,
+                             const Work& w, hr_grads* grads, hipStream_t st) {
+  if (S.n == 0) return;
+  hipLaunchKernelGGL(k_project_bwd, dim3((S.n + 127) / 128), dim3(128), 0, st, S, cams, g.means,
+                     g.log_scales, g.quats, g.opacity_logits, g.sh, w.rank_of, w.gacc,
+                     grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
+                     grads->sh);
+}
+
+void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,
+                             const float* grad_image, const float* grad_mesh_rgb, float* grad_tex,
+                             hipStream_t st) {
+  (void)m;
+  if (S.n_faces == 0 || !grad_tex || S.n_pix == 0) return;
+  hipLaunchKernelGGL(k_tex_bwd, dim3((unsigned)((S.n_pix + 255) / 256)), dim3(256), 0, st, S, w.cams,
+                     (const unsigned long long*)w.zbuf, w.tris, w.final_T, grad_image,
+                     grad_mesh_rgb, grad_tex);
+}
+
+void launch_loss(const float* image, const float* T, const float* mesh_rgb, const int32_t* tri,
+                 const float* target, int64_t n_pix, float lambda_t, float k, bool detach,
+                 float* loss, float* g_image, float* g_T, float* g_mesh, void* scratch,
+                 hipStream_t st) {
+  const int64_t nb = (n_pix + LB - 1) / LB;
+  double* partial = (double*)scratch;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_loss, dim3((unsigned)nb), dim3(LB), 0, st, image, T, mesh_rgb, tri, target,
+                       n_pix, lambda_t, k, detach ? 1 : 0, g_image, g_T, g_mesh, partial);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LB), 0, st, partial, nb, n_pix, loss);
+}
+
+}  // namespace hr

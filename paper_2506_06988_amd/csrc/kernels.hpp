@@ -1,0 +1,92 @@
+// Workspace view and launch wrappers of the HIP kernels (host side).
+#pragma once
+
+#include "common.hpp"
+
+namespace hr {
+
+// Device pointers into the caller's workspace (see plan.cpp for the layout).
+struct Work {
+  CamDev* cams;          // [n_cams]
+  // per (camera, Gaussian) item, M = n_cams * n
+  uint32_t* tiles;       // [M] tiles touched, 0 = culled
+  uint32_t* vis;         // [M] 1 = visible
+  uint32_t* vis_scan;    // [M] exclusive scan of vis
+  uint32_t* dkey;        // [M] fp32 depth bits
+  GRec* rec;             // [M]
+  uint2* rect;           // [M] packed tile rectangle
+  int32_t* rank_of;      // [M] depth rank, -1 = culled
+  // depth sort (radix, ping-pong) and per-rank arrays
+  uint32_t* skey[2];     // [M]
+  uint32_t* sval[2];     // [M]
+  uint32_t* rs_hist;     // [256 * rs_blocks]
+  int64_t rs_blocks;
+  uint32_t* vis_off;     // [n_cams + 1] first rank of each camera
+  GRec* rec_s;           // [M] by rank
+  uint2* rect_s;         // [M] by rank
+  uint32_t* tiles_s;     // [M + 1] by rank
+  uint32_t* item_s;      // [M] item of each rank
+  uint64_t* pair_off;    // [M + 1]
+  // tile binning
+  uint32_t* mat;         // chunk x tile counts, then column prefixes
+  int64_t chunk_rows;    // total chunk rows
+  uint32_t* tile_total;  // [n_tiles]
+  uint32_t* tile_start;  // [n_tiles]
+  uint32_t* lists;       // [key_cap] ranks, per tile sorted by rank
+  // counters: [0] n_vis, [1] overflow, [2..3] K (u64), [4] n_tris, [5] n_blocks,
+  // [6..7] sum n_processed (u64), [8..9] sum n_blended (u64)
+  uint32_t* counters;
+  // mesh
+  uint64_t* zbuf;        // [P] fp32 depth bits << 32 | triangle index
+  uint32_t* tri_cnt;     // [n_cams * F]
+  uint32_t* blk_cnt;     // [n_cams * F]
+  uint32_t* tri_off;     // [n_cams * F]
+  uint32_t* blk_off;     // [n_cams * F + 1]
+  TriRec* tris;          // [2 * n_cams * F]
+  // per pixel, kept for the backward
+  float* final_T;        // [P]
+  int32_t* n_contrib;    // [P]
+  float* mesh_rgb;       // [3P]
+  // backward accumulators, [M][9] by rank: u, v, conic a b c, opacity, r g b
+  float* gacc;
+  // scratch of the scans
+  void* scan_scratch;
+};
+
+// host launch wrappers (all asynchronous on `st`)
+void launch_project(const SetDev& S, const CamDev* cams, const hr_gaussians& g, const Work& w,
+                    int32_t* radii, hipStream_t st);
+void launch_depth_sort(const SetDev& S, const Work& w, hipStream_t st);
+void launch_binning(const SetDev& S, const Work& w, int n_cams, hr_outputs* out, hipStream_t st);
+void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* out,
+                 hipStream_t st);
+void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int batch, int variant,
+                          hipStream_t st);
+void launch_blend_backward(const SetDev& S, const Work& w, const float* grad_image,
+                           const float* grad_T, int batch, hipStream_t st);
+void launch_project_backward(const SetDev& S, const CamDev* cams, const hr_gaussians& g,
+                             const Work& w, hr_grads* grads, hipStream_t st);
+void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,
+                             const float* grad_image, const float* grad_mesh_rgb, float* grad_tex,
+                             hipStream_t st);
+void launch_loss(const float* image, const float* T, const float* mesh_rgb, const int32_t* tri,
+                 const float* target, int64_t n_pix, float lambda_t, float k, bool detach,
+                 float* loss, float* g_image, float* g_T, float* g_mesh, void* scratch,
+                 hipStream_t st);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+
+// camera upload by kernel argument (graph-capturable, no host staging buffer)
+constexpr int CAMS_PER_UPLOAD = 16;
+struct CamUpload {
+  CamDev c[CAMS_PER_UPLOAD];
+  int32_t first, count;
+};
+static_assert(sizeof(CamUpload) + 8 <= 4096, "camera upload must fit in kernel arguments");
+void launch_upload_cams(const CamUpload& u, CamDev* dst, hipStream_t st);
+void launch_counters_to_stats(const uint32_t* counters, hr_stats* stats, hipStream_t st);
+void launch_zero_gacc(float* gacc, const uint32_t* counters, hipStream_t st);
+void launch_count_mismatch(const float* a, const float* b, int64_t n, uint32_t* out,
+                           hipStream_t st);
+void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st);
+
+}  // namespace hr

@@ -1,0 +1,222 @@
+// Z-buffered rasterization of the textured mesh for every camera (Sec. 3.4:
+// the mesh is rendered first, giving I_m and D_m).
+//   k_mesh_count   per (camera, face): clip, snap, count kept triangles and
+//                  8x8 pixel blocks of their bounding boxes
+//   k_mesh_setup   per (camera, face): write the kept triangles compactly
+//   k_mesh_raster  one wave per (triangle, block): 64 lanes = 64 pixels test
+//                  integer edge functions and atomicMin a 64-bit key
+//                  (fp32 depth bits << 32 | triangle index) into the z-buffer.
+//                  Triangle indices increase with face id, so equal depths
+//                  resolve to the lower face whatever the launch order.
+//   k_mesh_resolve per pixel: perspective-correct UV and bilinear texture fetch
+#include "kernels.hpp"
+#include "mesh_math.hpp"
+
+namespace hr {
+namespace {
+
+__global__ __launch_bounds__(256) void k_mesh_count(SetDev S, const CamDev* __restrict__ cams,
+                                                    const float* __restrict__ verts,
+                                                    const int32_t* __restrict__ faces,
+                                                    const float* __restrict__ uvs,
+                                                    uint32_t* __restrict__ tri_cnt,
+                                                    uint32_t* __restrict__ blk_cnt) {
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t MF = (int64_t)S.n_faces * S.n_cams;
+  if (item >= MF) {
+    if (item == MF) blk_cnt[MF] = 0;
+    return;
+  }
+  const int cam = (int)(item / S.n_faces);
+  const int f = (int)(item - (int64_t)cam * S.n_faces);
+  const CamDev& C = cams[cam];
+  CV poly[4];
+  const int np = clip_face(C, (double)S.near_mesh, S.n_verts, verts, faces, uvs, f, poly);
+  uint32_t nt = 0, nb = 0;
+  for (int s = 0; s + 2 < np; ++s) {
+    TriRec T;
+    if (setup_tri(C, poly, s, T)) {
+      ++nt;
+      nb += (uint32_t)tri_blocks(T);
+    }
+  }
+  tri_cnt[item] = nt;
+  blk_cnt[item] = nb;
+}
+
+__global__ __launch_bounds__(256) void k_mesh_setup(SetDev S, const CamDev* __restrict__ cams,
+                                                    const float* __restrict__ verts,
+                                                    const int32_t* __restrict__ faces,
+                                                    const float* __restrict__ uvs,
+                                                    const int32_t* __restrict__ face_tex,
+                                                    const uint32_t* __restrict__ tri_cnt,
+                                                    const uint32_t* __restrict__ tri_off,
+                                                    TriRec* __restrict__ tris) {
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t MF = (int64_t)S.n_faces * S.n_cams;
+  if (item >= MF || tri_cnt[item] == 0) return;
+  const int cam = (int)(item / S.n_faces);
+  const int f = (int)(item - (int64_t)cam * S.n_faces);
+  const CamDev& C = cams[cam];
+  CV poly[4];
+  const int np = clip_face(C, (double)S.near_mesh, S.n_verts, verts, faces, uvs, f, poly);
+  uint32_t o = tri_off[item];
+  for (int s = 0; s + 2 < np; ++s) {
+    TriRec T;
+    if (setup_tri(C, poly, s, T)) {
+      T.face = f;
+      const int tx = face_tex[f];  // out-of-range texture ids are clamped
+      T.tex = tx < 0 ? 0 : (tx >= S.n_tex ? S.n_tex - 1 : tx);
+      T.cam = cam;
+      T.pad = 0;
+      tris[o++] = T;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mesh_raster(SetDev S, const CamDev* __restrict__ cams,
+                                                     const uint32_t* __restrict__ tri_off,
+                                                     const uint32_t* __restrict__ blk_off,
+                                                     const TriRec* __restrict__ tris,
+                                                     unsigned long long* __restrict__ zbuf) {
+  const int64_t MF = (int64_t)S.n_faces * S.n_cams;
+  const uint32_t nblk = blk_off[MF];
+  const int lane = __lane_id();
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nblk; b += waves) {
+    // (camera, face) entry holding block b
+    int64_t lo = 0, hi = MF - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (blk_off[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    uint32_t lb = b - blk_off[lo];
+    uint32_t t = tri_off[lo];
+    int nb0 = tri_blocks(tris[t]);
+    if ((int)lb >= nb0) {
+      lb -= nb0;
+      ++t;
+    }
+    const TriRec& T = tris[t];
+    const CamDev& C = cams[T.cam];
+    const int nbx = T.bx1 - T.bx0 + 1;
+    const int bx = T.bx0 + (int)(lb % nbx), by = T.by0 + (int)(lb / nbx);
+    const int i = bx * 8 + (lane & 7), j = by * 8 + (lane >> 3);
+    if (i >= C.W || j >= C.H) continue;
+    int64_t e[3];
+    if (!tri_cover(T, i, j, e)) continue;
+    const double z = tri_interp(T, e, nullptr);
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint(__double2float_rn(z)) << 32) | t;
+    atomicMin(&zbuf[C.pix_off + (int64_t)j * C.W + i], key);
+  }
+}
+
+__device__ __forceinline__ int find_cam_by_pix(const CamDev* cams, int n_cams, int64_t p) {
+  int lo = 0, hi = n_cams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cams[mid].pix_off <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __restrict__ cams,
+                                                      const unsigned long long* __restrict__ zbuf,
+                                                      const TriRec* __restrict__ tris,
+                                                      const float* __restrict__ tex,
+                                                      float* __restrict__ mesh_rgb_ws,
+                                                      float* __restrict__ mesh_rgb,
+                                                      float* __restrict__ mesh_depth,
+                                                      int32_t* __restrict__ tri_id) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= S.n_pix) return;
+  const int c = find_cam_by_pix(cams, S.n_cams, p);
+  const CamDev& C = cams[c];
+  const int64_t lp = p - C.pix_off;
+  const int64_t hw = (int64_t)C.W * C.H;
+  const int i = (int)(lp % C.W), j = (int)(lp / C.W);
+  const unsigned long long key = zbuf[p];
+  float rgb[3] = {0.f, 0.f, 0.f};
+  float depth = __int_as_float(0x7f800000);
+  int face = -1;
+  if (key != ~0ull) {
+    const TriRec& T = tris[(uint32_t)key];
+    int64_t e[3];
+    tri_cover(T, i, j, e);
+    double uv[2];
+    tri_interp(T, e, uv);
+    const Taps tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
+    const float wx = tp.fx, wy = tp.fy;
+    const float w00 = (1.f - wx) * (1.f - wy), w10 = wx * (1.f - wy), w01 = (1.f - wx) * wy,
+                w11 = wx * wy;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+      rgb[ch] = w00 * tex[tp.o00 + ch] + w10 * tex[tp.o10 + ch] + w01 * tex[tp.o01 + ch] +
+                w11 * tex[tp.o11 + ch];
+    depth = __uint_as_float((uint32_t)(key >> 32));
+    face = T.face;
+  }
+  const int64_t pl = 3 * C.pix_off;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    mesh_rgb_ws[pl + ch * hw + lp] = rgb[ch];
+    if (mesh_rgb) mesh_rgb[pl + ch * hw + lp] = rgb[ch];
+  }
+  if (mesh_depth) mesh_depth[p] = depth;
+  if (tri_id) tri_id[p] = face;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+unsigned fill_grid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(n)), dim3(256), 0, st, p, v, n);
+}
+
+void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(256), 0, st, p, v, n);
+}
+
+void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* out,
+                 hipStream_t st) {
+  launch_fill_u64(w.zbuf, ~0ull, S.n_pix, st);
+  const int64_t MF = (int64_t)S.n_faces * S.n_cams;
+  if (MF > 0) {
+    hipLaunchKernelGGL(k_mesh_count, dim3((unsigned)((MF + 1 + 255) / 256)), dim3(256), 0, st, S,
+                       w.cams, m.verts, m.faces, m.uvs, w.tri_cnt, w.blk_cnt);
+    scan_u32(w.tri_cnt, w.tri_off, MF, w.counters + 4, w.scan_scratch, st);
+    scan_u32(w.blk_cnt, w.blk_off, MF + 1, w.counters + 5, w.scan_scratch, st);
+    hipLaunchKernelGGL(k_mesh_setup, dim3((unsigned)((MF + 255) / 256)), dim3(256), 0, st, S,
+                       w.cams, m.verts, m.faces, m.uvs, m.face_tex, w.tri_cnt, w.tri_off, w.tris);
+    hipLaunchKernelGGL(k_mesh_raster, dim3(2048), dim3(256), 0, st, S, w.cams, w.tri_off,
+                       w.blk_off, w.tris, (unsigned long long*)w.zbuf);
+  }
+  const float* tex = MF > 0 ? m.tex : nullptr;
+  hipLaunchKernelGGL(k_mesh_resolve, dim3((unsigned)((S.n_pix + 255) / 256)), dim3(256), 0, st, S,
+                     w.cams, (const unsigned long long*)w.zbuf, w.tris, tex, w.mesh_rgb,
+                     out ? out->mesh_rgb : nullptr, out ? out->mesh_depth : nullptr,
+                     out ? out->tri_id : nullptr);
+}
+
+}  // namespace hr

@@ -1,0 +1,63 @@
+// Small helper kernels of the host runtime: camera upload through kernel
+// arguments, statistics export, accumulator clearing, output comparison.
+#include "kernels.hpp"
+
+namespace hr {
+
+namespace {
+
+__global__ void k_upload_cams(CamUpload u, CamDev* dst) {
+  const int k = threadIdx.x;
+  if (k < u.count) dst[u.first + k] = u.c[k];
+}
+
+__global__ void k_counters_to_stats(const uint32_t* __restrict__ c, hr_stats* __restrict__ s) {
+  s->n_visible = c[0];
+  s->overflow = c[1];
+  const uint64_t K = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
+  s->n_keys = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
+  s->n_tris = c[4];
+  s->n_processed = (uint64_t)c[6] | ((uint64_t)c[7] << 32);
+  s->n_blended = (uint64_t)c[8] | ((uint64_t)c[9] << 32);
+}
+
+// clears the [n_visible][9] gradient accumulators
+__global__ void k_zero_gacc(float* __restrict__ gacc, const uint32_t* __restrict__ counters) {
+  const int64_t n = (int64_t)counters[0] * 9;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    gacc[i] = 0.f;
+}
+
+__global__ void k_count_mismatch(const float* __restrict__ a, const float* __restrict__ b,
+                                 int64_t n, uint32_t* __restrict__ out) {
+  uint32_t bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad += __float_as_uint(a[i]) != __float_as_uint(b[i]);
+  if (bad) atomicAdd(out, bad);
+}
+
+}  // namespace
+
+void launch_upload_cams(const CamUpload& u, CamDev* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(64), 0, st, u, dst);
+}
+
+void launch_counters_to_stats(const uint32_t* counters, hr_stats* stats, hipStream_t st) {
+  hipLaunchKernelGGL(k_counters_to_stats, dim3(1), dim3(1), 0, st, counters, stats);
+}
+
+void launch_zero_gacc(float* gacc, const uint32_t* counters, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_gacc, dim3(2048), dim3(256), 0, st, gacc, counters);
+}
+
+void launch_count_mismatch(const float* a, const float* b, int64_t n, uint32_t* out,
+                           hipStream_t st) {
+  if (n <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_count_mismatch, dim3((unsigned)g), dim3(256), 0, st, a, b, n, out);
+}
+
+}  // namespace hr

@@ -1,0 +1,508 @@
+"""Python binding of libhybrid_raster (include/hr.h): argument marshalling only.
+
+Every step of the rasterizer runs in the HIP library; torch provides device
+memory and the current stream. Importing this module does not touch the GPU;
+`load()` raises when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhybrid_raster.so")
+
+HR_OK, HR_ERR_INVALID_ARGUMENT, HR_ERR_CAPACITY, HR_ERR_HIP, HR_ERR_UNSUPPORTED, HR_ERR_INTERNAL = range(6)
+HR_FLAG_NO_SYNC = 1 << 0
+HR_FLAG_DETACH_MASK = 1 << 1
+HR_FLAG_EXPORT_KEYS = 1 << 2
+
+P = C.c_void_p
+
+
+class hr_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("means", P), ("log_scales", P),
+                ("quats", P), ("opacity_logits", P), ("sh", P)]
+
+
+class hr_mesh(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("n_faces", C.c_int32), ("n_tex", C.c_int32),
+                ("tex_h", C.c_int32), ("tex_w", C.c_int32), ("verts", P), ("faces", P),
+                ("uvs", P), ("face_tex", P), ("tex", P)]
+
+
+class hr_camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_double),
+                ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class hr_settings(C.Structure):
+    _fields_ = [("bg", C.c_float * 3), ("low_pass", C.c_float), ("alpha_min", C.c_float),
+                ("alpha_max", C.c_float), ("t_min", C.c_float), ("near_gs", C.c_float),
+                ("near_mesh", C.c_float), ("clamp_fov", C.c_float), ("flags", C.c_uint32),
+                ("batch", C.c_int32), ("variant", C.c_int32)]
+
+
+class hr_outputs(C.Structure):
+    _fields_ = [(k, P) for k in ("image", "final_T", "mesh_rgb", "mesh_depth", "tri_id",
+                                 "n_contrib", "n_blended", "n_processed", "radii", "keys",
+                                 "values", "ranges", "stats")]
+
+
+class hr_grads(C.Structure):
+    _fields_ = [(k, P) for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex")]
+
+
+EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid",
+            "hr_render_hybrid_backward", "hr_loss_scratch_bytes", "hr_hybrid_loss", "hr_autotune",
+            "hr_batch_create", "hr_batch_launch", "hr_batch_destroy", "hr_status_string",
+            "hr_last_error", "hr_abi_version"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2506_06988_amd/build.py")
+    L = C.CDLL(path)
+    L.hr_default_settings.restype = hr_settings
+    L.hr_default_settings.argtypes = []
+    L.hr_query_workspace.restype = C.c_size_t
+    L.hr_query_workspace.argtypes = [P, P, P, C.c_int32, P, C.c_int64]
+    L.hr_render_hybrid.restype = C.c_int
+    L.hr_render_hybrid.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P]
+    L.hr_render_hybrid_backward.restype = C.c_int
+    L.hr_render_hybrid_backward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P,
+                                            P, P, P]
+    L.hr_loss_scratch_bytes.restype = C.c_size_t
+    L.hr_loss_scratch_bytes.argtypes = [C.c_int64]
+    L.hr_hybrid_loss.restype = C.c_int
+    L.hr_hybrid_loss.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_uint32, P, P,
+                                 P, P, P, P]
+    L.hr_autotune.restype = C.c_int
+    L.hr_autotune.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, C.c_int32, P]
+    L.hr_batch_create.restype = C.c_int
+    L.hr_batch_create.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P, C.c_float,
+                                  C.c_float, P, P, P, P, P, P, P, P]
+    L.hr_batch_launch.restype = C.c_int
+    L.hr_batch_launch.argtypes = [P, P]
+    L.hr_batch_destroy.restype = None
+    L.hr_batch_destroy.argtypes = [P]
+    L.hr_status_string.restype = C.c_char_p
+    L.hr_status_string.argtypes = [C.c_int]
+    L.hr_last_error.restype = C.c_char_p
+    L.hr_last_error.argtypes = []
+    L.hr_abi_version.restype = C.c_int32
+    L.hr_abi_version.argtypes = []
+    _lib = L
+    return L
+
+
+class HRError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def check(rc):
+    if rc != HR_OK:
+        raise HRError(rc, load().hr_last_error().decode())
+
+
+def default_settings(**kw) -> hr_settings:
+    s = load().hr_default_settings()
+    for k, v in kw.items():
+        if k == "bg":
+            for i in range(3):
+                s.bg[i] = float(v[i])
+        else:
+            setattr(s, k, v)
+    return s
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------- device data --
+@dataclasses.dataclass
+class DevGaussians:
+    means: "torch.Tensor"
+    log_scales: "torch.Tensor"
+    quats: "torch.Tensor"
+    opacity_logits: "torch.Tensor"
+    sh: "torch.Tensor"
+    sh_degree: int
+
+    @property
+    def n(self):
+        return int(self.means.shape[0])
+
+    def struct(self) -> hr_gaussians:
+        g = hr_gaussians()
+        g.n, g.sh_degree = self.n, self.sh_degree
+        g.means, g.log_scales, g.quats = _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats)
+        g.opacity_logits, g.sh = _ptr(self.opacity_logits), _ptr(self.sh)
+        return g
+
+
+@dataclasses.dataclass
+class DevMesh:
+    verts: "torch.Tensor"
+    faces: "torch.Tensor"
+    uvs: "torch.Tensor"
+    face_tex: "torch.Tensor"
+    tex: "torch.Tensor"
+
+    @property
+    def n_faces(self):
+        return int(self.faces.shape[0])
+
+    def struct(self, tex=None) -> hr_mesh:
+        m = hr_mesh()
+        t = self.tex if tex is None else tex
+        m.n_verts, m.n_faces = int(self.verts.shape[0]), self.n_faces
+        m.n_tex, m.tex_h, m.tex_w = int(t.shape[0]), int(t.shape[1]), int(t.shape[2])
+        m.verts, m.faces, m.uvs = _ptr(self.verts), _ptr(self.faces), _ptr(self.uvs)
+        m.face_tex, m.tex = _ptr(self.face_tex), _ptr(t)
+        return m
+
+
+def to_device(gaussians, mesh=None, device="cuda"):
+    import torch
+    f = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt).contiguous()
+    g = DevGaussians(f(gaussians.means), f(gaussians.log_scales), f(gaussians.quats),
+                     f(gaussians.opacity_logits), f(gaussians.sh), gaussians.sh_degree)
+    m = None
+    if mesh is not None and mesh.faces.shape[0] > 0:
+        m = DevMesh(f(mesh.verts), f(mesh.faces, torch.int32), f(mesh.uvs),
+                    f(mesh.face_tex, torch.int32), f(mesh.tex))
+    return g, m
+
+
+def empty_mesh_struct() -> hr_mesh:
+    m = hr_mesh()
+    m.n_verts = m.n_faces = 0
+    m.n_tex = m.tex_h = m.tex_w = 1
+    return m
+
+
+def camera_array(cams: Sequence) -> "C.Array":
+    arr = (hr_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].width, arr[i].height = int(c.width), int(c.height)
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        R = np.asarray(c.R, np.float64).reshape(9)
+        t = np.asarray(c.t, np.float64).reshape(3)
+        for k in range(9):
+            arr[i].R[k] = R[k]
+        for k in range(3):
+            arr[i].t[k] = t[k]
+    return arr
+
+
+def pixel_offsets(cams) -> List[int]:
+    off, o = [], 0
+    for c in cams:
+        off.append(o)
+        o += int(c.width) * int(c.height)
+    off.append(o)
+    return off
+
+
+def n_tiles(cams, tile=16) -> int:
+    return sum(((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile) for c in cams)
+
+
+# ------------------------------------------------------------- the renderer --
+@dataclasses.dataclass
+class Frame:
+    """Outputs of one forward, packed over cameras (see hr.h)."""
+    image: "torch.Tensor"
+    final_T: "torch.Tensor"
+    mesh_rgb: "torch.Tensor"
+    mesh_depth: "torch.Tensor"
+    tri_id: "torch.Tensor"
+    n_contrib: "torch.Tensor"
+    n_blended: "torch.Tensor"
+    n_processed: "torch.Tensor"
+    radii: "torch.Tensor"
+    stats: "torch.Tensor"
+    keys: Optional["torch.Tensor"] = None
+    values: Optional["torch.Tensor"] = None
+    ranges: Optional["torch.Tensor"] = None
+    offsets: Optional[List[int]] = None
+
+    def view(self, c, cams):
+        """(image [3,H,W], T [H,W], mesh_rgb, mesh_depth, tri_id, n_contrib, n_blended, n_processed)."""
+        o0 = self.offsets[c]
+        H, W = int(cams[c].height), int(cams[c].width)
+        hw = H * W
+        im = self.image[3 * o0:3 * o0 + 3 * hw].view(3, H, W)
+        mr = self.mesh_rgb[3 * o0:3 * o0 + 3 * hw].view(3, H, W)
+        sl = lambda t: t[o0:o0 + hw].view(H, W)
+        return (im, sl(self.final_T), mr, sl(self.mesh_depth), sl(self.tri_id), sl(self.n_contrib),
+                sl(self.n_blended), sl(self.n_processed))
+
+    def stats_dict(self):
+        s = self.stats.cpu().numpy().view(np.uint32)
+        return dict(n_visible=int(s[0]), n_keys=int(s[1]), overflow=int(s[2]), n_tris=int(s[3]),
+                    n_processed=int(s[4]) | (int(s[5]) << 32), n_blended=int(s[6]) | (int(s[7]) << 32))
+
+
+class Renderer:
+    """Owns the workspace of one scene/camera configuration."""
+
+    def __init__(self, gaussians: DevGaussians, mesh: Optional[DevMesh], cams, settings=None,
+                 key_capacity: Optional[int] = None):
+        import torch
+        self.L = load()
+        self.g = gaussians
+        self.mesh = mesh
+        self.cams = list(cams)
+        self.cam_arr = camera_array(self.cams)
+        self.settings = settings if settings is not None else default_settings()
+        self.offsets = pixel_offsets(self.cams)
+        self.P = self.offsets[-1]
+        self.tiles = n_tiles(self.cams)
+        self.device = gaussians.means.device
+        if key_capacity is None:
+            key_capacity = max(1 << 16, 64 * self.P)
+        self.key_capacity = int(min(key_capacity, 0xffffffff))
+        self.ws = None
+        self._alloc_ws()
+
+    def _structs(self, tex=None):
+        gs = self.g.struct()
+        ms = self.mesh.struct(tex) if self.mesh is not None else empty_mesh_struct()
+        return gs, ms
+
+    def _alloc_ws(self):
+        import torch
+        gs, ms = self._structs()
+        nbytes = self.L.hr_query_workspace(C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams),
+                                           C.byref(self.settings), self.key_capacity)
+        if nbytes == 0:
+            raise HRError(HR_ERR_INVALID_ARGUMENT, self.L.hr_last_error().decode())
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            torch.cuda.empty_cache() if self.ws is not None else None
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ws_bytes = int(self.ws.numel())
+
+    def new_frame(self, export_keys=False) -> Frame:
+        import torch
+        d = self.device
+        P, n = self.P, self.g.n
+        f = Frame(image=torch.empty(3 * P, dtype=torch.float32, device=d),
+                  final_T=torch.empty(P, dtype=torch.float32, device=d),
+                  mesh_rgb=torch.empty(3 * P, dtype=torch.float32, device=d),
+                  mesh_depth=torch.empty(P, dtype=torch.float32, device=d),
+                  tri_id=torch.empty(P, dtype=torch.int32, device=d),
+                  n_contrib=torch.empty(P, dtype=torch.int32, device=d),
+                  n_blended=torch.empty(P, dtype=torch.int32, device=d),
+                  n_processed=torch.empty(P, dtype=torch.int32, device=d),
+                  radii=torch.empty(max(1, n * len(self.cams)), dtype=torch.int32, device=d),
+                  stats=torch.zeros(4, dtype=torch.int64, device=d), offsets=self.offsets)
+        if export_keys:
+            f.keys = torch.empty(self.key_capacity, dtype=torch.int64, device=d)
+            f.values = torch.empty(self.key_capacity, dtype=torch.int32, device=d)
+            f.ranges = torch.empty(2 * self.tiles, dtype=torch.int32, device=d)
+        return f
+
+    def outputs_struct(self, f: Frame) -> hr_outputs:
+        o = hr_outputs()
+        o.image, o.final_T, o.mesh_rgb = _ptr(f.image), _ptr(f.final_T), _ptr(f.mesh_rgb)
+        o.mesh_depth, o.tri_id, o.n_contrib = _ptr(f.mesh_depth), _ptr(f.tri_id), _ptr(f.n_contrib)
+        o.n_blended, o.n_processed, o.radii = _ptr(f.n_blended), _ptr(f.n_processed), _ptr(f.radii)
+        o.keys, o.values, o.ranges = _ptr(f.keys), _ptr(f.values), _ptr(f.ranges)
+        o.stats = _ptr(f.stats)
+        return o
+
+    def render_hybrid(self, frame: Optional[Frame] = None, export_keys=False, tex=None,
+                      sync_check=True) -> Frame:
+        """hr_render_hybrid; grows the key capacity and retries on HR_ERR_CAPACITY."""
+        f = frame if frame is not None else self.new_frame(export_keys)
+        for _ in range(3):
+            gs, ms = self._structs(tex)
+            o = self.outputs_struct(f)
+            s = hr_settings.from_buffer_copy(self.settings)
+            if not sync_check:
+                s.flags |= HR_FLAG_NO_SYNC
+            rc = self.L.hr_render_hybrid(C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams),
+                                         C.byref(s), self.key_capacity, _ptr(self.ws),
+                                         self.ws_bytes, C.byref(o), _stream())
+            if rc != HR_ERR_CAPACITY:
+                check(rc)
+                return f
+            need = f.stats_dict()["n_keys"]
+            self.key_capacity = int(min(0xffffffff, need * 5 // 4 + 1024))
+            self._alloc_ws()
+            if export_keys:
+                f = self.new_frame(export_keys)
+        raise HRError(HR_ERR_CAPACITY, "key capacity did not converge")
+
+    def render_hybrid_backward(self, grad_image, grad_final_T=None, grad_mesh_rgb=None, grads=None,
+                               tex=None):
+        """hr_render_hybrid_backward; returns a dict of gradient tensors (accumulated into `grads`)."""
+        import torch
+        d = self.device
+        if grads is None:
+            grads = dict(means=torch.zeros_like(self.g.means), log_scales=torch.zeros_like(self.g.log_scales),
+                         quats=torch.zeros_like(self.g.quats),
+                         opacity_logits=torch.zeros_like(self.g.opacity_logits),
+                         sh=torch.zeros_like(self.g.sh))
+            if self.mesh is not None:
+                grads["tex"] = torch.zeros_like(self.mesh.tex if tex is None else tex)
+        gr = hr_grads()
+        for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex"):
+            setattr(gr, k, _ptr(grads.get(k)))
+        gs, ms = self._structs(tex)
+        check(self.L.hr_render_hybrid_backward(
+            C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams), C.byref(self.settings),
+            self.key_capacity, _ptr(self.ws), self.ws_bytes, _ptr(grad_image.contiguous()),
+            _ptr(None if grad_final_T is None else grad_final_T.contiguous()),
+            _ptr(None if grad_mesh_rgb is None else grad_mesh_rgb.contiguous()), C.byref(gr),
+            _stream()))
+        return grads
+
+    def autotune(self, frame: Frame, repeats=5):
+        gs, ms = self._structs()
+        o = self.outputs_struct(frame)
+        check(self.L.hr_autotune(C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams),
+                                 C.byref(self.settings), self.key_capacity, _ptr(self.ws),
+                                 self.ws_bytes, C.byref(o), int(repeats), _stream()))
+        return int(self.settings.batch), int(self.settings.variant)
+
+
+def hybrid_loss(image, final_T, mesh_rgb, tri_id, target, lambda_t=0.1, k=20.0, detach_mask=False):
+    """hr_hybrid_loss over packed planar buffers; returns (loss, g_image, g_T, g_mesh_rgb)."""
+    import torch
+    L = load()
+    n_pix = int(final_T.numel())
+    d = image.device
+    loss = torch.zeros(1, dtype=torch.float32, device=d)
+    gi = torch.empty_like(image)
+    gt = torch.empty_like(final_T)
+    gm = torch.empty_like(mesh_rgb)
+    scratch = torch.empty(int(L.hr_loss_scratch_bytes(n_pix)), dtype=torch.uint8, device=d)
+    check(L.hr_hybrid_loss(_ptr(image), _ptr(final_T), _ptr(mesh_rgb), _ptr(tri_id), _ptr(target),
+                           n_pix, float(lambda_t), float(k),
+                           HR_FLAG_DETACH_MASK if detach_mask else 0, _ptr(loss), _ptr(gi), _ptr(gt),
+                           _ptr(gm), _ptr(scratch), _stream()))
+    return loss, gi, gt, gm
+
+
+# --------------------------------------------------------------- autograd --
+def _autograd_fn():
+    import torch
+
+    class HybridRenderFn(torch.autograd.Function):
+        """(means, log_scales, quats, opacity_logits, sh, tex) -> (image, final_T, mesh_rgb).
+
+        All three outputs are differentiable: T through the transmittance-aware
+        loss, I_m into the texture. Counters and mesh buffers stay in the Frame.
+        """
+
+        @staticmethod
+        def forward(ctx, renderer, means, log_scales, quats, opacity_logits, sh, tex):
+            renderer.g = DevGaussians(means.detach().contiguous(), log_scales.detach().contiguous(),
+                                      quats.detach().contiguous(), opacity_logits.detach().contiguous(),
+                                      sh.detach().contiguous(), renderer.g.sh_degree)
+            t = None if tex is None else tex.detach().contiguous()
+            f = renderer.render_hybrid(tex=t)
+            ctx.renderer = renderer
+            ctx.tex = t
+            ctx.frame = f
+            return f.image, f.final_T, f.mesh_rgb
+
+        @staticmethod
+        def backward(ctx, g_image, g_T, g_mesh):
+            r = ctx.renderer
+            z = lambda g, like: torch.zeros_like(like) if g is None else g
+            grads = r.render_hybrid_backward(z(g_image, ctx.frame.image), g_T, g_mesh, tex=ctx.tex)
+            return (None, grads["means"], grads["log_scales"], grads["quats"],
+                    grads["opacity_logits"], grads["sh"], grads.get("tex"))
+
+    return HybridRenderFn
+
+
+_HybridRenderFn = None
+
+
+def HybridRenderFn():
+    global _HybridRenderFn
+    if _HybridRenderFn is None:
+        _HybridRenderFn = _autograd_fn()
+    return _HybridRenderFn
+
+
+# ---------------------------------------------------------- batched graph --
+class BatchedStep:
+    """hr_batch_create / hr_batch_launch: forward + loss + backward in one hipGraph."""
+
+    def __init__(self, renderer: Renderer, target, lambda_t=0.1, k=20.0, stream=None):
+        import torch
+        r = renderer
+        self.r = r
+        self.L = load()
+        d = r.device
+        self.frame = r.new_frame()
+        self.target = target.contiguous()
+        self.loss = torch.zeros(1, dtype=torch.float32, device=d)
+        self.g_image = torch.empty(3 * r.P, dtype=torch.float32, device=d)
+        self.g_T = torch.empty(r.P, dtype=torch.float32, device=d)
+        self.g_mesh = torch.empty(3 * r.P, dtype=torch.float32, device=d)
+        self.scratch = torch.empty(int(self.L.hr_loss_scratch_bytes(r.P)), dtype=torch.uint8, device=d)
+        self.grads = dict(means=torch.zeros_like(r.g.means), log_scales=torch.zeros_like(r.g.log_scales),
+                          quats=torch.zeros_like(r.g.quats),
+                          opacity_logits=torch.zeros_like(r.g.opacity_logits),
+                          sh=torch.zeros_like(r.g.sh))
+        if r.mesh is not None:
+            self.grads["tex"] = torch.zeros_like(r.mesh.tex)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        gr = hr_grads()
+        for k_ in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex"):
+            setattr(gr, k_, _ptr(self.grads.get(k_)))
+        gs, ms = r._structs()
+        o = r.outputs_struct(self.frame)
+        s = hr_settings.from_buffer_copy(r.settings)
+        s.flags |= HR_FLAG_NO_SYNC
+        self._keep = (gs, ms, o, s, gr)
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        check(self.L.hr_batch_create(C.byref(gs), C.byref(ms), r.cam_arr, len(r.cams), C.byref(s),
+                                     r.key_capacity, _ptr(r.ws), r.ws_bytes, C.byref(o),
+                                     _ptr(self.target), float(lambda_t), float(k), _ptr(self.loss),
+                                     _ptr(self.g_image), _ptr(self.g_T), _ptr(self.g_mesh),
+                                     _ptr(self.scratch), C.byref(gr),
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        check(self.L.hr_batch_launch(self.handle, C.c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if self.handle:
+            self.L.hr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,102 @@
+"""The C ABI without a GPU: symbols, host-side validation and workspace planning."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2506_06988_amd import hr, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "hr.h")).read()
+    return sorted(set(re.findall(r"\b(hr_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = hr.load()
+    names = header_functions()
+    assert "hr_render_hybrid" in names and "hr_render_hybrid_backward" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.hr_abi_version() == 1
+
+
+def _structs(n=10, deg=0, faces=0):
+    g = hr.hr_gaussians()
+    g.n, g.sh_degree = n, deg
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        setattr(g, k, 4096)
+    m = hr.empty_mesh_struct()
+    if faces:
+        m.n_verts, m.n_faces, m.n_tex, m.tex_h, m.tex_w = 4, faces, 1, 8, 8
+        for k in ("verts", "faces", "uvs", "face_tex", "tex"):
+            setattr(m, k, 4096)
+    return g, m
+
+
+def test_workspace_grows_with_inputs_and_capacity():
+    L = hr.load()
+    s = hr.default_settings()
+    cam = scenes.Camera(64, 48, 50.0, 50.0, 32.0, 24.0, np.eye(3), np.zeros(3))
+    cams = hr.camera_array([cam])
+    sizes = []
+    for n, cap in ((10, 1000), (1000, 1000), (1000, 100000)):
+        g, m = _structs(n)
+        sizes.append(L.hr_query_workspace(C.byref(g), C.byref(m), cams, 1, C.byref(s), cap))
+    assert 0 < sizes[0] < sizes[1] < sizes[2]
+    assert sizes[2] - sizes[1] >= 4 * 99000
+    cams2 = hr.camera_array([cam, cam])
+    g, m = _structs(1000)
+    assert L.hr_query_workspace(C.byref(g), C.byref(m), cams2, 2, C.byref(s), 1000) > sizes[1]
+
+
+@pytest.mark.parametrize("mutate, msg", [
+    (lambda g, m, s, c: setattr(g, "sh_degree", 4), "sh_degree"),
+    (lambda g, m, s, c: setattr(g, "n", -1), "n must"),
+    (lambda g, m, s, c: setattr(g, "means", None), "null Gaussian"),
+    (lambda g, m, s, c: setattr(g, "quats", 4100), "aligned"),
+    (lambda g, m, s, c: setattr(s, "alpha_min", 0.995), "alpha"),
+    (lambda g, m, s, c: setattr(s, "t_min", 0.0), "t_min"),
+    (lambda g, m, s, c: setattr(s, "batch", 48), "batch"),
+    (lambda g, m, s, c: setattr(c[0], "width", 0), "camera size"),
+    (lambda g, m, s, c: setattr(c[0], "fx", -1.0), "focal"),
+    (lambda g, m, s, c: setattr(c[0], "width", 8000) or setattr(c[0], "height", 8000), "16384 tiles"),
+])
+def test_invalid_arguments_are_rejected_before_any_launch(mutate, msg):
+    L = hr.load()
+    g, m = _structs(100)
+    s = hr.default_settings()
+    cams = hr.camera_array([scenes.Camera(64, 48, 50.0, 50.0, 32.0, 24.0, np.eye(3), np.zeros(3))])
+    mutate(g, m, s, cams)
+    assert L.hr_query_workspace(C.byref(g), C.byref(m), cams, 1, C.byref(s), 1000) == 0
+    assert msg in L.hr_last_error().decode()
+    # the render call fails the same way without touching the (bogus) pointers
+    out = hr.hr_outputs()
+    out.image = 4096
+    rc = L.hr_render_hybrid(C.byref(g), C.byref(m), cams, 1, C.byref(s), 1000, 4096, 1 << 30,
+                            C.byref(out), None)
+    assert rc in (hr.HR_ERR_INVALID_ARGUMENT, hr.HR_ERR_UNSUPPORTED)
+
+
+def test_mesh_arguments_and_capacity_bounds():
+    L = hr.load()
+    s = hr.default_settings()
+    cams = hr.camera_array([scenes.Camera(64, 48, 50.0, 50.0, 32.0, 24.0, np.eye(3), np.zeros(3))])
+    g, m = _structs(10, faces=2)
+    assert L.hr_query_workspace(C.byref(g), C.byref(m), cams, 1, C.byref(s), 1000) > 0
+    m.tex = None
+    assert L.hr_query_workspace(C.byref(g), C.byref(m), cams, 1, C.byref(s), 1000) == 0
+    g, m = _structs(10)
+    assert L.hr_query_workspace(C.byref(g), C.byref(m), cams, 1, C.byref(s), 1 << 32) == 0
+    assert L.hr_query_workspace(C.byref(g), C.byref(m), cams, 0, C.byref(s), 10) == 0
+
+
+def test_status_strings():
+    L = hr.load()
+    for k in range(6):
+        assert L.hr_status_string(k)
+    assert L.hr_status_string(hr.HR_ERR_CAPACITY) == b"key capacity too small"
