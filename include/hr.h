@@ -192,6 +192,15 @@ hr_status hr_render_hybrid_backward(const hr_gaussians* g, const hr_mesh* mesh,
                                     const float* grad_image, const float* grad_final_T,
                                     const float* grad_mesh_rgb, hr_grads* grads, void* stream);
 
+/* Re-runs only the per-tile blend and composite of the forward that last
+ * filled this workspace (all arguments equal to that forward's), rewriting
+ * the same outputs. Used to time the blend kernel on its own and by the
+ * autotuner. */
+hr_status hr_blend_forward(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                           int32_t n_cams, const hr_settings* s, int64_t key_capacity,
+                           void* workspace, size_t workspace_bytes, hr_outputs* out,
+                           void* stream);
+
 /* Loss of Sec. 3.4 over n_pix packed pixels:
  *   L = mean_{p,c} |I_h - I| + lambda_t * mean_{p,c} M_T(p) (I~ - I~_m)^2,
  *   M_T = 1 / (1 + exp(-k (T - 1/2))), I~ = I and I~_m = I_m where

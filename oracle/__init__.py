@@ -108,11 +108,14 @@ def _p(a):
 
 
 # The renderer's conventions, as FP32 values (the kernel's settings are FP32,
-# and both sides must compare against the same thresholds).
+# and both sides must compare against the same thresholds). amb_alpha and
+# amb_t are the relative slacks under which an alpha-skip or T-stop decision
+# counts as ambiguous: about 10x the relative error of alpha (~1e-6) and of T
+# (~1e-5 after tens of blends) that an FP32 evaluation carries.
 def default_params(**kw):
     d = dict(bg=(0.0, 0.0, 0.0), low_pass=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99,
              t_min=1e-4, near_gs=0.2, near_mesh=0.05, clamp_fov=1.3, tile=16, flags=0,
-             amb_alpha=2e-5, amb_t=1e-3)
+             amb_alpha=2e-5, amb_t=1e-4)
     d.update(kw)
     return d
 

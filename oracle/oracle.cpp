@@ -140,8 +140,10 @@ bool near_int(double x, double rel) {
   return d <= rel * std::max(1.0, std::fabs(x));
 }
 
+// FP64 results of two implementations differ by ~1e-15 relative; a rounding
+// or integer decision closer than that to its boundary may go either way.
 bool f32_boundary(double x) {
-  double e = std::fabs(x) * 1e-12;
+  double e = std::fabs(x) * 1e-14;
   return (float)(x + e) != (float)(x - e);
 }
 
@@ -236,7 +238,7 @@ Rec project(const or_scene& sc, const or_camera& cam, const or_params& p, int g)
   for (int i = 0; i < 3; ++i)
     r.pc[i] = W[3 * i] * mu[0] + W[3 * i + 1] * mu[1] + W[3 * i + 2] * mu[2] + cam.t[i];
   const double x = r.pc[0], y = r.pc[1], z = r.pc[2];
-  if (std::fabs(z - p.near_gs) <= 1e-12 * p.near_gs) r.amb = true;
+  if (std::fabs(z - p.near_gs) <= 1e-14 * p.near_gs) r.amb = true;
   if (!(z > p.near_gs)) return r;
 
   r.logit = sc.opacity_logits[g];
@@ -305,13 +307,13 @@ Rec project(const or_scene& sc, const or_camera& cam, const or_params& p, int g)
   const double lam = m + std::sqrt(std::max(0.1, m * m - det));
   const double r3 = 3.0 * std::sqrt(lam);
   r.r = (int)std::ceil(r3);
-  if (near_int(r3, 1e-11)) r.amb = true;
+  if (near_int(r3, 1e-13)) r.amb = true;
   const int TX = tiles_x(cam, p), TY = tiles_y(cam, p);
   const double T = (double)p.tile;
   const double ex0 = (r.u - r.r) / T, ex1 = (r.u + r.r) / T;
   const double ey0 = (r.v - r.r) / T, ey1 = (r.v + r.r) / T;
-  if (near_int(ex0, 1e-11) || near_int(ex1, 1e-11) || near_int(ey0, 1e-11) ||
-      near_int(ey1, 1e-11))
+  if (near_int(ex0, 1e-13) || near_int(ex1, 1e-13) || near_int(ey0, 1e-13) ||
+      near_int(ey1, 1e-13))
     r.amb = true;
   auto clampi = [](double v, int hi) {
     if (!(v > 0)) return 0;  // also catches NaN

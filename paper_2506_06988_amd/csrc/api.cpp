@@ -38,7 +38,7 @@ struct Plan {
   int64_t n, n_cams, M, F, MF, P, n_tiles, key_cap, rs_blocks, chunk_rows, mat_entries;
   size_t cams, counters, tiles, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, tiles_s, item_s, pair_off, mat, tile_total,
-      tile_start, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
+      tile_start, slice_cnt, slice_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, gacc, tune, scan_scratch, total;
   std::vector<CamDev> camdev;
 };
@@ -155,6 +155,8 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.mat = L.take(4 * p.mat_entries);
   p.tile_total = L.take(4 * p.n_tiles);
   p.tile_start = L.take(4 * p.n_tiles);
+  p.slice_cnt = L.take(4 * (p.chunk_rows + 1));
+  p.slice_off = L.take(4 * (p.chunk_rows + 1));
   p.lists = L.take(4 * key_cap);
   p.zbuf = L.take(8 * P);
   p.tri_cnt = L.take(4 * p.MF);
@@ -167,7 +169,8 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.mesh_rgb = L.take(12 * P);
   p.gacc = L.take(36 * M);
   p.tune = L.take(16 * P + 256);
-  int64_t longest = std::max<int64_t>({M + 1, 256 * p.rs_blocks, p.n_tiles, p.MF + 1, 1});
+  int64_t longest =
+      std::max<int64_t>({M + 1, 256 * p.rs_blocks, p.n_tiles, p.MF + 1, p.chunk_rows + 1, 1});
   p.scan_scratch = L.take(scan_scratch_bytes(longest) + 4096);
   p.total = L.off;
   return HR_OK;
@@ -201,6 +204,8 @@ Work make_work(const Plan& p, void* ws) {
   w.chunk_rows = p.chunk_rows;
   w.tile_total = (uint32_t*)(b + p.tile_total);
   w.tile_start = (uint32_t*)(b + p.tile_start);
+  w.slice_cnt = (uint32_t*)(b + p.slice_cnt);
+  w.slice_off = (uint32_t*)(b + p.slice_off);
   w.lists = (uint32_t*)(b + p.lists);
   w.zbuf = (uint64_t*)(b + p.zbuf);
   w.tri_cnt = (uint32_t*)(b + p.tri_cnt);
@@ -370,6 +375,25 @@ hr_status hr_render_hybrid_backward(const hr_gaussians* g, const hr_mesh* mesh,
   hipGetLastError();
   enqueue_backward(p, w, S, g, mesh, s, grad_image, grad_final_T, grad_mesh_rgb, grads, st);
   return hip_check("backward launch");
+}
+
+hr_status hr_blend_forward(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                           int32_t n_cams, const hr_settings* s, int64_t key_capacity,
+                           void* workspace, size_t workspace_bytes, hr_outputs* out,
+                           void* stream) {
+  Plan p;
+  hr_status rc = make_plan(g, mesh, cams, n_cams, s, key_capacity, p);
+  if (rc != HR_OK) return rc;
+  if ((rc = check_outputs(out)) != HR_OK) return rc;
+  if (!workspace || workspace_bytes < p.total)
+    return fail(HR_ERR_INVALID_ARGUMENT, "workspace smaller than hr_query_workspace()");
+  Work w = make_work(p, workspace);
+  SetDev S = make_setdev(p, g, mesh, s);
+  hipGetLastError();
+  hr_outputs o = *out;
+  o.stats = nullptr;
+  launch_blend_forward(S, w, &o, pick_batch(s), s->variant, (hipStream_t)stream);
+  return hip_check("blend launch");
 }
 
 size_t hr_loss_scratch_bytes(int64_t n_pix) {

@@ -7,6 +7,7 @@
 // stops at the first Gaussian whose depth reaches D_m, or before T would drop
 // under t_min; the workgroup leaves as soon as every pixel has stopped.
 #include "kernels.hpp"
+#include "window.hpp"
 
 namespace hr {
 namespace {
@@ -46,103 +47,152 @@ __device__ __forceinline__ float gauss_p2(const float4& a, const float4& b, floa
 }
 
 struct TileCtx {
-  int cam, tx, ty, i, j;
+  int cam, i, j;
   bool inside;
-  int64_t p;       // packed pixel
-  int64_t s, e;    // list range
+  int64_t p;  // packed pixel
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const SetDev& S, const CamDev* cams,
-                                            const uint32_t* tile_start, const uint32_t* tile_total,
-                                            int t) {
+__device__ __forceinline__ TileCtx tile_ctx(const CamDev* cams, int n_cams, int t) {
   TileCtx c;
-  c.cam = find_cam_by_tile(cams, S.n_cams, t);
+  c.cam = find_cam_by_tile(cams, n_cams, t);
   const CamDev& C = cams[c.cam];
   const int lt = t - C.tile_off;
-  c.ty = lt / C.TX;
-  c.tx = lt - c.ty * C.TX;
-  c.i = c.tx * TILE + (threadIdx.x & 15);
-  c.j = c.ty * TILE + (threadIdx.x >> 4);
+  const int ty = lt / C.TX;
+  const int tx = lt - ty * C.TX;
+  c.i = tx * TILE + (threadIdx.x & 15);
+  c.j = ty * TILE + (threadIdx.x >> 4);
   c.inside = c.i < C.W && c.j < C.H;
   c.p = C.pix_off + (int64_t)c.j * C.W + c.i;
-  c.s = tile_start[t];
-  c.e = c.s + tile_total[t];
-  if (c.e > S.key_cap) c.e = S.key_cap;
   return c;
 }
 
-template <int BG, bool PREFETCH>
+// Front-to-back blend of one staged batch for this thread's pixel.
+struct PixState {
+  float T, cr, cg, cb;
+  int nc, nbl, npro;
+  bool done;
+};
+
+__device__ __forceinline__ void blend_batch(const Staged* sh, int n, int64_t pos0, float px,
+                                            float py, float Dm, float amin, float amax, float tmin,
+                                            PixState& ps) {
+  for (int k = 0; k < n; ++k) {
+    const float4 a = sh[k].a, b = sh[k].b;
+    if (b.z >= Dm) {
+      ps.done = true;
+      ps.npro = (int)pos0 + k + 1;
+      return;
+    }
+    float dx, dy;
+    const float p2 = gauss_p2(a, b, px, py, dx, dy);
+    const float alpha = fminf(amax, b.y * __builtin_amdgcn_exp2f(p2));
+    if (alpha < amin) continue;
+    const float Tn = ps.T * (1.f - alpha);
+    if (Tn < tmin) {
+      ps.done = true;
+      ps.npro = (int)pos0 + k + 1;
+      return;
+    }
+    const float4 c = sh[k].c;
+    const float wgt = alpha * ps.T;
+    ps.cr = __builtin_fmaf(c.x, wgt, ps.cr);
+    ps.cg = __builtin_fmaf(c.y, wgt, ps.cg);
+    ps.cb = __builtin_fmaf(c.z, wgt, ps.cb);
+    ps.T = Tn;
+    ps.nc = (int)pos0 + k + 1;
+    ++ps.nbl;
+  }
+}
+
+// DEPTH 1: extract ranks, barrier, load and stage, barrier, blend.
+// DEPTH 2: the next batch's records are loaded into registers before the
+// current batch is blended and written to the other LDS buffer after it,
+// leaving one barrier per batch.
+template <int BG, int DEPTH>
 __global__ __launch_bounds__(256) void k_blend_fwd(
-    SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ tile_start,
+    SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
+    const uint32_t* __restrict__ mat, const uint32_t* __restrict__ tile_start,
     const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ lists,
     const GRec* __restrict__ rec_s, const unsigned long long* __restrict__ zbuf,
     const float* __restrict__ mesh_rgb, float* __restrict__ image, float* __restrict__ T_ws,
     int32_t* __restrict__ nc_ws, float* __restrict__ T_out, int32_t* __restrict__ nc_out,
     int32_t* __restrict__ nb_out, int32_t* __restrict__ np_out, uint32_t* __restrict__ counters) {
-  __shared__ Staged sh[BG];
+  __shared__ Staged sh[DEPTH][BG];
+  __shared__ uint32_t rk[DEPTH][BG];
+  __shared__ uint32_t bitmap[WIN_WORDS];
+  __shared__ uint32_t red4[4];
   __shared__ unsigned long long red[2];
   const int t = blockIdx.x;
-  const TileCtx tc = tile_ctx(S, cams, tile_start, tile_total, t);
+  const TileCtx tc = tile_ctx(cams, S.n_cams, t);
   const CamDev& C = cams[tc.cam];
+  const WinCtx W = win_ctx(C, tc.cam, t, vis_off, mat, tile_start, tile_total, S.key_cap);
   const float px = (float)tc.i + 0.5f, py = (float)tc.j + 0.5f;
   unsigned long long key = ~0ull;
   if (tc.inside) key = zbuf[tc.p];
   const float Dm = key == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(key >> 32));
   const float amin = S.alpha_min, amax = S.alpha_max, tmin = S.t_min;
-  float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
-  int nc = 0, nbl = 0, npro = (int)(tc.e - tc.s);
-  bool done = !tc.inside;
-  if (threadIdx.x == 0) red[0] = red[1] = 0;
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
-  GRec pre;
-  if (PREFETCH && threadIdx.x < BG && tc.s + threadIdx.x < tc.e)
-    pre = rec_s[min(lists[tc.s + threadIdx.x], rmax)];
-  for (int64_t b0 = tc.s; b0 < tc.e; b0 += BG) {
-    if (__syncthreads_and(done)) break;
-    const int n = (int)min((int64_t)BG, tc.e - b0);
-    if (threadIdx.x < n) {
-      if (PREFETCH) {
-        sh[threadIdx.x] = stage(pre);
-      } else {
-        sh[threadIdx.x] = stage(rec_s[min(lists[b0 + threadIdx.x], rmax)]);
-      }
-    }
+  PixState ps;
+  ps.T = 1.f;
+  ps.cr = ps.cg = ps.cb = 0.f;
+  ps.nc = ps.nbl = 0;
+  ps.npro = (int)W.lim;
+  ps.done = !tc.inside;
+  if (threadIdx.x == 0) red[0] = red[1] = 0;
+  bool all_done = false;
+  for (int w = 0; w < W.nwin && !all_done; ++w) {
+    int64_t a, b;
+    win_range(W, w, a, b);
+    if (a >= b) continue;
+    if (__syncthreads_and(ps.done)) break;
+    const uint32_t wbase = W.rbase + (uint32_t)w * WIN;
+    bitmap[threadIdx.x] = 0;
     __syncthreads();
-    if (PREFETCH && threadIdx.x < BG && b0 + BG + threadIdx.x < tc.e)
-      pre = rec_s[min(lists[b0 + BG + threadIdx.x], rmax)];
-    if (!done) {
-      for (int k = 0; k < n; ++k) {
-        const float4 a = sh[k].a, b = sh[k].b;
-        if (b.z >= Dm) {
-          done = true;
-          npro = (int)(b0 - tc.s) + k + 1;
+    win_mark(lists, W, a, b, wbase, bitmap);
+    __syncthreads();
+    const uint32_t word = bitmap[threadIdx.x];
+    uint32_t total;
+    const uint32_t pre = group_excl_scan((uint32_t)__popc(word), red4, total);
+    const int nbat = (int)((total + BG - 1) / BG);
+    if (DEPTH == 1) {
+      for (int bi = 0; bi < nbat; ++bi) {
+        const uint32_t q = (uint32_t)bi * BG;
+        const int n = (int)min((uint32_t)BG, total - q);
+        if (bi > 0 && __syncthreads_and(ps.done)) {
+          all_done = true;
           break;
         }
-        float dx, dy;
-        const float p2 = gauss_p2(a, b, px, py, dx, dy);
-        const float alpha = fminf(amax, b.y * __builtin_amdgcn_exp2f(p2));
-        if (alpha < amin) continue;
-        const float Tn = T * (1.f - alpha);
-        if (Tn < tmin) {
-          done = true;
-          npro = (int)(b0 - tc.s) + k + 1;
+        win_extract(word, pre, q, (uint32_t)n, wbase, rk[0]);
+        __syncthreads();
+        if (threadIdx.x < n) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)]);
+        __syncthreads();
+        if (!ps.done) blend_batch(sh[0], n, a + q, px, py, Dm, amin, amax, tmin, ps);
+      }
+    } else {
+      win_extract(word, pre, 0, (uint32_t)min((uint32_t)BG, total), wbase, rk[0]);
+      __syncthreads();
+      if (threadIdx.x < min((uint32_t)BG, total)) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)]);
+      for (int bi = 0; bi < nbat; ++bi) {
+        const int cur = bi & 1;
+        const uint32_t q = (uint32_t)bi * BG;
+        const int n = (int)min((uint32_t)BG, total - q);
+        const bool more = bi + 1 < nbat;
+        const int nn = more ? (int)min((uint32_t)BG, total - q - BG) : 0;
+        if (more) win_extract(word, pre, q + BG, (uint32_t)nn, wbase, rk[cur ^ 1]);
+        if (__syncthreads_and(ps.done)) {
+          all_done = true;
           break;
         }
-        const float4 c = sh[k].c;
-        const float wgt = alpha * T;
-        cr = __builtin_fmaf(c.x, wgt, cr);
-        cg = __builtin_fmaf(c.y, wgt, cg);
-        cb = __builtin_fmaf(c.z, wgt, cb);
-        T = Tn;
-        nc = (int)(b0 - tc.s) + k + 1;
-        ++nbl;
+        GRec nxt;
+        if (threadIdx.x < nn) nxt = rec_s[min(rk[cur ^ 1][threadIdx.x], rmax)];
+        if (!ps.done) blend_batch(sh[cur], n, a + q, px, py, Dm, amin, amax, tmin, ps);
+        if (threadIdx.x < nn) sh[cur ^ 1][threadIdx.x] = stage(nxt);
       }
     }
   }
   if (tc.inside) {
     const int64_t hw = (int64_t)C.W * C.H;
-    const int64_t lp = tc.p - C.pix_off;
-    const int64_t pl = 3 * C.pix_off + lp;
+    const int64_t pl = 3 * C.pix_off + (tc.p - C.pix_off);
     float br, bgc, bb;
     if (key != ~0ull) {
       br = mesh_rgb[pl];
@@ -153,20 +203,19 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
       bgc = S.bg[1];
       bb = S.bg[2];
     }
-    image[pl] = __builtin_fmaf(T, br, cr);
-    image[pl + hw] = __builtin_fmaf(T, bgc, cg);
-    image[pl + 2 * hw] = __builtin_fmaf(T, bb, cb);
-    T_ws[tc.p] = T;
-    nc_ws[tc.p] = nc;
-    if (T_out) T_out[tc.p] = T;
-    if (nc_out) nc_out[tc.p] = nc;
-    if (nb_out) nb_out[tc.p] = nbl;
-    if (np_out) np_out[tc.p] = npro;
+    image[pl] = __builtin_fmaf(ps.T, br, ps.cr);
+    image[pl + hw] = __builtin_fmaf(ps.T, bgc, ps.cg);
+    image[pl + 2 * hw] = __builtin_fmaf(ps.T, bb, ps.cb);
+    T_ws[tc.p] = ps.T;
+    nc_ws[tc.p] = ps.nc;
+    if (T_out) T_out[tc.p] = ps.T;
+    if (nc_out) nc_out[tc.p] = ps.nc;
+    if (nb_out) nb_out[tc.p] = ps.nbl;
+    if (np_out) np_out[tc.p] = ps.npro;
   } else {
-    npro = 0;
+    ps.npro = 0;
   }
-  // workgroup sums of the counters
-  unsigned long long sp = (unsigned long long)npro, sb = (unsigned long long)nbl;
+  unsigned long long sp = (unsigned long long)ps.npro, sb = (unsigned long long)ps.nbl;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     sp += __shfl_xor(sp, o, 64);
@@ -185,25 +234,34 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
 }
 
 // ------------------------------------------------------------- backward --
-// Gradient of one blended Gaussian at one pixel, written to 9 accumulators:
-// u, v, conic a, b, c, opacity, r, g, b.
+// Reverse sweep over list positions [0, max n_contrib) of the tile, window by
+// window from the last, batch by batch from the back. Each pixel recovers the
+// transmittance in front of a Gaussian by dividing by (1 - alpha), starting
+// from its stored final T. Per Gaussian and tile, the 9 record gradients (u,
+// v, conic a b c, opacity, r g b) are summed over each wave and added once
+// per wave.
 template <int BG>
 __global__ __launch_bounds__(256) void k_blend_bwd(
-    SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ tile_start,
+    SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
+    const uint32_t* __restrict__ mat, const uint32_t* __restrict__ tile_start,
     const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ lists,
     const GRec* __restrict__ rec_s, const unsigned long long* __restrict__ zbuf,
     const float* __restrict__ mesh_rgb, const float* __restrict__ T_ws,
     const int32_t* __restrict__ nc_ws, const float* __restrict__ grad_image,
     const float* __restrict__ grad_T, float* __restrict__ gacc) {
   __shared__ Staged sh[BG];
-  __shared__ float4 raw[BG];     // ca, cb, cc, unused
-  __shared__ uint32_t rank[BG];
+  __shared__ float4 raw[BG];  // ca, cb, cc, unused
+  __shared__ uint32_t rk[BG];
+  __shared__ uint32_t bitmap[WIN_WORDS];
+  __shared__ uint32_t red4[4];
   __shared__ int maxnc;
   const int t = blockIdx.x;
-  const TileCtx tc = tile_ctx(S, cams, tile_start, tile_total, t);
+  const TileCtx tc = tile_ctx(cams, S.n_cams, t);
   const CamDev& C = cams[tc.cam];
+  const WinCtx W = win_ctx(C, tc.cam, t, vis_off, mat, tile_start, tile_total, S.key_cap);
   const float px = (float)tc.i + 0.5f, py = (float)tc.j + 0.5f;
   const float amin = S.alpha_min, amax = S.alpha_max;
+  const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
   float gr = 0.f, gg = 0.f, gb = 0.f, gT = 0.f, Tf = 1.f;
   int nc = 0;
   if (threadIdx.x == 0) maxnc = 0;
@@ -231,79 +289,96 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
   __syncthreads();
   if (nc > 0) atomicMax(&maxnc, nc);
   __syncthreads();
-  const int last = maxnc;
+  const int64_t last = maxnc;
+  if (last == 0) return;
   float T = Tf, Sr = 0.f, Sg = 0.f, Sb = 0.f;
   const int lane = __lane_id();
-  for (int hi = last; hi > 0; hi -= BG) {
-    const int lo = hi - BG > 0 ? hi - BG : 0;
-    const int n = hi - lo;
-    if (threadIdx.x < n) {
-      const uint32_t r = min(lists[tc.s + lo + threadIdx.x], (uint32_t)((int64_t)S.n * S.n_cams - 1));
-      const GRec R = rec_s[r];
-      sh[threadIdx.x] = stage(R);
-      raw[threadIdx.x] = make_float4(R.ca, R.cb, R.cc, 0.f);
-      rank[threadIdx.x] = r;
-    }
+  for (int w = W.nwin - 1; w >= 0; --w) {
+    int64_t a, b;
+    win_range(W, w, a, b);
+    if (a >= b || a >= last) continue;
+    const uint32_t wbase = W.rbase + (uint32_t)w * WIN;
     __syncthreads();
-    for (int k = n - 1; k >= 0; --k) {
-      const int idx = lo + k + 1;  // 1-based list position
-      float g[9];
+    bitmap[threadIdx.x] = 0;
+    __syncthreads();
+    win_mark(lists, W, a, b, wbase, bitmap);
+    __syncthreads();
+    const uint32_t word = bitmap[threadIdx.x];
+    uint32_t total;
+    const uint32_t pre = group_excl_scan((uint32_t)__popc(word), red4, total);
+    const int64_t nproc = (last < a + (int64_t)total ? last : a + (int64_t)total) - a;
+    for (int64_t hi = nproc; hi > 0; hi -= BG) {
+      const int64_t lo = hi - BG > 0 ? hi - BG : 0;
+      const int n = (int)(hi - lo);
+      __syncthreads();
+      win_extract(word, pre, (uint32_t)lo, (uint32_t)n, wbase, rk);
+      __syncthreads();
+      if (threadIdx.x < n) {
+        const uint32_t r = min(rk[threadIdx.x], rmax);
+        const GRec R = rec_s[r];
+        sh[threadIdx.x] = stage(R);
+        raw[threadIdx.x] = make_float4(R.ca, R.cb, R.cc, 0.f);
+        rk[threadIdx.x] = r;
+      }
+      __syncthreads();
+      for (int k = n - 1; k >= 0; --k) {
+        const int64_t idx = a + lo + k + 1;  // 1-based list position
+        float g[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) g[q] = 0.f;
-      bool contrib = idx <= nc;
-      float alpha = 0.f, G = 0.f, dx = 0.f, dy = 0.f;
-      const float4 a = sh[k].a, b = sh[k].b;
-      if (contrib) {
-        const float p2 = gauss_p2(a, b, px, py, dx, dy);
-        G = __builtin_amdgcn_exp2f(p2);
-        const float ag = b.y * G;
-        alpha = fminf(amax, ag);
-        contrib = alpha >= amin;
+        for (int q = 0; q < 9; ++q) g[q] = 0.f;
+        bool contrib = idx <= nc;
+        const float4 sa = sh[k].a, sb = sh[k].b;
         if (contrib) {
-          const float4 c = sh[k].c;
-          T = T / (1.f - alpha);  // transmittance in front of this Gaussian
-          const float w = alpha * T;
-          g[6] = w * gr;
-          g[7] = w * gg;
-          g[8] = w * gb;
-          const float galpha = T * ((c.x - Sr) * gr + (c.y - Sg) * gg + (c.z - Sb) * gb) -
-                               gT * Tf / (1.f - alpha);
-          Sr = alpha * c.x + (1.f - alpha) * Sr;
-          Sg = alpha * c.y + (1.f - alpha) * Sg;
-          Sb = alpha * c.z + (1.f - alpha) * Sb;
-          if (ag < amax) {
-            g[5] = galpha * G;
-            // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy with dx = u - px
-            const float gp = galpha * b.y * G;
-            const float4 rw = raw[k];
-            g[0] = -gp * (rw.x * dx + rw.y * dy);
-            g[1] = -gp * (rw.z * dy + rw.y * dx);
-            g[2] = -0.5f * gp * dx * dx;
-            g[3] = -gp * dx * dy;
-            g[4] = -0.5f * gp * dy * dy;
+          float dx, dy;
+          const float p2 = gauss_p2(sa, sb, px, py, dx, dy);
+          const float G = __builtin_amdgcn_exp2f(p2);
+          const float ag = sb.y * G;
+          const float alpha = fminf(amax, ag);
+          contrib = alpha >= amin;
+          if (contrib) {
+            const float4 c = sh[k].c;
+            T = T / (1.f - alpha);  // transmittance in front of this Gaussian
+            const float wgt = alpha * T;
+            g[6] = wgt * gr;
+            g[7] = wgt * gg;
+            g[8] = wgt * gb;
+            const float galpha = T * ((c.x - Sr) * gr + (c.y - Sg) * gg + (c.z - Sb) * gb) -
+                                 gT * Tf / (1.f - alpha);
+            Sr = alpha * c.x + (1.f - alpha) * Sr;
+            Sg = alpha * c.y + (1.f - alpha) * Sg;
+            Sb = alpha * c.z + (1.f - alpha) * Sb;
+            if (ag < amax) {
+              g[5] = galpha * G;
+              // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy with dx = u - px
+              const float gp = galpha * sb.y * G;
+              const float4 rw = raw[k];
+              g[0] = -gp * (rw.x * dx + rw.y * dy);
+              g[1] = -gp * (rw.z * dy + rw.y * dx);
+              g[2] = -0.5f * gp * dx * dx;
+              g[3] = -gp * dx * dy;
+              g[4] = -0.5f * gp * dy * dy;
+            }
+          }
+        }
+        if (__ballot(contrib)) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) g[q] = wave_sum(g[q]);
+          if (lane == 0) {
+            float* dst = gacc + (size_t)rk[k] * 9;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) atomicAdd(dst + q, g[q]);
           }
         }
       }
-      const unsigned long long any = __ballot(contrib);
-      if (any) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) g[q] = wave_sum(g[q]);
-        if (lane == 0) {
-          float* dst = gacc + (size_t)rank[k] * 9;
-#pragma unroll
-          for (int q = 0; q < 9; ++q) atomicAdd(dst + q, g[q]);
-        }
-      }
     }
-    __syncthreads();
   }
 }
 
 }  // namespace
 
-#define HR_FWD(BG, PF)                                                                          \
-  hipLaunchKernelGGL((k_blend_fwd<BG, PF>), dim3(S.n_tiles), dim3(256), 0, st, S, w.cams,       \
-                     w.tile_start, w.tile_total, w.lists, w.rec_s,                              \
+#define HR_FWD(BG, D)                                                                          \
+  hipLaunchKernelGGL((k_blend_fwd<BG, D>), dim3(S.n_tiles), dim3(256), 0, st, S, w.cams,        \
+                     w.vis_off, w.mat, w.tile_start, w.tile_total, w.lists, w.rec_s,            \
                      (const unsigned long long*)w.zbuf, w.mesh_rgb, out->image, w.final_T,      \
                      w.n_contrib, out->final_T, out->n_contrib, out->n_blended, out->n_processed, \
                      w.counters)
@@ -311,18 +386,18 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
 void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int batch, int variant,
                           hipStream_t st) {
   if (S.n_tiles == 0) return;
-  const bool pf = variant == 1;
+  const bool d2 = variant == 1;
   switch (batch) {
-    case 32: if (pf) HR_FWD(32, true); else HR_FWD(32, false); break;
-    case 64: if (pf) HR_FWD(64, true); else HR_FWD(64, false); break;
-    case 128: if (pf) HR_FWD(128, true); else HR_FWD(128, false); break;
-    default: if (pf) HR_FWD(256, true); else HR_FWD(256, false); break;
+    case 32: if (d2) HR_FWD(32, 2); else HR_FWD(32, 1); break;
+    case 64: if (d2) HR_FWD(64, 2); else HR_FWD(64, 1); break;
+    case 128: if (d2) HR_FWD(128, 2); else HR_FWD(128, 1); break;
+    default: if (d2) HR_FWD(256, 2); else HR_FWD(256, 1); break;
   }
 }
 
 #define HR_BWD(BG)                                                                              \
   hipLaunchKernelGGL((k_blend_bwd<BG>), dim3(S.n_tiles), dim3(256), 0, st, S, w.cams,           \
-                     w.tile_start, w.tile_total, w.lists, w.rec_s,                              \
+                     w.vis_off, w.mat, w.tile_start, w.tile_total, w.lists, w.rec_s,            \
                      (const unsigned long long*)w.zbuf, w.mesh_rgb, w.final_T, w.n_contrib,     \
                      grad_image, grad_T, w.gacc)
 

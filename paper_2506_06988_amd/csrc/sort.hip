@@ -1,20 +1,27 @@
 // Depth ordering and tile binning (the "tile-wise sorting" of Sec. 1).
 //
 // Instead of radix-sorting one 64-bit (tile | depth) key per (tile, Gaussian)
-// pair, the pairs are produced already grouped by tile and in depth order:
+// pair, the pairs are produced grouped by tile and ordered by depth rank up to
+// small windows:
 //  1. the visible (camera, Gaussian) items are radix-sorted once by
 //     (camera, fp32 depth bits); stability keeps equal depths in index order,
 //     so an item's position (its rank) orders it by (depth, index);
-//  2. ranks are cut into chunks of CHUNK; a workgroup per chunk histograms
-//     its pairs per tile in LDS; a column scan turns the chunk x tile counts
-//     into each (chunk, tile) output offset and per-tile ranges;
-//  3. a second pass scatters each pair's rank into its tile's segment; within
-//     one (chunk, tile) sub-segment the order is that of LDS atomics;
-//  4. a workgroup per tile sorts its segment by rank in LDS, in windows of
-//     whole chunk groups (each window holds at most SORT_WIN ranks).
-// The result equals sorting all (tile, depth bits, index) triples, and the
-// key traffic is two writes and two reads of a 4-byte rank per pair.
+//  2. ranks are cut into chunks of CHUNK (the rows of a chunk x tile count
+//     matrix); the pairs of a chunk are cut into slices of SLICE pairs, the
+//     work units of persistent workgroups, so a few Gaussians that cover
+//     thousands of tiles spread over many workgroups;
+//  3. count pass: each slice histograms its pairs per tile in LDS and adds the
+//     bins into its chunk's row; a column scan turns the matrix into each
+//     (chunk, tile) sub-segment start and the per-tile totals and ranges;
+//  4. scatter pass: each slice reserves its share of every (chunk, tile)
+//     sub-segment with one atomic per bin and writes its ranks there; inside
+//     a sub-segment the order is that of the atomics.
+// Chunk sub-segments follow each other in rank order, so ordering a tile's
+// list only needs the small rank windows of window.hpp, which the blend
+// kernels do in LDS for the windows they reach. The key traffic is one write
+// of a 4-byte rank per pair and one read per pair the blend reaches.
 #include "kernels.hpp"
+#include "window.hpp"
 
 namespace hr {
 namespace {
@@ -22,6 +29,8 @@ namespace {
 constexpr int RS_B = 256;             // radix-sort threads per block
 constexpr int RS_ROUNDS = 8;          // striped rounds per block
 constexpr int RS_KPB = RS_B * RS_ROUNDS;
+constexpr int SLICE = 8192;           // pairs per binning work unit
+constexpr int BIN_GRID = 512;         // persistent binning workgroups (2 per CU)
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = __lane_id();
@@ -180,24 +189,6 @@ __device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, 
   return lo;
 }
 
-// pair j of a chunk -> (rank offset k in the chunk, tile of the camera)
-__device__ __forceinline__ void pair_tile(const uint32_t* poff, int nr, uint32_t j, const uint2* rect_s,
-                                          int64_t r0, int TX, int& k, int& tl) {
-  int lo = 0, hi = nr - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (poff[mid] <= j) lo = mid; else hi = mid - 1;
-  }
-  k = lo;
-  const uint2 rc = rect_s[r0 + lo];
-  const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
-  const uint32_t wdt = x1 - x0;
-  const uint32_t loc = j - poff[lo];
-  const uint32_t ty = y0 + loc / wdt;
-  const uint32_t tx = x0 + loc - (loc / wdt) * wdt;
-  tl = (int)(ty * (uint32_t)TX + tx);
-}
-
 struct ChunkInfo {
   int cam;
   int64_t c, r0, r1;
@@ -214,31 +205,171 @@ __device__ __forceinline__ ChunkInfo chunk_info(const CamDev* cams, int n_cams,
   return ci;
 }
 
-__global__ __launch_bounds__(256) void k_chunk_count(const CamDev* __restrict__ cams, int n_cams,
-                                                     const uint32_t* __restrict__ vis_off,
-                                                     const uint64_t* __restrict__ pair_off,
-                                                     const uint2* __restrict__ rect_s,
-                                                     uint32_t* __restrict__ mat) {
-  __shared__ uint32_t hist[MAX_TILES_PER_CAM];
-  __shared__ uint32_t poff[CHUNK + 1];
-  const ChunkInfo ci = chunk_info(cams, n_cams, vis_off, blockIdx.x);
-  if (ci.r0 >= ci.r1) return;
+// per chunk row: number of pair slices; clears the row of used chunks
+__global__ __launch_bounds__(256) void k_row_slices(const CamDev* __restrict__ cams, int n_cams,
+                                                    const uint32_t* __restrict__ vis_off,
+                                                    const uint64_t* __restrict__ pair_off,
+                                                    uint32_t* __restrict__ slice_cnt,
+                                                    uint32_t* __restrict__ mat) {
+  const int64_t row = blockIdx.x;
+  const ChunkInfo ci = chunk_info(cams, n_cams, vis_off, row);
+  if (ci.r0 >= ci.r1) {
+    if (threadIdx.x == 0) slice_cnt[row] = 0;
+    return;
+  }
   const CamDev& cam = cams[ci.cam];
   const int ntl = cam.TX * cam.TY;
-  const int nr = (int)(ci.r1 - ci.r0);
-  for (int t = threadIdx.x; t < ntl; t += 256) hist[t] = 0;
-  const uint64_t p0 = pair_off[ci.r0];
-  for (int k = threadIdx.x; k <= nr; k += 256) poff[k] = (uint32_t)(pair_off[ci.r0 + k] - p0);
-  __syncthreads();
-  const uint32_t np = poff[nr];
-  for (uint32_t j = threadIdx.x; j < np; j += 256) {
-    int k, tl;
-    pair_tile(poff, nr, j, rect_s, ci.r0, cam.TX, k, tl);
-    atomicAdd(&hist[tl], 1u);
+  if (threadIdx.x == 0) {
+    const uint64_t np = pair_off[ci.r1] - pair_off[ci.r0];
+    slice_cnt[row] = (uint32_t)((np + SLICE - 1) / SLICE);
   }
-  __syncthreads();
-  uint32_t* row = mat + cam.mat_off + ci.c * (int64_t)ntl;
-  for (int t = threadIdx.x; t < ntl; t += 256) row[t] = hist[t];
+  uint32_t* r = mat + cam.mat_off + ci.c * (int64_t)ntl;
+  for (int t = threadIdx.x; t < ntl; t += 256) r[t] = 0;
+}
+
+// A slice: up to SLICE consecutive pairs of one chunk, with the pair offsets
+// of the ranks it overlaps staged in LDS (relative to its first pair).
+struct Slice {
+  int cam, ntl, nitems;
+  int64_t row, c, ia;      // first rank overlapped
+  uint64_t p0;
+  uint32_t np;
+};
+
+__device__ __forceinline__ int64_t last_le(const uint64_t* a, int64_t lo, int64_t hi, uint64_t v) {
+  // largest index in [lo, hi) with a[index] <= v (a[lo] <= v assumed)
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool load_slice(const CamDev* cams, int n_cams, const uint32_t* vis_off,
+                                           const uint64_t* pair_off, const uint32_t* slice_off,
+                                           int64_t rows_total, uint32_t sl, Slice& S,
+                                           int32_t* poff) {
+  // row holding slice sl
+  int64_t lo = 0, hi = rows_total - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (slice_off[mid] <= sl) lo = mid; else hi = mid - 1;
+  }
+  const ChunkInfo ci = chunk_info(cams, n_cams, vis_off, lo);
+  S.row = lo;
+  S.cam = ci.cam;
+  S.c = ci.c;
+  S.ntl = cams[ci.cam].TX * cams[ci.cam].TY;
+  const uint64_t k = sl - slice_off[lo];
+  const uint64_t pc0 = pair_off[ci.r0], pc1 = pair_off[ci.r1];
+  S.p0 = pc0 + k * SLICE;
+  const uint64_t p1 = S.p0 + SLICE < pc1 ? S.p0 + SLICE : pc1;
+  S.np = (uint32_t)(p1 - S.p0);
+  S.ia = last_le(pair_off, ci.r0, ci.r1, S.p0);
+  const int64_t ib = last_le(pair_off, S.ia, ci.r1, p1 - 1);
+  S.nitems = (int)(ib - S.ia + 1);
+  for (int i = threadIdx.x; i <= S.nitems; i += blockDim.x)
+    poff[i] = (int32_t)((int64_t)pair_off[S.ia + i] - (int64_t)S.p0);
+  return S.np > 0;
+}
+
+// pair j of the slice -> (rank, tile of its camera)
+__device__ __forceinline__ void slice_pair(const Slice& S, const int32_t* poff, uint32_t j,
+                                           const uint2* __restrict__ rect_s, int TX, uint32_t& rank,
+                                           int& tl) {
+  int lo = 0, hi = S.nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (poff[mid] <= (int32_t)j) lo = mid; else hi = mid - 1;
+  }
+  rank = (uint32_t)(S.ia + lo);
+  const uint2 rc = rect_s[rank];
+  const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
+  const uint32_t wdt = x1 - x0;
+  const uint32_t loc = (uint32_t)((int32_t)j - poff[lo]);
+  const uint32_t ty = y0 + loc / wdt;
+  const uint32_t tx = x0 + loc - (loc / wdt) * wdt;
+  tl = (int)(ty * (uint32_t)TX + tx);
+}
+
+// Pass 1: per (chunk, tile) pair counts. Persistent workgroups take slices in
+// turn; each histograms its pairs in LDS and adds the non-zero bins into the
+// chunk's row of the count matrix.
+__global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ cams, int n_cams,
+                                                   const uint32_t* __restrict__ vis_off,
+                                                   const uint64_t* __restrict__ pair_off,
+                                                   const uint32_t* __restrict__ slice_off,
+                                                   int64_t rows_total,
+                                                   const uint32_t* __restrict__ counters,
+                                                   const uint2* __restrict__ rect_s,
+                                                   uint32_t* __restrict__ mat) {
+  __shared__ uint32_t hist[MAX_TILES_PER_CAM];
+  __shared__ int32_t poff[CHUNK + 1];
+  const uint32_t nsl = counters[12];
+  for (uint32_t sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
+    Slice S;
+    load_slice(cams, n_cams, vis_off, pair_off, slice_off, rows_total, sl, S, poff);
+    const CamDev& cam = cams[S.cam];
+    for (int t = threadIdx.x; t < S.ntl; t += 256) hist[t] = 0;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < S.np; j += 256) {
+      uint32_t r;
+      int tl;
+      slice_pair(S, poff, j, rect_s, cam.TX, r, tl);
+      atomicAdd(&hist[tl], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = mat + cam.mat_off + S.c * (int64_t)S.ntl;
+    for (int t = threadIdx.x; t < S.ntl; t += 256)
+      if (hist[t]) atomicAdd(&row[t], hist[t]);
+    __syncthreads();
+  }
+}
+
+// Pass 2: every slice reserves its share of each (chunk, tile) sub-segment
+// with one atomic per non-zero bin, then scatters its ranks with LDS atomics.
+// Afterwards a matrix entry holds the end of its sub-segment.
+__global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ cams, int n_cams,
+                                                     const uint32_t* __restrict__ vis_off,
+                                                     const uint64_t* __restrict__ pair_off,
+                                                     const uint32_t* __restrict__ slice_off,
+                                                     int64_t rows_total,
+                                                     const uint32_t* __restrict__ counters,
+                                                     const uint2* __restrict__ rect_s,
+                                                     uint32_t* __restrict__ mat,
+                                                     const uint32_t* __restrict__ tile_start,
+                                                     int64_t key_cap, uint32_t* __restrict__ lists) {
+  __shared__ uint32_t hist[MAX_TILES_PER_CAM];
+  __shared__ int32_t poff[CHUNK + 1];
+  const uint32_t nsl = counters[12];
+  for (uint32_t sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
+    Slice S;
+    load_slice(cams, n_cams, vis_off, pair_off, slice_off, rows_total, sl, S, poff);
+    const CamDev& cam = cams[S.cam];
+    for (int t = threadIdx.x; t < S.ntl; t += 256) hist[t] = 0;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < S.np; j += 256) {
+      uint32_t r;
+      int tl;
+      slice_pair(S, poff, j, rect_s, cam.TX, r, tl);
+      atomicAdd(&hist[tl], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = mat + cam.mat_off + S.c * (int64_t)S.ntl;
+    for (int t = threadIdx.x; t < S.ntl; t += 256) {
+      const uint32_t h = hist[t];
+      if (h) hist[t] = tile_start[cam.tile_off + t] + atomicAdd(&row[t], h);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < S.np; j += 256) {
+      uint32_t r;
+      int tl;
+      slice_pair(S, poff, j, rect_s, cam.TX, r, tl);
+      const uint32_t pos = atomicAdd(&hist[tl], 1u);
+      if ((int64_t)pos < key_cap) lists[pos] = r;
+    }
+    __syncthreads();
+  }
 }
 
 // per global tile: exclusive prefix over its camera's used chunk rows, and the tile total
@@ -273,137 +404,39 @@ __global__ __launch_bounds__(256) void k_ranges(int n_tiles, const uint32_t* __r
   ranges[2 * t + 1] = tile_start[t] + tile_total[t];
 }
 
-__global__ __launch_bounds__(256) void k_chunk_scatter(const CamDev* __restrict__ cams, int n_cams,
-                                                       const uint32_t* __restrict__ vis_off,
-                                                       const uint64_t* __restrict__ pair_off,
-                                                       const uint2* __restrict__ rect_s,
-                                                       const uint32_t* __restrict__ mat,
-                                                       const uint32_t* __restrict__ tile_start,
-                                                       int64_t key_cap,
-                                                       uint32_t* __restrict__ lists) {
-  __shared__ uint32_t cur[MAX_TILES_PER_CAM];
-  __shared__ uint32_t poff[CHUNK + 1];
-  const ChunkInfo ci = chunk_info(cams, n_cams, vis_off, blockIdx.x);
-  if (ci.r0 >= ci.r1) return;
-  const CamDev& cam = cams[ci.cam];
-  const int ntl = cam.TX * cam.TY;
-  const int nr = (int)(ci.r1 - ci.r0);
-  const uint32_t* row = mat + cam.mat_off + ci.c * (int64_t)ntl;
-  for (int t = threadIdx.x; t < ntl; t += 256) cur[t] = tile_start[cam.tile_off + t] + row[t];
-  const uint64_t p0 = pair_off[ci.r0];
-  for (int k = threadIdx.x; k <= nr; k += 256) poff[k] = (uint32_t)(pair_off[ci.r0 + k] - p0);
-  __syncthreads();
-  const uint32_t np = poff[nr];
-  for (uint32_t j = threadIdx.x; j < np; j += 256) {
-    int k, tl;
-    pair_tile(poff, nr, j, rect_s, ci.r0, cam.TX, k, tl);
-    const uint32_t pos = atomicAdd(&cur[tl], 1u);
-    if ((int64_t)pos < key_cap) lists[pos] = (uint32_t)(ci.r0 + k);
-  }
-}
-
-// LDS radix sort of n <= SORT_WIN keys in a[], 8-bit digits over `bits` bits
-__device__ void lds_sort(uint32_t* a, uint32_t* b, int n, int bits, uint32_t* cnt,
-                         uint32_t (*wcnt)[256]) {
-  const int tid = threadIdx.x, w = tid >> 6;
-  for (int sh = 0; sh < bits; sh += 8) {
-    cnt[tid] = 0;
-    for (int k = 0; k < 4; ++k) wcnt[k][tid] = 0;
-    __syncthreads();
-    for (int i = tid; i < n; i += 256) atomicAdd(&cnt[(a[i] >> sh) & 255u], 1u);
-    __syncthreads();
-    // exclusive scan of the 256 digit counts (one per thread)
-    {
-      const uint32_t v = cnt[tid];
-      uint32_t inc = v;
-      const int l = __lane_id();
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t u = __shfl_up(inc, o, 64);
-        if (l >= o) inc += u;
-      }
-      __syncthreads();
-      if (l == 63) wcnt[0][w] = inc;  // borrow row 0 for the wave totals
-      __syncthreads();
-      uint32_t basev = 0;
-      for (int k = 0; k < w; ++k) basev += wcnt[0][k];
-      __syncthreads();
-      cnt[tid] = basev + inc - v;
-      wcnt[0][tid] = 0;
-      __syncthreads();
-    }
-    for (int r0 = 0; r0 < n; r0 += 256) {
-      const int i = r0 + tid;
-      const bool valid = i < n;
-      const uint32_t kk = valid ? a[i] : 0u;
-      const uint32_t d = (kk >> sh) & 255u;
-      const uint64_t m = match_digit(d, valid);
-      const uint32_t below = (uint32_t)__popcll(m & lanemask_lt());
-      if (valid && below == 0) wcnt[w][d] = (uint32_t)__popcll(m);
-      __syncthreads();
-      if (valid) {
-        uint32_t pos = cnt[d] + below;
-        for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-        b[pos] = kk;
-      }
-      __syncthreads();
-      uint32_t s = 0;
-      for (int k = 0; k < 4; ++k) {
-        s += wcnt[k][tid];
-        wcnt[k][tid] = 0;
-      }
-      cnt[tid] += s;
-      __syncthreads();
-    }
-    for (int i = tid; i < n; i += 256) a[i] = b[i];
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(256) void k_tile_sort(const CamDev* __restrict__ cams, int n_cams,
-                                                   int n_tiles, const uint32_t* __restrict__ vis_off,
-                                                   const uint32_t* __restrict__ mat,
-                                                   const uint32_t* __restrict__ tile_start,
-                                                   const uint32_t* __restrict__ tile_total,
-                                                   int64_t key_cap, uint32_t* __restrict__ lists) {
-  __shared__ uint32_t A[SORT_WIN];
-  __shared__ uint32_t B[SORT_WIN];
-  __shared__ uint32_t cnt[256];
-  __shared__ uint32_t wcnt[4][256];
+// Orders every window of every tile in place (only for exporting the keys;
+// the blend kernels order the windows they reach themselves).
+__global__ __launch_bounds__(256) void k_tile_order(const CamDev* __restrict__ cams, int n_cams,
+                                                    const uint32_t* __restrict__ vis_off,
+                                                    const uint32_t* __restrict__ mat,
+                                                    const uint32_t* __restrict__ tile_start,
+                                                    const uint32_t* __restrict__ tile_total,
+                                                    int64_t key_cap, uint32_t* __restrict__ lists) {
+  __shared__ uint32_t bitmap[WIN_WORDS];
+  __shared__ uint32_t red[4];
   const int t = blockIdx.x;
   const int c = find_cam_by_tile(cams, n_cams, t);
-  const CamDev& cam = cams[c];
-  const int64_t s = tile_start[t];
-  int64_t e = s + tile_total[t];
-  if (e > key_cap) e = key_cap;
-  if (e - s <= 1) return;
-  const uint32_t base = vis_off[c];
-  const uint32_t nvc = vis_off[c + 1] - base;
-  int bits = 8;
-  while (bits < 32 && (nvc >> bits) != 0) bits += 8;
-  const int ntl = cam.TX * cam.TY;
-  const int tl = t - cam.tile_off;
-  const int64_t rows = ((int64_t)nvc + CHUNK - 1) / CHUNK;
-  constexpr int G = SORT_WIN / CHUNK;  // chunk rows per window
-  int64_t ws = s;
-  for (int64_t r = 0; ws < e; r += G) {
-    int64_t we;
-    if (e - ws <= SORT_WIN) {
-      we = e;
-    } else {
-      const int64_t rn = r + G;
-      we = rn < rows ? s + (int64_t)mat[cam.mat_off + rn * ntl + tl] : e;
-      if (we > e) we = e;
+  const WinCtx W = win_ctx(cams[c], c, t, vis_off, mat, tile_start, tile_total, key_cap);
+  for (int w = 0; w < W.nwin; ++w) {
+    int64_t a, b;
+    win_range(W, w, a, b);
+    if (a >= b) continue;
+    const uint32_t wbase = W.rbase + (uint32_t)w * WIN;
+    bitmap[threadIdx.x] = 0;
+    __syncthreads();
+    win_mark(lists, W, a, b, wbase, bitmap);
+    __syncthreads();
+    const uint32_t word = bitmap[threadIdx.x];
+    uint32_t total;
+    const uint32_t pre = group_excl_scan((uint32_t)__popc(word), red, total);
+    uint32_t wv = word, idx = pre;
+    while (wv) {
+      const uint32_t bit = __ffs(wv) - 1;
+      wv &= wv - 1;
+      lists[W.s + a + idx] = wbase + 32u * threadIdx.x + bit;
+      ++idx;
     }
-    const int n = (int)(we - ws);
-    if (n > 1) {
-      for (int i = threadIdx.x; i < n; i += 256) A[i] = lists[ws + i] - base;
-      __syncthreads();
-      lds_sort(A, B, n, bits, cnt, wcnt);
-      for (int i = threadIdx.x; i < n; i += 256) lists[ws + i] = A[i] + base;
-      __syncthreads();
-    }
-    ws = we;
+    __syncthreads();
   }
 }
 
@@ -474,25 +507,30 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, hr_outputs* out,
   uint64_t* Ktot = reinterpret_cast<uint64_t*>(w.counters + 10);
   scan_u64(w.tiles_s, w.pair_off, M + 1, Ktot, w.scan_scratch, st);
   hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, Ktot, S.key_cap, w.counters);
-  if (w.chunk_rows > 0)
-    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)w.chunk_rows), dim3(256), 0, st, w.cams,
-                       n_cams, w.vis_off, w.pair_off, w.rect_s, w.mat);
+  if (w.chunk_rows > 0) {
+    hipLaunchKernelGGL(k_row_slices, dim3((unsigned)w.chunk_rows), dim3(256), 0, st, w.cams, n_cams,
+                       w.vis_off, w.pair_off, w.slice_cnt, w.mat);
+    scan_u32(w.slice_cnt, w.slice_off, w.chunk_rows, w.counters + 12, w.scan_scratch, st);
+    hipLaunchKernelGGL(k_bin_count, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
+                       w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s, w.mat);
+  }
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
   scan_u32(w.tile_total, w.tile_start, S.n_tiles, nullptr, w.scan_scratch, st);
   if (w.chunk_rows > 0)
-    hipLaunchKernelGGL(k_chunk_scatter, dim3((unsigned)w.chunk_rows), dim3(256), 0, st, w.cams,
-                       n_cams, w.vis_off, w.pair_off, w.rect_s, w.mat, w.tile_start, S.key_cap,
-                       w.lists);
-  hipLaunchKernelGGL(k_tile_sort, dim3(S.n_tiles), dim3(256), 0, st, w.cams, n_cams, S.n_tiles,
-                     w.vis_off, w.mat, w.tile_start, w.tile_total, S.key_cap, w.lists);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
+                       w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s, w.mat,
+                       w.tile_start, S.key_cap, w.lists);
   if (out && out->ranges)
     hipLaunchKernelGGL(k_ranges, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, S.n_tiles,
                        w.tile_start, w.tile_total, out->ranges);
-  if (out && out->keys && out->values)
+  if (out && out->keys && out->values) {
+    hipLaunchKernelGGL(k_tile_order, dim3(S.n_tiles), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
+                       w.mat, w.tile_start, w.tile_total, S.key_cap, w.lists);
     hipLaunchKernelGGL(k_export_keys, dim3(S.n_tiles), dim3(256), 0, st, w.cams, n_cams, S.n_tiles,
                        w.tile_start, w.tile_total, w.lists, w.rec_s, S.key_cap, out->keys,
                        out->values);
+  }
 }
 
 }  // namespace hr

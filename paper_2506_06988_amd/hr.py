@@ -59,7 +59,7 @@ class hr_grads(C.Structure):
 
 
 EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid",
-            "hr_render_hybrid_backward", "hr_loss_scratch_bytes", "hr_hybrid_loss", "hr_autotune",
+            "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss", "hr_autotune",
             "hr_batch_create", "hr_batch_launch", "hr_batch_destroy", "hr_status_string",
             "hr_last_error", "hr_abi_version"]
 
@@ -83,6 +83,8 @@ def load(path: str = LIB_PATH):
     L.hr_render_hybrid_backward.restype = C.c_int
     L.hr_render_hybrid_backward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P,
                                             P, P, P]
+    L.hr_blend_forward.restype = C.c_int
+    L.hr_blend_forward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P]
     L.hr_loss_scratch_bytes.restype = C.c_size_t
     L.hr_loss_scratch_bytes.argtypes = [C.c_int64]
     L.hr_hybrid_loss.restype = C.c_int
@@ -379,6 +381,21 @@ class Renderer:
             _ptr(None if grad_mesh_rgb is None else grad_mesh_rgb.contiguous()), C.byref(gr),
             _stream()))
         return grads
+
+    def set_cameras(self, cams):
+        """Switch to other cameras of the same sizes (the workspace is reused)."""
+        cams = list(cams)
+        assert [(c.width, c.height) for c in cams] == [(c.width, c.height) for c in self.cams]
+        self.cams = cams
+        self.cam_arr = camera_array(cams)
+
+    def blend_forward(self, frame: Frame):
+        """hr_blend_forward: re-run only the blend of the last forward."""
+        gs, ms = self._structs()
+        o = self.outputs_struct(frame)
+        check(self.L.hr_blend_forward(C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams),
+                                      C.byref(self.settings), self.key_capacity, _ptr(self.ws),
+                                      self.ws_bytes, C.byref(o), _stream()))
 
     def autotune(self, frame: Frame, repeats=5):
         gs, ms = self._structs()

@@ -33,12 +33,16 @@ def gpu_render(hr, scene, cams=None, export_keys=False, settings=None, key_capac
     return r, f
 
 
-def check_view(f, cams, c, orc, amb_frac_max=2e-3, img_tol=1e-4):
+def check_view(f, cams, c, orc, amb_frac_max=None, img_tol=1e-4):
     im, T, mr, md, tri, nc, nb, npro = [x.cpu().numpy() for x in f.view(c, cams)]
     amb = orc["amb"] != 0
     mesh_amb = (orc["amb"] & 16) != 0
     frac = amb.mean()
     say(f"view {c}: {cams[c].width}x{cams[c].height} ambiguous px {amb.sum()} ({frac:.2e})")
+    if amb_frac_max is None:
+        # each examined pair lands in an alpha slack band of relative width
+        # 2e-5 with probability ~0.17 * 2e-5; add the T-stop band
+        amb_frac_max = 1e-3 + 1e-5 * float(orc["n_processed"].mean())
     assert frac <= amb_frac_max
     np.testing.assert_array_equal(tri, orc["tri_id"])
     ok = ~mesh_amb
@@ -109,6 +113,22 @@ def test_small_room_three_uneven_cameras_in_one_call(hr, seed):
         key_base += K
         tile_base += ntl
     assert st["n_keys"] == key_base
+
+
+def test_many_rank_windows_and_pair_slices(hr):
+    # > 8192 visible Gaussians per camera: tile lists span several rank
+    # windows, and chunks hold more pairs than one binning slice
+    say("case: windows and slices")
+    sc = scenes.small_room(31, n=40000, faces=4000, tex=64, width=320, height=240)
+    r, f = gpu_render(hr, sc, export_keys=True)
+    st = f.stats_dict()
+    say("stats", st)
+    assert st["n_visible"] > 8192 and st["n_keys"] > 4 * 8192
+    check_view(f, sc.cameras, 0, oracle.render(sc.gaussians, sc.mesh, sc.cameras[0]))
+    k, v, rg = oracle.keys(sc.gaussians, sc.cameras[0])
+    K = len(k)
+    np.testing.assert_array_equal(f.keys[:K].cpu().numpy().view(np.uint64), k)
+    np.testing.assert_array_equal(f.values[:K].cpu().numpy().view(np.uint32), v)
 
 
 def test_ragged_sizes_and_edge_cases(hr):
