@@ -241,6 +241,7 @@ SetDev make_setdev(const Plan& p, const hr_gaussians* g, const hr_mesh* m, const
   S.tex_h = m->n_faces > 0 ? m->tex_h : 1;
   S.tex_w = m->n_faces > 0 ? m->tex_w : 1;
   S.n_tiles = (int32_t)p.n_tiles;
+  for (const CamDev& d : p.camdev) S.max_tiles_cam = std::max(S.max_tiles_cam, d.TX * d.TY);
   S.n_pix = p.P;
   S.key_cap = p.key_cap;
   return S;

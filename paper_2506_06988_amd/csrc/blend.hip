@@ -362,8 +362,8 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
         }
         if (__ballot(contrib)) {
 #pragma unroll
-          for (int q = 0; q < 9; ++q) g[q] = wave_sum(g[q]);
-          if (lane == 0) {
+          for (int q = 0; q < 9; ++q) g[q] = wave_sum_to_last(g[q]);
+          if (lane == 63) {
             float* dst = gacc + (size_t)rk[k] * 9;
 #pragma unroll
             for (int q = 0; q < 9; ++q) atomicAdd(dst + q, g[q]);

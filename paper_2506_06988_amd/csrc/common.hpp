@@ -38,6 +38,7 @@ struct SetDev {
   int32_t n, sh_degree, n_cams, n_faces, n_verts;
   int32_t n_tex, tex_h, tex_w;
   int32_t n_tiles;   // over all cameras
+  int32_t max_tiles_cam;  // largest tile count of one camera
   int64_t n_pix;     // over all cameras
   int64_t key_cap;
 };
@@ -69,6 +70,26 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 __device__ __forceinline__ uint32_t f2u(float f) { return __float_as_uint(f); }
+
+// DPP lane move (row_mask/bank_mask select written rows/banks; lanes that have
+// no source or are not written read 0)
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Sum over the 64 lanes of a wave, complete in lane 63: shifts by 1, 2, 4, 8
+// within each row of 16 lanes, then row 0 -> row 1 and row 2 -> row 3
+// (broadcast of lane 15), then rows 0-1 -> rows 2-3 (broadcast of lane 31).
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+  v += dpp_f<0x111>(v);
+  v += dpp_f<0x112>(v);
+  v += dpp_f<0x114>(v);
+  v += dpp_f<0x118>(v);
+  v += dpp_f<0x142, 0xa>(v);
+  v += dpp_f<0x143, 0xc>(v);
+  return v;
+}
 
 }  // namespace hr
 

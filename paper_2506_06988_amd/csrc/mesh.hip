@@ -3,8 +3,9 @@
 //   k_mesh_count   per (camera, face): clip, snap, count kept triangles and
 //                  8x8 pixel blocks of their bounding boxes
 //   k_mesh_setup   per (camera, face): write the kept triangles compactly
-//   k_mesh_raster  one wave per (triangle, block): 64 lanes = 64 pixels test
-//                  integer edge functions and atomicMin a 64-bit key
+//   k_mesh_raster  (triangle, 8x8 block) work items, a contiguous run per wave;
+//                  64 lanes = 64 pixels test integer edge functions and
+//                  atomicMin a 64-bit key
 //                  (fp32 depth bits << 32 | triangle index) into the z-buffer.
 //                  Triangle indices increase with face id, so equal depths
 //                  resolve to the lower face whatever the launch order.
@@ -82,33 +83,44 @@ __global__ __launch_bounds__(256) void k_mesh_raster(SetDev S, const CamDev* __r
   const int64_t MF = (int64_t)S.n_faces * S.n_cams;
   const uint32_t nblk = blk_off[MF];
   const int lane = __lane_id();
-  const int waves = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nblk; b += waves) {
-    // (camera, face) entry holding block b
-    int64_t lo = 0, hi = MF - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (blk_off[mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    uint32_t lb = b - blk_off[lo];
-    uint32_t t = tri_off[lo];
-    int nb0 = tri_blocks(tris[t]);
-    if ((int)lb >= nb0) {
-      lb -= nb0;
-      ++t;
-    }
+  // each wave rasterizes a contiguous run of blocks: one search, then a walk
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t per = (nblk + waves - 1) / waves;
+  const uint32_t b0 = wid * per;
+  if (b0 >= nblk) return;
+  const uint32_t b1 = b0 + per < nblk ? b0 + per : nblk;
+  int64_t lo = 0, hi = MF - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (blk_off[mid] <= b0) lo = mid; else hi = mid - 1;
+  }
+  uint32_t t = tri_off[lo];
+  int lb = (int)(b0 - blk_off[lo]);
+  int nbt = tri_blocks(tris[t]);
+  if (lb >= nbt) {
+    lb -= nbt;
+    ++t;
+    nbt = tri_blocks(tris[t]);
+  }
+  for (uint32_t b = b0; b < b1; ++b) {
     const TriRec& T = tris[t];
     const CamDev& C = cams[T.cam];
     const int nbx = T.bx1 - T.bx0 + 1;
-    const int bx = T.bx0 + (int)(lb % nbx), by = T.by0 + (int)(lb / nbx);
+    const int bx = T.bx0 + lb % nbx, by = T.by0 + lb / nbx;
     const int i = bx * 8 + (lane & 7), j = by * 8 + (lane >> 3);
-    if (i >= C.W || j >= C.H) continue;
     int64_t e[3];
-    if (!tri_cover(T, i, j, e)) continue;
-    const double z = tri_interp(T, e, nullptr);
-    const unsigned long long key =
-        ((unsigned long long)__float_as_uint(__double2float_rn(z)) << 32) | t;
-    atomicMin(&zbuf[C.pix_off + (int64_t)j * C.W + i], key);
+    if (i < C.W && j < C.H && tri_cover(T, i, j, e)) {
+      const double z = tri_interp(T, e, nullptr);
+      const unsigned long long key =
+          ((unsigned long long)__float_as_uint(__double2float_rn(z)) << 32) | t;
+      atomicMin(&zbuf[C.pix_off + (int64_t)j * C.W + i], key);
+    }
+    if (++lb >= nbt && b + 1 < b1) {
+      lb = 0;
+      ++t;
+      nbt = tri_blocks(tris[t]);
+    }
   }
 }
 

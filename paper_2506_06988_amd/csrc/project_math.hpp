@@ -115,12 +115,12 @@ __device__ __forceinline__ void project_gaussian(const SetDev& S, const CamDev& 
   const float l0 = log_scales[3 * g], l1 = log_scales[3 * g + 1], l2 = log_scales[3 * g + 2];
   const float4 q4 = *reinterpret_cast<const float4*>(quats + 4 * (size_t)g);
   const float lg = logits[g];
-  bool fin = finite_f(m0) && finite_f(m1) && finite_f(m2) && finite_f(l0) && finite_f(l1) &&
-             finite_f(l2) && finite_f(q4.x) && finite_f(q4.y) && finite_f(q4.z) &&
-             finite_f(q4.w) && finite_f(lg);
-  const float* shg = sh + (size_t)g * K * 3;
-  for (int k = 0; k < 3 * K; ++k) fin = fin && finite_f(shg[k]);
+  // non-finite SH coefficients give a non-finite colour, which culls below
+  const bool fin = finite_f(m0) && finite_f(m1) && finite_f(m2) && finite_f(l0) &&
+                   finite_f(l1) && finite_f(l2) && finite_f(q4.x) && finite_f(q4.y) &&
+                   finite_f(q4.z) && finite_f(q4.w) && finite_f(lg);
   if (!fin) return;
+  const float* shg = sh + (size_t)g * K * 3;
 
   const double mu[3] = {m0, m1, m2};
   for (int i = 0; i < 3; ++i)
@@ -184,19 +184,41 @@ __device__ __forceinline__ void project_gaussian(const SetDev& S, const CamDev& 
   P.y1 = clamp_tile(floor((P.v + rr) / TILE) + 1.0, cam.TY);
   if ((P.x1 - P.x0) * (P.y1 - P.y0) <= 0) return;
   P.zf = __double2float_rn(z);
-  P.vis = true;
-  if (!need_colour) return;
+  if (!need_colour) {
+    P.vis = true;
+    return;
+  }
   const double d0 = mu[0] - cam.C[0], d1 = mu[1] - cam.C[1], d2 = mu[2] - cam.C[2];
   P.dnorm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   P.dir[0] = d0 / P.dnorm; P.dir[1] = d1 / P.dnorm; P.dir[2] = d2 / P.dnorm;
   double Y[16];
   sh_eval(P.dir, S.sh_degree, Y);
-  for (int ch = 0; ch < 3; ++ch) {
-    double acc = 0.5;
-    for (int k = 0; k < K; ++k) acc += Y[k] * (double)shg[3 * k + ch];
-    P.clamped[ch] = acc < 0.0;
-    P.rgb[ch] = P.clamped[ch] ? 0.0 : acc;
+  double acc[3] = {0.5, 0.5, 0.5};
+  if ((((uintptr_t)shg) & 15u) == 0 && (3 * K) % 4 == 0) {
+    // 3K floats as 16-byte vectors (K = 4, 16 give 12 and 48 floats)
+    const float4* v4 = reinterpret_cast<const float4*>(shg);
+    for (int i = 0; i < (3 * K) / 4; ++i) {
+      const float4 f = v4[i];
+      const float e[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int idx = 4 * i + k;
+        acc[idx % 3] += Y[idx / 3] * (double)e[k];
+      }
+    }
+  } else {
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * (double)shg[3 * k + ch];
   }
+  bool finite_rgb = true;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    finite_rgb = finite_rgb && isfinite(acc[ch]);
+    P.clamped[ch] = acc[ch] < 0.0;
+    P.rgb[ch] = P.clamped[ch] ? 0.0 : acc[ch];
+  }
+  P.vis = finite_rgb;
 }
 
 }  // namespace hr

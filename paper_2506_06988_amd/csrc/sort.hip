@@ -273,28 +273,59 @@ __device__ __forceinline__ bool load_slice(const CamDev* cams, int n_cams, const
   return S.np > 0;
 }
 
-// pair j of the slice -> (rank, tile of its camera)
-__device__ __forceinline__ void slice_pair(const Slice& S, const int32_t* poff, uint32_t j,
-                                           const uint2* __restrict__ rect_s, int TX, uint32_t& rank,
-                                           int& tl) {
-  int lo = 0, hi = S.nitems - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (poff[mid] <= (int32_t)j) lo = mid; else hi = mid - 1;
+// Calls f(rank, tile) for every pair of the slice. Ranks with at most SMALL
+// pairs in the slice are walked by one thread each (tile by tile across
+// their rectangle); larger ones are shared by the whole workgroup.
+constexpr int SMALL = 32;
+
+template <typename F>
+__device__ __forceinline__ void slice_pairs(const Slice& S, const int32_t* poff, const uint2* rects,
+                                            int TX, uint32_t* big, uint32_t* nbig, F&& f) {
+  for (int k = threadIdx.x; k < S.nitems; k += blockDim.x) {
+    const int32_t lo = poff[k] > 0 ? poff[k] : 0;
+    const int32_t hi = poff[k + 1] < (int32_t)S.np ? poff[k + 1] : (int32_t)S.np;
+    if (hi - lo > SMALL) {
+      big[atomicAdd(nbig, 1u)] = (uint32_t)k;
+      continue;
+    }
+    if (hi <= lo) continue;
+    const uint2 rc = rects[k];
+    const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
+    const uint32_t wdt = x1 - x0;
+    const uint32_t loc = (uint32_t)(lo - poff[k]);
+    uint32_t ty = y0 + loc / wdt, tx = x0 + loc % wdt;
+    const uint32_t r = (uint32_t)(S.ia + k);
+    for (int32_t j = lo; j < hi; ++j) {
+      f(r, (int)(ty * (uint32_t)TX + tx));
+      if (++tx == x1) {
+        tx = x0;
+        ++ty;
+      }
+    }
   }
-  rank = (uint32_t)(S.ia + lo);
-  const uint2 rc = rect_s[rank];
-  const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
-  const uint32_t wdt = x1 - x0;
-  const uint32_t loc = (uint32_t)((int32_t)j - poff[lo]);
-  const uint32_t ty = y0 + loc / wdt;
-  const uint32_t tx = x0 + loc - (loc / wdt) * wdt;
-  tl = (int)(ty * (uint32_t)TX + tx);
+  __syncthreads();
+  const uint32_t nb = *nbig;
+  for (uint32_t i = 0; i < nb; ++i) {
+    const int k = (int)big[i];
+    const int32_t lo = poff[k] > 0 ? poff[k] : 0;
+    const int32_t hi = poff[k + 1] < (int32_t)S.np ? poff[k + 1] : (int32_t)S.np;
+    const uint2 rc = rects[k];
+    const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
+    const uint32_t wdt = x1 - x0;
+    const uint32_t r = (uint32_t)(S.ia + k);
+    for (int32_t j = lo + (int32_t)threadIdx.x; j < hi; j += blockDim.x) {
+      const uint32_t loc = (uint32_t)(j - poff[k]);
+      const uint32_t ty = y0 + loc / wdt;
+      const uint32_t tx = x0 + loc - (loc / wdt) * wdt;
+      f(r, (int)(ty * (uint32_t)TX + tx));
+    }
+  }
 }
 
 // Pass 1: per (chunk, tile) pair counts. Persistent workgroups take slices in
-// turn; each histograms its pairs in LDS and adds the non-zero bins into the
-// chunk's row of the count matrix.
+// turn; each histograms its pairs per tile in LDS and adds the non-zero bins
+// into the chunk's row of the count matrix. HT = LDS histogram entries.
+template <int HT>
 __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ cams, int n_cams,
                                                    const uint32_t* __restrict__ vis_off,
                                                    const uint64_t* __restrict__ pair_off,
@@ -303,21 +334,22 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
                                                    const uint32_t* __restrict__ counters,
                                                    const uint2* __restrict__ rect_s,
                                                    uint32_t* __restrict__ mat) {
-  __shared__ uint32_t hist[MAX_TILES_PER_CAM];
+  __shared__ uint32_t hist[HT];
   __shared__ int32_t poff[CHUNK + 1];
+  __shared__ uint2 rects[CHUNK];
+  __shared__ uint32_t big[CHUNK];
+  __shared__ uint32_t nbig;
   const uint32_t nsl = counters[12];
   for (uint32_t sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
     Slice S;
     load_slice(cams, n_cams, vis_off, pair_off, slice_off, rows_total, sl, S, poff);
     const CamDev& cam = cams[S.cam];
+    for (int k = threadIdx.x; k < S.nitems; k += 256) rects[k] = rect_s[S.ia + k];
     for (int t = threadIdx.x; t < S.ntl; t += 256) hist[t] = 0;
+    if (threadIdx.x == 0) nbig = 0;
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < S.np; j += 256) {
-      uint32_t r;
-      int tl;
-      slice_pair(S, poff, j, rect_s, cam.TX, r, tl);
-      atomicAdd(&hist[tl], 1u);
-    }
+    slice_pairs(S, poff, rects, cam.TX, big, &nbig,
+                [&](uint32_t, int tl) { atomicAdd(&hist[tl], 1u); });
     __syncthreads();
     uint32_t* row = mat + cam.mat_off + S.c * (int64_t)S.ntl;
     for (int t = threadIdx.x; t < S.ntl; t += 256)
@@ -329,6 +361,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
 // Pass 2: every slice reserves its share of each (chunk, tile) sub-segment
 // with one atomic per non-zero bin, then scatters its ranks with LDS atomics.
 // Afterwards a matrix entry holds the end of its sub-segment.
+template <int HT>
 __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ cams, int n_cams,
                                                      const uint32_t* __restrict__ vis_off,
                                                      const uint64_t* __restrict__ pair_off,
@@ -339,35 +372,34 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
                                                      uint32_t* __restrict__ mat,
                                                      const uint32_t* __restrict__ tile_start,
                                                      int64_t key_cap, uint32_t* __restrict__ lists) {
-  __shared__ uint32_t hist[MAX_TILES_PER_CAM];
+  __shared__ uint32_t hist[HT];
   __shared__ int32_t poff[CHUNK + 1];
+  __shared__ uint2 rects[CHUNK];
+  __shared__ uint32_t big[CHUNK];
+  __shared__ uint32_t nbig;
   const uint32_t nsl = counters[12];
   for (uint32_t sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
     Slice S;
     load_slice(cams, n_cams, vis_off, pair_off, slice_off, rows_total, sl, S, poff);
     const CamDev& cam = cams[S.cam];
+    for (int k = threadIdx.x; k < S.nitems; k += 256) rects[k] = rect_s[S.ia + k];
     for (int t = threadIdx.x; t < S.ntl; t += 256) hist[t] = 0;
+    if (threadIdx.x == 0) nbig = 0;
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < S.np; j += 256) {
-      uint32_t r;
-      int tl;
-      slice_pair(S, poff, j, rect_s, cam.TX, r, tl);
-      atomicAdd(&hist[tl], 1u);
-    }
+    slice_pairs(S, poff, rects, cam.TX, big, &nbig,
+                [&](uint32_t, int tl) { atomicAdd(&hist[tl], 1u); });
     __syncthreads();
     uint32_t* row = mat + cam.mat_off + S.c * (int64_t)S.ntl;
     for (int t = threadIdx.x; t < S.ntl; t += 256) {
       const uint32_t h = hist[t];
       if (h) hist[t] = tile_start[cam.tile_off + t] + atomicAdd(&row[t], h);
     }
+    if (threadIdx.x == 0) nbig = 0;
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < S.np; j += 256) {
-      uint32_t r;
-      int tl;
-      slice_pair(S, poff, j, rect_s, cam.TX, r, tl);
+    slice_pairs(S, poff, rects, cam.TX, big, &nbig, [&](uint32_t r, int tl) {
       const uint32_t pos = atomicAdd(&hist[tl], 1u);
       if ((int64_t)pos < key_cap) lists[pos] = r;
-    }
+    });
     __syncthreads();
   }
 }
@@ -511,16 +543,28 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, hr_outputs* out,
     hipLaunchKernelGGL(k_row_slices, dim3((unsigned)w.chunk_rows), dim3(256), 0, st, w.cams, n_cams,
                        w.vis_off, w.pair_off, w.slice_cnt, w.mat);
     scan_u32(w.slice_cnt, w.slice_off, w.chunk_rows, w.counters + 12, w.scan_scratch, st);
-    hipLaunchKernelGGL(k_bin_count, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
-                       w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s, w.mat);
+    if (S.max_tiles_cam <= 8192)
+      hipLaunchKernelGGL(k_bin_count<8192>, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams,
+                         w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s,
+                         w.mat);
+    else
+      hipLaunchKernelGGL(k_bin_count<MAX_TILES_PER_CAM>, dim3(BIN_GRID), dim3(256), 0, st, w.cams,
+                         n_cams, w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters,
+                         w.rect_s, w.mat);
   }
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
   scan_u32(w.tile_total, w.tile_start, S.n_tiles, nullptr, w.scan_scratch, st);
-  if (w.chunk_rows > 0)
-    hipLaunchKernelGGL(k_bin_scatter, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
-                       w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s, w.mat,
-                       w.tile_start, S.key_cap, w.lists);
+  if (w.chunk_rows > 0) {
+    if (S.max_tiles_cam <= 8192)
+      hipLaunchKernelGGL(k_bin_scatter<8192>, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams,
+                         w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s,
+                         w.mat, w.tile_start, S.key_cap, w.lists);
+    else
+      hipLaunchKernelGGL(k_bin_scatter<MAX_TILES_PER_CAM>, dim3(BIN_GRID), dim3(256), 0, st,
+                         w.cams, n_cams, w.vis_off, w.pair_off, w.slice_off, w.chunk_rows,
+                         w.counters, w.rect_s, w.mat, w.tile_start, S.key_cap, w.lists);
+  }
   if (out && out->ranges)
     hipLaunchKernelGGL(k_ranges, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, S.n_tiles,
                        w.tile_start, w.tile_total, out->ranges);
