@@ -1,0 +1,197 @@
+"""Parity at the benchmark's full sizes, on sampled windows the oracle can afford.
+
+The GPU renders whole frames exactly as bench.py does; the oracle renders the
+same frame restricted to sampled 32x32 windows (its per-pixel result does not
+depend on the window). Gradients use a loss restricted to a 32x32 crop, so the
+oracle only needs the crop.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_06988_amd import scenes
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def windows(cam, n, rng, size=32):
+    out = []
+    for _ in range(n):
+        x0 = int(rng.integers(0, max(1, (cam.width - size) // 16 + 1))) * 16
+        y0 = int(rng.integers(0, max(1, (cam.height - size) // 16 + 1))) * 16
+        out.append((x0, y0, min(cam.width, x0 + size), min(cam.height, y0 + size)))
+    return out
+
+
+def check_window(view, orc, win):
+    x0, y0, x1, y1 = win
+    im, T, mr, md, tri, nc, nb, npro = [v[..., y0:y1, x0:x1] for v in view]
+    amb = orc["amb"] != 0
+    good = ~amb
+    np.testing.assert_array_equal(tri, orc["tri_id"])
+    np.testing.assert_allclose(mr, orc["mesh_rgb"], atol=1e-5)
+    d = np.abs(im - orc["image"])[:, good]
+    assert d.size == 0 or d.max() <= 1e-4, d.max()
+    assert np.abs(T - orc["final_T"])[good].max(initial=0) <= 1e-4
+    np.testing.assert_array_equal(nc[good], orc["n_contrib"][good])
+    np.testing.assert_array_equal(npro[good], orc["n_processed"][good])
+    return int(amb.sum()), amb.size
+
+
+def run_frames(hr, sc, cams, n_win, seed):
+    g, m = hr.to_device(sc.gaussians, sc.mesh)
+    r = hr.Renderer(g, m, cams)
+    f = r.render_hybrid()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    tot_amb = tot = 0
+    for c, cam in enumerate(cams):
+        view = [v.cpu().numpy() for v in f.view(c, cams)]
+        for win in windows(cam, n_win, rng):
+            orc = oracle.render(sc.gaussians, sc.mesh, cam, window=win)
+            a, n = check_window(view, orc, win)
+            tot_amb += a
+            tot += n
+    say(f"{sc.name}: {len(cams)} cameras, ambiguous {tot_amb}/{tot}; stats {f.stats_dict()}")
+    assert tot_amb <= 0.01 * tot
+    return r, f
+
+
+def test_720p_poses(hr):
+    say("case: 720p, 300k Gaussians, 8 poses")
+    sc = scenes.config2()
+    run_frames(hr, sc, sc.cameras[:4], 2, 1)
+
+
+def test_1080p_hybrid_and_gaussian_only(hr):
+    say("case: 1080p hybrid and Gaussian-only")
+    sc = scenes.config5("hybrid")
+    run_frames(hr, sc, [sc.cameras[1], sc.cameras[2]], 3, 2)
+    sg = scenes.config5("gaussian_only")
+    run_frames(hr, sg, [sg.cameras[1]], 3, 3)
+
+
+def test_sixteen_uneven_cameras_forward(hr):
+    say("case: 16 uneven cameras")
+    sc = scenes.config4()
+    run_frames(hr, sc, sc.cameras, 1, 4)
+
+
+def _crop_subscene(sc, cam, win):
+    """Gaussians whose tile rectangle meets the crop's tiles (the only ones
+    that can reach its pixels), in their original order."""
+    pr = oracle.project(sc.gaussians, cam)
+    x0, y0, x1, y1 = win
+    tx0, ty0, tx1, ty1 = x0 // 16, y0 // 16, (x1 + 15) // 16, (y1 + 15) // 16
+    r = pr["rect"]
+    sel = (pr["radius"] > 0) & (r[:, 0] < tx1) & (r[:, 1] > tx0) & (r[:, 2] < ty1) & (r[:, 3] > ty0)
+    return np.nonzero(sel)[0]
+
+
+def test_1600x1064_gradients_on_a_crop_vs_oracle_and_finite_differences(hr):
+    say("case: 1600x1064, 1M Gaussians, crop gradients")
+    sc = scenes.config3()
+    cam = sc.cameras[0]
+    g, m = hr.to_device(sc.gaussians, sc.mesh)
+    r = hr.Renderer(g, m, [cam])
+    f = r.render_hybrid()
+    torch.cuda.synchronize()
+    # a crop with mesh pixels and Gaussians
+    rng = np.random.default_rng(33)
+    view = [v.cpu().numpy() for v in f.view(0, [cam])]
+    for _ in range(50):
+        win = windows(cam, 1, rng)[0]
+        x0, y0, x1, y1 = win
+        if (view[4][y0:y1, x0:x1] >= 0).all() and view[6][y0:y1, x0:x1].mean() > 2:
+            break
+    say("crop", win)
+    orc = oracle.render(sc.gaussians, sc.mesh, cam, window=win)
+    check_window(view, orc, win)
+    tgt = sc.target[0][:, y0:y1, x0:x1]
+    L, gi, gt, gm = oracle.loss(orc["image"], orc["final_T"], orc["mesh_rgb"], orc["tri_id"], tgt)
+    amb = orc["amb"] != 0
+    gi[:, amb] = 0
+    gt[amb] = 0
+    gm[:, amb] = 0
+    H, W = cam.height, cam.width
+    full = lambda a, c: np.zeros((c, H, W) if c else (H, W), np.float32)
+    GI, GT, GM = full(None, 3), full(None, 0), full(None, 3)
+    GI[:, y0:y1, x0:x1] = gi
+    GT[y0:y1, x0:x1] = gt
+    GM[:, y0:y1, x0:x1] = gm
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1)).cuda()
+    grads = r.render_hybrid_backward(d(GI), d(GT), d(GM))
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in grads.items()}
+    ref = oracle.backward(sc.gaussians, sc.mesh, cam, gi.astype(np.float32).astype(np.float64),
+                          gt.astype(np.float32).astype(np.float64),
+                          gm.astype(np.float32).astype(np.float64), window=win)
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex"):
+        a, b = gpu[k].reshape(-1).astype(np.float64), ref[k].reshape(-1)
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        say(f"  {k}: |ref| {np.linalg.norm(b):.3e} rel err {rel:.2e}")
+        assert rel <= 1e-3, k
+
+    # FP64 finite differences of the crop loss, on the Gaussians that reach it
+    idx = _crop_subscene(sc, cam, win)
+    sub = sc.gaussians.subset(idx)
+    p64 = oracle.default_params(flags=oracle.FP64_RECORDS)
+    base = dict(means=sub.means.astype(np.float64), log_scales=sub.log_scales.astype(np.float64),
+                quats=sub.quats.astype(np.float64), opacity_logits=sub.opacity_logits.astype(np.float64),
+                sh=sub.sh.astype(np.float64))
+
+    def loss_at(over):
+        o = oracle.render(sub, sc.mesh, cam, params=p64, window=win, overrides=over)
+        return oracle.loss(o["image"], o["final_T"], o["mesh_rgb"], o["tri_id"], tgt)[0], o["trace"]
+
+    checked = bad = 0
+    frs = np.random.default_rng(7)
+    for name, arr in base.items():
+        g_gpu = gpu[name][idx].reshape(-1)
+        flat = arr.reshape(-1)
+        # sample parameters with a non-negligible gradient
+        cand = np.nonzero(np.abs(g_gpu) > 1e-3 * np.abs(g_gpu).max())[0]
+        for j in frs.choice(cand, size=min(len(cand), 45), replace=False):
+            h = 1e-6 * max(1.0, abs(flat[j]))
+            over = {k: v.copy() for k, v in base.items()}
+            over[name].reshape(-1)[j] = flat[j] + h
+            lp, tp = loss_at(over)
+            over[name].reshape(-1)[j] = flat[j] - h
+            lm, tm = loss_at(over)
+            if tp != tm:
+                continue  # a decision (L1 sign, skip, stop, clamp) flipped
+            fd = (lp - lm) / (2 * h)
+            checked += 1
+            if abs(fd - g_gpu[j]) > 1e-3 * abs(fd) + 1e-6 * np.abs(g_gpu).max():
+                bad += 1
+    say(f"  parameter FD samples {checked}, outside 1e-3: {bad}")
+    assert checked >= 200 and bad <= 0.01 * checked
+    # texels under the crop: the loss is quadratic in the texture on the mesh
+    # path, so a central difference with a large step is exact up to the L1 kinks
+    gtex = gpu["tex"].reshape(-1)
+    cand = np.nonzero(gtex != 0)[0]
+    tex = sc.mesh.tex
+    ok = 0
+    sel = frs.choice(cand, size=min(len(cand), 200), replace=False)
+    for j in sel:
+        t2 = tex.copy()
+        v0 = float(t2.reshape(-1)[j])
+        hh = 2.0 ** -12
+        t2.reshape(-1)[j] = v0 + hh
+        lp, tp = loss_at(dict(base, tex=t2))
+        t2.reshape(-1)[j] = v0 - hh
+        lm, tm = loss_at(dict(base, tex=t2))
+        if tp != tm:
+            continue
+        fd = (lp - lm) / (2 * hh)
+        ok += abs(fd - gtex[j]) <= 1e-3 * abs(fd) + 1e-6 * np.abs(gtex).max()
+    say(f"  texel FD samples {len(sel)}, within 1e-3: {ok}")
+    assert ok >= 0.98 * len(sel) and len(sel) >= 200
