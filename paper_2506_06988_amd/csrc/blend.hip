@@ -21,17 +21,18 @@ __device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, 
   return lo;
 }
 
-// LDS form of a record: conic pre-scaled so that G = exp2(p2)
+// LDS form of a record: conic pre-scaled so that G = exp2(p2), and the
+// exponent below which alpha = opacity * G falls under alpha_min
 struct Staged {
   float4 a;  // u, v, A2 = -ca/2 log2e, B2 = -cb log2e
-  float4 b;  // C2 = -cc/2 log2e, opacity, depth, unused
+  float4 b;  // C2 = -cc/2 log2e, opacity, depth, skip threshold log2(alpha_min / opacity)
   float4 c;  // r, g, b, unused
 };
 
-__device__ __forceinline__ Staged stage(const GRec& R) {
+__device__ __forceinline__ Staged stage(const GRec& R, float amin) {
   Staged s;
   s.a = make_float4(R.u, R.v, -0.5f * LOG2E * R.ca, -LOG2E * R.cb);
-  s.b = make_float4(-0.5f * LOG2E * R.cc, R.op, R.depth, 0.f);
+  s.b = make_float4(-0.5f * LOG2E * R.cc, R.op, R.depth, __log2f(amin / R.op));
   s.c = make_float4(R.r, R.g, R.b, 0.f);
   return s;
 }
@@ -73,34 +74,49 @@ struct PixState {
   bool done;
 };
 
+// number of staged entries in front of depth Dm (depths ascend in a batch)
+__device__ __forceinline__ int front_count(const Staged* sh, int n, float Dm) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sh[mid].b.z < Dm) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ void blend_batch(const Staged* sh, int n, int64_t pos0, float px,
-                                            float py, float Dm, float amin, float amax, float tmin,
+                                            float py, float Dm, float amax, float tmin,
                                             PixState& ps) {
-  for (int k = 0; k < n; ++k) {
-    const float4 a = sh[k].a, b = sh[k].b;
-    if (b.z >= Dm) {
-      ps.done = true;
-      ps.npro = (int)pos0 + k + 1;
-      return;
-    }
+  // a Gaussian at or behind the mesh ends the pixel (Sec. 3.4)
+  const int nv = front_count(sh, n, Dm);
+  int stop = nv < n ? nv : -1;  // entry that ends the pixel, if any
+  // single-exit loop: a T stop moves k past the end
+  const Staged* e = sh;
+  for (int k = 0; k < nv; ++k, ++e) {
+    const float4 a = e->a, b = e->b;
     float dx, dy;
     const float p2 = gauss_p2(a, b, px, py, dx, dy);
-    const float alpha = fminf(amax, b.y * __builtin_amdgcn_exp2f(p2));
-    if (alpha < amin) continue;
-    const float Tn = ps.T * (1.f - alpha);
-    if (Tn < tmin) {
-      ps.done = true;
-      ps.npro = (int)pos0 + k + 1;
-      return;
+    if (p2 >= b.w) {  // else alpha < alpha_min: skipped
+      const float alpha = fminf(amax, b.y * __builtin_amdgcn_exp2f(p2));
+      const float Tn = ps.T * (1.f - alpha);
+      if (Tn < tmin) {
+        stop = k;
+        k = nv;
+      } else {
+        const float4 c = e->c;
+        const float wgt = alpha * ps.T;
+        ps.cr = __builtin_fmaf(c.x, wgt, ps.cr);
+        ps.cg = __builtin_fmaf(c.y, wgt, ps.cg);
+        ps.cb = __builtin_fmaf(c.z, wgt, ps.cb);
+        ps.T = Tn;
+        ps.nc = (int)pos0 + k + 1;
+        ++ps.nbl;
+      }
     }
-    const float4 c = sh[k].c;
-    const float wgt = alpha * ps.T;
-    ps.cr = __builtin_fmaf(c.x, wgt, ps.cr);
-    ps.cg = __builtin_fmaf(c.y, wgt, ps.cg);
-    ps.cb = __builtin_fmaf(c.z, wgt, ps.cb);
-    ps.T = Tn;
-    ps.nc = (int)pos0 + k + 1;
-    ++ps.nbl;
+  }
+  if (stop >= 0) {
+    ps.done = true;
+    ps.npro = (int)pos0 + stop + 1;
   }
 }
 
@@ -164,14 +180,14 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
         }
         win_extract(word, pre, q, (uint32_t)n, wbase, rk[0]);
         __syncthreads();
-        if (threadIdx.x < n) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)]);
+        if (threadIdx.x < n) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)], amin);
         __syncthreads();
-        if (!ps.done) blend_batch(sh[0], n, a + q, px, py, Dm, amin, amax, tmin, ps);
+        if (!ps.done) blend_batch(sh[0], n, a + q, px, py, Dm, amax, tmin, ps);
       }
     } else {
       win_extract(word, pre, 0, (uint32_t)min((uint32_t)BG, total), wbase, rk[0]);
       __syncthreads();
-      if (threadIdx.x < min((uint32_t)BG, total)) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)]);
+      if (threadIdx.x < min((uint32_t)BG, total)) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)], amin);
       for (int bi = 0; bi < nbat; ++bi) {
         const int cur = bi & 1;
         const uint32_t q = (uint32_t)bi * BG;
@@ -185,8 +201,8 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
         }
         GRec nxt;
         if (threadIdx.x < nn) nxt = rec_s[min(rk[cur ^ 1][threadIdx.x], rmax)];
-        if (!ps.done) blend_batch(sh[cur], n, a + q, px, py, Dm, amin, amax, tmin, ps);
-        if (threadIdx.x < nn) sh[cur ^ 1][threadIdx.x] = stage(nxt);
+        if (!ps.done) blend_batch(sh[cur], n, a + q, px, py, Dm, amax, tmin, ps);
+        if (threadIdx.x < nn) sh[cur ^ 1][threadIdx.x] = stage(nxt, amin);
       }
     }
   }
@@ -316,7 +332,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
       if (threadIdx.x < n) {
         const uint32_t r = min(rk[threadIdx.x], rmax);
         const GRec R = rec_s[r];
-        sh[threadIdx.x] = stage(R);
+        sh[threadIdx.x] = stage(R, amin);
         raw[threadIdx.x] = make_float4(R.ca, R.cb, R.cc, 0.f);
         rk[threadIdx.x] = r;
       }
@@ -331,10 +347,10 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
         if (contrib) {
           float dx, dy;
           const float p2 = gauss_p2(sa, sb, px, py, dx, dy);
+          contrib = p2 >= sb.w;  // the forward's skip decision
           const float G = __builtin_amdgcn_exp2f(p2);
           const float ag = sb.y * G;
           const float alpha = fminf(amax, ag);
-          contrib = alpha >= amin;
           if (contrib) {
             const float4 c = sh[k].c;
             T = T / (1.f - alpha);  // transmittance in front of this Gaussian
