@@ -28,7 +28,12 @@ FP64_RECORDS = 1
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle core with g++ (host only, OpenMP)."""
+    """Compile the oracle core with g++ (host only, OpenMP).
+
+    ORACLE_LIB names another build of the core to load instead (the mutation
+    tests point it at copies with planted mistakes)."""
+    if os.environ.get("ORACLE_LIB"):
+        return os.environ["ORACLE_LIB"]
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["g++", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c++17",

@@ -167,16 +167,24 @@ __global__ __launch_bounds__(128) void k_project_bwd(
     for (int k = 0; k < 3 * K; ++k) g_sh[(size_t)g * K * 3 + k] += gshr[k];
 }
 
-__device__ __forceinline__ int find_cam_by_pix(const CamDev* cams, int n_cams, int64_t p) {
+
+__device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, int tile) {
   int lo = 0, hi = n_cams - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (cams[mid].pix_off <= p) lo = mid; else hi = mid - 1;
+    if (cams[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
-// dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights
+constexpr int TEX_LDS = 4096;  // texels of one tile's footprint accumulated in LDS
+
+// dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights.
+// One workgroup per tile: the texels the tile's pixels read from its most
+// common texture (the lowest texture id present) usually form a small box;
+// when the box fits in LDS the pixels accumulate there and the box is added
+// to the gradient with one global atomic per non-zero texel channel. Pixels
+// on other textures, and tiles whose box is too large, add directly.
 __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restrict__ cams,
                                                  const unsigned long long* __restrict__ zbuf,
                                                  const TriRec* __restrict__ tris,
@@ -184,39 +192,103 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
                                                  const float* __restrict__ grad_image,
                                                  const float* __restrict__ grad_mesh,
                                                  float* __restrict__ grad_tex) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= S.n_pix) return;
-  const unsigned long long key = zbuf[p];
-  if (key == ~0ull) return;
-  const int c = find_cam_by_pix(cams, S.n_cams, p);
+  __shared__ float acc[3 * TEX_LDS];
+  __shared__ int box[5];  // tex, x0, y0, x1, y1
+  const int t = blockIdx.x;
+  const int c = find_cam_by_tile(cams, S.n_cams, t);
   const CamDev& C = cams[c];
-  const int64_t lp = p - C.pix_off;
-  const int64_t hw = (int64_t)C.W * C.H;
-  const int i = (int)(lp % C.W), j = (int)(lp / C.W);
-  const float Tf = T_ws[p];
-  const int64_t pl = 3 * C.pix_off + lp;
-  float gm[3];
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    gm[ch] = (grad_image ? Tf * grad_image[pl + ch * hw] : 0.f) +
-             (grad_mesh ? grad_mesh[pl + ch * hw] : 0.f);
+  const int lt = t - C.tile_off;
+  const int ty = lt / C.TX, tx = lt - (lt / C.TX) * C.TX;
+  const int i = tx * TILE + (threadIdx.x & 15), j = ty * TILE + (threadIdx.x >> 4);
+  if (threadIdx.x == 0) {
+    box[0] = 0x7fffffff;
+    box[1] = box[2] = 0x7fffffff;
+    box[3] = box[4] = -1;
   }
-  if (gm[0] == 0.f && gm[1] == 0.f && gm[2] == 0.f) return;
-  const TriRec& T = tris[(uint32_t)key];
-  int64_t e[3];
-  tri_cover(T, i, j, e);
-  double uv[2];
-  tri_interp(T, e, uv);
-  const Taps tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
-  const float wx = tp.fx, wy = tp.fy;
-  const float w00 = (1.f - wx) * (1.f - wy), w10 = wx * (1.f - wy), w01 = (1.f - wx) * wy,
-              w11 = wx * wy;
+  bool live = false;
+  float gm[3] = {0.f, 0.f, 0.f};
+  Taps tp = {0, 0, 0, 0, 0.f, 0.f};
+  int tex = 0;
+  if (i < C.W && j < C.H) {
+    const int64_t p = C.pix_off + (int64_t)j * C.W + i;
+    const unsigned long long key = zbuf[p];
+    if (key != ~0ull) {
+      const int64_t hw = (int64_t)C.W * C.H;
+      const int64_t pl = 3 * C.pix_off + (p - C.pix_off);
+      const float Tf = T_ws[p];
 #pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    atomicAdd(grad_tex + tp.o00 + ch, w00 * gm[ch]);
-    atomicAdd(grad_tex + tp.o10 + ch, w10 * gm[ch]);
-    atomicAdd(grad_tex + tp.o01 + ch, w01 * gm[ch]);
-    atomicAdd(grad_tex + tp.o11 + ch, w11 * gm[ch]);
+      for (int ch = 0; ch < 3; ++ch)
+        gm[ch] = (grad_image ? Tf * grad_image[pl + ch * hw] : 0.f) +
+                 (grad_mesh ? grad_mesh[pl + ch * hw] : 0.f);
+      live = gm[0] != 0.f || gm[1] != 0.f || gm[2] != 0.f;
+      if (live) {
+        const TriRec& T = tris[(uint32_t)key];
+        int64_t e[3];
+        tri_cover(T, i, j, e);
+        double uv[2];
+        tri_interp(T, e, uv);
+        tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
+        tex = T.tex;
+      }
+    }
+  }
+  __syncthreads();
+  if (live) atomicMin(&box[0], tex);
+  __syncthreads();
+  const int rtex = box[0];
+  const int64_t plane = (int64_t)S.tex_h * S.tex_w;
+  // texel coordinates of the 4 taps relative to texture rtex
+  int xa = 0, ya = 0, xb = 0, yb = 0;
+  const bool mine = live && tex == rtex;
+  if (mine) {
+    const int64_t b = (int64_t)rtex * plane;
+    const int64_t q00 = tp.o00 / 3 - b, q11 = tp.o11 / 3 - b;
+    ya = (int)(q00 / S.tex_w);
+    xa = (int)(q00 - (int64_t)ya * S.tex_w);
+    yb = (int)(q11 / S.tex_w);
+    xb = (int)(q11 - (int64_t)yb * S.tex_w);
+    atomicMin(&box[1], xa);
+    atomicMin(&box[2], ya);
+    atomicMax(&box[3], xb);
+    atomicMax(&box[4], yb);
+  }
+  __syncthreads();
+  const int bx0 = box[1], by0 = box[2];
+  const int bw = box[3] - bx0 + 1, bh = box[4] - by0 + 1;
+  const bool use_lds = rtex != 0x7fffffff && bw > 0 && bh > 0 && bw * bh <= TEX_LDS;
+  const float wx = tp.fx, wy = tp.fy;
+  const float w4[4] = {(1.f - wx) * (1.f - wy), wx * (1.f - wy), (1.f - wx) * wy, wx * wy};
+  if (use_lds) {
+    for (int k = threadIdx.x; k < 3 * bw * bh; k += 256) acc[k] = 0.f;
+    __syncthreads();
+    if (mine) {
+      const int l00 = (ya - by0) * bw + (xa - bx0), l11 = (yb - by0) * bw + (xb - bx0);
+      const int l10 = (ya - by0) * bw + (xb - bx0), l01 = (yb - by0) * bw + (xa - bx0);
+      const int ls[4] = {l00, l10, l01, l11};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) atomicAdd(&acc[3 * ls[q] + ch], w4[q] * gm[ch]);
+    }
+  }
+  if (live && !(use_lds && mine)) {
+    const int64_t os[4] = {tp.o00, tp.o10, tp.o01, tp.o11};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) atomicAdd(grad_tex + os[q] + ch, w4[q] * gm[ch]);
+  }
+  if (use_lds) {
+    __syncthreads();
+    const int64_t base = (int64_t)rtex * plane;
+    for (int k = threadIdx.x; k < 3 * bw * bh; k += 256) {
+      const float v = acc[k];
+      if (v != 0.f) {
+        const int l = k / 3, ch = k - 3 * l;
+        const int yy = by0 + l / bw, xx = bx0 + l - (l / bw) * bw;
+        atomicAdd(grad_tex + (base + (int64_t)yy * S.tex_w + xx) * 3 + ch, v);
+      }
+    }
   }
 }
 
@@ -298,7 +370,7 @@ void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,
                              hipStream_t st) {
   (void)m;
   if (S.n_faces == 0 || !grad_tex || S.n_pix == 0) return;
-  hipLaunchKernelGGL(k_tex_bwd, dim3((unsigned)((S.n_pix + 255) / 256)), dim3(256), 0, st, S, w.cams,
+  hipLaunchKernelGGL(k_tex_bwd, dim3((unsigned)S.n_tiles), dim3(256), 0, st, S, w.cams,
                      (const unsigned long long*)w.zbuf, w.tris, w.final_T, grad_image,
                      grad_mesh_rgb, grad_tex);
 }

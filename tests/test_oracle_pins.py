@@ -270,6 +270,42 @@ def test_single_gaussian_pixel_closed_form():
     assert r > 0
 
 
+def test_anisotropic_gaussian_pixel_values():
+    # one rotated, anisotropic Gaussian seen off-axis: alpha(p) from Eq. 1 with
+    # Sigma' built independently (scipy rotation, finite-difference Jacobian)
+    rng = np.random.default_rng(14)
+    cam = scenes.Camera(48, 40, 45.0, 44.0, 24.3, 19.7, np.eye(3), np.zeros(3))
+    for _ in range(5):
+        mu = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(1.5, 3.0)])
+        q = rng.standard_normal(4)
+        ls = rng.uniform(-2.8, -1.6, 3)
+        g = gauss([mu], log_scales=[ls], quats=[q], logits=[rng.normal()], colours=[[1.0, 0.5, 0.25]])
+        mu64 = g.means[0].astype(np.float64)
+        qq = g.quats[0].astype(np.float64)
+        R = Rotation.from_quat([qq[1], qq[2], qq[3], qq[0]]).as_matrix()
+        Sig = R @ np.diag(np.exp(g.log_scales[0].astype(np.float64)) ** 2) @ R.T
+        h = 1e-6
+        Jfd = np.zeros((2, 3))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            Jfd[:, k] = (_pinhole(cam, mu64 + e) - _pinhole(cam, mu64 - e)) / (2 * h)
+        cov = Jfd @ Sig @ Jfd.T + LP * np.eye(2)
+        Q = np.linalg.inv(cov)
+        m2 = _pinhole(cam, mu64)
+        o = 1 / (1 + np.exp(-float(g.opacity_logits[0])))
+        out = oracle.render(g, None, cam, params=oracle.default_params(flags=oracle.FP64_RECORDS))
+        pr = oracle.project(g, cam)
+        x0, x1, y0, y1 = pr["rect"][0]
+        for _ in range(40):
+            i, j = int(rng.integers(0, 48)), int(rng.integers(0, 40))
+            d = np.array([i + 0.5, j + 0.5]) - m2
+            a = min(F32(0.99), o * np.exp(-0.5 * d @ Q @ d))
+            inside = x0 <= i // 16 < x1 and y0 <= j // 16 < y1
+            a = a if (a >= F32(1 / 255) and inside) else 0.0
+            np.testing.assert_allclose(out["image"][0, j, i], a, rtol=2e-6, atol=1e-9)
+
+
 def test_zero_gaussians_give_the_mesh():
     cam = one_cam(32, 32, 32.0)
     g = gauss(np.zeros((0, 3)))
