@@ -38,7 +38,7 @@ struct Plan {
   int64_t n, n_cams, M, F, MF, P, n_tiles, key_cap, rs_blocks, chunk_rows, mat_entries;
   size_t cams, counters, tiles, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, tiles_s, item_s, pair_off, mat, tile_total,
-      tile_start, slice_cnt, slice_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
+      tile_start, tile_order, slice_cnt, slice_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, gacc, tune, scan_scratch, total;
   std::vector<CamDev> camdev;
 };
@@ -155,6 +155,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.mat = L.take(4 * p.mat_entries);
   p.tile_total = L.take(4 * p.n_tiles);
   p.tile_start = L.take(4 * p.n_tiles);
+  p.tile_order = L.take(4 * p.n_tiles);
   p.slice_cnt = L.take(4 * (p.chunk_rows + 1));
   p.slice_off = L.take(4 * (p.chunk_rows + 1));
   p.lists = L.take(4 * key_cap);
@@ -204,6 +205,7 @@ Work make_work(const Plan& p, void* ws) {
   w.chunk_rows = p.chunk_rows;
   w.tile_total = (uint32_t*)(b + p.tile_total);
   w.tile_start = (uint32_t*)(b + p.tile_start);
+  w.tile_order = (uint32_t*)(b + p.tile_order);
   w.slice_cnt = (uint32_t*)(b + p.slice_cnt);
   w.slice_off = (uint32_t*)(b + p.slice_off);
   w.lists = (uint32_t*)(b + p.lists);

@@ -128,9 +128,10 @@ template <int BG, int DEPTH>
 __global__ __launch_bounds__(256) void k_blend_fwd(
     SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
     const uint32_t* __restrict__ mat, const uint32_t* __restrict__ tile_start,
-    const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ lists,
-    const GRec* __restrict__ rec_s, const unsigned long long* __restrict__ zbuf,
-    const float* __restrict__ mesh_rgb, float* __restrict__ image, float* __restrict__ T_ws,
+    const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ tile_order,
+    const uint32_t* __restrict__ lists, const GRec* __restrict__ rec_s,
+    const unsigned long long* __restrict__ zbuf, const float* __restrict__ mesh_rgb,
+    float* __restrict__ image, float* __restrict__ T_ws,
     int32_t* __restrict__ nc_ws, float* __restrict__ T_out, int32_t* __restrict__ nc_out,
     int32_t* __restrict__ nb_out, int32_t* __restrict__ np_out, uint32_t* __restrict__ counters) {
   __shared__ Staged sh[DEPTH][BG];
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
   __shared__ uint32_t bitmap[WIN_WORDS];
   __shared__ uint32_t red4[4];
   __shared__ unsigned long long red[2];
-  const int t = blockIdx.x;
+  const int t = (int)tile_order[blockIdx.x];
   const TileCtx tc = tile_ctx(cams, S.n_cams, t);
   const CamDev& C = cams[tc.cam];
   const WinCtx W = win_ctx(C, tc.cam, t, vis_off, mat, tile_start, tile_total, S.key_cap);
@@ -260,9 +261,10 @@ template <int BG>
 __global__ __launch_bounds__(256) void k_blend_bwd(
     SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
     const uint32_t* __restrict__ mat, const uint32_t* __restrict__ tile_start,
-    const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ lists,
-    const GRec* __restrict__ rec_s, const unsigned long long* __restrict__ zbuf,
-    const float* __restrict__ mesh_rgb, const float* __restrict__ T_ws,
+    const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ tile_order,
+    const uint32_t* __restrict__ lists, const GRec* __restrict__ rec_s,
+    const unsigned long long* __restrict__ zbuf, const float* __restrict__ mesh_rgb,
+    const float* __restrict__ T_ws,
     const int32_t* __restrict__ nc_ws, const float* __restrict__ grad_image,
     const float* __restrict__ grad_T, float* __restrict__ gacc) {
   __shared__ Staged sh[BG];
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
   __shared__ uint32_t bitmap[WIN_WORDS];
   __shared__ uint32_t red4[4];
   __shared__ int maxnc;
-  const int t = blockIdx.x;
+  const int t = (int)tile_order[blockIdx.x];
   const TileCtx tc = tile_ctx(cams, S.n_cams, t);
   const CamDev& C = cams[tc.cam];
   const WinCtx W = win_ctx(C, tc.cam, t, vis_off, mat, tile_start, tile_total, S.key_cap);
@@ -394,8 +396,9 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
 
 #define HR_FWD(BG, D)                                                                          \
   hipLaunchKernelGGL((k_blend_fwd<BG, D>), dim3(S.n_tiles), dim3(256), 0, st, S, w.cams,        \
-                     w.vis_off, w.mat, w.tile_start, w.tile_total, w.lists, w.rec_s,            \
-                     (const unsigned long long*)w.zbuf, w.mesh_rgb, out->image, w.final_T,      \
+                     w.vis_off, w.mat, w.tile_start, w.tile_total, w.tile_order, w.lists,       \
+                     w.rec_s, (const unsigned long long*)w.zbuf, w.mesh_rgb, out->image,        \
+                     w.final_T,                                                                 \
                      w.n_contrib, out->final_T, out->n_contrib, out->n_blended, out->n_processed, \
                      w.counters)
 
@@ -413,8 +416,9 @@ void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int b
 
 #define HR_BWD(BG)                                                                              \
   hipLaunchKernelGGL((k_blend_bwd<BG>), dim3(S.n_tiles), dim3(256), 0, st, S, w.cams,           \
-                     w.vis_off, w.mat, w.tile_start, w.tile_total, w.lists, w.rec_s,            \
-                     (const unsigned long long*)w.zbuf, w.mesh_rgb, w.final_T, w.n_contrib,     \
+                     w.vis_off, w.mat, w.tile_start, w.tile_total, w.tile_order, w.lists,       \
+                     w.rec_s, (const unsigned long long*)w.zbuf, w.mesh_rgb, w.final_T,         \
+                     w.n_contrib,                                                               \
                      grad_image, grad_T, w.gacc)
 
 void launch_blend_backward(const SetDev& S, const Work& w, const float* grad_image,

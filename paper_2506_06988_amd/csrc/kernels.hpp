@@ -34,6 +34,7 @@ struct Work {
   uint32_t* slice_off;   // [chunk_rows] exclusive scan of slice_cnt
   uint32_t* tile_total;  // [n_tiles]
   uint32_t* tile_start;  // [n_tiles]
+  uint32_t* tile_order;  // [n_tiles] blend schedule, longest lists first
   uint32_t* lists;       // [key_cap] ranks grouped by tile, chunk sub-segments in chunk order
   // counters: [0] n_vis, [1] overflow, [2..3] K (u64), [4] n_tris, [5] n_blocks,
   // [6..7] sum n_processed (u64), [8..9] sum n_blended (u64), [10..11] K scan total,

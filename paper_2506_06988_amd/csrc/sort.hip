@@ -472,6 +472,33 @@ __global__ __launch_bounds__(256) void k_tile_order(const CamDev* __restrict__ c
   }
 }
 
+// Blend schedule: tiles by decreasing list length (buckets of log2 length),
+// so the longest lists start first and the short ones fill in at the end.
+__global__ __launch_bounds__(256) void k_tile_schedule(int n_tiles, const uint32_t* __restrict__ tile_total,
+                                                       uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[33];
+  __shared__ uint32_t off[33];
+  if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += 256) {
+    const uint32_t L = tile_total[t];
+    atomicAdd(&cnt[L ? 32 - __clz(L) : 0], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int b = 32; b >= 0; --b) {
+      off[b] = acc;
+      acc += cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += 256) {
+    const uint32_t L = tile_total[t];
+    order[atomicAdd(&off[L ? 32 - __clz(L) : 0], 1u)] = (uint32_t)t;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_pair_total(const uint64_t* __restrict__ total,
                                                     int64_t key_cap, uint32_t* __restrict__ counters) {
   const uint64_t K = *total;
@@ -555,6 +582,8 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, hr_outputs* out,
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
   scan_u32(w.tile_total, w.tile_start, S.n_tiles, nullptr, w.scan_scratch, st);
+  hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(256), 0, st, S.n_tiles, w.tile_total,
+                     w.tile_order);
   if (w.chunk_rows > 0) {
     if (S.max_tiles_cam <= 8192)
       hipLaunchKernelGGL(k_bin_scatter<8192>, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams,
