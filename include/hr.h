@@ -119,7 +119,8 @@ typedef struct {
   float clamp_fov;    /* Jacobian direction clamp in units of tan(fov/2) (1.3) */
   uint32_t flags;     /* HR_FLAG_* */
   int32_t batch;      /* Gaussians staged in LDS per batch: 32,64,128,256 (0 = tuned default) */
-  int32_t variant;    /* blend kernel variant chosen by hr_autotune (0 = default) */
+  int32_t variant;    /* blend variant: bit 0 two-deep LDS staging, bit 1 persistent
+                         workgroups on a tile queue (chosen by hr_autotune; 0 = default) */
 } hr_settings;
 
 /* Counters written by the forward (device memory). */

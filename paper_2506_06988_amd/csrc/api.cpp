@@ -77,7 +77,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
     return fail(HR_ERR_INVALID_ARGUMENT, "low_pass must be >= 0 and clamp_fov > 0");
   if (s->batch != 0 && s->batch != 32 && s->batch != 64 && s->batch != 128 && s->batch != 256)
     return fail(HR_ERR_INVALID_ARGUMENT, "batch must be 0, 32, 64, 128 or 256");
-  if (s->variant < 0 || s->variant > 1) return fail(HR_ERR_INVALID_ARGUMENT, "variant must be 0 or 1");
+  if (s->variant < 0 || s->variant > 3) return fail(HR_ERR_INVALID_ARGUMENT, "variant must be in [0, 3]");
 
   p.n = g->n;
   p.n_cams = n_cams;
@@ -448,7 +448,7 @@ hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camer
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(HR_ERR_HIP, "event create failed");
-  for (int v = 0; v < 2; ++v)
+  for (int v = 0; v < 4; ++v)
     for (int bi = 0; bi < 4; ++bi) {
       std::vector<float> times;
       for (int r = 0; r < repeats + 1; ++r) {

@@ -124,28 +124,57 @@ __device__ __forceinline__ void blend_batch(const Staged* sh, int n, int64_t pos
 // DEPTH 2: the next batch's records are loaded into registers before the
 // current batch is blended and written to the other LDS buffer after it,
 // leaving one barrier per batch.
+struct FwdArgs {
+  SetDev S;
+  const CamDev* cams;
+  const uint32_t* vis_off;
+  const uint32_t* mat;
+  const uint32_t* tile_start;
+  const uint32_t* tile_total;
+  const uint32_t* tile_order;
+  const uint32_t* lists;
+  const GRec* rec_s;
+  const unsigned long long* zbuf;
+  const float* mesh_rgb;
+  float* image;
+  float* T_ws;
+  int32_t* nc_ws;
+  float* T_out;
+  int32_t* nc_out;
+  int32_t* nb_out;
+  int32_t* np_out;
+  uint32_t* counters;
+};
+
 template <int BG, int DEPTH>
-__global__ __launch_bounds__(256) void k_blend_fwd(
-    SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
-    const uint32_t* __restrict__ mat, const uint32_t* __restrict__ tile_start,
-    const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ tile_order,
-    const uint32_t* __restrict__ lists, const GRec* __restrict__ rec_s,
-    const unsigned long long* __restrict__ zbuf, const float* __restrict__ mesh_rgb,
-    float* __restrict__ image, float* __restrict__ T_ws,
-    int32_t* __restrict__ nc_ws, float* __restrict__ T_out, int32_t* __restrict__ nc_out,
-    int32_t* __restrict__ nb_out, int32_t* __restrict__ np_out, uint32_t* __restrict__ counters) {
-  __shared__ Staged sh[DEPTH][BG];
-  __shared__ uint32_t rk[DEPTH][BG];
-  __shared__ uint32_t bitmap[WIN_WORDS];
-  __shared__ uint32_t red4[4];
-  __shared__ unsigned long long red[2];
-  const int t = (int)tile_order[blockIdx.x];
+struct FwdShared {
+  Staged sh[DEPTH][BG];
+  uint32_t rk[DEPTH][BG];
+  uint32_t bitmap[WIN_WORDS];
+  uint32_t red4[4];
+  unsigned long long red[2];
+};
+
+// blend and composite one tile t (all 256 threads of the group)
+template <int BG, int DEPTH>
+__device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH>& L, int t) {
+  const SetDev& S = A.S;
+  const CamDev* __restrict__ cams = A.cams;
+  const uint32_t* __restrict__ lists = A.lists;
+  const GRec* __restrict__ rec_s = A.rec_s;
+  const float* __restrict__ mesh_rgb = A.mesh_rgb;
+  uint32_t* __restrict__ counters = A.counters;
+  auto& sh = L.sh;
+  auto& rk = L.rk;
+  auto& bitmap = L.bitmap;
+  auto& red4 = L.red4;
+  auto& red = L.red;
   const TileCtx tc = tile_ctx(cams, S.n_cams, t);
   const CamDev& C = cams[tc.cam];
-  const WinCtx W = win_ctx(C, tc.cam, t, vis_off, mat, tile_start, tile_total, S.key_cap);
+  const WinCtx W = win_ctx(C, tc.cam, t, A.vis_off, A.mat, A.tile_start, A.tile_total, S.key_cap);
   const float px = (float)tc.i + 0.5f, py = (float)tc.j + 0.5f;
   unsigned long long key = ~0ull;
-  if (tc.inside) key = zbuf[tc.p];
+  if (tc.inside) key = A.zbuf[tc.p];
   const float Dm = key == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(key >> 32));
   const float amin = S.alpha_min, amax = S.alpha_max, tmin = S.t_min;
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
@@ -220,15 +249,15 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
       bgc = S.bg[1];
       bb = S.bg[2];
     }
-    image[pl] = __builtin_fmaf(ps.T, br, ps.cr);
-    image[pl + hw] = __builtin_fmaf(ps.T, bgc, ps.cg);
-    image[pl + 2 * hw] = __builtin_fmaf(ps.T, bb, ps.cb);
-    T_ws[tc.p] = ps.T;
-    nc_ws[tc.p] = ps.nc;
-    if (T_out) T_out[tc.p] = ps.T;
-    if (nc_out) nc_out[tc.p] = ps.nc;
-    if (nb_out) nb_out[tc.p] = ps.nbl;
-    if (np_out) np_out[tc.p] = ps.npro;
+    A.image[pl] = __builtin_fmaf(ps.T, br, ps.cr);
+    A.image[pl + hw] = __builtin_fmaf(ps.T, bgc, ps.cg);
+    A.image[pl + 2 * hw] = __builtin_fmaf(ps.T, bb, ps.cb);
+    A.T_ws[tc.p] = ps.T;
+    A.nc_ws[tc.p] = ps.nc;
+    if (A.T_out) A.T_out[tc.p] = ps.T;
+    if (A.nc_out) A.nc_out[tc.p] = ps.nc;
+    if (A.nb_out) A.nb_out[tc.p] = ps.nbl;
+    if (A.np_out) A.np_out[tc.p] = ps.npro;
   } else {
     ps.npro = 0;
   }
@@ -247,6 +276,29 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
   if (threadIdx.x == 0) {
     atomicAdd(reinterpret_cast<unsigned long long*>(counters + 6), red[0]);
     atomicAdd(reinterpret_cast<unsigned long long*>(counters + 8), red[1]);
+  }
+  __syncthreads();  // LDS is reused by the next tile of a persistent group
+}
+
+// one workgroup per tile, in the longest-list-first order
+template <int BG, int DEPTH>
+__global__ __launch_bounds__(256) void k_blend_fwd(FwdArgs A) {
+  __shared__ FwdShared<BG, DEPTH> L;
+  blend_tile<BG, DEPTH>(A, L, (int)A.tile_order[blockIdx.x]);
+}
+
+// persistent workgroups pull tiles from an atomic queue over the same order
+template <int BG, int DEPTH>
+__global__ __launch_bounds__(256) void k_blend_fwd_persistent(FwdArgs A, uint32_t* queue) {
+  __shared__ FwdShared<BG, DEPTH> L;
+  __shared__ uint32_t next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t q = next;
+    __syncthreads();
+    if (q >= (uint32_t)A.S.n_tiles) break;
+    blend_tile<BG, DEPTH>(A, L, (int)A.tile_order[q]);
   }
 }
 
@@ -394,23 +446,39 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
 
 }  // namespace
 
-#define HR_FWD(BG, D)                                                                          \
-  hipLaunchKernelGGL((k_blend_fwd<BG, D>), dim3(S.n_tiles), dim3(256), 0, st, S, w.cams,        \
-                     w.vis_off, w.mat, w.tile_start, w.tile_total, w.tile_order, w.lists,       \
-                     w.rec_s, (const unsigned long long*)w.zbuf, w.mesh_rgb, out->image,        \
-                     w.final_T,                                                                 \
-                     w.n_contrib, out->final_T, out->n_contrib, out->n_blended, out->n_processed, \
-                     w.counters)
+template <int BG, int D>
+void launch_fwd(const FwdArgs& A, bool persistent, uint32_t* queue, hipStream_t st) {
+  if (!persistent) {
+    hipLaunchKernelGGL((k_blend_fwd<BG, D>), dim3(A.S.n_tiles), dim3(256), 0, st, A);
+    return;
+  }
+  static int grid = 0;
+  if (grid == 0) {
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_blend_fwd_persistent<BG, D>, 256, 0);
+    grid = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
+  }
+  launch_fill_u32(queue, 0u, 1, st);
+  hipLaunchKernelGGL((k_blend_fwd_persistent<BG, D>), dim3(grid), dim3(256), 0, st, A, queue);
+}
 
+// variant bit 0: two-deep staging; bit 1: persistent workgroups on a tile queue
 void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int batch, int variant,
                           hipStream_t st) {
   if (S.n_tiles == 0) return;
-  const bool d2 = variant == 1;
+  FwdArgs A{S, w.cams, w.vis_off, w.mat, w.tile_start, w.tile_total, w.tile_order, w.lists,
+            w.rec_s, (const unsigned long long*)w.zbuf, w.mesh_rgb, out->image, w.final_T,
+            w.n_contrib, out->final_T, out->n_contrib, out->n_blended, out->n_processed,
+            w.counters};
+  const bool d2 = (variant & 1) != 0, pers = (variant & 2) != 0;
+  uint32_t* queue = w.counters + 14;
   switch (batch) {
-    case 32: if (d2) HR_FWD(32, 2); else HR_FWD(32, 1); break;
-    case 64: if (d2) HR_FWD(64, 2); else HR_FWD(64, 1); break;
-    case 128: if (d2) HR_FWD(128, 2); else HR_FWD(128, 1); break;
-    default: if (d2) HR_FWD(256, 2); else HR_FWD(256, 1); break;
+    case 32: d2 ? launch_fwd<32, 2>(A, pers, queue, st) : launch_fwd<32, 1>(A, pers, queue, st); break;
+    case 64: d2 ? launch_fwd<64, 2>(A, pers, queue, st) : launch_fwd<64, 1>(A, pers, queue, st); break;
+    case 128: d2 ? launch_fwd<128, 2>(A, pers, queue, st) : launch_fwd<128, 1>(A, pers, queue, st); break;
+    default: d2 ? launch_fwd<256, 2>(A, pers, queue, st) : launch_fwd<256, 1>(A, pers, queue, st); break;
   }
 }
 

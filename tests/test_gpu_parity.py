@@ -161,7 +161,7 @@ def test_forward_is_deterministic_and_variants_bit_identical(hr):
     torch.cuda.synchronize()
     assert torch.equal(a, f2.image)
     for batch in (32, 64, 128, 256):
-        for variant in (0, 1):
+        for variant in (0, 1, 2, 3):
             r.settings.batch, r.settings.variant = batch, variant
             f3 = r.render_hybrid()
             torch.cuda.synchronize()
