@@ -216,6 +216,24 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
                          float* grad_image, float* grad_final_T, float* grad_mesh_rgb,
                          void* scratch, void* stream);
 
+/* Photometric loss of Eq. 3 with the transmittance-aware term of Sec. 3.4,
+ * over n_images images packed like the renderer's outputs (image i is
+ * sizes[2i] wide and sizes[2i+1] high; `sizes` is host memory):
+ *   L = (1 - lambda_c) mean|I_h - I| + lambda_c (1 - mean SSIM(I_h, I))
+ *       + lambda_t mean_{p,c} M_T(p) (I~ - I~_m)^2
+ * SSIM per channel with an 11x11 Gaussian window (sigma 1.5) over zero-padded
+ * images, C1 = 0.01^2, C2 = 0.03^2 (the paper's lambda_c is 0.2). mask_mode
+ * selects M_T as in the ablation of Table 3: 0 no L_t term, 1 M_T = 1,
+ * 2 M_T = T, 3 M_T = 1 / (1 + exp(-k (T - 1/2))). Writes the loss (device
+ * scalar) and dL/dI_h, dL/dT, dL/dI_m. `scratch` holds
+ * hr_full_loss_scratch_bytes(sizes, n_images) bytes (0 on invalid sizes). */
+size_t hr_full_loss_scratch_bytes(const int32_t* sizes, int32_t n_images);
+hr_status hr_full_loss(const float* image, const float* final_T, const float* mesh_rgb,
+                       const int32_t* tri_id, const float* target, const int32_t* sizes,
+                       int32_t n_images, float lambda_c, float lambda_t, float k,
+                       int32_t mask_mode, uint32_t flags, float* loss_out, float* grad_image,
+                       float* grad_final_T, float* grad_mesh_rgb, void* scratch, void* stream);
+
 /* Autotuner: times the blend variants (LDS batch size and staging depth) on
  * the inputs of a forward that has just run with this workspace, checks that
  * every variant's outputs are bit-identical, and writes the fastest choice to

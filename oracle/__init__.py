@@ -295,3 +295,68 @@ def loss(image, final_T, mesh_rgb, tri_id, target, lambda_t=0.1, k=20.0, detach_
     g_mesh = np.where(has, lambda_t * MT[None] * 2.0 * (Im - tgt) / n, 0.0)
     g_T = np.zeros_like(T) if detach_mask else lambda_t * sq * MT * (1.0 - MT) * k / n
     return L, g_image, g_T, g_mesh
+
+
+# ----------------------------------------------------------- full loss --
+MASK_MODES = ("none", "one", "T", "sigmoid")
+
+
+def ssim_window(size=11, sigma=1.5):
+    """Normalised 2-D Gaussian window, the outer product of a 1-D one."""
+    x = np.arange(size, dtype=np.float64) - (size - 1) / 2.0
+    g = np.exp(-(x * x) / (2.0 * sigma * sigma))
+    g /= g.sum()
+    return np.outer(g, g)
+
+
+def full_loss(images, final_T, mesh_rgb, tri_id, target, lambda_c=0.2, lambda_t=0.1, k=20.0,
+              mask_mode="sigmoid", detach_mask=False, c1=0.01 ** 2, c2=0.03 ** 2):
+    """Eq. 3 with the transmittance-aware term of Sec. 3.4, over several images.
+
+    L = (1 - lambda_c) * mean|I_h - I| + lambda_c * (1 - mean SSIM(I_h, I))
+        + lambda_t * mean_{p,c}[ M_T(p) (I~ - I~_m)^2 ]
+    SSIM per channel with an 11x11 Gaussian window (sigma 1.5) over zero-padded
+    images; M_T: "none" (no L_t), "one", "T", or "sigmoid" 1/(1+exp(-k(T-1/2)))
+    (the ablation of Table 3). Means run over every pixel and channel of every
+    image. Arguments are lists of per-image arrays ([3,H,W] and [H,W]).
+    Returns the loss and its gradients with respect to the images, T and I_m,
+    by reverse mode in float64 (plain PyTorch CPU).
+    """
+    import torch
+    f = lambda a: torch.tensor(np.asarray(a, np.float64), requires_grad=True)
+    X = [f(a) for a in images]
+    T = [f(a) for a in final_T]
+    M = [f(a) for a in mesh_rgb]
+    Y = [torch.tensor(np.asarray(a, np.float64)) for a in target]
+    has = [torch.tensor(np.asarray(a) >= 0) for a in tri_id]
+    n = sum(x.numel() for x in X)
+    w = torch.tensor(ssim_window())[None, None].repeat(3, 1, 1, 1)
+    l1 = sum((x - y).abs().sum() for x, y in zip(X, Y)) / n
+    ssim_sum = 0.0
+    for x, y in zip(X, Y):
+        xb, yb = x[None], y[None]
+        conv = lambda z: torch.nn.functional.conv2d(z, w, padding=5, groups=3)
+        mx, my = conv(xb), conv(yb)
+        sxx = conv(xb * xb) - mx * mx
+        syy = conv(yb * yb) - my * my
+        sxy = conv(xb * yb) - mx * my
+        s = ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+        ssim_sum = ssim_sum + s.sum()
+    L = (1 - lambda_c) * l1 + lambda_c * (1 - ssim_sum / n)
+    if mask_mode != "none":
+        lt = 0.0
+        for t, m, y, h in zip(T, M, Y, has):
+            if mask_mode == "one":
+                mt = torch.ones_like(t)
+            elif mask_mode == "T":
+                mt = t
+            else:
+                mt = 1.0 / (1.0 + torch.exp(-k * (t - 0.5)))
+            if detach_mask:
+                mt = mt.detach()
+            d = torch.where(h[None], y - m, torch.zeros_like(m))
+            lt = lt + (mt * (d * d).sum(0)).sum()
+        L = L + lambda_t * lt / n
+    L.backward()
+    z = lambda v, like: (v.grad if v.grad is not None else torch.zeros_like(like)).numpy()
+    return (float(L), [z(x, x) for x in X], [z(t, t) for t in T], [z(m, m) for m in M])

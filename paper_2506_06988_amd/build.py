@@ -13,7 +13,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhybrid_raster.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["api.cpp", "scan.hip", "project.hip", "sort.hip", "mesh.hip", "blend.hip", "bwd.hip",
-           "misc.hip"]
+           "misc.hip",
+           "ssim.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]

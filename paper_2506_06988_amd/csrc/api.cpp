@@ -419,6 +419,38 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
   return hip_check("loss launch");
 }
 
+size_t hr_full_loss_scratch_bytes(const int32_t* sizes, int32_t n_images) {
+  if (!sizes || n_images < 1) return 0;
+  int64_t P = 0, tiles = 0;
+  for (int i = 0; i < n_images; ++i) {
+    if (sizes[2 * i] < 1 || sizes[2 * i + 1] < 1) return 0;
+    P += (int64_t)sizes[2 * i] * sizes[2 * i + 1];
+    tiles += (int64_t)((sizes[2 * i] + TILE - 1) / TILE) * ((sizes[2 * i + 1] + TILE - 1) / TILE);
+  }
+  return full_loss_scratch_bytes(P, tiles, n_images);
+}
+
+hr_status hr_full_loss(const float* image, const float* final_T, const float* mesh_rgb,
+                       const int32_t* tri_id, const float* target, const int32_t* sizes,
+                       int32_t n_images, float lambda_c, float lambda_t, float k,
+                       int32_t mask_mode, uint32_t flags, float* loss_out, float* grad_image,
+                       float* grad_final_T, float* grad_mesh_rgb, void* scratch, void* stream) {
+  if (!sizes || n_images < 1) return fail(HR_ERR_INVALID_ARGUMENT, "need n_images >= 1 sizes");
+  for (int i = 0; i < n_images; ++i)
+    if (sizes[2 * i] < 1 || sizes[2 * i + 1] < 1 || sizes[2 * i] > 16384 || sizes[2 * i + 1] > 16384)
+      return fail(HR_ERR_INVALID_ARGUMENT, "image sizes must be in [1, 16384]");
+  if (mask_mode < 0 || mask_mode > 3) return fail(HR_ERR_INVALID_ARGUMENT, "mask_mode must be in [0, 3]");
+  if (!(lambda_c >= 0.f && lambda_c <= 1.f)) return fail(HR_ERR_INVALID_ARGUMENT, "lambda_c must be in [0, 1]");
+  if (!image || !final_T || !mesh_rgb || !tri_id || !target || !loss_out || !grad_image ||
+      !grad_final_T || !grad_mesh_rgb || !scratch)
+    return fail(HR_ERR_INVALID_ARGUMENT, "null loss argument");
+  hipGetLastError();
+  launch_full_loss(image, final_T, mesh_rgb, tri_id, target, sizes, n_images, lambda_c, lambda_t,
+                   k, mask_mode, (flags & HR_FLAG_DETACH_MASK) != 0, loss_out, grad_image,
+                   grad_final_T, grad_mesh_rgb, scratch, (hipStream_t)stream);
+  return hip_check("full loss launch");
+}
+
 hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
                       int32_t n_cams, hr_settings* s, int64_t key_capacity, void* workspace,
                       size_t workspace_bytes, hr_outputs* out, int32_t repeats, void* stream) {

@@ -59,7 +59,8 @@ class hr_grads(C.Structure):
 
 
 EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid",
-            "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss", "hr_autotune",
+            "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
+            "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_autotune",
             "hr_batch_create", "hr_batch_launch", "hr_batch_destroy", "hr_status_string",
             "hr_last_error", "hr_abi_version"]
 
@@ -90,6 +91,11 @@ def load(path: str = LIB_PATH):
     L.hr_hybrid_loss.restype = C.c_int
     L.hr_hybrid_loss.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_uint32, P, P,
                                  P, P, P, P]
+    L.hr_full_loss_scratch_bytes.restype = C.c_size_t
+    L.hr_full_loss_scratch_bytes.argtypes = [P, C.c_int32]
+    L.hr_full_loss.restype = C.c_int
+    L.hr_full_loss.argtypes = [P, P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float,
+                               C.c_int32, C.c_uint32, P, P, P, P, P, P]
     L.hr_autotune.restype = C.c_int
     L.hr_autotune.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, C.c_int32, P]
     L.hr_batch_create.restype = C.c_int
@@ -421,6 +427,32 @@ def hybrid_loss(image, final_T, mesh_rgb, tri_id, target, lambda_t=0.1, k=20.0, 
                            n_pix, float(lambda_t), float(k),
                            HR_FLAG_DETACH_MASK if detach_mask else 0, _ptr(loss), _ptr(gi), _ptr(gt),
                            _ptr(gm), _ptr(scratch), _stream()))
+    return loss, gi, gt, gm
+
+
+MASK_MODES = {"none": 0, "one": 1, "T": 2, "sigmoid": 3}
+
+
+def full_loss(image, final_T, mesh_rgb, tri_id, target, sizes, lambda_c=0.2, lambda_t=0.1, k=20.0,
+              mask_mode="sigmoid", detach_mask=False):
+    """hr_full_loss (Eq. 3 + transmittance-aware term) over packed images of the
+    given (width, height) sizes; returns (loss, g_image, g_T, g_mesh_rgb)."""
+    import torch
+    L = load()
+    sz = (C.c_int32 * (2 * len(sizes)))(*[int(v) for wh in sizes for v in wh])
+    d = image.device
+    loss = torch.zeros(1, dtype=torch.float32, device=d)
+    gi = torch.empty_like(image)
+    gt = torch.empty_like(final_T)
+    gm = torch.empty_like(mesh_rgb)
+    nb = int(L.hr_full_loss_scratch_bytes(sz, len(sizes)))
+    if nb == 0:
+        raise HRError(HR_ERR_INVALID_ARGUMENT, "invalid image sizes")
+    scratch = torch.empty(nb, dtype=torch.uint8, device=d)
+    check(L.hr_full_loss(_ptr(image), _ptr(final_T), _ptr(mesh_rgb), _ptr(tri_id), _ptr(target), sz,
+                         len(sizes), float(lambda_c), float(lambda_t), float(k),
+                         MASK_MODES[mask_mode], HR_FLAG_DETACH_MASK if detach_mask else 0,
+                         _ptr(loss), _ptr(gi), _ptr(gt), _ptr(gm), _ptr(scratch), _stream()))
     return loss, gi, gt, gm
 
 

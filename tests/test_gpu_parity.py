@@ -285,3 +285,28 @@ def test_graph_step_matches_eager(hr):
             np.testing.assert_allclose(step.grads[k].cpu().numpy(), ref[k].cpu().numpy(),
                                        rtol=1e-4, atol=1e-7 * float(ref[k].abs().max()) + 1e-12)
     step.close()
+
+
+@pytest.mark.parametrize("mode", ["none", "one", "T", "sigmoid"])
+def test_full_loss_kernel_matches_oracle(hr, mode):
+    say(f"case: full loss {mode}")
+    rng = np.random.default_rng(17)
+    sizes = [(37, 29), (64, 48), (5, 70)]
+    ims, tgts, Ts, Ims, tris = [], [], [], [], []
+    for (w, h) in sizes:
+        ims.append(rng.uniform(0, 1, (3, h, w)).astype(np.float32))
+        tgts.append(rng.uniform(0, 1, (3, h, w)).astype(np.float32))
+        Ts.append(rng.uniform(0, 1, (h, w)).astype(np.float32))
+        Ims.append(rng.uniform(0, 1, (3, h, w)).astype(np.float32))
+        tris.append(np.where(rng.uniform(size=(h, w)) < 0.6, 3, -1).astype(np.int32))
+    cat = lambda xs: torch.as_tensor(np.concatenate([x.reshape(-1) for x in xs])).cuda()
+    L, gI, gT, gM = hr.full_loss(cat(ims), cat(Ts), cat(Ims), cat(tris), cat(tgts), sizes,
+                                 mask_mode=mode)
+    torch.cuda.synchronize()
+    Lr, gi, gt, gm = oracle.full_loss(ims, Ts, Ims, tris, tgts, mask_mode=mode)
+    np.testing.assert_allclose(L.item(), Lr, rtol=2e-5)
+    for got, ref in ((gI, gi), (gT, gt), (gM, gm)):
+        ref = np.concatenate([r.reshape(-1) for r in ref])
+        got = got.cpu().numpy()
+        scale = max(np.abs(ref).max(), 1e-12)
+        np.testing.assert_allclose(got, ref, atol=2e-4 * scale, rtol=1e-3)

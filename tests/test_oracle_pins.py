@@ -588,3 +588,67 @@ def test_single_gaussian_opacity_derivative_closed_form():
     o = pr["opacity"][0]
     dC_do = G * (pr["rgb"][0, 1] - out["mesh_rgb"][1, j, i])
     np.testing.assert_allclose(an["opacity_logits"][0], dC_do * o * (1 - o), rtol=1e-10)
+
+
+# ------------------------------------------------------- full loss (Eq. 3) --
+def _ssim_scipy(x, y, c1=0.01 ** 2, c2=0.03 ** 2):
+    from scipy.ndimage import correlate
+    w = oracle.ssim_window()
+    out = []
+    for c in range(3):
+        cv = lambda z: correlate(z, w, mode="constant", cval=0.0)
+        mx, my = cv(x[c]), cv(y[c])
+        sxx = cv(x[c] * x[c]) - mx * mx
+        syy = cv(y[c] * y[c]) - my * my
+        sxy = cv(x[c] * y[c]) - mx * my
+        out.append(((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2)))
+    return np.stack(out)
+
+
+def test_full_loss_ssim_pins():
+    rng = np.random.default_rng(40)
+    H, W = 23, 31
+    x, y = rng.uniform(0, 1, (3, H, W)), rng.uniform(0, 1, (3, H, W))
+    T = rng.uniform(0, 1, (H, W))
+    tri = -np.ones((H, W), np.int32)
+    Im = np.zeros((3, H, W))
+    # identical images: SSIM = 1 everywhere, the loss is 0
+    L, gi, gt, gm = oracle.full_loss([x], [T], [Im], [tri], [x])
+    assert abs(L) < 1e-12
+    # against an independent correlation (scipy), zero padding
+    L, gi, gt, gm = oracle.full_loss([x], [T], [Im], [tri], [y], mask_mode="none")
+    s = _ssim_scipy(x, y)
+    ref = 0.8 * np.abs(x - y).mean() + 0.2 * (1 - s.mean())
+    np.testing.assert_allclose(L, ref, rtol=1e-12)
+    # constant images a, b: SSIM = (2ab + C1) / (a^2 + b^2 + C1) away from the borders
+    a, b = 0.3, 0.7
+    s = _ssim_scipy(np.full((3, H, W), a), np.full((3, H, W), b))
+    np.testing.assert_allclose(s[:, 5:-5, 5:-5], (2 * a * b + 1e-4) / (a * a + b * b + 1e-4), rtol=1e-12)
+    # window: normalised, symmetric, sigma 1.5
+    w = oracle.ssim_window()
+    assert abs(w.sum() - 1) < 1e-15 and np.allclose(w, w.T) and np.allclose(w, w[::-1])
+
+
+def test_full_loss_gradient_and_mask_variants():
+    rng = np.random.default_rng(41)
+    H, W = 14, 17
+    x, y, Im = (rng.uniform(0, 1, (3, H, W)) for _ in range(3))
+    T = rng.uniform(0, 1, (H, W))
+    tri = np.where(rng.uniform(size=(H, W)) < 0.6, 1, -1).astype(np.int32)
+    for mode in oracle.MASK_MODES:
+        L, gi, gt, gm = oracle.full_loss([x], [T], [Im], [tri], [y], mask_mode=mode)
+        h = 1e-6
+        for arr, g in ((x, gi[0]), (T, gt[0]), (Im, gm[0])):
+            for idx in [tuple(rng.integers(0, s) for s in arr.shape) for _ in range(6)]:
+                a0 = arr[idx]
+                arr[idx] = a0 + h
+                lp = oracle.full_loss([x], [T], [Im], [tri], [y], mask_mode=mode)[0]
+                arr[idx] = a0 - h
+                lm = oracle.full_loss([x], [T], [Im], [tri], [y], mask_mode=mode)[0]
+                arr[idx] = a0
+                np.testing.assert_allclose((lp - lm) / (2 * h), g[idx], rtol=1e-5, atol=1e-10)
+    # L_t reduces to the paper's sigmoid mask: M_T(0.5) = 1/2 and no term without a triangle
+    Ls = oracle.full_loss([x], [np.full((H, W), 0.5)], [Im], [tri], [y], mask_mode="sigmoid")[0]
+    L0 = oracle.full_loss([x], [np.full((H, W), 0.5)], [Im], [tri], [y], mask_mode="none")[0]
+    d = np.where(tri >= 0, y - Im, 0)
+    np.testing.assert_allclose(Ls - L0, 0.1 * 0.5 * (d * d).sum() / x.size, rtol=1e-12)
