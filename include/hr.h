@@ -160,6 +160,11 @@ typedef struct {
   float* opacity_logits;
   float* sh;
   float* tex;
+  /* densification statistics (3DGS-style, in pixel units): for every camera
+   * where the Gaussian is visible, |dL/d mean2D| is added to mean2d_norm and
+   * 1 to mean2d_count (both [n], nullable) */
+  float* mean2d_norm;
+  int32_t* mean2d_count;
 } hr_grads;
 
 /* hr_settings with the defaults listed above. */
@@ -215,6 +220,33 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
                          float lambda_t, float k, uint32_t flags, float* loss_out,
                          float* grad_image, float* grad_final_T, float* grad_mesh_rgb,
                          void* scratch, void* stream);
+
+/* One Adam step (Kingma and Ba, with bias correction) over several parameter
+ * groups: the joint optimisation of Sec. 3.4 / Alg. 1 updates the Gaussians and
+ * the texture map together. Per element, with g the gradient:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * lr is per group; when row > 0, elements whose index modulo row is below
+ * head use lr_head instead (the SH array: the degree-0 coefficients, 3 floats
+ * of every row of 3(d+1)^2, take a larger rate than the higher orders).
+ * `groups` is host memory (at most HR_ADAM_MAX_GROUPS); every array is device
+ * memory of n floats, updated in place; grad is only read. Groups must not
+ * overlap. Errors: HR_ERR_INVALID_ARGUMENT (null array with n > 0, n < 0,
+ * step < 1, betas outside [0,1), eps <= 0, head > row). */
+#define HR_ADAM_MAX_GROUPS 8
+typedef struct {
+  float* param;
+  const float* grad;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+  float lr_head;
+  int32_t head;
+  int32_t row;
+} hr_adam_group;
+hr_status hr_adam_step(const hr_adam_group* groups, int32_t n_groups, float beta1, float beta2,
+                       float eps, int32_t step, void* stream);
 
 /* Photometric loss of Eq. 3 with the transmittance-aware term of Sec. 3.4,
  * over n_images images packed like the renderer's outputs (image i is

@@ -11,6 +11,9 @@ Functions (one camera per call; several cameras are a loop):
   render(scene, cam)   image, T, counts, mesh buffers    (Sec. 3.1 Eq. 2, Sec. 3.4)
   backward(...)        reverse mode over a stored tape   (Sec. 3.4, texture optimisable)
   loss(...)            L1 + lambda * L_t with M_T        (Sec. 3.4, transmittance-aware supervision)
+  full_loss(...)       Eq. 3 with D-SSIM and the mask variants of Table 3
+  adam(...)            one Adam step                     (the optimiser of the joint optimisation)
+  lambda_t_schedule(i) the L_t weight of Alg. 1 at iteration i
 """
 from __future__ import annotations
 
@@ -89,7 +92,7 @@ class RenderOut_(C.Structure):
 
 class Grads_(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("means", "log_scales", "quats", "opacity_logits",
-                                          "sh", "tex")]
+                                          "sh", "tex", "mean2d")]
 
 
 def _setup(L):
@@ -238,14 +241,18 @@ def render(gaussians, mesh, cam, params=None, window=None, overrides=None):
 
 def backward(gaussians, mesh, cam, g_image, g_T=None, g_mesh_rgb=None, params=None, window=None,
              overrides=None, want_tex=True):
-    """Gradient of sum(g_image*I_h) + sum(g_T*T) + sum(g_mesh_rgb*I_m) over the window."""
+    """Gradient of sum(g_image*I_h) + sum(g_T*T) + sum(g_mesh_rgb*I_m) over the window.
+
+    Besides the parameter gradients, `mean2d` [n,2] is the gradient with
+    respect to each Gaussian's projected mean (u, v) in pixels: the quantity
+    whose norm 3DGS densification accumulates."""
     P = _params(params or default_params())
     sa = _SceneArrays(gaussians, mesh, overrides)
     x0, y0, x1, y1 = window or (0, 0, cam.width, cam.height)
     n = gaussians.n
     K = (gaussians.sh_degree + 1) ** 2
     out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
-               opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)))
+               opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)), mean2d=np.zeros((n, 2)))
     if want_tex and mesh is not None and mesh.faces.shape[0] > 0:
         out["tex"] = np.zeros(mesh.tex.shape, np.float64)
     o = Grads_(**{k: _p(v) for k, v in out.items()})
@@ -360,3 +367,26 @@ def full_loss(images, final_T, mesh_rgb, tri_id, target, lambda_c=0.2, lambda_t=
     L.backward()
     z = lambda v, like: (v.grad if v.grad is not None else torch.zeros_like(like)).numpy()
     return (float(L), [z(x, x) for x in X], [z(t, t) for t in T], [z(m, m) for m in M])
+
+
+def adam(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, lr_head=None, head=0,
+         row=0):
+    """One Adam step (Kingma and Ba, Algorithm 1, with bias-corrected moments) in
+    float64; returns the new (param, m, v). When row > 0, elements whose flat
+    index modulo row is below head take lr_head (the degree-0 SH rate)."""
+    p = np.asarray(param, np.float64).reshape(-1)
+    g = np.asarray(grad, np.float64).reshape(-1)
+    m1 = beta1 * np.asarray(m, np.float64).reshape(-1) + (1.0 - beta1) * g
+    v1 = beta2 * np.asarray(v, np.float64).reshape(-1) + (1.0 - beta2) * g * g
+    m_hat = m1 / (1.0 - beta1 ** step)
+    v_hat = v1 / (1.0 - beta2 ** step)
+    rate = np.full(p.shape, float(lr))
+    if row > 0:
+        rate[(np.arange(p.size) % row) < head] = lr_head
+    return p - rate * m_hat / (np.sqrt(v_hat) + eps), m1, v1
+
+
+def lambda_t_schedule(i, lam=0.1, warmup=3000, densify_until=15000):
+    """Weight of L_t at iteration i (Alg. 1): the full loss strictly after the
+    warm-up and strictly before the end of densification, L_c alone otherwise."""
+    return lam if warmup < i < densify_until else 0.0

@@ -99,6 +99,7 @@ typedef struct {
   double* opacity_logits;
   double* sh;        // [n,K,3]
   double* tex;       // [n_tex,H,W,3]
+  double* mean2d;    // [n,2] gradient w.r.t. the projected mean (u, v), in pixels
 } or_grads;
 }
 
@@ -856,6 +857,10 @@ int or_backward(const or_scene* sc, const or_camera* cam, const or_params* p, in
 #pragma omp parallel for schedule(static)
   for (int g = 0; g < n; ++g) {
     const double* gr = &grec[(size_t)g * 9];
+    if (o->mean2d) {
+      o->mean2d[2 * g] += gr[0];
+      o->mean2d[2 * g + 1] += gr[1];
+    }
     bool any = false;
     for (int k = 0; k < 9; ++k) any = any || gr[k] != 0.0;
     if (!any) continue;

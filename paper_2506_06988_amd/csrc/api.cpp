@@ -419,6 +419,26 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
   return hip_check("loss launch");
 }
 
+hr_status hr_adam_step(const hr_adam_group* groups, int32_t n_groups, float beta1, float beta2,
+                       float eps, int32_t step, void* stream) {
+  if (!groups || n_groups < 1 || n_groups > HR_ADAM_MAX_GROUPS)
+    return fail(HR_ERR_INVALID_ARGUMENT, "need 1..8 Adam groups");
+  if (step < 1) return fail(HR_ERR_INVALID_ARGUMENT, "step counts from 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    return fail(HR_ERR_INVALID_ARGUMENT, "need 0 <= beta < 1 and eps > 0");
+  for (int k = 0; k < n_groups; ++k) {
+    const hr_adam_group& G = groups[k];
+    if (G.n < 0) return fail(HR_ERR_INVALID_ARGUMENT, "negative Adam group size");
+    if (G.n > 0 && (!G.param || !G.grad || !G.m || !G.v))
+      return fail(HR_ERR_INVALID_ARGUMENT, "null Adam array");
+    if (G.row < 0 || G.head < 0 || (G.row > 0 && G.head > G.row))
+      return fail(HR_ERR_INVALID_ARGUMENT, "Adam head/row out of range");
+  }
+  hipGetLastError();
+  launch_adam(groups, n_groups, beta1, beta2, eps, step, (hipStream_t)stream);
+  return hip_check("adam launch");
+}
+
 size_t hr_full_loss_scratch_bytes(const int32_t* sizes, int32_t n_images) {
   if (!sizes || n_images < 1) return 0;
   int64_t P = 0, tiles = 0;

@@ -1,6 +1,8 @@
 // Backward of the projection (chain rule from the per-rank record gradients
 // to the Gaussian parameters, summed over cameras in registers), backward of
 // the bilinear texture fetch, and the loss of Sec. 3.4.
+#include <cmath>
+
 #include "kernels.hpp"
 #include "mesh_math.hpp"
 #include "project_math.hpp"
@@ -16,9 +18,12 @@ __global__ __launch_bounds__(128) void k_project_bwd(
     const float* __restrict__ logits, const float* __restrict__ sh,
     const int32_t* __restrict__ rank_of, const float* __restrict__ gacc,
     float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
-    float* __restrict__ g_logit, float* __restrict__ g_sh) {
+    float* __restrict__ g_logit, float* __restrict__ g_sh, float* __restrict__ m2d_norm,
+    int32_t* __restrict__ m2d_count) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= S.n) return;
+  float stat_norm = 0.f;
+  int stat_cnt = 0;
   const int K = (S.sh_degree + 1) * (S.sh_degree + 1);
   double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glg = 0;
   float gshr[48];
@@ -37,6 +42,8 @@ __global__ __launch_bounds__(128) void k_project_bwd(
       G9[q] = ga[q];
       nz = nz || G9[q] != 0.0;
     }
+    stat_norm += sqrtf(ga[0] * ga[0] + ga[1] * ga[1]);
+    ++stat_cnt;
     if (!nz) continue;
     any = true;
     const CamDev& cam = cams[c];
@@ -155,6 +162,8 @@ __global__ __launch_bounds__(128) void k_project_bwd(
 #pragma unroll
     for (int a = 0; a < 4; ++a) gq[a] += (gqn[a] - P.qn[a] * dq) / P.qnorm;
   }
+  if (m2d_norm && stat_cnt) m2d_norm[g] += stat_norm;
+  if (m2d_count && stat_cnt) m2d_count[g] += stat_cnt;
   if (!any) return;
   if (g_means)
     for (int a = 0; a < 3; ++a) g_means[3 * g + a] += (float)gmu[a];
@@ -354,7 +363,54 @@ __global__ __launch_bounds__(LB) void k_loss_final(const double* __restrict__ pa
   }
 }
 
+struct AdamArgs {
+  hr_adam_group g[HR_ADAM_MAX_GROUPS];
+  int64_t start[HR_ADAM_MAX_GROUPS + 1];
+  int32_t n_groups;
+  float b1, b2, eps, c1, c2;  // c1 = 1 - b1^step, c2 = 1 - b2^step
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamArgs A) {
+  const int64_t total = A.start[A.n_groups];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int k = 0;
+    while (i >= A.start[k + 1]) ++k;
+    const int64_t j = i - A.start[k];
+    const hr_adam_group& G = A.g[k];
+    const float lr = (G.row > 0 && (int)((uint64_t)j % (uint32_t)G.row) < G.head) ? G.lr_head : G.lr;
+    const float gr = G.grad[j];
+    const float m = A.b1 * G.m[j] + (1.f - A.b1) * gr;
+    const float v = A.b2 * G.v[j] + (1.f - A.b2) * gr * gr;
+    G.m[j] = m;
+    G.v[j] = v;
+    G.param[j] -= lr * (m / A.c1) / (sqrtf(v / A.c2) + A.eps);
+  }
+}
+
 }  // namespace
+
+void launch_adam(const hr_adam_group* groups, int n_groups, float b1, float b2, float eps,
+                 int step, hipStream_t st) {
+  AdamArgs A;
+  A.n_groups = n_groups;
+  A.b1 = b1;
+  A.b2 = b2;
+  A.eps = eps;
+  A.c1 = (float)(1.0 - std::pow((double)b1, step));
+  A.c2 = (float)(1.0 - std::pow((double)b2, step));
+  int64_t acc = 0;
+  for (int k = 0; k < n_groups; ++k) {
+    A.g[k] = groups[k];
+    A.start[k] = acc;
+    acc += groups[k].n;
+  }
+  A.start[n_groups] = acc;
+  if (acc == 0) return;
+  int64_t grid = (acc + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)grid), dim3(256), 0, st, A);
+}
 
 void launch_project_backward(const SetDev& S, const CamDev* cams, const hr_gaussians& g,
                              const Work& w, hr_grads* grads, hipStream_t st) {
@@ -362,7 +418,7 @@ void launch_project_backward(const SetDev& S, const CamDev* cams, const hr_gauss
   hipLaunchKernelGGL(k_project_bwd, dim3((S.n + 127) / 128), dim3(128), 0, st, S, cams, g.means,
                      g.log_scales, g.quats, g.opacity_logits, g.sh, w.rank_of, w.gacc,
                      grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
-                     grads->sh);
+                     grads->sh, grads->mean2d_norm, grads->mean2d_count);
 }
 
 void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,

@@ -55,12 +55,18 @@ class hr_outputs(C.Structure):
 
 
 class hr_grads(C.Structure):
-    _fields_ = [(k, P) for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex")]
+    _fields_ = [(k, P) for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex",
+                                 "mean2d_norm", "mean2d_count")]
+
+
+class hr_adam_group(C.Structure):
+    _fields_ = [("param", P), ("grad", P), ("m", P), ("v", P), ("n", C.c_int64), ("lr", C.c_float),
+                ("lr_head", C.c_float), ("head", C.c_int32), ("row", C.c_int32)]
 
 
 EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid",
             "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
-            "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_autotune",
+            "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_autotune",
             "hr_batch_create", "hr_batch_launch", "hr_batch_destroy", "hr_status_string",
             "hr_last_error", "hr_abi_version"]
 
@@ -91,6 +97,8 @@ def load(path: str = LIB_PATH):
     L.hr_hybrid_loss.restype = C.c_int
     L.hr_hybrid_loss.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_uint32, P, P,
                                  P, P, P, P]
+    L.hr_adam_step.restype = C.c_int
+    L.hr_adam_step.argtypes = [P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_int32, P]
     L.hr_full_loss_scratch_bytes.restype = C.c_size_t
     L.hr_full_loss_scratch_bytes.argtypes = [P, C.c_int32]
     L.hr_full_loss.restype = C.c_int
@@ -377,7 +385,8 @@ class Renderer:
             if self.mesh is not None:
                 grads["tex"] = torch.zeros_like(self.mesh.tex if tex is None else tex)
         gr = hr_grads()
-        for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex"):
+        for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex", "mean2d_norm",
+                  "mean2d_count"):
             setattr(gr, k, _ptr(grads.get(k)))
         gs, ms = self._structs(tex)
         check(self.L.hr_render_hybrid_backward(
@@ -431,6 +440,23 @@ def hybrid_loss(image, final_T, mesh_rgb, tri_id, target, lambda_t=0.1, k=20.0, 
 
 
 MASK_MODES = {"none": 0, "one": 1, "T": 2, "sigmoid": 3}
+
+
+def adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15):
+    """hr_adam_step over [(param, grad, m, v, lr[, lr_head, head, row]), ...]
+    (contiguous float32 device tensors of equal sizes within a group)."""
+    arr = (hr_adam_group * len(groups))()
+    for i, grp in enumerate(groups):
+        p_, g_, m_, v_, lr = grp[:5]
+        lr_head, head, row = grp[5:] if len(grp) > 5 else (lr, 0, 0)
+        for t in (g_, m_, v_):
+            assert t.numel() == p_.numel() and t.is_contiguous() and t.dtype == p_.dtype
+        assert p_.is_contiguous()
+        arr[i].param, arr[i].grad, arr[i].m, arr[i].v = _ptr(p_), _ptr(g_), _ptr(m_), _ptr(v_)
+        arr[i].n, arr[i].lr = int(p_.numel()), float(lr)
+        arr[i].lr_head, arr[i].head, arr[i].row = float(lr_head), int(head), int(row)
+    check(load().hr_adam_step(arr, len(groups), float(beta1), float(beta2), float(eps), int(step),
+                              _stream()))
 
 
 def full_loss(image, final_T, mesh_rgb, tri_id, target, sizes, lambda_c=0.2, lambda_t=0.1, k=20.0,

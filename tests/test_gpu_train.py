@@ -1,0 +1,187 @@
+"""Training-step entry points on the GPU: the Adam step, the densification
+statistics accumulated by the backward, and the Alg. 1 iteration."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_06988_amd import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tiny(seed, n=30, deg=3, w=48, h=40):
+    rng = np.random.default_rng(seed)
+    means = np.column_stack([rng.uniform(-0.6, 0.6, n), rng.uniform(-0.5, 0.5, n), rng.uniform(1.5, 3.0, n)])
+    sh = np.concatenate([((rng.uniform(0, 1, (n, 1, 3)) - 0.5) / scenes.Y00),
+                         rng.normal(0, 0.2, (n, (deg + 1) ** 2 - 1, 3))], 1)
+    g = scenes.make_gaussians(means, rng.uniform(-3.0, -1.8, (n, 3)), rng.standard_normal((n, 4)),
+                              rng.normal(0, 1, n), sh, deg)
+    mesh = scenes.quad_mesh(rng, z=2.4, half=1.0, tex_size=16)
+    cam = scenes.Camera(w, h, 40.0, 40.0, w / 2 + 0.3, h / 2 - 0.2, np.eye(3), np.zeros(3))
+    return scenes.Scene(f"tiny{seed}", g, mesh, [cam])
+
+
+def side_camera(w, h, dx):
+    c = scenes.look_camera(w, h, [dx, 0.05, -0.1], 0.12 * dx, 0.03)
+    return scenes.Camera(w, h, 40.0, 40.0, w / 2, h / 2, c.R, c.t)
+
+
+def test_adam_kernel_matches_oracle(hr):
+    say("case: Adam groups of 0, 1, 1000, 70001 elements and an SH group with a head rate")
+    rng = np.random.default_rng(3)
+    K3 = 48
+    spec = [(0, 1e-2, None), (1, 3e-3, None), (1000, 5e-2, None), (70001, 1e-3, None),
+            (97 * K3, 2.5e-3 / 20, 2.5e-3)]
+    host, dev = [], []
+    for n, lr, lr_head in spec:
+        p = rng.normal(size=n).astype(np.float32)
+        host.append([p.astype(np.float64), np.zeros(n), np.zeros(n)])
+        t = lambda a: torch.as_tensor(a, dtype=torch.float32).cuda().contiguous()
+        dev.append([t(p), None, t(np.zeros(n)), t(np.zeros(n))])
+    for step in range(1, 4):
+        groups = []
+        for (n, lr, lr_head), h, d in zip(spec, host, dev):
+            g = (rng.normal(size=n) * rng.choice([1e-3, 1.0, 30.0])).astype(np.float32)
+            d[1] = torch.as_tensor(g).cuda()
+            kw = dict(lr_head=lr_head, head=3, row=K3) if lr_head else {}
+            h[0], h[1], h[2] = oracle.adam(h[0], g.astype(np.float64), h[1], h[2], lr, step, **kw)
+            groups.append(tuple(d) + ((lr, lr_head, 3, K3) if lr_head else (lr,)))
+        hr.adam_step(groups, step)
+        torch.cuda.synchronize()
+        for (n, lr, lr_head), h, d in zip(spec, host, dev):
+            if n == 0:
+                continue
+            p = d[0].cpu().numpy().astype(np.float64)
+            top = max(lr, lr_head or 0)
+            tol = 4 * np.spacing(np.abs(h[0]).astype(np.float32)).astype(np.float64) + 1e-5 * top
+            assert (np.abs(p - h[0]) <= tol).all(), (n, step, np.abs(p - h[0]).max())
+            np.testing.assert_allclose(d[2].cpu().numpy(), h[1], rtol=1e-5, atol=1e-9)
+            np.testing.assert_allclose(d[3].cpu().numpy(), h[2], rtol=1e-5, atol=1e-12)
+    say("  3 steps within FP32 rounding of the oracle")
+    # argument checks happen on the host
+    z = torch.zeros(4, device="cuda")
+    with pytest.raises(hr.HRError):
+        hr.adam_step([(z, z, z, z, 1e-3)], 0)
+    with pytest.raises(hr.HRError):
+        hr.adam_step([(z, z, z, z, 1e-3)] * 9, 1)
+    with pytest.raises(hr.HRError):
+        hr.adam_step([(z, z, z, z, 1e-3, 1e-2, 5, 4)], 1)
+
+
+def test_densification_statistics_match_oracle(hr):
+    say("case: |dL/dmean2D| and visibility counts over 2 cameras")
+    sc = tiny(111, n=40)
+    cams = [sc.cameras[0], side_camera(40, 36, 0.2)]
+    g, m = hr.to_device(sc.gaussians, sc.mesh)
+    r = hr.Renderer(g, m, cams)
+    r.render_hybrid()
+    rng = np.random.default_rng(5)
+    ups, ref_norm, ref_count = [], np.zeros(40), np.zeros(40, np.int64)
+    for cam in cams:
+        orc = oracle.render(sc.gaussians, sc.mesh, cam)
+        gi = rng.normal(size=(3, cam.height, cam.width)).astype(np.float32)
+        gi[:, orc["amb"] != 0] = 0
+        ups.append(gi)
+        ref = oracle.backward(sc.gaussians, sc.mesh, cam, gi, None, None)
+        ref_norm += np.linalg.norm(ref["mean2d"], axis=1)
+        pr = oracle.project(sc.gaussians, cam)
+        assert not pr["amb"].any()
+        ref_count += pr["radius"] > 0
+    grads = dict(means=torch.zeros_like(g.means), mean2d_norm=torch.zeros(40, device="cuda"),
+                 mean2d_count=torch.zeros(40, dtype=torch.int32, device="cuda"))
+    r.render_hybrid_backward(torch.as_tensor(np.concatenate([u.reshape(-1) for u in ups])).cuda(),
+                             grads=grads)
+    # a second backward accumulates
+    r.render_hybrid_backward(torch.as_tensor(np.concatenate([u.reshape(-1) for u in ups])).cuda(),
+                             grads=grads)
+    torch.cuda.synchronize()
+    cnt = grads["mean2d_count"].cpu().numpy()
+    nrm = grads["mean2d_norm"].cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(cnt, 2 * ref_count)
+    assert ref_count.min() < 2 <= ref_count.max() and np.count_nonzero(ref_norm) > 10
+    rel = np.linalg.norm(nrm - 2 * ref_norm) / np.linalg.norm(2 * ref_norm)
+    say(f"  counts exact; norm rel err {rel:.2e}")
+    assert rel <= 1e-3
+    assert (np.abs(nrm - 2 * ref_norm) <= 2e-3 * (2 * ref_norm) + 1e-6 * ref_norm.max()).all()
+
+
+def _scene_views(seed, n=60):
+    sc = tiny(seed, n=n)
+    w, h = sc.cameras[0].width, sc.cameras[0].height
+    return sc, [sc.cameras[0], side_camera(w, h, 0.15), side_camera(w, h, -0.15)]
+
+
+def test_trainer_iteration_is_the_composition_of_entry_points(hr):
+    say("case: two training iterations vs the entry points called one by one")
+    from paper_2506_06988_amd import train
+    sc, views = _scene_views(121)
+    w, h = views[0].width, views[0].height
+    gen = torch.Generator("cuda").manual_seed(4)
+    targets = [torch.rand(3, h, w, device="cuda", generator=gen) for _ in views]
+    g, m = hr.to_device(sc.gaussians, sc.mesh)
+    T = train.Trainer(g, m, views, targets, warmup=0, densify_until=10)
+    losses = [T.step().item() for _ in range(2)]
+    # by hand
+    g2, m2 = hr.to_device(sc.gaussians, sc.mesh)
+    r = hr.Renderer(g2, m2, [views[0]])
+    params = dict(means=g2.means, log_scales=g2.log_scales, quats=g2.quats,
+                  opacity_logits=g2.opacity_logits, sh=g2.sh, tex=m2.tex)
+    mom = {k: torch.zeros_like(v) for k, v in params.items()}
+    vel = {k: torch.zeros_like(v) for k, v in params.items()}
+    lr = train.DEFAULT_LRS
+    K3 = 3 * (g2.sh_degree + 1) ** 2
+    for it in range(2):
+        r.set_cameras([views[it]])
+        f = r.render_hybrid()
+        lt = train.lambda_t(it, warmup=0, densify_until=10)
+        assert lt == (0.0 if it == 0 else 0.1)
+        loss, gi, gt, gm = hr.full_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id,
+                                        targets[it].reshape(-1), [(w, h)], lambda_t=lt)
+        np.testing.assert_allclose(loss.item(), losses[it], rtol=1e-6)
+        grads = r.render_hybrid_backward(gi, gt, gm)
+        pos = train.exp_lr(it, lr["position_init"], lr["position_final"], 30000)
+        rates = dict(means=(pos,), log_scales=(lr["scaling"],), quats=(lr["rotation"],),
+                     opacity_logits=(lr["opacity"],), sh=(lr["sh_rest"], lr["sh_dc"], 3, K3),
+                     tex=(lr["texture"],))
+        hr.adam_step([(params[k], grads[k], mom[k], vel[k]) + rates[k] for k in params], it + 1)
+    torch.cuda.synchronize()
+    for k in params:
+        a, b = T.params[k].cpu().numpy(), params[k].cpu().numpy()
+        # gradients are sums of float atomics, so the two runs may differ in
+        # rounding; an element whose gradient is at rounding level may move by
+        # a different Adam step
+        close = np.abs(a - b) <= 1e-6 * np.abs(b) + 1e-7
+        say(f"  {k}: elements not within 1e-6: {(~close).sum()} / {close.size}")
+        assert (~close).mean() <= 1e-3, k
+
+
+def test_training_reduces_the_loss(hr):
+    say("case: 240 iterations of the Alg. 1 schedule on oracle-rendered targets")
+    from paper_2506_06988_amd import train
+    sc, views = _scene_views(131)
+    targets = [torch.as_tensor(oracle.render(sc.gaussians, sc.mesh, c)["image"],
+                               dtype=torch.float32).cuda() for c in views]
+    rng = np.random.default_rng(2)
+    gs = sc.gaussians
+    start = scenes.make_gaussians(gs.means + rng.normal(0, 0.02, gs.means.shape), gs.log_scales,
+                                  gs.quats, gs.opacity_logits + rng.normal(0, 0.5, gs.opacity_logits.shape),
+                                  gs.sh + rng.normal(0, 0.3, gs.sh.shape), gs.sh_degree)
+    mesh = scenes.Mesh(sc.mesh.verts, sc.mesh.faces, sc.mesh.uvs, sc.mesh.face_tex,
+                       np.clip(sc.mesh.tex + rng.normal(0, 0.2, sc.mesh.tex.shape), 0, 1).astype(np.float32))
+    g, m = hr.to_device(start, mesh)
+    T = train.Trainer(g, m, views, targets, max_iters=240, warmup=30, densify_until=180,
+                      lrs=dict(texture=1e-2))
+    losses = [T.step().item() for _ in range(240)]
+    first, last = np.mean(losses[:6]), np.mean(losses[-6:])
+    say(f"  loss {first:.4f} -> {last:.4f}; visible-view count max {int(T.grads['mean2d_count'].max())}")
+    assert np.isfinite(losses).all()
+    assert last < 0.6 * first
+    assert int(T.grads["mean2d_count"].max()) <= 240

@@ -652,3 +652,72 @@ def test_full_loss_gradient_and_mask_variants():
     L0 = oracle.full_loss([x], [np.full((H, W), 0.5)], [Im], [tri], [y], mask_mode="none")[0]
     d = np.where(tri >= 0, y - Im, 0)
     np.testing.assert_allclose(Ls - L0, 0.1 * 0.5 * (d * d).sum() / x.size, rtol=1e-12)
+
+
+# ------------------------------------------------- training-step oracles --
+def test_mean2d_gradient_is_the_principal_point_derivative():
+    # shifting (cx, cy) moves every projected mean by the same amount and
+    # changes nothing else of a Gaussians-only frame, so dF/dcx = sum_g dF/du_g
+    g, _, cam = tiny_scene(41, n=6, with_mesh=False)
+    rng = np.random.default_rng(4)
+    pr64 = oracle.default_params(flags=oracle.FP64_RECORDS)
+    gi = rng.normal(size=(3, 32, 32))
+    gt = rng.normal(size=(32, 32))
+    an = oracle.backward(g, None, cam, gi, gt, None, params=pr64)
+
+    def F(gs, dcx, dcy):
+        c = scenes.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx + dcx, cam.cy + dcy,
+                          cam.R, cam.t)
+        o = oracle.render(gs, None, c, params=pr64)
+        return np.sum(gi * o["image"]) + np.sum(gt * o["final_T"]), o["trace"]
+
+    h = 1e-6
+    for gs, ref in [(g, an["mean2d"].sum(0))] + [
+            (g.subset(np.array([j])), None) for j in range(3)]:
+        if ref is None:
+            ref = oracle.backward(gs, None, cam, gi, gt, None, params=pr64)["mean2d"][0]
+        for axis in range(2):
+            d = [0.0, 0.0]
+            d[axis] = h
+            fp, tp = F(gs, *d)
+            fm, tm = F(gs, -d[0], -d[1])
+            assert tp == tm
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - ref[axis]) <= 1e-6 * max(1.0, abs(ref[axis])), (axis, fd, ref[axis])
+
+
+def test_adam_matches_torch_optim_and_the_first_step_closed_form():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(8)
+    K3 = 12  # one SH row of degree 1: 4 coefficients x 3 channels
+    p0 = rng.normal(size=5 * K3)
+    grads = [rng.normal(size=p0.size) * s for s in (1.0, 1e-3, 10.0, 0.5)]
+    lr, lr_dc = 1e-2, 3e-2
+    # torch reference: the head columns form their own parameter group
+    head = (np.arange(p0.size) % K3) < 3
+    t_dc = torch.tensor(p0[head], dtype=torch.float64, requires_grad=True)
+    t_rest = torch.tensor(p0[~head], dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([{"params": [t_dc], "lr": lr_dc}, {"params": [t_rest], "lr": lr}],
+                           betas=(0.9, 0.999), eps=1e-15)
+    p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    for step, gr in enumerate(grads, 1):
+        p, m, v = oracle.adam(p, gr, m, v, lr, step, lr_head=lr_dc, head=3, row=K3)
+        t_dc.grad = torch.tensor(gr[head])
+        t_rest.grad = torch.tensor(gr[~head])
+        opt.step()
+        np.testing.assert_allclose(p[head], t_dc.detach().numpy(), rtol=0, atol=1e-13)
+        np.testing.assert_allclose(p[~head], t_rest.detach().numpy(), rtol=0, atol=1e-13)
+        if step == 1:
+            # bias correction makes the first step lr * g / (|g| + eps)
+            rate = np.where(head, lr_dc, lr)
+            np.testing.assert_allclose(p, p0 - rate * gr / (np.abs(gr) + 1e-15), rtol=0, atol=1e-15)
+
+
+def test_lambda_t_schedule_boundaries():
+    # Alg. 1: L_t only strictly after the warm-up and strictly before the end of densification
+    assert oracle.lambda_t_schedule(0) == 0.0
+    assert oracle.lambda_t_schedule(3000) == 0.0
+    assert oracle.lambda_t_schedule(3001) == 0.1
+    assert oracle.lambda_t_schedule(14999) == 0.1
+    assert oracle.lambda_t_schedule(15000) == 0.0
+    assert oracle.lambda_t_schedule(29999) == 0.0
