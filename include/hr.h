@@ -105,7 +105,15 @@ typedef struct {
 enum {
   HR_FLAG_NO_SYNC = 1u << 0,      /* never synchronise to check the capacity */
   HR_FLAG_DETACH_MASK = 1u << 1,  /* loss: no gradient through M_T */
-  HR_FLAG_EXPORT_KEYS = 1u << 2   /* forward: fill hr_outputs.keys/values/ranges */
+  HR_FLAG_EXPORT_KEYS = 1u << 2,  /* forward: fill hr_outputs.keys/values/ranges */
+  /* forward: leave out of the tile lists every (Gaussian, tile) pair whose
+   * fp32 depth is >= the largest mesh depth over the tile's pixels (only
+   * tiles whose pixels all have a face). Such a Gaussian reaches the depth
+   * stop of Sec. 3.4 in every pixel of the tile, so images, T, n_contrib and
+   * n_blended are unchanged; n_processed loses the one stopping candidate
+   * where it was dropped; keys/ranges, n_keys and the capacity requirement
+   * count the kept pairs only. */
+  HR_FLAG_CULL_BEHIND_MESH = 1u << 3
 };
 
 typedef struct {

@@ -28,6 +28,7 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FP64_RECORDS = 1
+CULL_MESH = 2  # drop (Gaussian, tile) pairs at or behind the tile's largest mesh depth
 
 
 def build(force: bool = False) -> str:
@@ -205,9 +206,10 @@ def project(gaussians, cam, params=None):
     return out
 
 
-def keys(gaussians, cam, params=None):
+def keys(gaussians, cam, params=None, mesh=None):
+    """Sorted tile keys; the mesh matters only with the CULL_MESH flag."""
     P = _params(params or default_params())
-    sa = _SceneArrays(gaussians, None)
+    sa = _SceneArrays(gaussians, mesh)
     c = _camera(cam)
     K = lib().or_keys(C.byref(sa.s), C.byref(c), C.byref(P), None, None, None, 0)
     assert K >= 0

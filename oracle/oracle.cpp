@@ -62,7 +62,7 @@ typedef struct {
   double amb_alpha, amb_t;  // relative slack under which a decision is tagged
 } or_params;
 
-enum { OR_FP64_RECORDS = 1 };
+enum { OR_FP64_RECORDS = 1, OR_CULL_MESH = 2 };
 
 // per-Gaussian record export
 typedef struct {
@@ -618,6 +618,43 @@ void blend_pixel(const std::vector<Rec>& recs, const std::vector<Cand>& list, co
   *hash = h;
 }
 
+// Joint rasterization (Sec. 3.4): each pixel stops at the first Gaussian
+// whose fp32 depth is not below its fp32 mesh depth. A Gaussian at or beyond
+// the largest mesh depth of every pixel of a tile therefore stops every pixel
+// there, and with OR_CULL_MESH it is removed from that tile's list (tiles with
+// a pixel that has no face keep their lists). The tile's pixels are those of
+// the image, whatever the window.
+void cull_behind_mesh(const or_scene& sc, const or_camera& cam, const or_params& p,
+                      const std::vector<Rec>& recs, int tx0, int ty0, int tx1, int ty1,
+                      std::vector<std::vector<Cand>>& lists) {
+  if (sc.n_faces == 0) return;
+  const int x0 = tx0 * p.tile, y0 = ty0 * p.tile;
+  const int x1 = std::min(tx1 * p.tile, cam.width), y1 = std::min(ty1 * p.tile, cam.height);
+  std::vector<MeshPix> pix;
+  mesh_pass(sc, cam, p, x0, y0, x1, y1, pix);
+  const int ww = x1 - x0, ntx = tx1 - tx0;
+  for (int ty = ty0; ty < ty1; ++ty)
+    for (int tx = tx0; tx < tx1; ++tx) {
+      bool covered = true;
+      float dmax = 0.f;
+      for (int j = ty * p.tile; j < std::min((ty + 1) * p.tile, cam.height) && covered; ++j)
+        for (int i = tx * p.tile; i < std::min((tx + 1) * p.tile, cam.width); ++i) {
+          const MeshPix& mp = pix[(size_t)(j - y0) * ww + (i - x0)];
+          if (mp.key == ~0ull) {
+            covered = false;
+            break;
+          }
+          dmax = std::max(dmax, (float)mp.z);
+        }
+      if (!covered) continue;
+      auto& l = lists[(size_t)(ty - ty0) * ntx + (tx - tx0)];
+      std::vector<Cand> kept;
+      for (const Cand& c : l)
+        if ((float)recs[c.g].zf < dmax) kept.push_back(c);
+      l.swap(kept);
+    }
+}
+
 struct Frame {
   std::vector<Rec> recs;
   std::vector<MeshPix> mesh;
@@ -635,6 +672,7 @@ Frame prepare(const or_scene& sc, const or_camera& cam, const or_params& p, int 
   f.tx1 = (wx1 + p.tile - 1) / p.tile;
   f.ty1 = (wy1 + p.tile - 1) / p.tile;
   f.lists = tile_lists(f.recs, f.tx0, f.ty0, f.tx1, f.ty1);
+  if (p.flags & OR_CULL_MESH) cull_behind_mesh(sc, cam, p, f.recs, f.tx0, f.ty0, f.tx1, f.ty1, f.lists);
   return f;
 }
 
@@ -679,6 +717,7 @@ int64_t or_keys(const or_scene* sc, const or_camera* cam, const or_params* p, ui
   std::vector<Rec> recs = project_all(*sc, *cam, *p);
   const int TX = tiles_x(*cam, *p), TY = tiles_y(*cam, *p);
   auto lists = tile_lists(recs, 0, 0, TX, TY);
+  if (p->flags & OR_CULL_MESH) cull_behind_mesh(*sc, *cam, *p, recs, 0, 0, TX, TY, lists);
   int64_t K = 0;
   for (auto& l : lists) K += (int64_t)l.size();
   if (keys && values && ranges && capacity >= K) {

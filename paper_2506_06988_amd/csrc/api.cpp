@@ -38,7 +38,7 @@ struct Plan {
   int64_t n, n_cams, M, F, MF, P, n_tiles, key_cap, rs_blocks, chunk_rows, mat_entries;
   size_t cams, counters, tiles, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, tiles_s, item_s, pair_off, mat, tile_total,
-      tile_start, tile_order, slice_cnt, slice_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
+      tile_start, tile_order, tile_dmax, slice_cnt, slice_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, gacc, tune, scan_scratch, total;
   std::vector<CamDev> camdev;
 };
@@ -156,6 +156,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.tile_total = L.take(4 * p.n_tiles);
   p.tile_start = L.take(4 * p.n_tiles);
   p.tile_order = L.take(4 * p.n_tiles);
+  p.tile_dmax = L.take(4 * p.n_tiles);
   p.slice_cnt = L.take(4 * (p.chunk_rows + 1));
   p.slice_off = L.take(4 * (p.chunk_rows + 1));
   p.lists = L.take(4 * key_cap);
@@ -206,6 +207,7 @@ Work make_work(const Plan& p, void* ws) {
   w.tile_total = (uint32_t*)(b + p.tile_total);
   w.tile_start = (uint32_t*)(b + p.tile_start);
   w.tile_order = (uint32_t*)(b + p.tile_order);
+  w.tile_dmax = (uint32_t*)(b + p.tile_dmax);
   w.slice_cnt = (uint32_t*)(b + p.slice_cnt);
   w.slice_off = (uint32_t*)(b + p.slice_off);
   w.lists = (uint32_t*)(b + p.lists);
@@ -274,9 +276,11 @@ void enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const hr_gau
   launch_fill_u32(w.counters, 0u, 64, st);
   upload_cams(p, w, st);
   launch_mesh(S, *m, w, out, st);
+  const bool cull = (s->flags & HR_FLAG_CULL_BEHIND_MESH) && S.n_faces > 0;
+  if (cull) launch_tile_dmax(S, w, st);
   launch_project(S, w.cams, *g, w, out->radii, st);
   launch_depth_sort(S, w, st);
-  launch_binning(S, w, (int)p.n_cams, out, st);
+  launch_binning(S, w, (int)p.n_cams, cull, out, st);
   launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
   if (out->stats) launch_counters_to_stats(w.counters, out->stats, st);
 }

@@ -35,10 +35,11 @@ struct Work {
   uint32_t* tile_total;  // [n_tiles]
   uint32_t* tile_start;  // [n_tiles]
   uint32_t* tile_order;  // [n_tiles] blend schedule, longest lists first
+  uint32_t* tile_dmax;   // [n_tiles] largest mesh depth bits over the tile (culling)
   uint32_t* lists;       // [key_cap] ranks grouped by tile, chunk sub-segments in chunk order
   // counters: [0] n_vis, [1] overflow, [2..3] K (u64), [4] n_tris, [5] n_blocks,
   // [6..7] sum n_processed (u64), [8..9] sum n_blended (u64), [10..11] K scan total,
-  // [12] binning slices
+  // [12] binning slices, [13] pairs kept in the tile lists
   uint32_t* counters;
   // mesh
   uint64_t* zbuf;        // [P] fp32 depth bits << 32 | triangle index
@@ -61,7 +62,9 @@ struct Work {
 void launch_project(const SetDev& S, const CamDev* cams, const hr_gaussians& g, const Work& w,
                     int32_t* radii, hipStream_t st);
 void launch_depth_sort(const SetDev& S, const Work& w, hipStream_t st);
-void launch_binning(const SetDev& S, const Work& w, int n_cams, hr_outputs* out, hipStream_t st);
+void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, hr_outputs* out,
+                    hipStream_t st);
+void launch_tile_dmax(const SetDev& S, const Work& w, hipStream_t st);
 void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* out,
                  hipStream_t st);
 void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int batch, int variant,

@@ -179,6 +179,38 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
   if (tri_id) tri_id[p] = face;
 }
 
+__device__ __forceinline__ int find_cam_by_tile_m(const CamDev* cams, int n_cams, int tile) {
+  int lo = 0, hi = n_cams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cams[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Per tile: the largest fp32 mesh depth over its pixels inside the image, as
+// bits (depths are positive, so bit order is value order); a pixel without a
+// face makes it 0xffffffff, above every finite or infinite depth. One
+// workgroup per tile, one thread per pixel.
+__global__ __launch_bounds__(256) void k_tile_dmax(SetDev S, const CamDev* __restrict__ cams,
+                                                   const unsigned long long* __restrict__ zbuf,
+                                                   uint32_t* __restrict__ tile_dmax) {
+  __shared__ uint32_t red;
+  const int t = blockIdx.x;
+  const int c = find_cam_by_tile_m(cams, S.n_cams, t);
+  const CamDev& C = cams[c];
+  const int tl = t - C.tile_off;
+  const int i = (tl % C.TX) * TILE + (int)(threadIdx.x % TILE);
+  const int j = (tl / C.TX) * TILE + (int)(threadIdx.x / TILE);
+  uint32_t v = 0;
+  if (i < C.W && j < C.H) v = (uint32_t)(zbuf[C.pix_off + (int64_t)j * C.W + i] >> 32);
+  if (threadIdx.x == 0) red = 0;
+  __syncthreads();
+  atomicMax(&red, v);
+  __syncthreads();
+  if (threadIdx.x == 0) tile_dmax[t] = red;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -229,6 +261,12 @@ void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* o
                      w.cams, (const unsigned long long*)w.zbuf, w.tris, tex, w.mesh_rgb,
                      out ? out->mesh_rgb : nullptr, out ? out->mesh_depth : nullptr,
                      out ? out->tri_id : nullptr);
+}
+
+void launch_tile_dmax(const SetDev& S, const Work& w, hipStream_t st) {
+  if (S.n_tiles == 0) return;
+  hipLaunchKernelGGL(k_tile_dmax, dim3((unsigned)S.n_tiles), dim3(256), 0, st, S, w.cams,
+                     (const unsigned long long*)w.zbuf, w.tile_dmax);
 }
 
 }  // namespace hr

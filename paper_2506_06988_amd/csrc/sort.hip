@@ -322,6 +322,22 @@ __device__ __forceinline__ void slice_pairs(const Slice& S, const int32_t* poff,
   }
 }
 
+// Stages the rectangles of the slice's ranks in LDS and, when culling behind
+// the mesh, their depth bits.
+__device__ __forceinline__ void stage_ranks(const Slice& S, const uint2* rect_s, const GRec* rec_s,
+                                            const uint32_t* tile_dmax, uint2* rects,
+                                            uint32_t* deps) {
+  for (int k = threadIdx.x; k < S.nitems; k += blockDim.x) rects[k] = rect_s[S.ia + k];
+  if (tile_dmax)
+    for (int k = threadIdx.x; k < S.nitems; k += blockDim.x)
+      deps[k] = __float_as_uint(rec_s[S.ia + k].depth);
+}
+
+// Mesh-depth culling (Sec. 3.4, joint rasterization): a pixel stops at the
+// first Gaussian whose depth reaches its mesh depth, so a Gaussian at or
+// behind the largest mesh depth of a tile (every pixel covered) can never
+// be blended there; such (Gaussian, tile) pairs are left out of the lists.
+
 // Pass 1: per (chunk, tile) pair counts. Persistent workgroups take slices in
 // turn; each histograms its pairs per tile in LDS and adds the non-zero bins
 // into the chunk's row of the count matrix. HT = LDS histogram entries.
@@ -333,10 +349,13 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
                                                    int64_t rows_total,
                                                    const uint32_t* __restrict__ counters,
                                                    const uint2* __restrict__ rect_s,
+                                                   const GRec* __restrict__ rec_s,
+                                                   const uint32_t* __restrict__ tile_dmax,
                                                    uint32_t* __restrict__ mat) {
   __shared__ uint32_t hist[HT];
   __shared__ int32_t poff[CHUNK + 1];
   __shared__ uint2 rects[CHUNK];
+  __shared__ uint32_t deps[CHUNK];
   __shared__ uint32_t big[CHUNK];
   __shared__ uint32_t nbig;
   const uint32_t nsl = counters[12];
@@ -344,12 +363,14 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
     Slice S;
     load_slice(cams, n_cams, vis_off, pair_off, slice_off, rows_total, sl, S, poff);
     const CamDev& cam = cams[S.cam];
-    for (int k = threadIdx.x; k < S.nitems; k += 256) rects[k] = rect_s[S.ia + k];
+    stage_ranks(S, rect_s, rec_s, tile_dmax, rects, deps);
     for (int t = threadIdx.x; t < S.ntl; t += 256) hist[t] = 0;
     if (threadIdx.x == 0) nbig = 0;
     __syncthreads();
-    slice_pairs(S, poff, rects, cam.TX, big, &nbig,
-                [&](uint32_t, int tl) { atomicAdd(&hist[tl], 1u); });
+    const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off : nullptr;
+    slice_pairs(S, poff, rects, cam.TX, big, &nbig, [&](uint32_t r, int tl) {
+      if (!tdm || deps[r - (uint32_t)S.ia] < tdm[tl]) atomicAdd(&hist[tl], 1u);
+    });
     __syncthreads();
     uint32_t* row = mat + cam.mat_off + S.c * (int64_t)S.ntl;
     for (int t = threadIdx.x; t < S.ntl; t += 256)
@@ -369,12 +390,15 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
                                                      int64_t rows_total,
                                                      const uint32_t* __restrict__ counters,
                                                      const uint2* __restrict__ rect_s,
+                                                     const GRec* __restrict__ rec_s,
+                                                     const uint32_t* __restrict__ tile_dmax,
                                                      uint32_t* __restrict__ mat,
                                                      const uint32_t* __restrict__ tile_start,
                                                      int64_t key_cap, uint32_t* __restrict__ lists) {
   __shared__ uint32_t hist[HT];
   __shared__ int32_t poff[CHUNK + 1];
   __shared__ uint2 rects[CHUNK];
+  __shared__ uint32_t deps[CHUNK];
   __shared__ uint32_t big[CHUNK];
   __shared__ uint32_t nbig;
   const uint32_t nsl = counters[12];
@@ -382,12 +406,15 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
     Slice S;
     load_slice(cams, n_cams, vis_off, pair_off, slice_off, rows_total, sl, S, poff);
     const CamDev& cam = cams[S.cam];
-    for (int k = threadIdx.x; k < S.nitems; k += 256) rects[k] = rect_s[S.ia + k];
+    stage_ranks(S, rect_s, rec_s, tile_dmax, rects, deps);
     for (int t = threadIdx.x; t < S.ntl; t += 256) hist[t] = 0;
     if (threadIdx.x == 0) nbig = 0;
     __syncthreads();
-    slice_pairs(S, poff, rects, cam.TX, big, &nbig,
-                [&](uint32_t, int tl) { atomicAdd(&hist[tl], 1u); });
+    const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off : nullptr;
+    auto keep = [&](uint32_t r, int tl) { return !tdm || deps[r - (uint32_t)S.ia] < tdm[tl]; };
+    slice_pairs(S, poff, rects, cam.TX, big, &nbig, [&](uint32_t r, int tl) {
+      if (keep(r, tl)) atomicAdd(&hist[tl], 1u);
+    });
     __syncthreads();
     uint32_t* row = mat + cam.mat_off + S.c * (int64_t)S.ntl;
     for (int t = threadIdx.x; t < S.ntl; t += 256) {
@@ -397,6 +424,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
     if (threadIdx.x == 0) nbig = 0;
     __syncthreads();
     slice_pairs(S, poff, rects, cam.TX, big, &nbig, [&](uint32_t r, int tl) {
+      if (!keep(r, tl)) return;
       const uint32_t pos = atomicAdd(&hist[tl], 1u);
       if ((int64_t)pos < key_cap) lists[pos] = r;
     });
@@ -507,6 +535,18 @@ __global__ __launch_bounds__(256) void k_pair_total(const uint64_t* __restrict__
   counters[1] = K > (uint64_t)key_cap ? 1u : 0u;
 }
 
+// After culling: the lists hold counters[13] pairs (exact while the uncut
+// total K fits 32 bits, which every valid capacity implies); the capacity
+// check and the reported key count use it.
+__global__ __launch_bounds__(256) void k_kept_total(int64_t key_cap, uint32_t* __restrict__ counters) {
+  const uint64_t K = (uint64_t)counters[2] | ((uint64_t)counters[3] << 32);
+  if (K > 0xffffffffull) return;  // overflow already flagged by k_pair_total
+  const uint32_t kept = counters[13];
+  counters[2] = kept;
+  counters[3] = 0;
+  counters[1] = (int64_t)kept > key_cap ? 1u : 0u;
+}
+
 __global__ __launch_bounds__(256) void k_export_keys(const CamDev* __restrict__ cams, int n_cams,
                                                      int n_tiles,
                                                      const uint32_t* __restrict__ tile_start,
@@ -561,7 +601,9 @@ void launch_depth_sort(const SetDev& S, const Work& w, hipStream_t st) {
                      w.tiles_s, w.item_s, w.rank_of);
 }
 
-void launch_binning(const SetDev& S, const Work& w, int n_cams, hr_outputs* out, hipStream_t st) {
+void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, hr_outputs* out,
+                    hipStream_t st) {
+  const uint32_t* tdm = cull ? w.tile_dmax : nullptr;
   const int64_t M = (int64_t)S.n * S.n_cams;
   uint64_t* Ktot = reinterpret_cast<uint64_t*>(w.counters + 10);
   scan_u64(w.tiles_s, w.pair_off, M + 1, Ktot, w.scan_scratch, st);
@@ -573,26 +615,28 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, hr_outputs* out,
     if (S.max_tiles_cam <= 8192)
       hipLaunchKernelGGL(k_bin_count<8192>, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams,
                          w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s,
-                         w.mat);
+                         w.rec_s, tdm, w.mat);
     else
       hipLaunchKernelGGL(k_bin_count<MAX_TILES_PER_CAM>, dim3(BIN_GRID), dim3(256), 0, st, w.cams,
                          n_cams, w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters,
-                         w.rect_s, w.mat);
+                         w.rect_s, w.rec_s, tdm, w.mat);
   }
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
-  scan_u32(w.tile_total, w.tile_start, S.n_tiles, nullptr, w.scan_scratch, st);
+  scan_u32(w.tile_total, w.tile_start, S.n_tiles, w.counters + 13, w.scan_scratch, st);
+  hipLaunchKernelGGL(k_kept_total, dim3(1), dim3(1), 0, st, S.key_cap, w.counters);
   hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(256), 0, st, S.n_tiles, w.tile_total,
                      w.tile_order);
   if (w.chunk_rows > 0) {
     if (S.max_tiles_cam <= 8192)
       hipLaunchKernelGGL(k_bin_scatter<8192>, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams,
                          w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s,
-                         w.mat, w.tile_start, S.key_cap, w.lists);
+                         w.rec_s, tdm, w.mat, w.tile_start, S.key_cap, w.lists);
     else
       hipLaunchKernelGGL(k_bin_scatter<MAX_TILES_PER_CAM>, dim3(BIN_GRID), dim3(256), 0, st,
                          w.cams, n_cams, w.vis_off, w.pair_off, w.slice_off, w.chunk_rows,
-                         w.counters, w.rect_s, w.mat, w.tile_start, S.key_cap, w.lists);
+                         w.counters, w.rect_s, w.rec_s, tdm, w.mat, w.tile_start, S.key_cap,
+                         w.lists);
   }
   if (out && out->ranges)
     hipLaunchKernelGGL(k_ranges, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, S.n_tiles,

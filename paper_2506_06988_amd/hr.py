@@ -20,6 +20,7 @@ HR_OK, HR_ERR_INVALID_ARGUMENT, HR_ERR_CAPACITY, HR_ERR_HIP, HR_ERR_UNSUPPORTED,
 HR_FLAG_NO_SYNC = 1 << 0
 HR_FLAG_DETACH_MASK = 1 << 1
 HR_FLAG_EXPORT_KEYS = 1 << 2
+HR_FLAG_CULL_BEHIND_MESH = 1 << 3
 
 P = C.c_void_p
 

@@ -189,6 +189,22 @@ def wall_gaussians(rng, n, degree=3, log_scale_range=(-6.0, -3.0)) -> Gaussians:
     return make_gaussians(means, ls, q, op, sh, degree)
 
 
+def outside_gaussians(rng, n, degree=3, margin=1.5, log_scale_range=(-4.0, -2.0)) -> Gaussians:
+    """Gaussians in a shell up to `margin` outside the room box: what the
+    walls hide from every camera inside (mesh-depth culling drops them)."""
+    lo, hi = ROOM_MIN - margin, ROOM_MAX + margin
+    out = np.zeros((0, 3))
+    while out.shape[0] < n:
+        p = rng.uniform(lo, hi, size=(2 * n, 3))
+        inside = np.all((p > ROOM_MIN + 0.05) & (p < ROOM_MAX - 0.05), axis=1)
+        wall = np.any((p > ROOM_MIN - 0.05) & (p < ROOM_MIN + 0.05) | (p > ROOM_MAX - 0.05) & (p < ROOM_MAX + 0.05), axis=1)
+        out = np.concatenate([out, p[~inside & ~wall]])
+    means = out[:n]
+    ls = rng.uniform(log_scale_range[0], log_scale_range[1], size=(n, 3))
+    sh = _sh_coeffs(rng, n, degree, rng.uniform(0.0, 1.0, size=(n, 3)))
+    return make_gaussians(means, ls, _quats(rng, n), rng.standard_normal(n), sh, degree)
+
+
 def concat_gaussians(a: Gaussians, b: Gaussians) -> Gaussians:
     assert a.sh_degree == b.sh_degree
     return Gaussians(*(np.concatenate([x, y]) for x, y in

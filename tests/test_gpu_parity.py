@@ -310,3 +310,42 @@ def test_full_loss_kernel_matches_oracle(hr, mode):
         got = got.cpu().numpy()
         scale = max(np.abs(ref).max(), 1e-12)
         np.testing.assert_allclose(got, ref, atol=2e-4 * scale, rtol=1e-3)
+
+
+def test_mesh_depth_culling_matches_oracle(hr):
+    say("case: mesh-depth culling, room with Gaussians outside the walls, 2 cameras")
+    rng = np.random.default_rng(61)
+    room = scenes.small_room(61, n=3000, faces=2000, tex=32)
+    g = scenes.concat_gaussians(room.gaussians, scenes.outside_gaussians(rng, 3000))
+    sc = scenes.Scene("room_outside", g, room.mesh, [])
+    cams = [scenes.random_room_camera(rng, w, h) for (w, h) in ((96, 80), (70, 45))]
+    st = hr.default_settings(flags=hr.HR_FLAG_CULL_BEHIND_MESH)
+    r, f = gpu_render(hr, sc, cams=cams, export_keys=True, settings=st)
+    stats = f.stats_dict()
+    pc = oracle.default_params(flags=oracle.CULL_MESH)
+    ranges = f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    keys = f.keys.cpu().numpy().view(np.uint64)
+    vals = f.values.cpu().numpy().view(np.uint32)
+    key_base = tile_base = uncut = 0
+    for c, cam in enumerate(cams):
+        orc = oracle.render(g, sc.mesh, cam, params=pc)
+        check_view(f, cams, c, orc)
+        k, v, rg = oracle.keys(g, cam, params=pc, mesh=sc.mesh)
+        uncut += len(oracle.keys(g, cam)[0])
+        ntl = rg.shape[0]
+        np.testing.assert_array_equal(ranges[tile_base:tile_base + ntl] - key_base, rg)
+        K = len(k)
+        np.testing.assert_array_equal(keys[key_base:key_base + K] - (np.uint64(tile_base) << np.uint64(32)), k)
+        np.testing.assert_array_equal(vals[key_base:key_base + K], v)
+        key_base += K
+        tile_base += ntl
+    say(f"  kept pairs {key_base} of {uncut}")
+    assert stats["n_keys"] == key_base and key_base < 0.9 * uncut
+    # a capacity between the kept and the uncut count is enough
+    cap = (key_base + uncut) // 2
+    r2, f2 = gpu_render(hr, sc, cams=cams, settings=st, key_capacity=cap)
+    assert r2.key_capacity == cap  # no retry with a larger capacity was needed
+    assert torch.equal(f2.image, f.image) and f2.stats_dict()["n_keys"] == key_base
+    # and the images are those of the uncut lists
+    r3, f3 = gpu_render(hr, sc, cams=cams)
+    assert torch.equal(f3.image, f.image) and torch.equal(f3.final_T, f.final_T)

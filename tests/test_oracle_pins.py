@@ -721,3 +721,57 @@ def test_lambda_t_schedule_boundaries():
     assert oracle.lambda_t_schedule(14999) == 0.1
     assert oracle.lambda_t_schedule(15000) == 0.0
     assert oracle.lambda_t_schedule(29999) == 0.0
+
+
+# ------------------------------------------------- mesh-depth culling --
+def _cull_scene(seed):
+    rng = np.random.default_rng(seed)
+    n = 80
+    means = np.column_stack([rng.uniform(-1.2, 1.2, n), rng.uniform(-0.9, 0.9, n), rng.uniform(1.5, 3.2, n)])
+    g = scenes.make_gaussians(means, rng.uniform(-3.0, -1.8, (n, 3)), rng.standard_normal((n, 4)),
+                              rng.normal(0, 1, n), ((rng.uniform(0, 1, (n, 1, 3)) - 0.5) / scenes.Y00), 0)
+    # a tilted quad that covers the whole view, so every tile is covered
+    mesh = scenes.quad_mesh(rng, z=2.6, half=3.0, tex_size=8)
+    mesh.verts[:, 2] += 0.2 * mesh.verts[:, 0]
+    cam = scenes.Camera(64, 48, 40.0, 40.0, 32.0, 24.0, np.eye(3), np.zeros(3))
+    return g, mesh, cam
+
+
+def test_mesh_depth_culling_keeps_the_image_and_drops_only_stopped_pairs():
+    g, mesh, cam = _cull_scene(51)
+    base = oracle.render(g, mesh, cam)
+    pc = oracle.default_params(flags=oracle.CULL_MESH)
+    cut = oracle.render(g, mesh, cam, params=pc)
+    assert (base["tri_id"] >= 0).all()
+    for k in ("image", "final_T", "n_contrib", "n_blended", "tri_id", "mesh_rgb"):
+        np.testing.assert_array_equal(cut[k], base[k])
+    dp = base["n_processed"] - cut["n_processed"]
+    assert dp.min() >= 0 and dp.max() <= 1 and dp.sum() > 0
+    # the key sets: the uncut keys minus the pairs whose depth is not below the
+    # tile's largest mesh depth (from the rendered depth map)
+    k0, v0, _ = oracle.keys(g, cam)
+    k1, v1, r1 = oracle.keys(g, cam, params=pc, mesh=mesh)
+    TX = 4
+    dmax = base["mesh_depth"].reshape(3, 16, TX, 16).max(axis=(1, 3)).reshape(-1).astype(np.float32)
+    tile = (k0 >> np.uint64(32)).astype(np.int64)
+    depth = (k0 & np.uint64(0xffffffff)).astype(np.uint32).view(np.float32)
+    keep = depth < dmax[tile]
+    assert 0 < (~keep).sum() < keep.size
+    np.testing.assert_array_equal(k1, k0[keep])
+    np.testing.assert_array_equal(v1, v0[keep])
+    counts = np.bincount(tile[keep], minlength=12)
+    np.testing.assert_array_equal(r1[:, 1] - r1[:, 0], counts)
+
+
+def test_mesh_depth_culling_leaves_tiles_with_an_uncovered_pixel():
+    g, _, cam = _cull_scene(52)
+    rng = np.random.default_rng(3)
+    small = scenes.quad_mesh(rng, z=2.6, half=0.5, tex_size=8)  # covers only part of the view
+    pc = oracle.default_params(flags=oracle.CULL_MESH)
+    base = oracle.render(g, small, cam)
+    cut = oracle.render(g, small, cam, params=pc)
+    for k in ("image", "final_T", "n_contrib", "n_blended", "n_processed"):
+        np.testing.assert_array_equal(cut[k], base[k])
+    k0, _, _ = oracle.keys(g, cam)
+    k1, _, _ = oracle.keys(g, cam, params=pc, mesh=small)
+    np.testing.assert_array_equal(k0, k1)
