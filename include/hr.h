@@ -237,6 +237,9 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
  * lr is per group; when row > 0, elements whose index modulo row is below
  * head use lr_head instead (the SH array: the degree-0 coefficients, 3 floats
  * of every row of 3(d+1)^2, take a larger rate than the higher orders).
+ * The betas come in double so that 1-b1, 1-b2 and the bias corrections are
+ * formed before rounding to FP32 (1-0.999 rounded from an FP32 0.999 is off
+ * by 1.3e-5 relative).
  * `groups` is host memory (at most HR_ADAM_MAX_GROUPS); every array is device
  * memory of n floats, updated in place; grad is only read. Groups must not
  * overlap. Errors: HR_ERR_INVALID_ARGUMENT (null array with n > 0, n < 0,
@@ -253,8 +256,8 @@ typedef struct {
   int32_t head;
   int32_t row;
 } hr_adam_group;
-hr_status hr_adam_step(const hr_adam_group* groups, int32_t n_groups, float beta1, float beta2,
-                       float eps, int32_t step, void* stream);
+hr_status hr_adam_step(const hr_adam_group* groups, int32_t n_groups, double beta1, double beta2,
+                       double eps, int32_t step, void* stream);
 
 /* Photometric loss of Eq. 3 with the transmittance-aware term of Sec. 3.4,
  * over n_images images packed like the renderer's outputs (image i is

@@ -423,12 +423,12 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
   return hip_check("loss launch");
 }
 
-hr_status hr_adam_step(const hr_adam_group* groups, int32_t n_groups, float beta1, float beta2,
-                       float eps, int32_t step, void* stream) {
+hr_status hr_adam_step(const hr_adam_group* groups, int32_t n_groups, double beta1, double beta2,
+                       double eps, int32_t step, void* stream) {
   if (!groups || n_groups < 1 || n_groups > HR_ADAM_MAX_GROUPS)
     return fail(HR_ERR_INVALID_ARGUMENT, "need 1..8 Adam groups");
   if (step < 1) return fail(HR_ERR_INVALID_ARGUMENT, "step counts from 1");
-  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0))
     return fail(HR_ERR_INVALID_ARGUMENT, "need 0 <= beta < 1 and eps > 0");
   for (int k = 0; k < n_groups; ++k) {
     const hr_adam_group& G = groups[k];

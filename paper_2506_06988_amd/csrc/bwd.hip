@@ -367,7 +367,7 @@ struct AdamArgs {
   hr_adam_group g[HR_ADAM_MAX_GROUPS];
   int64_t start[HR_ADAM_MAX_GROUPS + 1];
   int32_t n_groups;
-  float b1, b2, eps, c1, c2;  // c1 = 1 - b1^step, c2 = 1 - b2^step
+  float b1, b2, omb1, omb2, eps, c1, c2;  // omb = 1 - b; c1 = 1 - b1^step, c2 = 1 - b2^step
 };
 
 __global__ __launch_bounds__(256) void k_adam(AdamArgs A) {
@@ -380,8 +380,8 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A) {
     const hr_adam_group& G = A.g[k];
     const float lr = (G.row > 0 && (int)((uint64_t)j % (uint32_t)G.row) < G.head) ? G.lr_head : G.lr;
     const float gr = G.grad[j];
-    const float m = A.b1 * G.m[j] + (1.f - A.b1) * gr;
-    const float v = A.b2 * G.v[j] + (1.f - A.b2) * gr * gr;
+    const float m = A.b1 * G.m[j] + A.omb1 * gr;
+    const float v = A.b2 * G.v[j] + A.omb2 * gr * gr;
     G.m[j] = m;
     G.v[j] = v;
     G.param[j] -= lr * (m / A.c1) / (sqrtf(v / A.c2) + A.eps);
@@ -390,15 +390,17 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A) {
 
 }  // namespace
 
-void launch_adam(const hr_adam_group* groups, int n_groups, float b1, float b2, float eps,
+void launch_adam(const hr_adam_group* groups, int n_groups, double b1, double b2, double eps,
                  int step, hipStream_t st) {
   AdamArgs A;
   A.n_groups = n_groups;
-  A.b1 = b1;
-  A.b2 = b2;
-  A.eps = eps;
-  A.c1 = (float)(1.0 - std::pow((double)b1, step));
-  A.c2 = (float)(1.0 - std::pow((double)b2, step));
+  A.b1 = (float)b1;
+  A.b2 = (float)b2;
+  A.omb1 = (float)(1.0 - b1);
+  A.omb2 = (float)(1.0 - b2);
+  A.eps = (float)eps;
+  A.c1 = (float)(1.0 - std::pow(b1, step));
+  A.c2 = (float)(1.0 - std::pow(b2, step));
   int64_t acc = 0;
   for (int k = 0; k < n_groups; ++k) {
     A.g[k] = groups[k];

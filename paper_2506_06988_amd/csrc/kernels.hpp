@@ -81,7 +81,7 @@ void launch_loss(const float* image, const float* T, const float* mesh_rgb, cons
                  float* loss, float* g_image, float* g_T, float* g_mesh, void* scratch,
                  hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
-void launch_adam(const hr_adam_group* groups, int n_groups, float b1, float b2, float eps,
+void launch_adam(const hr_adam_group* groups, int n_groups, double b1, double b2, double eps,
                  int step, hipStream_t st);
 size_t full_loss_scratch_bytes(int64_t n_pix, int64_t n_tiles, int32_t n_imgs);
 void launch_full_loss(const float* image, const float* T, const float* mesh, const int32_t* tri,

@@ -99,7 +99,7 @@ def load(path: str = LIB_PATH):
     L.hr_hybrid_loss.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_uint32, P, P,
                                  P, P, P, P]
     L.hr_adam_step.restype = C.c_int
-    L.hr_adam_step.argtypes = [P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_int32, P]
+    L.hr_adam_step.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, P]
     L.hr_full_loss_scratch_bytes.restype = C.c_size_t
     L.hr_full_loss_scratch_bytes.argtypes = [P, C.c_int32]
     L.hr_full_loss.restype = C.c_int
