@@ -29,9 +29,14 @@ METRIC = ("1080p hybrid frames/s and batched fwd+bwd views/s; "
           "Gaussian-pixel blends/s vs VALU peak")
 # VALU lane-operation rate of the MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU lane-operations the blend spends per examined (Gaussian, pixel) pair:
-# counted from the kernel's inner loop (see the blend section of the design notes)
-BLEND_OPS_PER_PAIR = 22
+# Algorithmic VALU lane-operations of the blend (an FMA is one operation, the
+# exponential one): per examined (Gaussian, pixel) pair, the offset (2), the
+# conic quadratic form (5), exp and the opacity product (2), the alpha and
+# depth tests (2); per blended pair, the alpha clamp (1), alpha*T (1), the
+# colour update (3), the transmittance update (1) and its test (1). Staging,
+# addressing and loop control are not counted.
+BLEND_OPS_EXAMINED = 11
+BLEND_OPS_BLENDED = 7
 
 
 def log(*a):
@@ -46,7 +51,26 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gaussian-only", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for counter runs: view 0 of the headline workload, 3 blend launches "
+                         "and 3 copies of a 256 MiB buffer (the scale of the byte counters)")
     return ap.parse_args()
+
+
+def pmc_probe(torch, hr, scenes, dev):
+    sc = scenes.config5("hybrid")
+    g, m = hr.to_device(sc.gaussians, sc.mesh, device=dev)
+    r = hr.Renderer(g, m, [sc.cameras[0]])
+    frame = r.render_hybrid(sync_check=True)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        r.blend_forward(frame)
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"pmc probe done: stats {frame.stats_dict()}, copy bytes {src.numel() * 4}")
 
 
 def timed_frames(torch, r, frame, views, steps, warmup):
@@ -84,6 +108,9 @@ def main():
     hr.load()
     assert torch.cuda.is_available()
     dev = "cuda:0"
+    if args.pmc_probe:
+        pmc_probe(torch, hr, scenes, dev)
+        return
 
     # ----------------------------------------------------- headline: 1080p
     t = time.perf_counter()
@@ -124,7 +151,8 @@ def main():
     blend_s = e0.elapsed_time(e1) / 1e3 / nb
     pairs = stats["n_processed"]
     blends_per_s = pairs / blend_s
-    achieved = pairs * BLEND_OPS_PER_PAIR / blend_s / 1e12
+    ops = pairs * BLEND_OPS_EXAMINED + stats["n_blended"] * BLEND_OPS_BLENDED
+    achieved = ops / blend_s / 1e12
     log(f"blend kernel: {blend_s * 1e3:.3f} ms, {pairs} pairs examined, {stats['n_blended']} blended, "
         f"{blends_per_s:.3e} pairs/s, {achieved:.2f} TOP/s")
     hyb_stats = stats
@@ -153,7 +181,8 @@ def main():
         "stats_view0": hyb_stats,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                     "kernel": "k_blend_fwd", "ops_per_pair": BLEND_OPS_PER_PAIR},
+                     "kernel": "k_blend_fwd", "ops_per_examined": BLEND_OPS_EXAMINED,
+                     "ops_per_blended": BLEND_OPS_BLENDED, "ops_per_launch": ops},
     }
     del sc
 

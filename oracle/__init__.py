@@ -28,6 +28,7 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FP64_RECORDS = 1
+MIP_2D = 4  # Mip-Splatting 2D filter: low_pass is the pixel filter, opacity compensated
 CULL_MESH = 2  # drop (Gaussian, tile) pairs at or behind the tile's largest mesh depth
 
 
@@ -64,7 +65,7 @@ class Scene_(C.Structure):
                 ("n_verts", C.c_int32), ("n_faces", C.c_int32), ("n_tex", C.c_int32),
                 ("tex_h", C.c_int32), ("tex_w", C.c_int32),
                 ("verts", C.c_void_p), ("faces", C.c_void_p), ("uvs", C.c_void_p),
-                ("face_tex", C.c_void_p), ("tex", C.c_void_p)]
+                ("face_tex", C.c_void_p), ("tex", C.c_void_p), ("filter3d", C.c_void_p)]
 
 
 class Camera_(C.Structure):
@@ -110,6 +111,8 @@ def _setup(L):
     L.or_sh_basis.restype = None
     L.or_quat_to_rot.argtypes = [P, P]
     L.or_quat_to_rot.restype = None
+    L.or_mip_filter3d.argtypes = [P, P, C.c_int, P, C.c_double, P]
+    L.or_mip_filter3d.restype = C.c_int
 
 
 def _p(a):
@@ -159,9 +162,10 @@ def _camera(cam):
 class _SceneArrays:
     """FP64 copies of the FP32 scene arrays, kept alive for the C call."""
 
-    def __init__(self, g, mesh, overrides=None):
+    def __init__(self, g, mesh, overrides=None, filter3d=None):
         o = overrides or {}
         f64 = lambda a: np.ascontiguousarray(a, np.float64)
+        self.filter3d = None if filter3d is None else f64(filter3d)
         self.means = f64(o.get("means", g.means))
         self.log_scales = f64(o.get("log_scales", g.log_scales))
         self.quats = f64(o.get("quats", g.quats))
@@ -172,6 +176,9 @@ class _SceneArrays:
         s.sh_degree = g.sh_degree
         s.means, s.log_scales, s.quats = _p(self.means), _p(self.log_scales), _p(self.quats)
         s.opacity_logits, s.sh = _p(self.opacity_logits), _p(self.sh)
+        if self.filter3d is not None:
+            assert self.filter3d.shape == (s.n,)
+            s.filter3d = _p(self.filter3d)
         if mesh is not None and mesh.faces.shape[0] > 0:
             self.verts = f64(mesh.verts)
             self.faces = np.ascontiguousarray(mesh.faces, np.int32)
@@ -190,9 +197,9 @@ class _SceneArrays:
         self.s = s
 
 
-def project(gaussians, cam, params=None):
+def project(gaussians, cam, params=None, filter3d=None):
     P = _params(params or default_params())
-    sa = _SceneArrays(gaussians, None)
+    sa = _SceneArrays(gaussians, None, filter3d=filter3d)
     n = gaussians.n
     out = dict(mean2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), cov2d=np.zeros((n, 3)),
                opacity=np.zeros(n), rgb=np.zeros((n, 3)), depth=np.zeros(n),
@@ -206,10 +213,10 @@ def project(gaussians, cam, params=None):
     return out
 
 
-def keys(gaussians, cam, params=None, mesh=None):
+def keys(gaussians, cam, params=None, mesh=None, filter3d=None):
     """Sorted tile keys; the mesh matters only with the CULL_MESH flag."""
     P = _params(params or default_params())
-    sa = _SceneArrays(gaussians, mesh)
+    sa = _SceneArrays(gaussians, mesh, filter3d=filter3d)
     c = _camera(cam)
     K = lib().or_keys(C.byref(sa.s), C.byref(c), C.byref(P), None, None, None, 0)
     assert K >= 0
@@ -222,10 +229,10 @@ def keys(gaussians, cam, params=None, mesh=None):
     return k, v, r
 
 
-def render(gaussians, mesh, cam, params=None, window=None, overrides=None):
+def render(gaussians, mesh, cam, params=None, window=None, overrides=None, filter3d=None):
     """Forward render; `window` = (x0, y0, x1, y1) restricts the pixels computed."""
     P = _params(params or default_params())
-    sa = _SceneArrays(gaussians, mesh, overrides)
+    sa = _SceneArrays(gaussians, mesh, overrides, filter3d)
     x0, y0, x1, y1 = window or (0, 0, cam.width, cam.height)
     h, w = y1 - y0, x1 - x0
     out = dict(image=np.zeros((3, h, w)), final_T=np.zeros((h, w)),
@@ -242,14 +249,14 @@ def render(gaussians, mesh, cam, params=None, window=None, overrides=None):
 
 
 def backward(gaussians, mesh, cam, g_image, g_T=None, g_mesh_rgb=None, params=None, window=None,
-             overrides=None, want_tex=True):
+             overrides=None, want_tex=True, filter3d=None):
     """Gradient of sum(g_image*I_h) + sum(g_T*T) + sum(g_mesh_rgb*I_m) over the window.
 
     Besides the parameter gradients, `mean2d` [n,2] is the gradient with
     respect to each Gaussian's projected mean (u, v) in pixels: the quantity
     whose norm 3DGS densification accumulates."""
     P = _params(params or default_params())
-    sa = _SceneArrays(gaussians, mesh, overrides)
+    sa = _SceneArrays(gaussians, mesh, overrides, filter3d)
     x0, y0, x1, y1 = window or (0, 0, cam.width, cam.height)
     n = gaussians.n
     K = (gaussians.sh_degree + 1) ** 2
@@ -392,3 +399,14 @@ def lambda_t_schedule(i, lam=0.1, warmup=3000, densify_until=15000):
     """Weight of L_t at iteration i (Alg. 1): the full loss strictly after the
     warm-up and strictly before the end of densification, L_c alone otherwise."""
     return lam if warmup < i < densify_until else 0.0
+
+
+def mip_filter3d(gaussians, cams, s=0.2, params=None):
+    """Mip-Splatting 3D smoothing variance per Gaussian (s over the squared
+    highest sampling rate fx/z among the cameras that see it)."""
+    P = _params(params or default_params())
+    sa = _SceneArrays(gaussians, None)
+    arr = (Camera_ * len(cams))(*[_camera(c) for c in cams])
+    out = np.zeros(gaussians.n)
+    assert lib().or_mip_filter3d(C.byref(sa.s), arr, len(cams), C.byref(P), float(s), _p(out)) == 0
+    return out

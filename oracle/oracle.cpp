@@ -46,6 +46,7 @@ typedef struct {
   const double* uvs;       // [F,3,2]
   const int32_t* face_tex; // [F]
   const float* tex;        // [n_tex,tex_h,tex_w,3]
+  const double* filter3d;  // [n] Mip-Splatting 3D smoothing variance, or null
 } or_scene;
 
 typedef struct {
@@ -62,7 +63,7 @@ typedef struct {
   double amb_alpha, amb_t;  // relative slack under which a decision is tagged
 } or_params;
 
-enum { OR_FP64_RECORDS = 1, OR_CULL_MESH = 2 };
+enum { OR_FP64_RECORDS = 1, OR_CULL_MESH = 2, OR_MIP_2D = 4 };
 
 // per-Gaussian record export
 typedef struct {
@@ -106,6 +107,7 @@ typedef struct {
 namespace {
 
 constexpr double PI = 3.14159265358979323846;
+constexpr double MIP2D_FLOOR = 2.5e-5;  // lower bound of the 2D filter's determinant ratio
 
 struct Rec {
   bool vis = false, amb = false;
@@ -122,6 +124,10 @@ struct Rec {
   double zf;  // fp32(z) as double
   // values the blend uses (FP32-rounded unless OR_FP64_RECORDS)
   double bu, bv, bcon[3], bop, brgb[3];
+  // Mip-Splatting: 3D smoothing variance f3 and its opacity factor c3; 2D
+  // filter opacity factor c2 (c2lo: at its floor); opr = op c3 c2
+  double f3 = 0.0, c3 = 1.0, c2 = 1.0, opr;
+  bool c2lo = false;
   // backward intermediates
   double s[3], qn[4], qnorm, Rq[9], Sc[9], J[6];
   bool clx, cly;
@@ -258,6 +264,16 @@ Rec project(const or_scene& sc, const or_camera& cam, const or_params& p, int g)
       for (int k = 0; k < 3; ++k) a += M[3 * i + k] * M[3 * j + k];
       Sig[3 * i + j] = a;
     }
+  // Mip-Splatting 3D smoothing: Sigma + f3 I, opacity scaled by
+  // sqrt(det Sigma / det(Sigma + f3 I)) = prod_i s_i / sqrt(s_i^2 + f3)
+  if (sc.filter3d) {
+    r.f3 = sc.filter3d[g];
+    if (!(std::isfinite(r.f3) && r.f3 >= 0.0)) return r;
+    for (int i = 0; i < 3; ++i) {
+      Sig[4 * i] += r.f3;
+      r.c3 *= r.s[i] / std::sqrt(r.s[i] * r.s[i] + r.f3);
+    }
+  }
   double WS[9];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
@@ -299,6 +315,16 @@ Rec project(const or_scene& sc, const or_camera& cam, const or_params& p, int g)
   r.cov[2] = C2[3] + p.low_pass;
   const double det = r.cov[0] * r.cov[2] - r.cov[1] * r.cov[1];
   if (!(det > 0)) return r;
+  // Mip-Splatting 2D filter: the low-pass variance is the pixel filter, and the
+  // opacity is scaled by sqrt(det(Sigma') / det(Sigma' + low_pass I)), the ratio
+  // floored at MIP2D_FLOOR
+  if (p.flags & OR_MIP_2D) {
+    const double d0 = (r.cov[0] - p.low_pass) * (r.cov[2] - p.low_pass) - r.cov[1] * r.cov[1];
+    const double ratio = d0 / det;
+    r.c2lo = !(ratio > MIP2D_FLOOR);
+    r.c2 = std::sqrt(r.c2lo ? MIP2D_FLOOR : ratio);
+  }
+  r.opr = r.op * r.c3 * r.c2;
   r.con[0] = r.cov[2] / det;
   r.con[1] = -r.cov[1] / det;
   r.con[2] = r.cov[0] / det;
@@ -348,10 +374,10 @@ Rec project(const or_scene& sc, const or_camera& cam, const or_params& p, int g)
   if (f32_boundary(z)) r.amb = true;
   r.vis = true;
   if (p.flags & OR_FP64_RECORDS) {
-    r.bu = r.u; r.bv = r.v; r.bop = r.op;
+    r.bu = r.u; r.bv = r.v; r.bop = r.opr;
     for (int i = 0; i < 3; ++i) { r.bcon[i] = r.con[i]; r.brgb[i] = r.rgb[i]; }
   } else {
-    r.bu = r32(r.u); r.bv = r32(r.v); r.bop = r32(r.op);
+    r.bu = r32(r.u); r.bv = r32(r.v); r.bop = r32(r.opr);
     for (int i = 0; i < 3; ++i) { r.bcon[i] = r32(r.con[i]); r.brgb[i] = r32(r.rgb[i]); }
   }
   return r;
@@ -698,7 +724,7 @@ int or_project(const or_scene* sc, const or_camera* cam, const or_params* p, or_
       if (o->cov2d) o->cov2d[3 * g + i] = r.cov[i];
       if (o->rgb) o->rgb[3 * g + i] = r.rgb[i];
     }
-    if (o->opacity) o->opacity[g] = r.op;
+    if (o->opacity) o->opacity[g] = r.opr;  // the record's opacity (Mip factors included)
     if (o->depth) o->depth[g] = r.pc[2];
     if (o->depth_bits) o->depth_bits[g] = r.dbits;
     if (o->rect) {
@@ -706,6 +732,42 @@ int or_project(const or_scene* sc, const or_camera* cam, const or_params* p, or_
       o->rect[4 * g + 2] = r.y0; o->rect[4 * g + 3] = r.y1;
     }
   }
+  return 0;
+}
+
+// Mip-Splatting 3D smoothing variance of every Gaussian: s / nu^2, with nu
+// the highest sampling rate fx / z over the cameras that see the centre in
+// front of the near plane inside the view widened by 15% on each side.
+// Gaussians no camera sees take the largest variance of the seen ones (0
+// when none is seen).
+int or_mip_filter3d(const or_scene* sc, const or_camera* cams, int n_cams, const or_params* p,
+                    double s, double* out) {
+  if (!sc || !cams || !p || !out || n_cams < 1) return 1;
+  double vmax = 0.0;
+  std::vector<char> seen(sc->n, 0);
+  for (int g = 0; g < sc->n; ++g) {
+    const double* mu = sc->means + 3 * (size_t)g;
+    double nu = 0.0;
+    for (int c = 0; c < n_cams; ++c) {
+      const or_camera& cam = cams[c];
+      double pc[3];
+      for (int i = 0; i < 3; ++i)
+        pc[i] = cam.R[3 * i] * mu[0] + cam.R[3 * i + 1] * mu[1] + cam.R[3 * i + 2] * mu[2] + cam.t[i];
+      if (!(pc[2] > p->near_gs)) continue;
+      const double u = cam.fx * pc[0] / pc[2] + cam.cx, v = cam.fy * pc[1] / pc[2] + cam.cy;
+      if (u < -0.15 * cam.width || u > 1.15 * cam.width || v < -0.15 * cam.height ||
+          v > 1.15 * cam.height)
+        continue;
+      nu = std::max(nu, cam.fx / pc[2]);
+    }
+    if (nu > 0.0) {
+      seen[g] = 1;
+      out[g] = s / (nu * nu);
+      vmax = std::max(vmax, out[g]);
+    }
+  }
+  for (int g = 0; g < sc->n; ++g)
+    if (!seen[g]) out[g] = vmax;
   return 0;
 }
 
@@ -905,8 +967,24 @@ int or_backward(const or_scene* sc, const or_camera* cam, const or_params* p, in
     if (!any) continue;
     const Rec& r = f.recs[g];
     double gpc[3] = {0, 0, 0}, gmu[3] = {0, 0, 0};
-    // opacity
-    if (o->opacity_logits) o->opacity_logits[g] += gr[5] * r.op * (1.0 - r.op);
+    // opacity: the record holds op c3 c2
+    if (o->opacity_logits) o->opacity_logits[g] += gr[5] * r.c3 * r.c2 * r.op * (1.0 - r.op);
+    // c3 = prod s_i / sqrt(s_i^2 + f3):  d c3 / d log s_i = c3 f3 / (s_i^2 + f3)
+    double gls_mip[3] = {0, 0, 0};
+    if (r.f3 > 0.0)
+      for (int i = 0; i < 3; ++i)
+        gls_mip[i] = gr[5] * r.op * r.c2 * r.c3 * r.f3 / (r.s[i] * r.s[i] + r.f3);
+    // c2 = sqrt(D0 / D1), D1 = det(cov), D0 = det(cov - low_pass I):
+    // d c2 = c2 / 2 (dD0 / D0 - dD1 / D1), as a gradient on (a, b, c) of cov
+    double gcov_mip[3] = {0, 0, 0};
+    if ((p->flags & OR_MIP_2D) && !r.c2lo) {
+      const double a = r.cov[0], b = r.cov[1], c = r.cov[2], k = p->low_pass;
+      const double D1 = a * c - b * b, D0 = (a - k) * (c - k) - b * b;
+      const double gc2 = gr[5] * r.op * r.c3 * 0.5 * r.c2;
+      gcov_mip[0] = gc2 * ((c - k) / D0 - c / D1);
+      gcov_mip[1] = gc2 * (-2.0 * b / D0 + 2.0 * b / D1);
+      gcov_mip[2] = gc2 * ((a - k) / D0 - a / D1);
+    }
     // colour
     {
       double Y[16], GY[16][3];
@@ -932,6 +1010,11 @@ int or_backward(const or_scene* sc, const or_camera* cam, const or_params* p, in
       for (int c = 0; c < 2; ++c) QG[2 * a + c] = Q[2 * a] * Gm[c] + Q[2 * a + 1] * Gm[2 + c];
     for (int a = 0; a < 2; ++a)
       for (int c = 0; c < 2; ++c) H[2 * a + c] = -(QG[2 * a] * Q[c] + QG[2 * a + 1] * Q[2 + c]);
+    // the off-diagonal b of cov sits in two entries of the symmetric matrix
+    H[0] += gcov_mip[0];
+    H[1] += 0.5 * gcov_mip[1];
+    H[2] += 0.5 * gcov_mip[1];
+    H[3] += gcov_mip[2];
     // Sigma' = J Sc J^T + lp I:  dSc = J^T H J,  dJ = 2 H J Sc
     double gSc[9], HJ[6], gJ[6];
     for (int a = 0; a < 2; ++a)
@@ -999,7 +1082,7 @@ int or_backward(const or_scene* sc, const or_camera* cam, const or_params* p, in
         gs += gM[3 * a + c] * r.Rq[3 * a + c];
         gR[3 * a + c] = gM[3 * a + c] * r.s[c];
       }
-      if (o->log_scales) o->log_scales[3 * g + c] += gs * r.s[c];
+      if (o->log_scales) o->log_scales[3 * g + c] += gs * r.s[c] + gls_mip[c];
     }
     const double w = r.qn[0], qx = r.qn[1], qy = r.qn[2], qz = r.qn[3];
     double gq[4];

@@ -63,7 +63,9 @@ def test_adam_kernel_matches_oracle(hr):
             top = max(lr, lr_head or 0)
             tol = 4 * np.spacing(np.abs(h[0]).astype(np.float32)).astype(np.float64) + 1e-5 * top
             assert (np.abs(p - h[0]) <= tol).all(), (n, step, np.abs(p - h[0]).max())
-            np.testing.assert_allclose(d[2].cpu().numpy(), h[1], rtol=1e-5, atol=1e-9)
+            # m = b1 m + (1 - b1) g can cancel: FP32 rounding of the terms bounds its error
+            np.testing.assert_allclose(d[2].cpu().numpy(), h[1], rtol=1e-5,
+                                       atol=1e-6 * np.abs(h[1]).max())
             np.testing.assert_allclose(d[3].cpu().numpy(), h[2], rtol=1e-5, atol=1e-12)
     say("  3 steps within FP32 rounding of the oracle")
     # argument checks happen on the host
@@ -78,7 +80,12 @@ def test_adam_kernel_matches_oracle(hr):
 
 def test_densification_statistics_match_oracle(hr):
     say("case: |dL/dmean2D| and visibility counts over 2 cameras")
-    sc = tiny(111, n=40)
+    sc = tiny(111, n=38)
+    # plus one Gaussian in front of the near plane and one outside both views
+    k = sc.gaussians.sh.shape[1]
+    extra = scenes.make_gaussians([[0.0, 0.0, 0.1], [3.0, 0.0, 2.0]], np.full((2, 3), -2.5),
+                                  [[1, 0, 0, 0]] * 2, [1.0, 1.0], np.full((2, k, 3), 0.1), 3)
+    sc = scenes.Scene("tiny111x", scenes.concat_gaussians(sc.gaussians, extra), sc.mesh, sc.cameras)
     cams = [sc.cameras[0], side_camera(40, 36, 0.2)]
     g, m = hr.to_device(sc.gaussians, sc.mesh)
     r = hr.Renderer(g, m, cams)
@@ -106,7 +113,7 @@ def test_densification_statistics_match_oracle(hr):
     cnt = grads["mean2d_count"].cpu().numpy()
     nrm = grads["mean2d_norm"].cpu().numpy().astype(np.float64)
     np.testing.assert_array_equal(cnt, 2 * ref_count)
-    assert ref_count.min() < 2 <= ref_count.max() and np.count_nonzero(ref_norm) > 10
+    assert ref_count[-2:].max() == 0 and ref_count.max() == 2 and np.count_nonzero(ref_norm) > 10
     rel = np.linalg.norm(nrm - 2 * ref_norm) / np.linalg.norm(2 * ref_norm)
     say(f"  counts exact; norm rel err {rel:.2e}")
     assert rel <= 1e-3

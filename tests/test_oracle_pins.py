@@ -515,19 +515,22 @@ def tiny_scene(seed, n=12, deg=3, with_mesh=True):
 
 @pytest.mark.parametrize("seed", [21, 22])
 def test_oracle_gradient_matches_finite_differences(seed):
+    _fd_check(seed, oracle.default_params(flags=oracle.FP64_RECORDS), None)
+
+
+def _fd_check(seed, pr64, filter3d):
     g, mesh, cam = tiny_scene(seed)
     rng = np.random.default_rng(seed + 1)
-    pr64 = oracle.default_params(flags=oracle.FP64_RECORDS)
     gi = rng.normal(size=(3, 32, 32))
     gt = rng.normal(size=(32, 32))
     gm = rng.normal(size=(3, 32, 32))
 
     def F(over):
-        o = oracle.render(g, mesh, cam, params=pr64, overrides=over)
+        o = oracle.render(g, mesh, cam, params=pr64, overrides=over, filter3d=filter3d)
         return (np.sum(gi * o["image"]) + np.sum(gt * o["final_T"]) + np.sum(gm * o["mesh_rgb"]),
                 o["trace"])
 
-    an = oracle.backward(g, mesh, cam, gi, gt, gm, params=pr64)
+    an = oracle.backward(g, mesh, cam, gi, gt, gm, params=pr64, filter3d=filter3d)
     base = dict(means=g.means.astype(np.float64), log_scales=g.log_scales.astype(np.float64),
                 quats=g.quats.astype(np.float64), opacity_logits=g.opacity_logits.astype(np.float64),
                 sh=g.sh.astype(np.float64))
@@ -775,3 +778,69 @@ def test_mesh_depth_culling_leaves_tiles_with_an_uncovered_pixel():
     k0, _, _ = oracle.keys(g, cam)
     k1, _, _ = oracle.keys(g, cam, params=pc, mesh=small)
     np.testing.assert_array_equal(k0, k1)
+
+
+
+# ------------------------------------------- Mip-Splatting filters (host method) --
+def test_mip_filters_on_a_centred_isotropic_gaussian():
+    # 3D smoothing adds f3 to every variance and scales the opacity by
+    # (s^2 / (s^2 + f3))^(3/2); the 2D filter keeps low_pass as the pixel
+    # filter and scales the opacity by sqrt(det / det_filtered) = v / (v + k)
+    cam = one_cam()
+    k = F32(0.1)
+    pm = oracle.default_params(low_pass=0.1, flags=oracle.MIP_2D)
+    for z, ls, f3 in ((2.0, -3.0, 2e-3), (3.5, -2.2, 1e-2), (5.0, -4.0, 0.0)):
+        g = gauss([[0, 0, z]], log_scales=[[ls] * 3], logits=[0.7])
+        pr = oracle.project(g, cam, params=pm, filter3d=np.array([f3]))
+        s2 = math.exp(float(np.float32(ls))) ** 2
+        v = (64.0 / z) ** 2 * (s2 + f3)
+        np.testing.assert_allclose(pr["cov2d"][0], [v + k, 0.0, v + k], rtol=1e-13, atol=1e-15)
+        op = 1 / (1 + math.exp(-float(np.float32(0.7))))
+        want = op * (s2 / (s2 + f3)) ** 1.5 * v / (v + k)
+        np.testing.assert_allclose(pr["opacity"][0], want, rtol=1e-13)
+
+
+def test_mip_2d_filter_preserves_the_unfiltered_mass():
+    # the compensated opacity makes the filtered footprint carry the mass of
+    # the unfiltered one: sum over pixels of alpha = 2 pi o sqrt(det Sigma'_0),
+    # less the tail under alpha_min (2 pi alpha_min sqrt(det Sigma')); a
+    # footprint of variance ~0.3 px^2 sampled on the pixel grid sums to its
+    # integral within ~1e-3 (Poisson summation)
+    cam = one_cam()
+    pm = oracle.default_params(low_pass=0.1, flags=oracle.MIP_2D)
+    for ls, u0 in ((-3.5, 0.3), (-3.3, 0.71), (-3.66, 0.5)):
+        g = gauss([[u0 * 3.0 / 64, -0.2 * 3.0 / 64, 3.0]], log_scales=[[ls] * 3], logits=[3.0],
+                  colours=[[1.0, 1.0, 1.0]])
+        out = oracle.render(g, None, cam, params=pm)
+        v0 = (64.0 / 3.0 * math.exp(float(np.float32(ls)))) ** 2
+        k = F32(0.1)
+        op = 1 / (1 + math.exp(-3.0))
+        want = 2 * math.pi * (op * v0 - F32(1 / 255) * (v0 + k))
+        got = out["image"][0].sum()
+        assert abs(got / want - 1) < 1e-2, (ls, got, want)
+
+
+def test_mip_3d_filter_is_the_highest_sampling_rate_over_the_views():
+    # A at the origin; B one unit further back; C facing away. fx = 100, 64x64.
+    mk = lambda R, t: scenes.Camera(64, 64, 100.0, 100.0, 32.0, 32.0, np.asarray(R, float), np.asarray(t, float))
+    A = mk(np.eye(3), [0, 0, 0])
+    B = mk(np.eye(3), [0, 0, 2.0])
+    C = mk(np.diag([-1.0, 1.0, -1.0]), [0, 0, 0])
+    g = gauss([[0, 0, 4.0], [10.0, 0, 4.0], [0.5, 0, 8.0], [0.0, 0.0, -4.0]])
+    f3 = oracle.mip_filter3d(g, [A, B, C], s=0.2)
+    nu1 = 100.0 / 4.0        # A sees it at depth 4, B at 6, C not at all
+    nu3 = 100.0 / 8.0        # A at depth 8, B at 10
+    nu4 = 100.0 / 4.0        # only C sees it (at depth 4)
+    np.testing.assert_allclose(f3[0], 0.2 / nu1 ** 2, rtol=1e-12)
+    np.testing.assert_allclose(f3[2], 0.2 / nu3 ** 2, rtol=1e-12)
+    np.testing.assert_allclose(f3[3], 0.2 / nu4 ** 2, rtol=1e-12)
+    # outside every view (u = 282 in A): the largest variance of the seen ones
+    np.testing.assert_allclose(f3[1], 0.2 / nu3 ** 2, rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [23, 24])
+def test_oracle_gradient_with_mip_filters_matches_finite_differences(seed):
+    g, _, _ = tiny_scene(seed)
+    f3 = np.random.default_rng(seed).uniform(0.2, 1.0, g.n) * np.exp(2 * g.log_scales.astype(np.float64)).mean(1)
+    pm = oracle.default_params(low_pass=0.1, flags=oracle.FP64_RECORDS | oracle.MIP_2D)
+    _fd_check(seed, pm, f3)
