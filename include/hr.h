@@ -79,6 +79,10 @@ typedef struct {
   const float* quats;      /* [n,4] (w,x,y,z), normalised by the library */
   const float* opacity_logits; /* [n] opacity = sigmoid(logit) */
   const float* sh;         /* [n,K,3] real SH coefficients per channel */
+  /* [n] Mip-Splatting 3D smoothing variance (world units^2), or null for none:
+   * Sigma + f3 I, opacity scaled by prod_i s_i / sqrt(s_i^2 + f3). A negative
+   * or non-finite entry culls its Gaussian. See hr_mip_filter3d. */
+  const float* filter3d;
 } hr_gaussians;
 
 /* Textured triangle mesh (Sec. 3.1 "Textured mesh"). Each face corner has
@@ -113,7 +117,12 @@ enum {
    * n_blended are unchanged; n_processed loses the one stopping candidate
    * where it was dropped; keys/ranges, n_keys and the capacity requirement
    * count the kept pairs only. */
-  HR_FLAG_CULL_BEHIND_MESH = 1u << 3
+  HR_FLAG_CULL_BEHIND_MESH = 1u << 3,
+  /* Mip-Splatting 2D filter (the anti-aliased host method of Table 1):
+   * low_pass is the pixel filter variance (0.1 for that method) and the
+   * opacity is scaled by sqrt(det Sigma' / det(Sigma' + low_pass I)), the
+   * ratio floored at 2.5e-5. Forward and backward must agree on it. */
+  HR_FLAG_MIP_2D = 1u << 4
 };
 
 typedef struct {
@@ -228,6 +237,16 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
                          float lambda_t, float k, uint32_t flags, float* loss_out,
                          float* grad_image, float* grad_final_T, float* grad_mesh_rgb,
                          void* scratch, void* stream);
+
+/* Mip-Splatting 3D smoothing variance of every Gaussian for a set of
+ * training views: scale / nu^2, nu the highest sampling rate fx / z over the
+ * views that see the centre beyond settings->near_gs and inside the image
+ * widened by 15% on each side; Gaussians no view sees take the largest
+ * variance of the seen ones (0 when none is seen). scale is 0.2 for that
+ * method. filter3d_out: device [n], written. Any number of cameras. */
+hr_status hr_mip_filter3d(const hr_gaussians* gaussians, const hr_camera* cams, int32_t n_cams,
+                          const hr_settings* settings, double scale, float* filter3d_out,
+                          void* stream);
 
 /* One Adam step (Kingma and Ba, with bias correction) over several parameter
  * groups: the joint optimisation of Sec. 3.4 / Alg. 1 updates the Gaussians and

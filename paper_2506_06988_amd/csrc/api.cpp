@@ -248,6 +248,8 @@ SetDev make_setdev(const Plan& p, const hr_gaussians* g, const hr_mesh* m, const
   for (const CamDev& d : p.camdev) S.max_tiles_cam = std::max(S.max_tiles_cam, d.TX * d.TY);
   S.n_pix = p.P;
   S.key_cap = p.key_cap;
+  S.filter3d = g->n > 0 ? g->filter3d : nullptr;
+  S.mip2d = (s->flags & HR_FLAG_MIP_2D) ? 1 : 0;
   return S;
 }
 
@@ -421,6 +423,31 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
               (flags & HR_FLAG_DETACH_MASK) != 0, loss_out, grad_image, grad_final_T,
               grad_mesh_rgb, scratch, (hipStream_t)stream);
   return hip_check("loss launch");
+}
+
+hr_status hr_mip_filter3d(const hr_gaussians* g, const hr_camera* cams, int32_t n_cams,
+                          const hr_settings* s, double scale, float* filter3d_out, void* stream) {
+  if (!g || !cams || !s) return fail(HR_ERR_INVALID_ARGUMENT, "null argument");
+  if (n_cams < 1) return fail(HR_ERR_INVALID_ARGUMENT, "need at least one camera");
+  if (g->n < 0) return fail(HR_ERR_INVALID_ARGUMENT, "n must be >= 0");
+  if (g->n > 0 && (!g->means || !filter3d_out)) return fail(HR_ERR_INVALID_ARGUMENT, "null array");
+  if (!(scale >= 0.0) || !std::isfinite(scale)) return fail(HR_ERR_INVALID_ARGUMENT, "scale must be >= 0");
+  std::vector<CamDev> cd(n_cams);
+  for (int c = 0; c < n_cams; ++c) {
+    const hr_camera& h = cams[c];
+    if (h.width < 1 || h.height < 1 || !(h.fx > 0) || !(h.fy > 0))
+      return fail(HR_ERR_INVALID_ARGUMENT, "camera size and focal must be positive");
+    std::memset(&cd[c], 0, sizeof(CamDev));
+    cd[c].fx = h.fx; cd[c].fy = h.fy; cd[c].cx = h.cx; cd[c].cy = h.cy;
+    for (int k = 0; k < 9; ++k) cd[c].R[k] = h.R[k];
+    for (int k = 0; k < 3; ++k) cd[c].t[k] = h.t[k];
+    cd[c].W = h.width;
+    cd[c].H = h.height;
+  }
+  hipGetLastError();
+  launch_mip_filter3d(g->means, g->n, cd.data(), n_cams, s->near_gs, scale, filter3d_out,
+                      (hipStream_t)stream);
+  return hip_check("mip filter launch");
 }
 
 hr_status hr_adam_step(const hr_adam_group* groups, int32_t n_groups, double beta1, double beta2,

@@ -50,8 +50,24 @@ __global__ __launch_bounds__(128) void k_project_bwd(
     Proj P;
     project_gaussian(S, cam, means, log_scales, quats, logits, sh, g, P, true);
     if (!P.vis) continue;
-    // opacity
-    glg += G9[5] * P.op * (1.0 - P.op);
+    // opacity: the record holds op c3 c2 (Mip-Splatting factors, 1 otherwise)
+    glg += G9[5] * P.c3 * P.c2 * P.op * (1.0 - P.op);
+    // d c3 / d log s_i = c3 f3 / (s_i^2 + f3)
+    if (P.f3 > 0.0)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        gls[i] += G9[5] * P.op * P.c2 * P.c3 * P.f3 / (P.s[i] * P.s[i] + P.f3);
+    // c2 = sqrt(D0 / D1), D1 = det Sigma', D0 = det(Sigma' - lp I):
+    // d c2 = c2 / 2 (dD0 / D0 - dD1 / D1) on the entries (a, b, c) of Sigma'
+    double gma = 0.0, gmb = 0.0, gmc = 0.0;
+    if (S.mip2d && !P.c2lo) {
+      const double a = P.cov[0], b = P.cov[1], c = P.cov[2], lp = (double)S.low_pass;
+      const double D1 = a * c - b * b, D0 = (a - lp) * (c - lp) - b * b;
+      const double gc2 = G9[5] * P.op * P.c3 * 0.5 * P.c2;
+      gma = gc2 * ((c - lp) / D0 - c / D1);
+      gmb = gc2 * (2.0 * b / D1 - 2.0 * b / D0);
+      gmc = gc2 * ((a - lp) / D0 - a / D1);
+    }
     // colour: SH coefficients and the view direction
     double Y[16];
     sh_eval(P.dir, S.sh_degree, Y);
@@ -76,8 +92,10 @@ __global__ __launch_bounds__(128) void k_project_bwd(
     const double G00 = G9[2], G01 = 0.5 * G9[3], G11 = G9[4];
     const double a00 = q00 * G00 + q01 * G01, a01 = q00 * G01 + q01 * G11;
     const double a10 = q01 * G00 + q11 * G01, a11 = q01 * G01 + q11 * G11;
-    const double H00 = -(a00 * q00 + a01 * q01), H01 = -(a00 * q01 + a01 * q11);
-    const double H11 = -(a10 * q01 + a11 * q11);
+    // plus the 2D filter's factor; b sits in both off-diagonal entries
+    const double H00 = -(a00 * q00 + a01 * q01) + gma;
+    const double H01 = -(a00 * q01 + a01 * q11) + 0.5 * gmb;
+    const double H11 = -(a10 * q01 + a11 * q11) + gmc;
     // Sigma' = J Sc J^T + lp:  gSc = J^T H J,  gJ = 2 H J Sc
     const double j00 = P.J[0], j02 = P.J[1], j11 = P.J[2], j12 = P.J[3];
     // HJ (2x3): row a = H[a][0] J[0][:] + H[a][1] J[1][:], J rows (j00,0,j02), (0,j11,j12)

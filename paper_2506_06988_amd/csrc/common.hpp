@@ -18,6 +18,9 @@ constexpr int MAX_TILES_PER_CAM = 16384;     // LDS tile histogram of the binnin
 constexpr float LOG2E = 1.4426950408889634f;
 
 // Camera as the kernels see it.
+// floor of the determinant ratio of the Mip-Splatting 2D filter
+constexpr double MIP2D_FLOOR = 2.5e-5;
+
 struct CamDev {
   double fx, fy, cx, cy;
   double R[9];
@@ -41,6 +44,8 @@ struct SetDev {
   int32_t max_tiles_cam;  // largest tile count of one camera
   int64_t n_pix;     // over all cameras
   int64_t key_cap;
+  const float* filter3d;  // [n] Mip-Splatting 3D smoothing variance, or null
+  int32_t mip2d;          // Mip-Splatting 2D filter with opacity compensation
 };
 
 // Projected Gaussian as the blend reads it (48 bytes, FP32).

@@ -97,6 +97,8 @@ struct CamUpload {
 };
 static_assert(sizeof(CamUpload) + 8 <= 4096, "camera upload must fit in kernel arguments");
 void launch_upload_cams(const CamUpload& u, CamDev* dst, hipStream_t st);
+void launch_mip_filter3d(const float* means, int n, const CamDev* cams, int n_cams, float near,
+                         double scale, float* f3, hipStream_t st);
 void launch_counters_to_stats(const uint32_t* counters, hr_stats* stats, hipStream_t st);
 void launch_zero_gacc(float* gacc, const uint32_t* counters, hipStream_t st);
 void launch_count_mismatch(const float* a, const float* b, int64_t n, uint32_t* out,

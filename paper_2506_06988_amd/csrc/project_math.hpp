@@ -29,6 +29,10 @@ struct Proj {
   double rgb[3];
   bool clamped[3];
   float zf;
+  // Mip-Splatting: 3D variance f3 and opacity factor c3, 2D factor c2 (c2lo:
+  // at its floor); opr = op c3 c2 is the record's opacity
+  double f3, c3, c2, opr;
+  bool c2lo;
 };
 
 // Real spherical harmonics without the Condon-Shortley phase, orthonormal on
@@ -150,6 +154,19 @@ __device__ __forceinline__ void project_gaussian(const SetDev& S, const CamDev& 
   auto dot3 = [&](int i, int k) { return N[3 * i] * N[3 * k] + N[3 * i + 1] * N[3 * k + 1] + N[3 * i + 2] * N[3 * k + 2]; };
   P.Sc[0] = dot3(0, 0); P.Sc[1] = dot3(0, 1); P.Sc[2] = dot3(0, 2);
   P.Sc[3] = dot3(1, 1); P.Sc[4] = dot3(1, 2); P.Sc[5] = dot3(2, 2);
+  // Mip-Splatting 3D smoothing: W (Sigma + f3 I) W^T = N N^T + f3 I
+  P.f3 = 0.0;
+  P.c3 = 1.0;
+  if (S.filter3d) {
+    const float f = S.filter3d[g];
+    if (!(isfinite(f) && f >= 0.f)) return;
+    P.f3 = (double)f;
+    P.Sc[0] += P.f3;
+    P.Sc[3] += P.f3;
+    P.Sc[5] += P.f3;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) P.c3 *= P.s[i] / sqrt(P.s[i] * P.s[i] + P.f3);
+  }
 
   const double xz = x / z, yz = y / z;
   P.clx = xz < -cam.limx || xz > cam.limx;
@@ -168,6 +185,16 @@ __device__ __forceinline__ void project_gaussian(const SetDev& S, const CamDev& 
   P.cov[2] = t11 * j11 + t12 * j12 + (double)S.low_pass;
   const double det = P.cov[0] * P.cov[2] - P.cov[1] * P.cov[1];
   if (!(det > 0.0)) return;
+  // Mip-Splatting 2D filter: opacity times sqrt(det(Sigma') / det(Sigma' + lp I))
+  P.c2 = 1.0;
+  P.c2lo = false;
+  if (S.mip2d) {
+    const double lp = (double)S.low_pass;
+    const double ratio = ((P.cov[0] - lp) * (P.cov[2] - lp) - P.cov[1] * P.cov[1]) / det;
+    P.c2lo = !(ratio > MIP2D_FLOOR);
+    P.c2 = sqrt(P.c2lo ? MIP2D_FLOOR : ratio);
+  }
+  P.opr = P.op * P.c3 * P.c2;
   const double idet = 1.0 / det;
   P.con[0] = P.cov[2] * idet;
   P.con[1] = -P.cov[1] * idet;

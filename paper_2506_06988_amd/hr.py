@@ -21,13 +21,14 @@ HR_FLAG_NO_SYNC = 1 << 0
 HR_FLAG_DETACH_MASK = 1 << 1
 HR_FLAG_EXPORT_KEYS = 1 << 2
 HR_FLAG_CULL_BEHIND_MESH = 1 << 3
+HR_FLAG_MIP_2D = 1 << 4
 
 P = C.c_void_p
 
 
 class hr_gaussians(C.Structure):
     _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("means", P), ("log_scales", P),
-                ("quats", P), ("opacity_logits", P), ("sh", P)]
+                ("quats", P), ("opacity_logits", P), ("sh", P), ("filter3d", P)]
 
 
 class hr_mesh(C.Structure):
@@ -67,7 +68,7 @@ class hr_adam_group(C.Structure):
 
 EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid",
             "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
-            "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_autotune",
+            "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_mip_filter3d", "hr_autotune",
             "hr_batch_create", "hr_batch_launch", "hr_batch_destroy", "hr_status_string",
             "hr_last_error", "hr_abi_version"]
 
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH):
     L.hr_hybrid_loss.restype = C.c_int
     L.hr_hybrid_loss.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_uint32, P, P,
                                  P, P, P, P]
+    L.hr_mip_filter3d.restype = C.c_int
+    L.hr_mip_filter3d.argtypes = [P, P, C.c_int32, P, C.c_double, P, P]
     L.hr_adam_step.restype = C.c_int
     L.hr_adam_step.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, P]
     L.hr_full_loss_scratch_bytes.restype = C.c_size_t
@@ -164,6 +167,7 @@ class DevGaussians:
     opacity_logits: "torch.Tensor"
     sh: "torch.Tensor"
     sh_degree: int
+    filter3d: Optional["torch.Tensor"] = None  # [n] Mip-Splatting 3D smoothing variance
 
     @property
     def n(self):
@@ -174,6 +178,9 @@ class DevGaussians:
         g.n, g.sh_degree = self.n, self.sh_degree
         g.means, g.log_scales, g.quats = _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats)
         g.opacity_logits, g.sh = _ptr(self.opacity_logits), _ptr(self.sh)
+        if self.filter3d is not None:
+            assert self.filter3d.numel() == self.n and self.filter3d.is_contiguous()
+        g.filter3d = _ptr(self.filter3d)
         return g
 
 
@@ -443,6 +450,17 @@ def hybrid_loss(image, final_T, mesh_rgb, tri_id, target, lambda_t=0.1, k=20.0, 
 MASK_MODES = {"none": 0, "one": 1, "T": 2, "sigmoid": 3}
 
 
+def mip_filter3d(gaussians: DevGaussians, cams, settings=None, scale=0.2, out=None):
+    """hr_mip_filter3d: the Mip-Splatting 3D smoothing variance [n] for these views."""
+    import torch
+    out = torch.empty(gaussians.n, dtype=torch.float32, device=gaussians.means.device) if out is None else out
+    st = settings if settings is not None else default_settings()
+    g = gaussians.struct()
+    check(load().hr_mip_filter3d(C.byref(g), camera_array(cams), len(cams), C.byref(st),
+                                 float(scale), _ptr(out), _stream()))
+    return out
+
+
 def adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15):
     """hr_adam_step over [(param, grad, m, v, lr[, lr_head, head, row]), ...]
     (contiguous float32 device tensors of equal sizes within a group)."""
@@ -498,7 +516,8 @@ def _autograd_fn():
         def forward(ctx, renderer, means, log_scales, quats, opacity_logits, sh, tex):
             renderer.g = DevGaussians(means.detach().contiguous(), log_scales.detach().contiguous(),
                                       quats.detach().contiguous(), opacity_logits.detach().contiguous(),
-                                      sh.detach().contiguous(), renderer.g.sh_degree)
+                                      sh.detach().contiguous(), renderer.g.sh_degree,
+                                      renderer.g.filter3d)
             t = None if tex is None else tex.detach().contiguous()
             f = renderer.render_hybrid(tex=t)
             ctx.renderer = renderer

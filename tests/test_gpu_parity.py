@@ -349,3 +349,51 @@ def test_mesh_depth_culling_matches_oracle(hr):
     # and the images are those of the uncut lists
     r3, f3 = gpu_render(hr, sc, cams=cams)
     assert torch.equal(f3.image, f.image) and torch.equal(f3.final_T, f.final_T)
+
+
+def test_mip_filter3d_matches_oracle(hr):
+    say("case: Mip-Splatting 3D filter over 20 training views")
+    sc = scenes.small_room(71, n=5000, faces=200, tex=8)
+    rng = np.random.default_rng(71)
+    cams = [scenes.random_room_camera(rng, *wh) for wh in [(96, 80), (40, 30)] * 10]
+    # a few Gaussians outside the room, unseen by every view
+    g = scenes.concat_gaussians(sc.gaussians, scenes.outside_gaussians(rng, 50, margin=40.0))
+    dg, _ = hr.to_device(g, None)
+    got = hr.mip_filter3d(dg, cams).cpu().numpy().astype(np.float64)
+    ref = oracle.mip_filter3d(g, cams, s=0.2)
+    np.testing.assert_allclose(got, ref, rtol=2e-6)
+    say(f"  seen by none: {int((ref == ref.max()).sum())}, range {ref.min():.3e}..{ref.max():.3e}")
+
+
+@pytest.mark.parametrize("seed", [131, 132])
+def test_mip_filters_forward_and_backward_match_oracle(hr, seed):
+    say(f"case: Mip-Splatting filters, seed {seed}")
+    sc = tiny(seed, n=40)
+    cam = sc.cameras[0]
+    rng = np.random.default_rng(seed)
+    s2 = np.exp(2.0 * sc.gaussians.log_scales.astype(np.float64)).mean(1)
+    f3 = (rng.uniform(0.2, 1.5, sc.gaussians.n) * s2).astype(np.float32)
+    st = hr.default_settings(low_pass=0.1, flags=hr.HR_FLAG_MIP_2D)
+    pm = oracle.default_params(low_pass=0.1, flags=oracle.MIP_2D)
+    g, m = hr.to_device(sc.gaussians, sc.mesh)
+    g.filter3d = torch.as_tensor(f3).cuda()
+    r = hr.Renderer(g, m, [cam], st)
+    f = r.render_hybrid()
+    torch.cuda.synchronize()
+    orc = oracle.render(sc.gaussians, sc.mesh, cam, params=pm, filter3d=f3)
+    check_view(f, [cam], 0, orc)
+    # the filters change the image
+    plain = oracle.render(sc.gaussians, sc.mesh, cam)
+    assert np.abs(plain["image"] - orc["image"]).max() > 1e-2
+    amb = orc["amb"] != 0
+    H, W = cam.height, cam.width
+    gi = rng.normal(size=(3, H, W)).astype(np.float32)
+    gt = rng.normal(size=(H, W)).astype(np.float32)
+    gi[:, amb] = 0
+    gt[amb] = 0
+    d = lambda a: torch.as_tensor(a.reshape(-1)).cuda()
+    grads = r.render_hybrid_backward(d(gi), d(gt))
+    torch.cuda.synchronize()
+    ref = oracle.backward(sc.gaussians, sc.mesh, cam, gi, gt, None, params=pm, filter3d=f3)
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex"):
+        _grad_compare(k, grads[k].cpu().numpy(), ref[k])
