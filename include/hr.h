@@ -137,7 +137,9 @@ typedef struct {
   uint32_t flags;     /* HR_FLAG_* */
   int32_t batch;      /* Gaussians staged in LDS per batch: 32,64,128,256 (0 = tuned default) */
   int32_t variant;    /* blend variant: bit 0 two-deep LDS staging, bit 1 persistent
-                         workgroups on a tile queue (chosen by hr_autotune; 0 = default) */
+                         workgroups on a tile queue, bit 2 one 64-lane wave per tile with
+                         four pixels per lane (batch 64 or 128; bits 0-1 ignored; also
+                         selects the backward kernel). Chosen by hr_autotune; 0 = default */
 } hr_settings;
 
 /* Counters written by the forward (device memory). */

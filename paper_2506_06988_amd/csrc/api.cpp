@@ -293,7 +293,7 @@ void enqueue_backward(const Plan& p, const Work& w, const SetDev& S, const hr_ga
                       hipStream_t st) {
   (void)p;
   launch_zero_gacc(w.gacc, w.counters, st);
-  launch_blend_backward(S, w, grad_image, grad_T, pick_batch(s), st);
+  launch_blend_backward(S, w, grad_image, grad_T, pick_batch(s), s->variant, st);
   launch_project_backward(S, w.cams, *g, w, grads, st);
   launch_texture_backward(S, *m, w, grad_image, grad_mesh, grads->tex, st);
 }
@@ -531,12 +531,19 @@ hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camer
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(HR_ERR_HIP, "event create failed");
+  // 256-thread kernels: 4 batch sizes x {one-deep, two-deep staging} x {one
+  // group per tile, persistent groups}; one-wave kernels: 2 batch sizes
+  std::vector<std::pair<int, int>> cfg;
   for (int v = 0; v < 4; ++v)
-    for (int bi = 0; bi < 4; ++bi) {
+    for (int bi = 0; bi < 4; ++bi) cfg.emplace_back(batches[bi], v);
+  cfg.emplace_back(64, 4);
+  cfg.emplace_back(128, 4);
+  for (const auto& bv : cfg) {
+      const int batch = bv.first, v = bv.second;
       std::vector<float> times;
       for (int r = 0; r < repeats + 1; ++r) {
         hipEventRecord(e0, st);
-        launch_blend_forward(S, w, &o, batches[bi], v, st);
+        launch_blend_forward(S, w, &o, batch, v, st);
         hipEventRecord(e1, st);
         hipEventSynchronize(e1);
         float ms = 0.f;
@@ -554,16 +561,16 @@ hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camer
       if (bad) {
         hipEventDestroy(e0);
         hipEventDestroy(e1);
-        return fail(HR_ERR_INTERNAL, "blend variant batch=" + std::to_string(batches[bi]) +
-                                         " prefetch=" + std::to_string(v) +
+        return fail(HR_ERR_INTERNAL, "blend variant batch=" + std::to_string(batch) +
+                                         " variant=" + std::to_string(v) +
                                          " is not bit-identical to the default");
       }
       if (med < best) {
         best = med;
-        best_b = batches[bi];
+        best_b = batch;
         best_v = v;
       }
-    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   s->batch = best_b;

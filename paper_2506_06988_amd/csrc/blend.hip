@@ -444,6 +444,359 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
   }
 }
 
+
+// ------------------------------------------------- one wave per tile --
+// A 64-lane workgroup per 16x16 tile; lane l owns the column l % 16 and the
+// four rows 4 (l / 16) .. 4 (l / 16) + 3. Each staged record read from LDS
+// then serves four pixels, the window bitmap is owned four words per lane,
+// and one wave-wide reduction per Gaussian in the backward covers 256
+// pixels. The per-pixel arithmetic is that of the 256-thread kernels, in the
+// same order, so images are bit-identical.
+constexpr int WPIX = 4;
+
+// bitmap words 4 l .. 4 l + 3 of this lane: counts and exclusive prefix
+struct WinWords {
+  uint32_t w[WPIX];
+  uint32_t pre, total;
+};
+
+__device__ __forceinline__ WinWords wave_words(const uint32_t* bitmap) {
+  WinWords ww;
+  const int l = threadIdx.x;
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int q = 0; q < WPIX; ++q) {
+    ww.w[q] = bitmap[WPIX * l + q];
+    cnt += __popc(ww.w[q]);
+  }
+  uint32_t inc = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(inc, o, 64);
+    if (l >= o) inc += u;
+  }
+  ww.total = __shfl(inc, 63, 64);
+  ww.pre = inc - cnt;
+  return ww;
+}
+
+// ranks of the window-ordered entries [q, q + n) into rk
+__device__ __forceinline__ void wave_extract(const WinWords& ww, uint32_t q, uint32_t n,
+                                             uint32_t wbase, uint32_t* rk) {
+  uint32_t idx = ww.pre;
+#pragma unroll
+  for (int h = 0; h < WPIX; ++h) {
+    uint32_t wv = ww.w[h];
+    const uint32_t cnt = __popc(wv);
+    if (idx + cnt > q && idx < q + n) {
+      const uint32_t bit0 = wbase + 32u * (WPIX * threadIdx.x + h);
+      uint32_t k = idx;
+      while (wv) {
+        const uint32_t b = __ffs(wv) - 1;
+        wv &= wv - 1;
+        if (k >= q && k < q + n) rk[k - q] = bit0 + b;
+        ++k;
+      }
+    }
+    idx += cnt;
+  }
+}
+
+template <int BG>
+__global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
+  __shared__ Staged sh[BG];
+  __shared__ uint32_t rk[BG];
+  __shared__ uint32_t bitmap[WIN_WORDS];
+  const SetDev& S = A.S;
+  const int t = (int)A.tile_order[blockIdx.x];
+  const int cam = find_cam_by_tile(A.cams, S.n_cams, t);
+  const CamDev& C = A.cams[cam];
+  const int lt = t - C.tile_off;
+  const int ty = lt / C.TX, tx = lt - (lt / C.TX) * C.TX;
+  const int lane = threadIdx.x;
+  const int i = tx * TILE + (lane & 15);
+  const int j0 = ty * TILE + WPIX * (lane >> 4);
+  const WinCtx W = win_ctx(C, cam, t, A.vis_off, A.mat, A.tile_start, A.tile_total, S.key_cap);
+  const float px = (float)i + 0.5f;
+  const float amin = S.alpha_min, amax = S.alpha_max, tmin = S.t_min;
+  const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
+  float T[WPIX], cr[WPIX], cg[WPIX], cb[WPIX], Dm[WPIX], py[WPIX];
+  int nc[WPIX], nbl[WPIX], npro[WPIX];
+  bool done[WPIX];
+  unsigned long long key[WPIX];
+#pragma unroll
+  for (int r = 0; r < WPIX; ++r) {
+    const int j = j0 + r;
+    const bool inside = i < C.W && j < C.H;
+    key[r] = inside ? A.zbuf[C.pix_off + (int64_t)j * C.W + i] : ~0ull;
+    Dm[r] = key[r] == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(key[r] >> 32));
+    py[r] = (float)j + 0.5f;
+    T[r] = 1.f;
+    cr[r] = cg[r] = cb[r] = 0.f;
+    nc[r] = nbl[r] = 0;
+    npro[r] = (int)W.lim;
+    done[r] = !inside;
+  }
+  auto lane_done = [&]() { return done[0] && done[1] && done[2] && done[3]; };
+  bool all_done = false;
+  for (int w = 0; w < W.nwin && !all_done; ++w) {
+    int64_t a, b;
+    win_range(W, w, a, b);
+    if (a >= b) continue;
+    if (__all(lane_done())) break;
+    const uint32_t wbase = W.rbase + (uint32_t)w * WIN;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < WPIX; ++q) bitmap[WPIX * lane + q] = 0;
+    __syncthreads();
+    win_mark(A.lists, W, a, b, wbase, bitmap);
+    __syncthreads();
+    const WinWords ww = wave_words(bitmap);
+    const int nbat = (int)((ww.total + BG - 1) / BG);
+    for (int bi = 0; bi < nbat; ++bi) {
+      const uint32_t q = (uint32_t)bi * BG;
+      const int n = (int)min((uint32_t)BG, ww.total - q);
+      if (bi > 0 && __all(lane_done())) {
+        all_done = true;
+        break;
+      }
+      __syncthreads();
+      wave_extract(ww, q, (uint32_t)n, wbase, rk);
+      __syncthreads();
+      for (int s2 = lane; s2 < n; s2 += 64) sh[s2] = stage(A.rec_s[min(rk[s2], rmax)], amin);
+      __syncthreads();
+      const int pos0 = (int)(a + q) + 1;
+      const Staged* e = sh;
+      for (int k = 0; k < n; ++k, ++e) {
+        if (lane_done()) continue;
+        const float4 ea = e->a, eb = e->b;
+        const float dx = ea.x - px;
+        const float dxx = dx * dx;
+        const int pos = pos0 + k;
+#pragma unroll
+        for (int r = 0; r < WPIX; ++r) {
+          if (done[r]) continue;
+          if (eb.z >= Dm[r]) {  // at or behind the mesh: the pixel ends (Sec. 3.4)
+            done[r] = true;
+            npro[r] = pos;
+            continue;
+          }
+          const float dy = ea.y - py[r];
+          const float dyy = dy * dy, dxy = dx * dy;
+          const float p2 = __builtin_fmaf(ea.z, dxx, __builtin_fmaf(eb.x, dyy, ea.w * dxy));
+          if (p2 >= eb.w) {
+            const float alpha = fminf(amax, eb.y * __builtin_amdgcn_exp2f(p2));
+            const float Tn = T[r] * (1.f - alpha);
+            if (Tn < tmin) {
+              done[r] = true;
+              npro[r] = pos;
+            } else {
+              const float4 c = e->c;
+              const float wgt = alpha * T[r];
+              cr[r] = __builtin_fmaf(c.x, wgt, cr[r]);
+              cg[r] = __builtin_fmaf(c.y, wgt, cg[r]);
+              cb[r] = __builtin_fmaf(c.z, wgt, cb[r]);
+              T[r] = Tn;
+              nc[r] = pos;
+              ++nbl[r];
+            }
+          }
+        }
+      }
+    }
+  }
+  unsigned long long sp = 0, sb = 0;
+  const int64_t hw = (int64_t)C.W * C.H;
+#pragma unroll
+  for (int r = 0; r < WPIX; ++r) {
+    const int j = j0 + r;
+    if (!(i < C.W && j < C.H)) continue;
+    const int64_t p = C.pix_off + (int64_t)j * C.W + i;
+    const int64_t pl = 3 * C.pix_off + (p - C.pix_off);
+    float br, bgc, bb;
+    if (key[r] != ~0ull) {
+      br = A.mesh_rgb[pl];
+      bgc = A.mesh_rgb[pl + hw];
+      bb = A.mesh_rgb[pl + 2 * hw];
+    } else {
+      br = S.bg[0];
+      bgc = S.bg[1];
+      bb = S.bg[2];
+    }
+    A.image[pl] = __builtin_fmaf(T[r], br, cr[r]);
+    A.image[pl + hw] = __builtin_fmaf(T[r], bgc, cg[r]);
+    A.image[pl + 2 * hw] = __builtin_fmaf(T[r], bb, cb[r]);
+    A.T_ws[p] = T[r];
+    A.nc_ws[p] = nc[r];
+    if (A.T_out) A.T_out[p] = T[r];
+    if (A.nc_out) A.nc_out[p] = nc[r];
+    if (A.nb_out) A.nb_out[p] = nbl[r];
+    if (A.np_out) A.np_out[p] = npro[r];
+    sp += (unsigned long long)npro[r];
+    sb += (unsigned long long)nbl[r];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sp += __shfl_xor(sp, o, 64);
+    sb += __shfl_xor(sb, o, 64);
+  }
+  if (lane == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(A.counters + 6), sp);
+    atomicAdd(reinterpret_cast<unsigned long long*>(A.counters + 8), sb);
+  }
+}
+
+template <int BG>
+__global__ __launch_bounds__(64) void k_blend_bwd_w(
+    SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
+    const uint32_t* __restrict__ mat, const uint32_t* __restrict__ tile_start,
+    const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ tile_order,
+    const uint32_t* __restrict__ lists, const GRec* __restrict__ rec_s,
+    const unsigned long long* __restrict__ zbuf, const float* __restrict__ mesh_rgb,
+    const float* __restrict__ T_ws, const int32_t* __restrict__ nc_ws,
+    const float* __restrict__ grad_image, const float* __restrict__ grad_T,
+    float* __restrict__ gacc) {
+  __shared__ Staged sh[BG];
+  __shared__ uint32_t rk[BG];
+  __shared__ uint32_t bitmap[WIN_WORDS];
+  const int t = (int)tile_order[blockIdx.x];
+  const int cam = find_cam_by_tile(cams, S.n_cams, t);
+  const CamDev& C = cams[cam];
+  const int lt = t - C.tile_off;
+  const int ty = lt / C.TX, tx = lt - (lt / C.TX) * C.TX;
+  const int lane = threadIdx.x;
+  const int i = tx * TILE + (lane & 15);
+  const int j0 = ty * TILE + WPIX * (lane >> 4);
+  const WinCtx W = win_ctx(C, cam, t, vis_off, mat, tile_start, tile_total, S.key_cap);
+  const float px = (float)i + 0.5f;
+  const float amin = S.alpha_min, amax = S.alpha_max;
+  const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
+  const int64_t hw = (int64_t)C.W * C.H;
+  float gr[WPIX], gg[WPIX], gb[WPIX], gT[WPIX], Tf[WPIX], T[WPIX], Sr[WPIX], Sg[WPIX], Sb[WPIX],
+      py[WPIX];
+  int nc[WPIX];
+  int lmax = 0;
+#pragma unroll
+  for (int r = 0; r < WPIX; ++r) {
+    const int j = j0 + r;
+    py[r] = (float)j + 0.5f;
+    gr[r] = gg[r] = gb[r] = gT[r] = 0.f;
+    Tf[r] = 1.f;
+    nc[r] = 0;
+    if (i < C.W && j < C.H) {
+      const int64_t p = C.pix_off + (int64_t)j * C.W + i;
+      const int64_t pl = 3 * C.pix_off + (p - C.pix_off);
+      gr[r] = grad_image[pl];
+      gg[r] = grad_image[pl + hw];
+      gb[r] = grad_image[pl + 2 * hw];
+      Tf[r] = T_ws[p];
+      nc[r] = nc_ws[p];
+      float br, bgc, bb;
+      if (zbuf[p] != ~0ull) {
+        br = mesh_rgb[pl];
+        bgc = mesh_rgb[pl + hw];
+        bb = mesh_rgb[pl + 2 * hw];
+      } else {
+        br = S.bg[0];
+        bgc = S.bg[1];
+        bb = S.bg[2];
+      }
+      // I_h = C + T (I_m or bg): T receives the background's colour gradient
+      gT[r] = (grad_T ? grad_T[p] : 0.f) + gr[r] * br + gg[r] * bgc + gb[r] * bb;
+    }
+    T[r] = Tf[r];
+    Sr[r] = Sg[r] = Sb[r] = 0.f;
+    lmax = max(lmax, nc[r]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o, 64));
+  const int64_t last = lmax;
+  if (last == 0) return;
+  for (int w = W.nwin - 1; w >= 0; --w) {
+    int64_t a, b;
+    win_range(W, w, a, b);
+    if (a >= b || a >= last) continue;
+    const uint32_t wbase = W.rbase + (uint32_t)w * WIN;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < WPIX; ++q) bitmap[WPIX * lane + q] = 0;
+    __syncthreads();
+    win_mark(lists, W, a, b, wbase, bitmap);
+    __syncthreads();
+    const WinWords ww = wave_words(bitmap);
+    const int64_t nproc = (last < a + (int64_t)ww.total ? last : a + (int64_t)ww.total) - a;
+    for (int64_t hi = nproc; hi > 0; hi -= BG) {
+      const int64_t lo = hi - BG > 0 ? hi - BG : 0;
+      const int n = (int)(hi - lo);
+      __syncthreads();
+      wave_extract(ww, (uint32_t)lo, (uint32_t)n, wbase, rk);
+      __syncthreads();
+      for (int s2 = lane; s2 < n; s2 += 64) {
+        const uint32_t r = min(rk[s2], rmax);
+        sh[s2] = stage(rec_s[r], amin);
+        rk[s2] = r;
+      }
+      __syncthreads();
+      for (int k = n - 1; k >= 0; --k) {
+        const int idx = (int)(a + lo + k + 1);  // 1-based list position
+        const float4 ea = sh[k].a, eb = sh[k].b;
+        const float dx = ea.x - px;
+        const float dxx = dx * dx;
+        float g[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q] = 0.f;
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < WPIX; ++r) {
+          if (idx > nc[r]) continue;
+          const float dy = ea.y - py[r];
+          const float dyy = dy * dy, dxy = dx * dy;
+          const float p2 = __builtin_fmaf(ea.z, dxx, __builtin_fmaf(eb.x, dyy, ea.w * dxy));
+          if (!(p2 >= eb.w)) continue;  // the forward's skip decision
+          any = true;
+          const float G = __builtin_amdgcn_exp2f(p2);
+          const float ag = eb.y * G;
+          const float alpha = fminf(amax, ag);
+          const float4 c = sh[k].c;
+          T[r] = T[r] / (1.f - alpha);  // transmittance in front of this Gaussian
+          const float wgt = alpha * T[r];
+          g[6] += wgt * gr[r];
+          g[7] += wgt * gg[r];
+          g[8] += wgt * gb[r];
+          const float galpha = T[r] * ((c.x - Sr[r]) * gr[r] + (c.y - Sg[r]) * gg[r] +
+                                       (c.z - Sb[r]) * gb[r]) -
+                               gT[r] * Tf[r] / (1.f - alpha);
+          Sr[r] = alpha * c.x + (1.f - alpha) * Sr[r];
+          Sg[r] = alpha * c.y + (1.f - alpha) * Sg[r];
+          Sb[r] = alpha * c.z + (1.f - alpha) * Sb[r];
+          if (ag < amax) {
+            g[5] += galpha * G;
+            // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy, dx = u - px; the
+            // staged exponent holds A2 = -ca log2e / 2, B2 = -cb log2e,
+            // C2 = -cc log2e / 2
+            const float gp = galpha * eb.y * G;
+            const float gl = gp * LN2F;
+            g[0] += gl * (2.f * ea.z * dx + ea.w * dy);
+            g[1] += gl * (2.f * eb.x * dy + ea.w * dx);
+            g[2] += -0.5f * gp * dxx;
+            g[3] += -gp * dxy;
+            g[4] += -0.5f * gp * dyy;
+          }
+        }
+        if (__any(any)) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) g[q] = wave_sum_to_last(g[q]);
+          if (lane == 63) {
+            float* dst = gacc + (size_t)rk[k] * 9;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) atomicAdd(dst + q, g[q]);
+          }
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 template <int BG, int D>
@@ -474,6 +827,13 @@ void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int b
             w.counters};
   const bool d2 = (variant & 1) != 0, pers = (variant & 2) != 0;
   uint32_t* queue = w.counters + 14;
+  if (variant & 4) {
+    if (batch >= 128)
+      hipLaunchKernelGGL(k_blend_fwd_w<128>, dim3(A.S.n_tiles), dim3(64), 0, st, A);
+    else
+      hipLaunchKernelGGL(k_blend_fwd_w<64>, dim3(A.S.n_tiles), dim3(64), 0, st, A);
+    return;
+  }
   switch (batch) {
     case 32: d2 ? launch_fwd<32, 2>(A, pers, queue, st) : launch_fwd<32, 1>(A, pers, queue, st); break;
     case 64: d2 ? launch_fwd<64, 2>(A, pers, queue, st) : launch_fwd<64, 1>(A, pers, queue, st); break;
@@ -489,9 +849,20 @@ void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int b
                      w.n_contrib,                                                               \
                      grad_image, grad_T, w.gacc)
 
+#define HR_BWD_W(BG)                                                                            \
+  hipLaunchKernelGGL((k_blend_bwd_w<BG>), dim3(S.n_tiles), dim3(64), 0, st, S, w.cams,          \
+                     w.vis_off, w.mat, w.tile_start, w.tile_total, w.tile_order, w.lists,       \
+                     w.rec_s, (const unsigned long long*)w.zbuf, w.mesh_rgb, w.final_T,         \
+                     w.n_contrib, grad_image, grad_T, w.gacc)
+
 void launch_blend_backward(const SetDev& S, const Work& w, const float* grad_image,
-                           const float* grad_T, int batch, hipStream_t st) {
+                           const float* grad_T, int batch, int variant, hipStream_t st) {
   if (S.n_tiles == 0) return;
+  if (variant & 4) {
+    if (batch >= 128) HR_BWD_W(128);
+    else HR_BWD_W(64);
+    return;
+  }
   switch (batch) {
     case 32: HR_BWD(32); break;
     case 64: HR_BWD(64); break;

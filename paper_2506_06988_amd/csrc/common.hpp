@@ -20,6 +20,7 @@ constexpr float LOG2E = 1.4426950408889634f;
 // Camera as the kernels see it.
 // floor of the determinant ratio of the Mip-Splatting 2D filter
 constexpr double MIP2D_FLOOR = 2.5e-5;
+constexpr float LN2F = 0.69314718055994531f;
 
 struct CamDev {
   double fx, fy, cx, cy;

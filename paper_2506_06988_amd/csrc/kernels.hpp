@@ -70,7 +70,7 @@ void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* o
 void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int batch, int variant,
                           hipStream_t st);
 void launch_blend_backward(const SetDev& S, const Work& w, const float* grad_image,
-                           const float* grad_T, int batch, hipStream_t st);
+                           const float* grad_T, int batch, int variant, hipStream_t st);
 void launch_project_backward(const SetDev& S, const CamDev* cams, const hr_gaussians& g,
                              const Work& w, hr_grads* grads, hipStream_t st);
 void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,

@@ -85,13 +85,14 @@ def test_config1_keys_values_ranges_bit_exact(hr):
     np.testing.assert_array_equal(f.radii.cpu().numpy(), pr["radius"])
 
 
-@pytest.mark.parametrize("seed", [7, 8])
-def test_small_room_three_uneven_cameras_in_one_call(hr, seed):
-    say(f"case: small room seed {seed}")
+@pytest.mark.parametrize("seed,variant", [(7, 0), (8, 0), (7, 4)])
+def test_small_room_three_uneven_cameras_in_one_call(hr, seed, variant):
+    say(f"case: small room seed {seed} variant {variant}")
     sc = scenes.small_room(seed, n=4000, faces=3000, tex=64, n_cams=1)
     rng = np.random.default_rng(seed + 50)
     cams = [scenes.random_room_camera(rng, w, h) for (w, h) in ((96, 80), (50, 37), (130, 70))]
-    r, f = gpu_render(hr, sc, cams=cams, export_keys=True)
+    r, f = gpu_render(hr, sc, cams=cams, export_keys=True,
+                      settings=hr.default_settings(variant=variant))
     st = f.stats_dict()
     say("stats", st)
     key_base = 0
@@ -129,6 +130,20 @@ def test_many_rank_windows_and_pair_slices(hr):
     K = len(k)
     np.testing.assert_array_equal(f.keys[:K].cpu().numpy().view(np.uint64), k)
     np.testing.assert_array_equal(f.values[:K].cpu().numpy().view(np.uint32), v)
+    # the one-wave kernels over the same windows: identical forward, and a
+    # backward equal up to the order of its float atomics
+    gi = torch.randn(3 * r.P, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    g0 = r.render_hybrid_backward(gi)
+    outs0 = [x.clone() for x in (f.image, f.final_T, f.n_contrib, f.n_blended, f.n_processed)]
+    r.settings.variant, r.settings.batch = 4, 128
+    f4 = r.render_hybrid()
+    g4 = r.render_hybrid_backward(gi)
+    torch.cuda.synchronize()
+    for x, y in zip(outs0, (f4.image, f4.final_T, f4.n_contrib, f4.n_blended, f4.n_processed)):
+        assert torch.equal(x, y)
+    for k_ in g0:
+        a_, b_ = g0[k_].double(), g4[k_].double()
+        assert float((a_ - b_).norm()) <= 1e-4 * float(a_.norm()) + 1e-12, k_
 
 
 def test_ragged_sizes_and_edge_cases(hr):
@@ -160,12 +175,16 @@ def test_forward_is_deterministic_and_variants_bit_identical(hr):
     f2 = r.render_hybrid()
     torch.cuda.synchronize()
     assert torch.equal(a, f2.image)
+    ref = [x.clone() for x in (f2.final_T, f2.n_contrib, f2.n_blended, f2.n_processed, f2.stats)]
     for batch in (32, 64, 128, 256):
-        for variant in (0, 1, 2, 3):
+        for variant in (0, 1, 2, 3, 4):
             r.settings.batch, r.settings.variant = batch, variant
             f3 = r.render_hybrid()
             torch.cuda.synchronize()
             assert torch.equal(a, f3.image), (batch, variant)
+            got = (f3.final_T, f3.n_contrib, f3.n_blended, f3.n_processed, f3.stats)
+            for x, y in zip(ref, got):
+                assert torch.equal(x, y), (batch, variant)
     b, v = r.autotune(f3, repeats=2)
     say("autotune ->", b, v)
 
@@ -214,12 +233,12 @@ def tiny(seed, n=30, deg=3, w=48, h=40):
     return scenes.Scene(f"tiny{seed}", g, mesh, [cam])
 
 
-@pytest.mark.parametrize("seed", [101, 102, 103])
-def test_backward_matches_oracle_gradient(hr, seed):
-    say(f"case: backward seed {seed}")
+@pytest.mark.parametrize("seed,variant", [(101, 0), (102, 0), (103, 0), (101, 4), (104, 4)])
+def test_backward_matches_oracle_gradient(hr, seed, variant):
+    say(f"case: backward seed {seed} variant {variant}")
     sc = tiny(seed)
     cam = sc.cameras[0]
-    r, f = gpu_render(hr, sc)
+    r, f = gpu_render(hr, sc, settings=hr.default_settings(variant=variant))
     orc = oracle.render(sc.gaussians, sc.mesh, cam)
     amb = orc["amb"] != 0
     rng = np.random.default_rng(seed)
