@@ -125,37 +125,51 @@ def main():
         r.set_cameras([sc.cameras[v]])
         r.render_hybrid(frame, sync_check=True)
     torch.cuda.synchronize()
-    r.set_cameras([sc.cameras[0]])
-    r.render_hybrid(frame)
-    r.autotune(frame, repeats=3)
+    # tune the blend on 8 of the views rendered together (one call, the mix
+    # of the workload), then use the choice for single-view frames
+    tv = sc.cameras[::4]
+    rt = hr.Renderer(g, m, tv)
+    ft = rt.render_hybrid(sync_check=True)
+    rt.autotune(ft, repeats=3)
+    r.settings.batch, r.settings.variant = rt.settings.batch, rt.settings.variant
+    del rt, ft
+    torch.cuda.empty_cache()
     log(f"autotuned blend: batch {r.settings.batch} variant {r.settings.variant}")
     sec, wall = timed_frames(torch, r, frame, sc.cameras, args.steps, args.warmup)
     fps = 1.0 / sec
     log(f"1080p hybrid: {sec * 1e3:.3f} ms/frame ({fps:.1f} frames/s), wall {wall * 1e3:.3f} ms")
 
-    # blend kernel alone on view 0 (events on the launch stream)
-    r.set_cameras([sc.cameras[0]])
-    r.render_hybrid(frame)
-    torch.cuda.synchronize()
-    st = r.L and torch.cuda.current_stream()
-    stats = frame.stats_dict()
-    nb = max(8, args.steps // 4)
-    for _ in range(3):
-        r.blend_forward(frame)
+    # the blend kernel alone over the same 32 views: each view is rendered,
+    # then its blend re-run (hr_blend_forward) `nb` times between events on
+    # the launch stream; the work is the views' examined and blended pairs
+    st = torch.cuda.current_stream()
+    nb = 4
+    blend_s = 0.0
+    pairs = blended = 0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(nb):
+    for v in range(len(sc.cameras)):
+        r.set_cameras([sc.cameras[v]])
+        r.render_hybrid(frame)
         r.blend_forward(frame)
-    e1.record(st)
-    torch.cuda.synchronize()
-    blend_s = e0.elapsed_time(e1) / 1e3 / nb
-    pairs = stats["n_processed"]
-    blends_per_s = pairs / blend_s
-    ops = pairs * BLEND_OPS_EXAMINED + stats["n_blended"] * BLEND_OPS_BLENDED
+        torch.cuda.synchronize()
+        stats = frame.stats_dict()
+        e0.record(st)
+        for _ in range(nb):
+            r.blend_forward(frame)
+        e1.record(st)
+        torch.cuda.synchronize()
+        blend_s += e0.elapsed_time(e1) / 1e3
+        pairs += nb * stats["n_processed"]
+        blended += nb * stats["n_blended"]
+    launches = nb * len(sc.cameras)
+    ops = pairs * BLEND_OPS_EXAMINED + blended * BLEND_OPS_BLENDED
     achieved = ops / blend_s / 1e12
-    log(f"blend kernel: {blend_s * 1e3:.3f} ms, {pairs} pairs examined, {stats['n_blended']} blended, "
+    blends_per_s = pairs / blend_s
+    log(f"blend kernel over {len(sc.cameras)} views: {blend_s / launches * 1e3:.3f} ms/launch, "
+        f"{pairs // launches} pairs examined and {blended // launches} blended per launch, "
         f"{blends_per_s:.3e} pairs/s, {achieved:.2f} TOP/s")
-    hyb_stats = stats
+    hyb_stats = dict(pairs_examined_per_view=pairs // launches,
+                     pairs_blended_per_view=blended // launches)
     del r, frame, g, m
     torch.cuda.empty_cache()
 
@@ -177,12 +191,14 @@ def main():
                    "gaussians": 600000, "faces": int(sc.mesh.n_faces), "width": 1920,
                    "height": 1080, "views": len(sc.cameras)},
         "blend_pairs_per_s": blends_per_s,
-        "blend_ms": round(blend_s * 1e3, 4),
-        "stats_view0": hyb_stats,
+        "blend_ms_per_launch": round(blend_s / launches * 1e3, 4),
+        "blend_stats": hyb_stats,
+        "blend_tuning": {"batch": int(r.settings.batch), "variant": int(r.settings.variant)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
                      "kernel": "k_blend_fwd", "ops_per_examined": BLEND_OPS_EXAMINED,
-                     "ops_per_blended": BLEND_OPS_BLENDED, "ops_per_launch": ops},
+                     "ops_per_blended": BLEND_OPS_BLENDED, "ops_per_launch": ops // launches,
+                     "avg_launch_ms": round(blend_s / launches * 1e3, 4)},
     }
     del sc
 
@@ -210,6 +226,12 @@ def main():
         f = r.render_hybrid(sync_check=True)
         torch.cuda.synchronize()
         target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
+        r.autotune(f, repeats=2)
+        L0, gi0, gt0, _ = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target)
+        r.autotune_backward(gi0, gt0, repeats=2)
+        log(f"batched tuning: forward batch {r.settings.batch}, backward batch "
+            f"{r.settings.batch_bwd}, variant {r.settings.variant}")
+        del L0, gi0, gt0
         step = hr.BatchedStep(r, target)
         for _ in range(2):
             step.launch()
@@ -226,6 +248,9 @@ def main():
         log(f"batched fwd+bwd (16 cams, graph): {bsec * 1e3:.2f} ms/step, {views_s:.1f} views/s, "
             f"loss {step.loss.item():.5f}")
         result["batched_fwd_bwd_views_per_s"] = round(views_s, 2)
+        result["batched_tuning"] = {"batch": int(r.settings.batch),
+                                    "batch_bwd": int(r.settings.batch_bwd),
+                                    "variant": int(r.settings.variant)}
         result["batched_ms_per_step"] = round(bsec * 1e3, 3)
         step.close()
         del step, r, f, g, m, s4

@@ -138,8 +138,11 @@ typedef struct {
   int32_t batch;      /* Gaussians staged in LDS per batch: 32,64,128,256 (0 = tuned default) */
   int32_t variant;    /* blend variant: bit 0 two-deep LDS staging, bit 1 persistent
                          workgroups on a tile queue, bit 2 one 64-lane wave per tile with
-                         four pixels per lane (batch 64 or 128; bits 0-1 ignored; also
-                         selects the backward kernel). Chosen by hr_autotune; 0 = default */
+                         four pixels per lane (batch 64 or 128; bits 0-1 ignored) - these
+                         three chosen by hr_autotune; bit 3 the backward in one wave per
+                         tile (chosen by hr_autotune_backward). 0 = default */
+  int32_t batch_bwd;  /* Gaussians staged per batch by the backward: 0 (= batch), 32, 64,
+                         128, 256 */
 } hr_settings;
 
 /* Counters written by the forward (device memory). */
@@ -297,6 +300,17 @@ hr_status hr_full_loss(const float* image, const float* final_T, const float* me
                        int32_t n_images, float lambda_c, float lambda_t, float k,
                        int32_t mask_mode, uint32_t flags, float* loss_out, float* grad_image,
                        float* grad_final_T, float* grad_mesh_rgb, void* scratch, void* stream);
+
+/* Backward autotuner: with the workspace of a forward just run on the same
+ * arguments, times the backward blend (256-thread and one-wave kernels, LDS
+ * batch 64 and 128) on the given upstream gradients and writes the fastest
+ * choice to s->batch_bwd and bit 3 of s->variant. No gradient output is
+ * touched. Synchronises the stream. */
+hr_status hr_autotune_backward(const hr_gaussians* gaussians, const hr_mesh* mesh,
+                               const hr_camera* cams, int32_t n_cams, hr_settings* s,
+                               int64_t key_capacity, void* workspace, size_t workspace_bytes,
+                               const float* grad_image, const float* grad_final_T,
+                               int32_t repeats, void* stream);
 
 /* Autotuner: times the blend variants (LDS batch size and staging depth) on
  * the inputs of a forward that has just run with this workspace, checks that

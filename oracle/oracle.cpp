@@ -475,8 +475,10 @@ void mesh_pass(const or_scene& sc, const or_camera& cam, const or_params& p, int
         const double v = cam.fy * tv[k].p[1] / tv[k].p[2] + cam.cy;
         const double su = u * SUBPIX, sv = v * SUBPIX;
         if (!(std::fabs(su) <= (double)GUARD && std::fabs(sv) <= (double)GUARD)) skip = true;
-        if (std::fabs(std::fabs(su - std::floor(su)) - 0.5) <= 1e-9 * std::max(1.0, std::fabs(su)) ||
-            std::fabs(std::fabs(sv - std::floor(sv)) - 0.5) <= 1e-9 * std::max(1.0, std::fabs(sv)))
+        // two FP64 evaluations of the projection differ by ~1e-15 relative;
+        // a snap within 1e-13 of a rounding midpoint may round either way
+        if (std::fabs(std::fabs(su - std::floor(su)) - 0.5) <= 1e-13 * std::max(1.0, std::fabs(su)) ||
+            std::fabs(std::fabs(sv - std::floor(sv)) - 0.5) <= 1e-13 * std::max(1.0, std::fabs(sv)))
           amb = true;
         X[k] = skip ? 0 : (int64_t)std::nearbyint(su);
         Yv[k] = skip ? 0 : (int64_t)std::nearbyint(sv);

@@ -77,7 +77,10 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
     return fail(HR_ERR_INVALID_ARGUMENT, "low_pass must be >= 0 and clamp_fov > 0");
   if (s->batch != 0 && s->batch != 32 && s->batch != 64 && s->batch != 128 && s->batch != 256)
     return fail(HR_ERR_INVALID_ARGUMENT, "batch must be 0, 32, 64, 128 or 256");
-  if (s->variant < 0 || s->variant > 3) return fail(HR_ERR_INVALID_ARGUMENT, "variant must be in [0, 3]");
+  if (s->batch_bwd != 0 && s->batch_bwd != 32 && s->batch_bwd != 64 && s->batch_bwd != 128 &&
+      s->batch_bwd != 256)
+    return fail(HR_ERR_INVALID_ARGUMENT, "batch_bwd must be 0, 32, 64, 128 or 256");
+  if (s->variant < 0 || s->variant > 15) return fail(HR_ERR_INVALID_ARGUMENT, "variant must be in [0, 15]");
 
   p.n = g->n;
   p.n_cams = n_cams;
@@ -271,6 +274,7 @@ void upload_cams(const Plan& p, const Work& w, hipStream_t st) {
 }
 
 int pick_batch(const hr_settings* s) { return s->batch == 0 ? 64 : s->batch; }
+int pick_batch_bwd(const hr_settings* s) { return s->batch_bwd == 0 ? pick_batch(s) : s->batch_bwd; }
 
 // enqueue the whole forward
 void enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
@@ -293,7 +297,7 @@ void enqueue_backward(const Plan& p, const Work& w, const SetDev& S, const hr_ga
                       hipStream_t st) {
   (void)p;
   launch_zero_gacc(w.gacc, w.counters, st);
-  launch_blend_backward(S, w, grad_image, grad_T, pick_batch(s), s->variant, st);
+  launch_blend_backward(S, w, grad_image, grad_T, pick_batch_bwd(s), s->variant, st);
   launch_project_backward(S, w.cams, *g, w, grads, st);
   launch_texture_backward(S, *m, w, grad_image, grad_mesh, grads->tex, st);
 }
@@ -325,6 +329,7 @@ hr_settings hr_default_settings(void) {
   s.flags = 0;
   s.batch = 0;
   s.variant = 0;
+  s.batch_bwd = 0;
   return s;
 }
 
@@ -574,10 +579,57 @@ hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camer
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   s->batch = best_b;
-  s->variant = best_v;
+  s->variant = best_v | (s->variant & 8);
   // leave the outputs of the chosen variant in place
   launch_blend_forward(S, w, &o, best_b, best_v, st);
   return hip_check("autotune");
+}
+
+hr_status hr_autotune_backward(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                               int32_t n_cams, hr_settings* s, int64_t key_capacity,
+                               void* workspace, size_t workspace_bytes, const float* grad_image,
+                               const float* grad_T, int32_t repeats, void* stream) {
+  Plan p;
+  hr_status rc = make_plan(g, mesh, cams, n_cams, s, key_capacity, p);
+  if (rc != HR_OK) return rc;
+  if (!workspace || workspace_bytes < p.total)
+    return fail(HR_ERR_INVALID_ARGUMENT, "workspace smaller than hr_query_workspace()");
+  if (!grad_image) return fail(HR_ERR_INVALID_ARGUMENT, "grad_image is required");
+  if (repeats < 1) repeats = 1;
+  hipStream_t st = (hipStream_t)stream;
+  Work w = make_work(p, workspace);
+  SetDev S = make_setdev(p, g, mesh, s);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(HR_ERR_HIP, "event create failed");
+  const int cand[4][2] = {{64, 0}, {128, 0}, {64, 8}, {128, 8}};
+  float best = 1e30f;
+  int best_b = 64, best_v = 0;
+  for (const auto& c : cand) {
+    std::vector<float> times;
+    for (int r = 0; r < repeats + 1; ++r) {
+      hipEventRecord(e0, st);
+      launch_zero_gacc(w.gacc, w.counters, st);
+      launch_blend_backward(S, w, grad_image, grad_T, c[0], c[1], st);
+      hipEventRecord(e1, st);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) times.push_back(ms);
+    }
+    std::sort(times.begin(), times.end());
+    const float med = times[times.size() / 2];
+    if (med < best) {
+      best = med;
+      best_b = c[0];
+      best_v = c[1];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  s->batch_bwd = best_b;
+  s->variant = (s->variant & 7) | best_v;
+  return hip_check("backward autotune");
 }
 
 struct hr_batch {

@@ -858,7 +858,7 @@ void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int b
 void launch_blend_backward(const SetDev& S, const Work& w, const float* grad_image,
                            const float* grad_T, int batch, int variant, hipStream_t st) {
   if (S.n_tiles == 0) return;
-  if (variant & 4) {
+  if (variant & 8) {
     if (batch >= 128) HR_BWD_W(128);
     else HR_BWD_W(64);
     return;

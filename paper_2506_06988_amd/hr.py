@@ -47,7 +47,7 @@ class hr_settings(C.Structure):
     _fields_ = [("bg", C.c_float * 3), ("low_pass", C.c_float), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("t_min", C.c_float), ("near_gs", C.c_float),
                 ("near_mesh", C.c_float), ("clamp_fov", C.c_float), ("flags", C.c_uint32),
-                ("batch", C.c_int32), ("variant", C.c_int32)]
+                ("batch", C.c_int32), ("variant", C.c_int32), ("batch_bwd", C.c_int32)]
 
 
 class hr_outputs(C.Structure):
@@ -68,7 +68,7 @@ class hr_adam_group(C.Structure):
 
 EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid",
             "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
-            "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_mip_filter3d", "hr_autotune",
+            "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_mip_filter3d", "hr_autotune", "hr_autotune_backward",
             "hr_batch_create", "hr_batch_launch", "hr_batch_destroy", "hr_status_string",
             "hr_last_error", "hr_abi_version"]
 
@@ -108,6 +108,9 @@ def load(path: str = LIB_PATH):
     L.hr_full_loss.restype = C.c_int
     L.hr_full_loss.argtypes = [P, P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float,
                                C.c_int32, C.c_uint32, P, P, P, P, P, P]
+    L.hr_autotune_backward.restype = C.c_int
+    L.hr_autotune_backward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P,
+                                       C.c_int32, P]
     L.hr_autotune.restype = C.c_int
     L.hr_autotune.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, C.c_int32, P]
     L.hr_batch_create.restype = C.c_int
@@ -427,6 +430,16 @@ class Renderer:
                                  C.byref(self.settings), self.key_capacity, _ptr(self.ws),
                                  self.ws_bytes, C.byref(o), int(repeats), _stream()))
         return int(self.settings.batch), int(self.settings.variant)
+
+    def autotune_backward(self, grad_image, grad_final_T=None, repeats=5):
+        """hr_autotune_backward after a forward of this renderer; returns (batch_bwd, variant)."""
+        gs, ms = self._structs()
+        check(self.L.hr_autotune_backward(
+            C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams), C.byref(self.settings),
+            self.key_capacity, _ptr(self.ws), self.ws_bytes, _ptr(grad_image.contiguous()),
+            _ptr(None if grad_final_T is None else grad_final_T.contiguous()), int(repeats),
+            _stream()))
+        return int(self.settings.batch_bwd), int(self.settings.variant)
 
 
 def hybrid_loss(image, final_T, mesh_rgb, tri_id, target, lambda_t=0.1, k=20.0, detach_mask=False):

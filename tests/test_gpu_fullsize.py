@@ -36,6 +36,7 @@ def check_window(view, orc, win):
     im, T, mr, md, tri, nc, nb, npro = [v[..., y0:y1, x0:x1] for v in view]
     amb = orc["amb"] != 0
     good = ~amb
+    check_window.examined += float(orc["n_processed"].sum())
     np.testing.assert_array_equal(tri, orc["tri_id"])
     np.testing.assert_allclose(mr, orc["mesh_rgb"], atol=1e-5)
     d = np.abs(im - orc["image"])[:, good]
@@ -46,6 +47,9 @@ def check_window(view, orc, win):
     return int(amb.sum()), amb.size
 
 
+check_window.examined = 0.0
+
+
 def run_frames(hr, sc, cams, n_win, seed):
     g, m = hr.to_device(sc.gaussians, sc.mesh)
     r = hr.Renderer(g, m, cams)
@@ -53,6 +57,7 @@ def run_frames(hr, sc, cams, n_win, seed):
     torch.cuda.synchronize()
     rng = np.random.default_rng(seed)
     tot_amb = tot = 0
+    check_window.examined = 0.0
     for c, cam in enumerate(cams):
         view = [v.cpu().numpy() for v in f.view(c, cams)]
         for win in windows(cam, n_win, rng):
@@ -60,8 +65,12 @@ def run_frames(hr, sc, cams, n_win, seed):
             a, n = check_window(view, orc, win)
             tot_amb += a
             tot += n
-    say(f"{sc.name}: {len(cams)} cameras, ambiguous {tot_amb}/{tot}; stats {f.stats_dict()}")
-    assert tot_amb <= 0.01 * tot
+    # the bar of the parity tests: each examined pair lands in the alpha
+    # slack band with probability ~0.17 x 2e-5, plus the T-stop band
+    bar = 1e-3 + 1e-5 * check_window.examined / tot
+    say(f"{sc.name}: {len(cams)} cameras, ambiguous {tot_amb}/{tot} (bar {bar:.2e}); "
+        f"stats {f.stats_dict()}")
+    assert tot_amb <= bar * tot
     return r, f
 
 

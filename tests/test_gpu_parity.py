@@ -135,9 +135,12 @@ def test_many_rank_windows_and_pair_slices(hr):
     gi = torch.randn(3 * r.P, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
     g0 = r.render_hybrid_backward(gi)
     outs0 = [x.clone() for x in (f.image, f.final_T, f.n_contrib, f.n_blended, f.n_processed)]
-    r.settings.variant, r.settings.batch = 4, 128
+    r.settings.variant, r.settings.batch = 12, 128
     f4 = r.render_hybrid()
     g4 = r.render_hybrid_backward(gi)
+    bb, bv = r.autotune_backward(gi, repeats=2)
+    say(f"  backward autotune -> batch {bb} variant {bv}")
+    assert bv & 4 and bb in (64, 128)
     torch.cuda.synchronize()
     for x, y in zip(outs0, (f4.image, f4.final_T, f4.n_contrib, f4.n_blended, f4.n_processed)):
         assert torch.equal(x, y)
@@ -233,7 +236,7 @@ def tiny(seed, n=30, deg=3, w=48, h=40):
     return scenes.Scene(f"tiny{seed}", g, mesh, [cam])
 
 
-@pytest.mark.parametrize("seed,variant", [(101, 0), (102, 0), (103, 0), (101, 4), (104, 4)])
+@pytest.mark.parametrize("seed,variant", [(101, 0), (102, 0), (103, 0), (101, 12), (104, 8)])
 def test_backward_matches_oracle_gradient(hr, seed, variant):
     say(f"case: backward seed {seed} variant {variant}")
     sc = tiny(seed)
