@@ -170,6 +170,7 @@ def main():
         f"{blends_per_s:.3e} pairs/s, {achieved:.2f} TOP/s")
     hyb_stats = dict(pairs_examined_per_view=pairs // launches,
                      pairs_blended_per_view=blended // launches)
+    tuning = {"batch": int(r.settings.batch), "variant": int(r.settings.variant)}
     del r, frame, g, m
     torch.cuda.empty_cache()
 
@@ -193,7 +194,7 @@ def main():
         "blend_pairs_per_s": blends_per_s,
         "blend_ms_per_launch": round(blend_s / launches * 1e3, 4),
         "blend_stats": hyb_stats,
-        "blend_tuning": {"batch": int(r.settings.batch), "variant": int(r.settings.variant)},
+        "blend_tuning": tuning,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
                      "kernel": "k_blend_fwd", "ops_per_examined": BLEND_OPS_EXAMINED,
