@@ -52,19 +52,23 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gaussian-only", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="for counter runs: view 0 of the headline workload, 3 blend launches "
-                         "and 3 copies of a 256 MiB buffer (the scale of the byte counters)")
+                    help="for counter runs: views 1 and 2 of the headline workload, 3 blend "
+                         "launches each, and 3 copies of a 256 MiB buffer (the scale of the "
+                         "byte counters)")
     return ap.parse_args()
 
 
 def pmc_probe(torch, hr, scenes, dev):
     sc = scenes.config5("hybrid")
     g, m = hr.to_device(sc.gaussians, sc.mesh, device=dev)
-    r = hr.Renderer(g, m, [sc.cameras[0]])
-    frame = r.render_hybrid(sync_check=True)
+    r = hr.Renderer(g, m, [sc.cameras[1]])
+    frame = r.new_frame()
+    for v in (1, 2):  # two interior views with 1.2e5 and 1.7e5 visible Gaussians
+        r.set_cameras([sc.cameras[v]])
+        r.render_hybrid(frame, sync_check=True)
+        for _ in range(3):
+            r.blend_forward(frame)
     torch.cuda.synchronize()
-    for _ in range(3):
-        r.blend_forward(frame)
     src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(3):

@@ -35,10 +35,11 @@ struct Layout {
 
 // Offsets of every workspace region (bytes from the workspace base).
 struct Plan {
-  int64_t n, n_cams, M, F, MF, P, n_tiles, key_cap, rs_blocks, chunk_rows, mat_entries;
+  int64_t n, n_cams, M, F, MF, P, n_tiles, key_cap, rs_blocks, chunk_rows, mat_entries,
+      bin_items;
   size_t cams, counters, tiles, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, tiles_s, item_s, pair_off, mat, tile_total,
-      tile_start, tile_order, tile_dmax, slice_cnt, slice_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
+      tile_start, tile_order, tile_dmax, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, gacc, tune, scan_scratch, total;
   std::vector<CamDev> camdev;
 };
@@ -90,7 +91,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.key_cap = key_cap;
   if (p.M > (int64_t)0x7fffffff) return fail(HR_ERR_UNSUPPORTED, "n * n_cams must be < 2^31");
   p.camdev.resize(n_cams);
-  int64_t P = 0, tiles = 0, rows = 0, mat = 0;
+  int64_t P = 0, tiles = 0, rows = 0, mat = 0, items = 0;
   for (int c = 0; c < n_cams; ++c) {
     const hr_camera& h = cams[c];
     if (h.width < 1 || h.height < 1 || h.width > 16384 || h.height > 16384)
@@ -125,11 +126,14 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
     tiles += ntl;
     rows += d.chunk_rows;
     mat += (int64_t)d.chunk_rows * ntl;
+    items += (int64_t)d.chunk_rows * d.TY;
   }
   if (tiles > 0x7fffffffll) return fail(HR_ERR_UNSUPPORTED, "too many tiles");
   p.P = P;
   p.n_tiles = tiles;
   p.chunk_rows = rows;
+  if (items > 0xffffffffll) return fail(HR_ERR_UNSUPPORTED, "too many binning items");
+  p.bin_items = items;
   p.mat_entries = mat;
   p.rs_blocks = (p.M + 2047) / 2048;
 
@@ -160,8 +164,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.tile_start = L.take(4 * p.n_tiles);
   p.tile_order = L.take(4 * p.n_tiles);
   p.tile_dmax = L.take(4 * p.n_tiles);
-  p.slice_cnt = L.take(4 * (p.chunk_rows + 1));
-  p.slice_off = L.take(4 * (p.chunk_rows + 1));
+  p.item_off = L.take(4 * (p.n_cams + 1));
   p.lists = L.take(4 * key_cap);
   p.zbuf = L.take(8 * P);
   p.tri_cnt = L.take(4 * p.MF);
@@ -211,8 +214,8 @@ Work make_work(const Plan& p, void* ws) {
   w.tile_start = (uint32_t*)(b + p.tile_start);
   w.tile_order = (uint32_t*)(b + p.tile_order);
   w.tile_dmax = (uint32_t*)(b + p.tile_dmax);
-  w.slice_cnt = (uint32_t*)(b + p.slice_cnt);
-  w.slice_off = (uint32_t*)(b + p.slice_off);
+  w.item_off = (uint32_t*)(b + p.item_off);
+  w.bin_items_max = p.bin_items;
   w.lists = (uint32_t*)(b + p.lists);
   w.zbuf = (uint64_t*)(b + p.zbuf);
   w.tri_cnt = (uint32_t*)(b + p.tri_cnt);

@@ -14,6 +14,7 @@ constexpr int CHUNK = 2048;     // depth ranks per binning chunk
 constexpr int SORT_WIN = 8192;  // ranks one workgroup sorts in LDS at once
 constexpr int SUBPIX = 256;     // fixed-point steps per pixel for mesh vertices
 constexpr int64_t GUARD = (int64_t)1 << 29;  // |vertex| bound in fixed point (2^21 px)
+constexpr int MAX_TILE_COLS = 1024;       // 16384 px / 16
 constexpr int MAX_TILES_PER_CAM = 16384;     // LDS tile histogram of the binning kernels
 constexpr float LOG2E = 1.4426950408889634f;
 

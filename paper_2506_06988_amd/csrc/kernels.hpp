@@ -30,8 +30,8 @@ struct Work {
   // tile binning
   uint32_t* mat;         // chunk x tile counts, then column prefixes
   int64_t chunk_rows;    // total chunk rows
-  uint32_t* slice_cnt;   // [chunk_rows] pair slices per chunk row
-  uint32_t* slice_off;   // [chunk_rows] exclusive scan of slice_cnt
+  int64_t bin_items_max; // (chunk, tile row) binning items if every chunk were used
+  uint32_t* item_off;    // [n_cams + 1] first binning item of each camera, then the total
   uint32_t* tile_total;  // [n_tiles]
   uint32_t* tile_start;  // [n_tiles]
   uint32_t* tile_order;  // [n_tiles] blend schedule, longest lists first
@@ -39,7 +39,7 @@ struct Work {
   uint32_t* lists;       // [key_cap] ranks grouped by tile, chunk sub-segments in chunk order
   // counters: [0] n_vis, [1] overflow, [2..3] K (u64), [4] n_tris, [5] n_blocks,
   // [6..7] sum n_processed (u64), [8..9] sum n_blended (u64), [10..11] K scan total,
-  // [12] binning slices, [13] pairs kept in the tile lists
+  // [13] pairs kept in the tile lists
   uint32_t* counters;
   // mesh
   uint64_t* zbuf;        // [P] fp32 depth bits << 32 | triangle index

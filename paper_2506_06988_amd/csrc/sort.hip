@@ -7,19 +7,24 @@
 //     (camera, fp32 depth bits); stability keeps equal depths in index order,
 //     so an item's position (its rank) orders it by (depth, index);
 //  2. ranks are cut into chunks of CHUNK (the rows of a chunk x tile count
-//     matrix); the pairs of a chunk are cut into slices of SLICE pairs, the
-//     work units of persistent workgroups, so a few Gaussians that cover
-//     thousands of tiles spread over many workgroups;
-//  3. count pass: each slice histograms its pairs per tile in LDS and adds the
-//     bins into its chunk's row; a column scan turns the matrix into each
-//     (chunk, tile) sub-segment start and the per-tile totals and ranges;
-//  4. scatter pass: each slice reserves its share of every (chunk, tile)
-//     sub-segment with one atomic per bin and writes its ranks there; inside
-//     a sub-segment the order is that of the atomics.
+//     matrix); the work unit of both binning passes is one (chunk, tile row):
+//     the chunk's Gaussians whose tile rectangle spans that row, each
+//     contributing one run of tiles [x0, x1);
+//  3. count pass: a run adds +1 at x0 and -1 at x1 of an LDS difference row,
+//     whose prefix sum is the chunk's count for every tile of the row - two
+//     LDS atomics per (Gaussian, row) however many tiles it covers; a column
+//     scan turns the matrix into (chunk, tile) sub-segment starts, and the
+//     per-tile totals and ranges;
+//  4. scatter pass: the same unit writes every rank of its runs into the
+//     sub-segments of its row, a cursor per tile in LDS. One workgroup owns
+//     all of the (chunk, tile) sub-segments of its row, so its writes fill
+//     whole cache lines before they leave L2.
 // Chunk sub-segments follow each other in rank order, so ordering a tile's
 // list only needs the small rank windows of window.hpp, which the blend
 // kernels do in LDS for the windows they reach. The key traffic is one write
 // of a 4-byte rank per pair and one read per pair the blend reaches.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "window.hpp"
 
@@ -29,8 +34,9 @@ namespace {
 constexpr int RS_B = 256;             // radix-sort threads per block
 constexpr int RS_ROUNDS = 8;          // striped rounds per block
 constexpr int RS_KPB = RS_B * RS_ROUNDS;
-constexpr int SLICE = 8192;           // pairs per binning work unit
-constexpr int BIN_GRID = 512;         // persistent binning workgroups (2 per CU)
+constexpr int BIN_GRID = 2048;        // persistent binning workgroups (8 per CU)
+constexpr int MAX_TX = MAX_TILE_COLS; // widest tile row of a camera
+constexpr int WIDE_RUN = 32;          // runs wider than this are written by the whole group
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = __lane_id();
@@ -205,229 +211,160 @@ __device__ __forceinline__ ChunkInfo chunk_info(const CamDev* cams, int n_cams,
   return ci;
 }
 
-// per chunk row: number of pair slices; clears the row of used chunks
-__global__ __launch_bounds__(256) void k_row_slices(const CamDev* __restrict__ cams, int n_cams,
-                                                    const uint32_t* __restrict__ vis_off,
-                                                    const uint64_t* __restrict__ pair_off,
-                                                    uint32_t* __restrict__ slice_cnt,
-                                                    uint32_t* __restrict__ mat) {
-  const int64_t row = blockIdx.x;
-  const ChunkInfo ci = chunk_info(cams, n_cams, vis_off, row);
-  if (ci.r0 >= ci.r1) {
-    if (threadIdx.x == 0) slice_cnt[row] = 0;
-    return;
+// Binning items of every camera: (used chunk row, tile row) pairs, item_off[c]
+// the first of camera c and item_off[n_cams] the total.
+__global__ void k_bin_items(const CamDev* __restrict__ cams, int n_cams,
+                            const uint32_t* __restrict__ vis_off, uint32_t* __restrict__ item_off) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  uint32_t acc = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    item_off[c] = acc;
+    const uint32_t rows = (vis_off[c + 1] - vis_off[c] + CHUNK - 1) / CHUNK;
+    acc += rows * (uint32_t)cams[c].TY;
   }
-  const CamDev& cam = cams[ci.cam];
-  const int ntl = cam.TX * cam.TY;
-  if (threadIdx.x == 0) {
-    const uint64_t np = pair_off[ci.r1] - pair_off[ci.r0];
-    slice_cnt[row] = (uint32_t)((np + SLICE - 1) / SLICE);
-  }
-  uint32_t* r = mat + cam.mat_off + ci.c * (int64_t)ntl;
-  for (int t = threadIdx.x; t < ntl; t += 256) r[t] = 0;
+  item_off[n_cams] = acc;
 }
 
-// A slice: up to SLICE consecutive pairs of one chunk, with the pair offsets
-// of the ranks it overlaps staged in LDS (relative to its first pair).
-struct Slice {
-  int cam, ntl, nitems;
-  int64_t row, c, ia;      // first rank overlapped
-  uint64_t p0;
-  uint32_t np;
+struct BinItem {
+  int cam, y, TX, ntl;
+  int64_t chunk, r0, r1;  // chunk index in the camera; its ranks [r0, r1)
 };
 
-__device__ __forceinline__ int64_t last_le(const uint64_t* a, int64_t lo, int64_t hi, uint64_t v) {
-  // largest index in [lo, hi) with a[index] <= v (a[lo] <= v assumed)
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a[mid] <= v) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ bool load_slice(const CamDev* cams, int n_cams, const uint32_t* vis_off,
-                                           const uint64_t* pair_off, const uint32_t* slice_off,
-                                           int64_t rows_total, uint32_t sl, Slice& S,
-                                           int32_t* poff) {
-  // row holding slice sl
-  int64_t lo = 0, hi = rows_total - 1;
+__device__ __forceinline__ BinItem bin_item(const CamDev* cams, int n_cams,
+                                            const uint32_t* vis_off, const uint32_t* item_off,
+                                            uint32_t item) {
+  int lo = 0, hi = n_cams - 1;
   while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (slice_off[mid] <= sl) lo = mid; else hi = mid - 1;
+    const int mid = (lo + hi + 1) >> 1;
+    if (item_off[mid] <= item) lo = mid; else hi = mid - 1;
   }
-  const ChunkInfo ci = chunk_info(cams, n_cams, vis_off, lo);
-  S.row = lo;
-  S.cam = ci.cam;
-  S.c = ci.c;
-  S.ntl = cams[ci.cam].TX * cams[ci.cam].TY;
-  const uint64_t k = sl - slice_off[lo];
-  const uint64_t pc0 = pair_off[ci.r0], pc1 = pair_off[ci.r1];
-  S.p0 = pc0 + k * SLICE;
-  const uint64_t p1 = S.p0 + SLICE < pc1 ? S.p0 + SLICE : pc1;
-  S.np = (uint32_t)(p1 - S.p0);
-  S.ia = last_le(pair_off, ci.r0, ci.r1, S.p0);
-  const int64_t ib = last_le(pair_off, S.ia, ci.r1, p1 - 1);
-  S.nitems = (int)(ib - S.ia + 1);
-  for (int i = threadIdx.x; i <= S.nitems; i += blockDim.x)
-    poff[i] = (int32_t)((int64_t)pair_off[S.ia + i] - (int64_t)S.p0);
-  return S.np > 0;
+  BinItem b;
+  b.cam = lo;
+  const CamDev& cam = cams[lo];
+  const uint32_t li = item - item_off[lo];
+  b.chunk = li / (uint32_t)cam.TY;
+  b.y = (int)(li - (uint32_t)b.chunk * (uint32_t)cam.TY);
+  b.TX = cam.TX;
+  b.ntl = cam.TX * cam.TY;
+  b.r0 = (int64_t)vis_off[lo] + b.chunk * CHUNK;
+  const int64_t e = vis_off[lo + 1];
+  b.r1 = b.r0 + CHUNK < e ? b.r0 + CHUNK : e;
+  return b;
 }
 
-// Calls f(rank, tile) for every pair of the slice. Ranks with at most SMALL
-// pairs in the slice are walked by one thread each (tile by tile across
-// their rectangle); larger ones are shared by the whole workgroup.
-constexpr int SMALL = 32;
-
-template <typename F>
-__device__ __forceinline__ void slice_pairs(const Slice& S, const int32_t* poff, const uint2* rects,
-                                            int TX, uint32_t* big, uint32_t* nbig, F&& f) {
-  for (int k = threadIdx.x; k < S.nitems; k += blockDim.x) {
-    const int32_t lo = poff[k] > 0 ? poff[k] : 0;
-    const int32_t hi = poff[k + 1] < (int32_t)S.np ? poff[k + 1] : (int32_t)S.np;
-    if (hi - lo > SMALL) {
-      big[atomicAdd(nbig, 1u)] = (uint32_t)k;
-      continue;
-    }
-    if (hi <= lo) continue;
-    const uint2 rc = rects[k];
-    const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
-    const uint32_t wdt = x1 - x0;
-    const uint32_t loc = (uint32_t)(lo - poff[k]);
-    uint32_t ty = y0 + loc / wdt, tx = x0 + loc % wdt;
-    const uint32_t r = (uint32_t)(S.ia + k);
-    for (int32_t j = lo; j < hi; ++j) {
-      f(r, (int)(ty * (uint32_t)TX + tx));
-      if (++tx == x1) {
-        tx = x0;
-        ++ty;
-      }
-    }
-  }
-  __syncthreads();
-  const uint32_t nb = *nbig;
-  for (uint32_t i = 0; i < nb; ++i) {
-    const int k = (int)big[i];
-    const int32_t lo = poff[k] > 0 ? poff[k] : 0;
-    const int32_t hi = poff[k + 1] < (int32_t)S.np ? poff[k + 1] : (int32_t)S.np;
-    const uint2 rc = rects[k];
-    const uint32_t x0 = rc.x & 0xffffu, x1 = rc.x >> 16, y0 = rc.y & 0xffffu;
-    const uint32_t wdt = x1 - x0;
-    const uint32_t r = (uint32_t)(S.ia + k);
-    for (int32_t j = lo + (int32_t)threadIdx.x; j < hi; j += blockDim.x) {
-      const uint32_t loc = (uint32_t)(j - poff[k]);
-      const uint32_t ty = y0 + loc / wdt;
-      const uint32_t tx = x0 + loc - (loc / wdt) * wdt;
-      f(r, (int)(ty * (uint32_t)TX + tx));
-    }
-  }
+// The run of rank k in tile row y, or an empty one.
+__device__ __forceinline__ bool row_run(const uint2 rc, int y, int& x0, int& x1) {
+  x0 = (int)(rc.x & 0xffffu);
+  x1 = (int)(rc.x >> 16);
+  return y >= (int)(rc.y & 0xffffu) && y < (int)(rc.y >> 16);
 }
 
-// Stages the rectangles of the slice's ranks in LDS and, when culling behind
-// the mesh, their depth bits.
-__device__ __forceinline__ void stage_ranks(const Slice& S, const uint2* rect_s, const GRec* rec_s,
-                                            const uint32_t* tile_dmax, uint2* rects,
-                                            uint32_t* deps) {
-  for (int k = threadIdx.x; k < S.nitems; k += blockDim.x) rects[k] = rect_s[S.ia + k];
-  if (tile_dmax)
-    for (int k = threadIdx.x; k < S.nitems; k += blockDim.x)
-      deps[k] = __float_as_uint(rec_s[S.ia + k].depth);
-}
-
-// Mesh-depth culling (Sec. 3.4, joint rasterization): a pixel stops at the
-// first Gaussian whose depth reaches its mesh depth, so a Gaussian at or
-// behind the largest mesh depth of a tile (every pixel covered) can never
-// be blended there; such (Gaussian, tile) pairs are left out of the lists.
-
-// Pass 1: per (chunk, tile) pair counts. Persistent workgroups take slices in
-// turn; each histograms its pairs per tile in LDS and adds the non-zero bins
-// into the chunk's row of the count matrix. HT = LDS histogram entries.
-template <int HT>
+// Count pass: per (chunk, tile row), the chunk's pair count of every tile of
+// the row, written to the chunk's row of the count matrix.
 __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ cams, int n_cams,
                                                    const uint32_t* __restrict__ vis_off,
-                                                   const uint64_t* __restrict__ pair_off,
-                                                   const uint32_t* __restrict__ slice_off,
-                                                   int64_t rows_total,
-                                                   const uint32_t* __restrict__ counters,
+                                                   const uint32_t* __restrict__ item_off,
                                                    const uint2* __restrict__ rect_s,
                                                    const GRec* __restrict__ rec_s,
                                                    const uint32_t* __restrict__ tile_dmax,
                                                    uint32_t* __restrict__ mat) {
-  __shared__ uint32_t hist[HT];
-  __shared__ int32_t poff[CHUNK + 1];
-  __shared__ uint2 rects[CHUNK];
-  __shared__ uint32_t deps[CHUNK];
-  __shared__ uint32_t big[CHUNK];
-  __shared__ uint32_t nbig;
-  const uint32_t nsl = counters[12];
-  for (uint32_t sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
-    Slice S;
-    load_slice(cams, n_cams, vis_off, pair_off, slice_off, rows_total, sl, S, poff);
-    const CamDev& cam = cams[S.cam];
-    stage_ranks(S, rect_s, rec_s, tile_dmax, rects, deps);
-    for (int t = threadIdx.x; t < S.ntl; t += 256) hist[t] = 0;
-    if (threadIdx.x == 0) nbig = 0;
+  __shared__ int32_t diff[MAX_TX + 1];
+  __shared__ uint32_t red4[4];
+  const uint32_t n_items = item_off[n_cams];
+  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const BinItem B = bin_item(cams, n_cams, vis_off, item_off, it);
+    const CamDev& cam = cams[B.cam];
+    for (int x = threadIdx.x; x <= B.TX; x += 256) diff[x] = 0;
     __syncthreads();
-    const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off : nullptr;
-    slice_pairs(S, poff, rects, cam.TX, big, &nbig, [&](uint32_t r, int tl) {
-      if (!tdm || deps[r - (uint32_t)S.ia] < tdm[tl]) atomicAdd(&hist[tl], 1u);
-    });
+    const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off + B.y * B.TX : nullptr;
+    for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
+      int x0, x1;
+      if (!row_run(rect_s[k], B.y, x0, x1)) continue;
+      if (!tdm) {
+        atomicAdd(&diff[x0], 1);
+        atomicSub(&diff[x1], 1);
+      } else {
+        const uint32_t dep = __float_as_uint(rec_s[k].depth);
+        for (int x = x0; x < x1; ++x)
+          if (dep < tdm[x]) {
+            atomicAdd(&diff[x], 1);
+            atomicSub(&diff[x + 1], 1);
+          }
+      }
+    }
     __syncthreads();
-    uint32_t* row = mat + cam.mat_off + S.c * (int64_t)S.ntl;
-    for (int t = threadIdx.x; t < S.ntl; t += 256)
-      if (hist[t]) atomicAdd(&row[t], hist[t]);
+    // inclusive prefix of the difference row: 4 consecutive entries per thread
+    const int x0 = 4 * threadIdx.x;
+    int32_t v[4], s4 = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = x0 + q < B.TX ? diff[x0 + q] : 0;
+      s4 += v[q];
+    }
+    uint32_t total;
+    int32_t run = (int32_t)group_excl_scan((uint32_t)s4, red4, total);
+    uint32_t* row = mat + cam.mat_off + B.chunk * B.ntl + (int64_t)B.y * B.TX;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      run += v[q];
+      if (x0 + q < B.TX) row[x0 + q] = (uint32_t)run;
+    }
     __syncthreads();
   }
 }
 
-// Pass 2: every slice reserves its share of each (chunk, tile) sub-segment
-// with one atomic per non-zero bin, then scatters its ranks with LDS atomics.
-// Afterwards a matrix entry holds the end of its sub-segment.
-template <int HT>
+// Scatter pass: per (chunk, tile row), every rank of the row's runs goes to
+// the next free entry of its tile's sub-segment; afterwards the matrix entry
+// holds the end of that sub-segment (relative to the tile start).
 __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ cams, int n_cams,
                                                      const uint32_t* __restrict__ vis_off,
-                                                     const uint64_t* __restrict__ pair_off,
-                                                     const uint32_t* __restrict__ slice_off,
-                                                     int64_t rows_total,
-                                                     const uint32_t* __restrict__ counters,
+                                                     const uint32_t* __restrict__ item_off,
                                                      const uint2* __restrict__ rect_s,
                                                      const GRec* __restrict__ rec_s,
                                                      const uint32_t* __restrict__ tile_dmax,
                                                      uint32_t* __restrict__ mat,
                                                      const uint32_t* __restrict__ tile_start,
                                                      int64_t key_cap, uint32_t* __restrict__ lists) {
-  __shared__ uint32_t hist[HT];
-  __shared__ int32_t poff[CHUNK + 1];
-  __shared__ uint2 rects[CHUNK];
-  __shared__ uint32_t deps[CHUNK];
-  __shared__ uint32_t big[CHUNK];
-  __shared__ uint32_t nbig;
-  const uint32_t nsl = counters[12];
-  for (uint32_t sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
-    Slice S;
-    load_slice(cams, n_cams, vis_off, pair_off, slice_off, rows_total, sl, S, poff);
-    const CamDev& cam = cams[S.cam];
-    stage_ranks(S, rect_s, rec_s, tile_dmax, rects, deps);
-    for (int t = threadIdx.x; t < S.ntl; t += 256) hist[t] = 0;
-    if (threadIdx.x == 0) nbig = 0;
+  __shared__ uint32_t cur[MAX_TX];
+  __shared__ uint32_t wide[CHUNK];
+  __shared__ uint32_t nwide;
+  const uint32_t n_items = item_off[n_cams];
+  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const BinItem B = bin_item(cams, n_cams, vis_off, item_off, it);
+    const CamDev& cam = cams[B.cam];
+    const int trow = cam.tile_off + B.y * B.TX;
+    uint32_t* row = mat + cam.mat_off + B.chunk * B.ntl + (int64_t)B.y * B.TX;
+    for (int x = threadIdx.x; x < B.TX; x += 256) cur[x] = tile_start[trow + x] + row[x];
+    if (threadIdx.x == 0) nwide = 0;
     __syncthreads();
-    const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off : nullptr;
-    auto keep = [&](uint32_t r, int tl) { return !tdm || deps[r - (uint32_t)S.ia] < tdm[tl]; };
-    slice_pairs(S, poff, rects, cam.TX, big, &nbig, [&](uint32_t r, int tl) {
-      if (keep(r, tl)) atomicAdd(&hist[tl], 1u);
-    });
-    __syncthreads();
-    uint32_t* row = mat + cam.mat_off + S.c * (int64_t)S.ntl;
-    for (int t = threadIdx.x; t < S.ntl; t += 256) {
-      const uint32_t h = hist[t];
-      if (h) hist[t] = tile_start[cam.tile_off + t] + atomicAdd(&row[t], h);
+    const uint32_t* tdm = tile_dmax ? tile_dmax + trow : nullptr;
+    auto put = [&](int64_t k, int x) {
+      const uint32_t pos = atomicAdd(&cur[x], 1u);
+      if ((int64_t)pos < key_cap) lists[pos] = (uint32_t)k;
+    };
+    for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
+      int x0, x1;
+      if (!row_run(rect_s[k], B.y, x0, x1)) continue;
+      if (x1 - x0 > WIDE_RUN) {
+        wide[atomicAdd(&nwide, 1u)] = (uint32_t)(k - B.r0);
+        continue;
+      }
+      const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
+      for (int x = x0; x < x1; ++x)
+        if (!tdm || dep < tdm[x]) put(k, x);
     }
-    if (threadIdx.x == 0) nbig = 0;
     __syncthreads();
-    slice_pairs(S, poff, rects, cam.TX, big, &nbig, [&](uint32_t r, int tl) {
-      if (!keep(r, tl)) return;
-      const uint32_t pos = atomicAdd(&hist[tl], 1u);
-      if ((int64_t)pos < key_cap) lists[pos] = r;
-    });
+    const uint32_t nw = nwide;
+    for (uint32_t i = 0; i < nw; ++i) {
+      const int64_t k = B.r0 + wide[i];
+      int x0, x1;
+      row_run(rect_s[k], B.y, x0, x1);
+      const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
+      for (int x = x0 + (int)threadIdx.x; x < x1; x += 256)
+        if (!tdm || dep < tdm[x]) put(k, x);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < B.TX; x += 256) row[x] = cur[x] - tile_start[trow + x];
     __syncthreads();
   }
 }
@@ -608,36 +545,21 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, hr_ou
   uint64_t* Ktot = reinterpret_cast<uint64_t*>(w.counters + 10);
   scan_u64(w.tiles_s, w.pair_off, M + 1, Ktot, w.scan_scratch, st);
   hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, Ktot, S.key_cap, w.counters);
-  if (w.chunk_rows > 0) {
-    hipLaunchKernelGGL(k_row_slices, dim3((unsigned)w.chunk_rows), dim3(256), 0, st, w.cams, n_cams,
-                       w.vis_off, w.pair_off, w.slice_cnt, w.mat);
-    scan_u32(w.slice_cnt, w.slice_off, w.chunk_rows, w.counters + 12, w.scan_scratch, st);
-    if (S.max_tiles_cam <= 8192)
-      hipLaunchKernelGGL(k_bin_count<8192>, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams,
-                         w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s,
-                         w.rec_s, tdm, w.mat);
-    else
-      hipLaunchKernelGGL(k_bin_count<MAX_TILES_PER_CAM>, dim3(BIN_GRID), dim3(256), 0, st, w.cams,
-                         n_cams, w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters,
-                         w.rect_s, w.rec_s, tdm, w.mat);
-  }
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(BIN_GRID, w.bin_items_max));
+  hipLaunchKernelGGL(k_bin_items, dim3(1), dim3(64), 0, st, w.cams, n_cams, w.vis_off, w.item_off);
+  if (w.bin_items_max > 0)
+    hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
+                       w.item_off, w.rect_s, w.rec_s, tdm, w.mat);
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
   scan_u32(w.tile_total, w.tile_start, S.n_tiles, w.counters + 13, w.scan_scratch, st);
   hipLaunchKernelGGL(k_kept_total, dim3(1), dim3(1), 0, st, S.key_cap, w.counters);
   hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(256), 0, st, S.n_tiles, w.tile_total,
                      w.tile_order);
-  if (w.chunk_rows > 0) {
-    if (S.max_tiles_cam <= 8192)
-      hipLaunchKernelGGL(k_bin_scatter<8192>, dim3(BIN_GRID), dim3(256), 0, st, w.cams, n_cams,
-                         w.vis_off, w.pair_off, w.slice_off, w.chunk_rows, w.counters, w.rect_s,
-                         w.rec_s, tdm, w.mat, w.tile_start, S.key_cap, w.lists);
-    else
-      hipLaunchKernelGGL(k_bin_scatter<MAX_TILES_PER_CAM>, dim3(BIN_GRID), dim3(256), 0, st,
-                         w.cams, n_cams, w.vis_off, w.pair_off, w.slice_off, w.chunk_rows,
-                         w.counters, w.rect_s, w.rec_s, tdm, w.mat, w.tile_start, S.key_cap,
-                         w.lists);
-  }
+  if (w.bin_items_max > 0)
+    hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
+                       w.item_off, w.rect_s, w.rec_s, tdm, w.mat, w.tile_start, S.key_cap,
+                       w.lists);
   if (out && out->ranges)
     hipLaunchKernelGGL(k_ranges, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, S.n_tiles,
                        w.tile_start, w.tile_total, out->ranges);
