@@ -52,49 +52,32 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gaussian-only", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="for counter runs: views 1 and 2 of the headline workload, 3 blend "
-                         "launches each, and 3 copies of a 256 MiB buffer (the scale of the "
-                         "byte counters)")
+                    help="for counter runs: every view of the headline workload once (plus one "
+                         "extra blend), then 3 copies of a 256 MiB buffer (the scale of the byte "
+                         "counters)")
     return ap.parse_args()
 
 
 def pmc_probe(torch, hr, scenes, dev):
+    """One forward and one extra blend (batch 256, variant 0) of each of the
+    32 headline views, then 3 copies of a 256 MiB buffer: the dispatches the
+    byte counters are read over, and the copy that scales them."""
     sc = scenes.config5("hybrid")
     g, m = hr.to_device(sc.gaussians, sc.mesh, device=dev)
-    r = hr.Renderer(g, m, [sc.cameras[1]])
+    r = hr.Renderer(g, m, [sc.cameras[0]])
+    r.settings.batch, r.settings.variant = 256, 0
     frame = r.new_frame()
-    for v in (1, 2):  # two interior views with 1.2e5 and 1.7e5 visible Gaussians
+    for v in range(len(sc.cameras)):
         r.set_cameras([sc.cameras[v]])
         r.render_hybrid(frame, sync_check=True)
-        for _ in range(3):
-            r.blend_forward(frame)
+        r.blend_forward(frame)
     torch.cuda.synchronize()
     src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    log(f"pmc probe done: stats {frame.stats_dict()}, copy bytes {src.numel() * 4}")
-
-
-def timed_frames(torch, r, frame, views, steps, warmup):
-    """Renders views round robin; returns seconds per frame (events on the stream)."""
-    for k in range(warmup):
-        r.set_cameras([views[k % len(views)]])
-        r.render_hybrid(frame, sync_check=True)
-    torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(st)
-    for k in range(steps):
-        r.set_cameras([views[k % len(views)]])
-        r.render_hybrid(frame, sync_check=False)
-    e1.record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3 / steps, wall / steps
+    log(f"pmc probe done: 32 views, copy bytes {src.numel() * 4}")
 
 
 def main():

@@ -36,7 +36,8 @@ constexpr int RS_ROUNDS = 8;          // striped rounds per block
 constexpr int RS_KPB = RS_B * RS_ROUNDS;
 constexpr int BIN_GRID = 2048;        // persistent binning workgroups (8 per CU)
 constexpr int MAX_TX = MAX_TILE_COLS; // widest tile row of a camera
-constexpr int WIDE_RUN = 32;          // runs wider than this are written by the whole group
+constexpr int WIDE_RUN = 64;          // runs wider than this are written by the whole group
+constexpr int GROUP = 16;             // lanes that share one rank's run in the scatter
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = __lane_id();
@@ -342,15 +343,18 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
       const uint32_t pos = atomicAdd(&cur[x], 1u);
       if ((int64_t)pos < key_cap) lists[pos] = (uint32_t)k;
     };
-    for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
-      int x0, x1;
-      if (!row_run(rect_s[k], B.y, x0, x1)) continue;
-      if (x1 - x0 > WIDE_RUN) {
-        wide[atomicAdd(&nwide, 1u)] = (uint32_t)(k - B.r0);
-        continue;
+    // groups of GROUP lanes take one rank each and spread its run over their
+    // lanes, so one LDS atomic instruction serves up to GROUP tiles of a run
+    const int grp = (int)threadIdx.x / GROUP, sub = (int)threadIdx.x % GROUP;
+    for (int64_t k0 = B.r0; k0 < B.r1; k0 += 256 / GROUP) {
+      const int64_t k = k0 + grp;
+      int x0 = 0, x1 = 0;
+      if (k < B.r1 && row_run(rect_s[k], B.y, x0, x1) && x1 - x0 > WIDE_RUN) {
+        if (sub == 0) wide[atomicAdd(&nwide, 1u)] = (uint32_t)(k - B.r0);
+        x1 = x0;
       }
-      const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
-      for (int x = x0; x < x1; ++x)
+      const uint32_t dep = (tdm && x1 > x0) ? __float_as_uint(rec_s[k].depth) : 0u;
+      for (int x = x0 + sub; x < x1; x += GROUP)
         if (!tdm || dep < tdm[x]) put(k, x);
     }
     __syncthreads();
