@@ -80,6 +80,26 @@ def pmc_probe(torch, hr, scenes, dev):
     log(f"pmc probe done: 32 views, copy bytes {src.numel() * 4}")
 
 
+def timed_frames(torch, r, frame, views, steps, warmup):
+    """Renders views round robin; returns seconds per frame (events on the stream)."""
+    for k in range(warmup):
+        r.set_cameras([views[k % len(views)]])
+        r.render_hybrid(frame, sync_check=True)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for k in range(steps):
+        r.set_cameras([views[k % len(views)]])
+        r.render_hybrid(frame, sync_check=False)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3 / steps, wall / steps
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

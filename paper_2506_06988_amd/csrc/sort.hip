@@ -36,7 +36,7 @@ constexpr int RS_ROUNDS = 8;          // striped rounds per block
 constexpr int RS_KPB = RS_B * RS_ROUNDS;
 constexpr int BIN_GRID = 2048;        // persistent binning workgroups (8 per CU)
 constexpr int MAX_TX = MAX_TILE_COLS; // widest tile row of a camera
-constexpr int WIDE_RUN = 64;          // runs wider than this are written by the whole group
+constexpr int WIDE_RUN = 32;          // runs wider than this are written tile-major
 constexpr int GROUP = 16;             // lanes that share one rank's run in the scatter
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -316,7 +316,11 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
 
 // Scatter pass: per (chunk, tile row), every rank of the row's runs goes to
 // the next free entry of its tile's sub-segment; afterwards the matrix entry
-// holds the end of that sub-segment (relative to the tile start).
+// holds the end of that sub-segment (relative to the tile start). Narrow runs
+// are spread over groups of GROUP lanes with one LDS cursor atomic per tile;
+// wide runs are then written tile-major: each thread owns the cursors of its
+// tiles in registers and walks the wide ranks in order (no atomics, and each
+// thread's stores run along its own sub-segment).
 __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ cams, int n_cams,
                                                      const uint32_t* __restrict__ vis_off,
                                                      const uint32_t* __restrict__ item_off,
@@ -327,8 +331,10 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
                                                      const uint32_t* __restrict__ tile_start,
                                                      int64_t key_cap, uint32_t* __restrict__ lists) {
   __shared__ uint32_t cur[MAX_TX];
-  __shared__ uint32_t wide[CHUNK];
+  __shared__ uint32_t wide[CHUNK];      // x0 | x1 << 10 | rank offset << 21
+  __shared__ uint32_t wide_dep[CHUNK];  // depth bits (culling only)
   __shared__ uint32_t nwide;
+  static_assert(MAX_TX <= 1024 && CHUNK <= 2048, "wide run packing");
   const uint32_t n_items = item_off[n_cams];
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const BinItem B = bin_item(cams, n_cams, vis_off, item_off, it);
@@ -339,36 +345,45 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
     if (threadIdx.x == 0) nwide = 0;
     __syncthreads();
     const uint32_t* tdm = tile_dmax ? tile_dmax + trow : nullptr;
-    auto put = [&](int64_t k, int x) {
-      const uint32_t pos = atomicAdd(&cur[x], 1u);
-      if ((int64_t)pos < key_cap) lists[pos] = (uint32_t)k;
-    };
-    // groups of GROUP lanes take one rank each and spread its run over their
-    // lanes, so one LDS atomic instruction serves up to GROUP tiles of a run
+    // narrow runs: groups of GROUP lanes take one rank each
     const int grp = (int)threadIdx.x / GROUP, sub = (int)threadIdx.x % GROUP;
     for (int64_t k0 = B.r0; k0 < B.r1; k0 += 256 / GROUP) {
       const int64_t k = k0 + grp;
       int x0 = 0, x1 = 0;
-      if (k < B.r1 && row_run(rect_s[k], B.y, x0, x1) && x1 - x0 > WIDE_RUN) {
-        if (sub == 0) wide[atomicAdd(&nwide, 1u)] = (uint32_t)(k - B.r0);
+      if (k >= B.r1 || !row_run(rect_s[k], B.y, x0, x1)) {
+        x1 = x0;  // no run in this row
+      } else if (x1 - x0 > WIDE_RUN) {
+        if (sub == 0) {
+          const uint32_t q = atomicAdd(&nwide, 1u);
+          wide[q] = (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k - B.r0) << 21);
+          if (tdm) wide_dep[q] = __float_as_uint(rec_s[k].depth);
+        }
         x1 = x0;
       }
       const uint32_t dep = (tdm && x1 > x0) ? __float_as_uint(rec_s[k].depth) : 0u;
       for (int x = x0 + sub; x < x1; x += GROUP)
-        if (!tdm || dep < tdm[x]) put(k, x);
+        if (!tdm || dep < tdm[x]) {
+          const uint32_t pos = atomicAdd(&cur[x], 1u);
+          if ((int64_t)pos < key_cap) lists[pos] = (uint32_t)k;
+        }
     }
     __syncthreads();
+    // wide runs, tile-major
     const uint32_t nw = nwide;
-    for (uint32_t i = 0; i < nw; ++i) {
-      const int64_t k = B.r0 + wide[i];
-      int x0, x1;
-      row_run(rect_s[k], B.y, x0, x1);
-      const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
-      for (int x = x0 + (int)threadIdx.x; x < x1; x += 256)
-        if (!tdm || dep < tdm[x]) put(k, x);
+    for (int x = threadIdx.x; x < B.TX; x += 256) {
+      uint32_t c = cur[x];
+      const uint32_t tx = (uint32_t)x, lim = tdm ? tdm[x] : 0u;
+      for (uint32_t i = 0; i < nw; ++i) {
+        const uint32_t wr = wide[i];
+        const bool in = tx >= (wr & 1023u) && tx < ((wr >> 10) & 2047u) &&
+                        (!tdm || wide_dep[i] < lim);
+        if (in) {
+          if ((int64_t)c < key_cap) lists[c] = (uint32_t)B.r0 + (wr >> 21);
+          ++c;
+        }
+      }
+      row[x] = c - tile_start[trow + x];
     }
-    __syncthreads();
-    for (int x = threadIdx.x; x < B.TX; x += 256) row[x] = cur[x] - tile_start[trow + x];
     __syncthreads();
   }
 }
