@@ -36,8 +36,8 @@ constexpr int RS_ROUNDS = 8;          // striped rounds per block
 constexpr int RS_KPB = RS_B * RS_ROUNDS;
 constexpr int BIN_GRID = 2048;        // persistent binning workgroups (8 per CU)
 constexpr int MAX_TX = MAX_TILE_COLS; // widest tile row of a camera
-constexpr int WIDE_RUN = 32;          // runs wider than this are written tile-major
-constexpr int GROUP = 16;             // lanes that share one rank's run in the scatter
+constexpr int NARROW_RUN = 4;         // runs up to this wide are written by one lane
+constexpr int GROUP = 16;             // lanes that share one medium run in the scatter
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = __lane_id();
@@ -316,11 +316,12 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
 
 // Scatter pass: per (chunk, tile row), every rank of the row's runs goes to
 // the next free entry of its tile's sub-segment; afterwards the matrix entry
-// holds the end of that sub-segment (relative to the tile start). Narrow runs
-// are spread over groups of GROUP lanes with one LDS cursor atomic per tile;
-// wide runs are then written tile-major: each thread owns the cursors of its
-// tiles in registers and walks the wide ranks in order (no atomics, and each
-// thread's stores run along its own sub-segment).
+// holds the end of that sub-segment (relative to the tile start). Runs are
+// written three ways by width: short ones (at most NARROW_RUN tiles) by one
+// lane each, medium ones by groups of GROUP lanes (one LDS cursor atomic per
+// tile in both), and runs over more than half of the row tile-major: each
+// thread owns the cursors of its tiles in registers and walks those ranks in
+// order, without atomics, its stores running along its own sub-segment.
 __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ cams, int n_cams,
                                                      const uint32_t* __restrict__ vis_off,
                                                      const uint32_t* __restrict__ item_off,
@@ -333,8 +334,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
   __shared__ uint32_t cur[MAX_TX];
   __shared__ uint32_t wide[CHUNK];      // x0 | x1 << 10 | rank offset << 21
   __shared__ uint32_t wide_dep[CHUNK];  // depth bits (culling only)
-  __shared__ uint32_t nwide;
-  static_assert(MAX_TX <= 1024 && CHUNK <= 2048, "wide run packing");
+  __shared__ uint32_t mid[CHUNK];       // medium runs, same packing
+  __shared__ uint32_t nwide, nmid;
+  static_assert(MAX_TX <= 1024 && CHUNK <= 2048, "run packing");
   const uint32_t n_items = item_off[n_cams];
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const BinItem B = bin_item(cams, n_cams, vis_off, item_off, it);
@@ -342,30 +344,43 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
     const int trow = cam.tile_off + B.y * B.TX;
     uint32_t* row = mat + cam.mat_off + B.chunk * B.ntl + (int64_t)B.y * B.TX;
     for (int x = threadIdx.x; x < B.TX; x += 256) cur[x] = tile_start[trow + x] + row[x];
-    if (threadIdx.x == 0) nwide = 0;
+    if (threadIdx.x == 0) nwide = nmid = 0;
     __syncthreads();
     const uint32_t* tdm = tile_dmax ? tile_dmax + trow : nullptr;
-    // narrow runs: groups of GROUP lanes take one rank each
-    const int grp = (int)threadIdx.x / GROUP, sub = (int)threadIdx.x % GROUP;
-    for (int64_t k0 = B.r0; k0 < B.r1; k0 += 256 / GROUP) {
-      const int64_t k = k0 + grp;
-      int x0 = 0, x1 = 0;
-      if (k >= B.r1 || !row_run(rect_s[k], B.y, x0, x1)) {
-        x1 = x0;  // no run in this row
-      } else if (x1 - x0 > WIDE_RUN) {
-        if (sub == 0) {
-          const uint32_t q = atomicAdd(&nwide, 1u);
-          wide[q] = (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k - B.r0) << 21);
-          if (tdm) wide_dep[q] = __float_as_uint(rec_s[k].depth);
-        }
-        x1 = x0;
+    auto put = [&](uint32_t k, int x) {
+      const uint32_t pos = atomicAdd(&cur[x], 1u);
+      if ((int64_t)pos < key_cap) lists[pos] = k;
+    };
+    const int half = B.TX / 2;
+    // short runs by one lane; the others are sorted into the two lists
+    for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
+      int x0, x1;
+      if (!row_run(rect_s[k], B.y, x0, x1)) continue;
+      const uint32_t packed = (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k - B.r0) << 21);
+      const int w = x1 - x0;
+      if (w > NARROW_RUN && w > half) {
+        const uint32_t q = atomicAdd(&nwide, 1u);
+        wide[q] = packed;
+        if (tdm) wide_dep[q] = __float_as_uint(rec_s[k].depth);
+      } else if (w > NARROW_RUN) {
+        mid[atomicAdd(&nmid, 1u)] = packed;
+      } else {
+        const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
+        for (int x = x0; x < x1; ++x)
+          if (!tdm || dep < tdm[x]) put((uint32_t)k, x);
       }
-      const uint32_t dep = (tdm && x1 > x0) ? __float_as_uint(rec_s[k].depth) : 0u;
-      for (int x = x0 + sub; x < x1; x += GROUP)
-        if (!tdm || dep < tdm[x]) {
-          const uint32_t pos = atomicAdd(&cur[x], 1u);
-          if ((int64_t)pos < key_cap) lists[pos] = (uint32_t)k;
-        }
+    }
+    __syncthreads();
+    // medium runs: groups of GROUP lanes take one rank each
+    const uint32_t nm = nmid;
+    const int grp = (int)threadIdx.x / GROUP, sub = (int)threadIdx.x % GROUP;
+    for (uint32_t i = (uint32_t)grp; i < nm; i += 256 / GROUP) {
+      const uint32_t wr = mid[i];
+      const uint32_t k = (uint32_t)B.r0 + (wr >> 21);
+      const int x1 = (int)((wr >> 10) & 2047u);
+      const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
+      for (int x = (int)(wr & 1023u) + sub; x < x1; x += GROUP)
+        if (!tdm || dep < tdm[x]) put(k, x);
     }
     __syncthreads();
     // wide runs, tile-major
