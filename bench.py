@@ -37,6 +37,10 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # addressing and loop control are not counted.
 BLEND_OPS_EXAMINED = 11
 BLEND_OPS_BLENDED = 7
+# HBM bytes per blend launch over the 32 headline views, from the FETCH_SIZE
+# and WRITE_SIZE counter passes of `bench.py --pmc-probe` (scaled by a 256 MiB
+# copy: FETCH x2, WRITE x1), valid for the configuration they were taken with
+BLEND_TRAFFIC = {"batch": 256, "variant": 0, "bytes_per_launch": 202.9e6}
 
 
 def log(*a):
@@ -203,7 +207,11 @@ def main():
         "blend_stats": hyb_stats,
         "blend_tuning": tuning,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": (BLEND_TRAFFIC["bytes_per_launch"]
+                                 if (tuning["batch"], tuning["variant"]) ==
+                                 (BLEND_TRAFFIC["batch"], BLEND_TRAFFIC["variant"]) else None),
+                     "traffic_unit": "HBM bytes per launch",
                      "kernel": "k_blend_fwd", "ops_per_examined": BLEND_OPS_EXAMINED,
                      "ops_per_blended": BLEND_OPS_BLENDED, "ops_per_launch": ops // launches,
                      "avg_launch_ms": round(blend_s / launches * 1e3, 4)},
