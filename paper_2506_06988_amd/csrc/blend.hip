@@ -21,30 +21,31 @@ __device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, 
   return lo;
 }
 
-// LDS form of a record: conic pre-scaled so that G = exp2(p2), and the
-// exponent below which alpha = opacity * G falls under alpha_min
+// LDS form of a record: conic pre-scaled by log2(e) and the opacity folded
+// into the exponent, so that the unclamped alpha = opacity * G is exp2(p2);
+// alpha < alpha_min is then p2 < log2(alpha_min), one threshold for all
 struct Staged {
   float4 a;  // u, v, A2 = -ca/2 log2e, B2 = -cb log2e
-  float4 b;  // C2 = -cc/2 log2e, opacity, depth, skip threshold log2(alpha_min / opacity)
+  float4 b;  // C2 = -cc/2 log2e, log2(opacity), depth, opacity
   float4 c;  // r, g, b, unused
 };
 
-__device__ __forceinline__ Staged stage(const GRec& R, float amin) {
+__device__ __forceinline__ Staged stage(const GRec& R) {
   Staged s;
   s.a = make_float4(R.u, R.v, -0.5f * LOG2E * R.ca, -LOG2E * R.cb);
-  s.b = make_float4(-0.5f * LOG2E * R.cc, R.op, R.depth, __log2f(amin / R.op));
+  s.b = make_float4(-0.5f * LOG2E * R.cc, __log2f(R.op), R.depth, R.op);
   s.c = make_float4(R.r, R.g, R.b, 0.f);
   return s;
 }
 
-// exponent (log2 units) of the Gaussian at pixel centre (px, py); the
+// log2 of the unclamped alpha of the Gaussian at pixel centre (px, py); the
 // operation order is fixed so the backward reproduces the forward bit for bit
 __device__ __forceinline__ float gauss_p2(const float4& a, const float4& b, float px, float py,
                                           float& dx, float& dy) {
   dx = a.x - px;
   dy = a.y - py;
   const float dxx = dx * dx, dyy = dy * dy, dxy = dx * dy;
-  return __builtin_fmaf(a.z, dxx, __builtin_fmaf(b.x, dyy, a.w * dxy));
+  return __builtin_fmaf(a.z, dxx, __builtin_fmaf(b.x, dyy, __builtin_fmaf(a.w, dxy, b.y)));
 }
 
 struct TileCtx {
@@ -85,8 +86,8 @@ __device__ __forceinline__ int front_count(const Staged* sh, int n, float Dm) {
 }
 
 __device__ __forceinline__ void blend_batch(const Staged* sh, int n, int64_t pos0, float px,
-                                            float py, float Dm, float amax, float tmin,
-                                            PixState& ps) {
+                                            float py, float Dm, float lthr, float amax,
+                                            float tmin, PixState& ps) {
   // a Gaussian at or behind the mesh ends the pixel (Sec. 3.4)
   const int nv = front_count(sh, n, Dm);
   int stop = nv < n ? nv : -1;  // entry that ends the pixel, if any
@@ -96,8 +97,8 @@ __device__ __forceinline__ void blend_batch(const Staged* sh, int n, int64_t pos
     const float4 a = e->a, b = e->b;
     float dx, dy;
     const float p2 = gauss_p2(a, b, px, py, dx, dy);
-    if (p2 >= b.w) {  // else alpha < alpha_min: skipped
-      const float alpha = fminf(amax, b.y * __builtin_amdgcn_exp2f(p2));
+    if (p2 >= lthr) {  // else alpha < alpha_min: skipped
+      const float alpha = fminf(amax, __builtin_amdgcn_exp2f(p2));
       const float Tn = ps.T * (1.f - alpha);
       if (Tn < tmin) {
         stop = k;
@@ -176,7 +177,7 @@ __device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH
   unsigned long long key = ~0ull;
   if (tc.inside) key = A.zbuf[tc.p];
   const float Dm = key == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(key >> 32));
-  const float amin = S.alpha_min, amax = S.alpha_max, tmin = S.t_min;
+  const float lthr = __log2f(S.alpha_min), amax = S.alpha_max, tmin = S.t_min;
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
   PixState ps;
   ps.T = 1.f;
@@ -210,14 +211,14 @@ __device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH
         }
         win_extract(word, pre, q, (uint32_t)n, wbase, rk[0]);
         __syncthreads();
-        if (threadIdx.x < n) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)], amin);
+        if (threadIdx.x < n) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)]);
         __syncthreads();
-        if (!ps.done) blend_batch(sh[0], n, a + q, px, py, Dm, amax, tmin, ps);
+        if (!ps.done) blend_batch(sh[0], n, a + q, px, py, Dm, lthr, amax, tmin, ps);
       }
     } else {
       win_extract(word, pre, 0, (uint32_t)min((uint32_t)BG, total), wbase, rk[0]);
       __syncthreads();
-      if (threadIdx.x < min((uint32_t)BG, total)) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)], amin);
+      if (threadIdx.x < min((uint32_t)BG, total)) sh[0][threadIdx.x] = stage(rec_s[min(rk[0][threadIdx.x], rmax)]);
       for (int bi = 0; bi < nbat; ++bi) {
         const int cur = bi & 1;
         const uint32_t q = (uint32_t)bi * BG;
@@ -231,8 +232,8 @@ __device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH
         }
         GRec nxt;
         if (threadIdx.x < nn) nxt = rec_s[min(rk[cur ^ 1][threadIdx.x], rmax)];
-        if (!ps.done) blend_batch(sh[cur], n, a + q, px, py, Dm, amax, tmin, ps);
-        if (threadIdx.x < nn) sh[cur ^ 1][threadIdx.x] = stage(nxt, amin);
+        if (!ps.done) blend_batch(sh[cur], n, a + q, px, py, Dm, lthr, amax, tmin, ps);
+        if (threadIdx.x < nn) sh[cur ^ 1][threadIdx.x] = stage(nxt);
       }
     }
   }
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
   const CamDev& C = cams[tc.cam];
   const WinCtx W = win_ctx(C, tc.cam, t, vis_off, mat, tile_start, tile_total, S.key_cap);
   const float px = (float)tc.i + 0.5f, py = (float)tc.j + 0.5f;
-  const float amin = S.alpha_min, amax = S.alpha_max;
+  const float lthr = __log2f(S.alpha_min), amax = S.alpha_max;
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
   float gr = 0.f, gg = 0.f, gb = 0.f, gT = 0.f, Tf = 1.f;
   int nc = 0;
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
       if (threadIdx.x < n) {
         const uint32_t r = min(rk[threadIdx.x], rmax);
         const GRec R = rec_s[r];
-        sh[threadIdx.x] = stage(R, amin);
+        sh[threadIdx.x] = stage(R);
         raw[threadIdx.x] = make_float4(R.ca, R.cb, R.cc, 0.f);
         rk[threadIdx.x] = r;
       }
@@ -401,26 +402,28 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
         if (contrib) {
           float dx, dy;
           const float p2 = gauss_p2(sa, sb, px, py, dx, dy);
-          contrib = p2 >= sb.w;  // the forward's skip decision
-          const float G = __builtin_amdgcn_exp2f(p2);
-          const float ag = sb.y * G;
+          contrib = p2 >= lthr;  // the forward's skip decision
+          const float ag = __builtin_amdgcn_exp2f(p2);  // opacity * G
           const float alpha = fminf(amax, ag);
           if (contrib) {
             const float4 c = sh[k].c;
-            T = T / (1.f - alpha);  // transmittance in front of this Gaussian
+            // transmittance in front of this Gaussian (v_rcp: 1 ulp, against
+            // the ~10 instructions of a correctly rounded division)
+            const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+            T = T * inv;
             const float wgt = alpha * T;
             g[6] = wgt * gr;
             g[7] = wgt * gg;
             g[8] = wgt * gb;
             const float galpha = T * ((c.x - Sr) * gr + (c.y - Sg) * gg + (c.z - Sb) * gb) -
-                                 gT * Tf / (1.f - alpha);
+                                 gT * Tf * inv;
             Sr = alpha * c.x + (1.f - alpha) * Sr;
             Sg = alpha * c.y + (1.f - alpha) * Sg;
             Sb = alpha * c.z + (1.f - alpha) * Sb;
             if (ag < amax) {
-              g[5] = galpha * G;
+              g[5] = galpha * ag * __builtin_amdgcn_rcpf(sb.w);  // d alpha / d opacity = G
               // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy with dx = u - px
-              const float gp = galpha * sb.y * G;
+              const float gp = galpha * ag;
               const float4 rw = raw[k];
               g[0] = -gp * (rw.x * dx + rw.y * dy);
               g[1] = -gp * (rw.z * dy + rw.y * dx);
@@ -518,7 +521,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
   const int j0 = ty * TILE + WPIX * (lane >> 4);
   const WinCtx W = win_ctx(C, cam, t, A.vis_off, A.mat, A.tile_start, A.tile_total, S.key_cap);
   const float px = (float)i + 0.5f;
-  const float amin = S.alpha_min, amax = S.alpha_max, tmin = S.t_min;
+  const float lthr = __log2f(S.alpha_min), amax = S.alpha_max, tmin = S.t_min;
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
   float T[WPIX], cr[WPIX], cg[WPIX], cb[WPIX], Dm[WPIX], py[WPIX];
   int nc[WPIX], nbl[WPIX], npro[WPIX];
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
       __syncthreads();
       wave_extract(ww, q, (uint32_t)n, wbase, rk);
       __syncthreads();
-      for (int s2 = lane; s2 < n; s2 += 64) sh[s2] = stage(A.rec_s[min(rk[s2], rmax)], amin);
+      for (int s2 = lane; s2 < n; s2 += 64) sh[s2] = stage(A.rec_s[min(rk[s2], rmax)]);
       __syncthreads();
       const int pos0 = (int)(a + q) + 1;
       const Staged* e = sh;
@@ -583,9 +586,10 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
           }
           const float dy = ea.y - py[r];
           const float dyy = dy * dy, dxy = dx * dy;
-          const float p2 = __builtin_fmaf(ea.z, dxx, __builtin_fmaf(eb.x, dyy, ea.w * dxy));
-          if (p2 >= eb.w) {
-            const float alpha = fminf(amax, eb.y * __builtin_amdgcn_exp2f(p2));
+          const float p2 =
+              __builtin_fmaf(ea.z, dxx, __builtin_fmaf(eb.x, dyy, __builtin_fmaf(ea.w, dxy, eb.y)));
+          if (p2 >= lthr) {
+            const float alpha = fminf(amax, __builtin_amdgcn_exp2f(p2));
             const float Tn = T[r] * (1.f - alpha);
             if (Tn < tmin) {
               done[r] = true;
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
   const int j0 = ty * TILE + WPIX * (lane >> 4);
   const WinCtx W = win_ctx(C, cam, t, vis_off, mat, tile_start, tile_total, S.key_cap);
   const float px = (float)i + 0.5f;
-  const float amin = S.alpha_min, amax = S.alpha_max;
+  const float lthr = __log2f(S.alpha_min), amax = S.alpha_max;
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
   const int64_t hw = (int64_t)C.W * C.H;
   float gr[WPIX], gg[WPIX], gb[WPIX], gT[WPIX], Tf[WPIX], T[WPIX], Sr[WPIX], Sg[WPIX], Sb[WPIX],
@@ -733,7 +737,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
       __syncthreads();
       for (int s2 = lane; s2 < n; s2 += 64) {
         const uint32_t r = min(rk[s2], rmax);
-        sh[s2] = stage(rec_s[r], amin);
+        sh[s2] = stage(rec_s[r]);
         rk[s2] = r;
       }
       __syncthreads();
@@ -742,6 +746,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
         const float4 ea = sh[k].a, eb = sh[k].b;
         const float dx = ea.x - px;
         const float dxx = dx * dx;
+        const float iop = __builtin_amdgcn_rcpf(eb.w);
         float g[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) g[q] = 0.f;
@@ -751,30 +756,32 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
           if (idx > nc[r]) continue;
           const float dy = ea.y - py[r];
           const float dyy = dy * dy, dxy = dx * dy;
-          const float p2 = __builtin_fmaf(ea.z, dxx, __builtin_fmaf(eb.x, dyy, ea.w * dxy));
-          if (!(p2 >= eb.w)) continue;  // the forward's skip decision
+          const float p2 =
+              __builtin_fmaf(ea.z, dxx, __builtin_fmaf(eb.x, dyy, __builtin_fmaf(ea.w, dxy, eb.y)));
+          if (!(p2 >= lthr)) continue;  // the forward's skip decision
           any = true;
-          const float G = __builtin_amdgcn_exp2f(p2);
-          const float ag = eb.y * G;
+          const float ag = __builtin_amdgcn_exp2f(p2);  // opacity * G
           const float alpha = fminf(amax, ag);
           const float4 c = sh[k].c;
-          T[r] = T[r] / (1.f - alpha);  // transmittance in front of this Gaussian
+          // transmittance in front of this Gaussian (v_rcp, 1 ulp)
+          const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+          T[r] = T[r] * inv;
           const float wgt = alpha * T[r];
           g[6] += wgt * gr[r];
           g[7] += wgt * gg[r];
           g[8] += wgt * gb[r];
           const float galpha = T[r] * ((c.x - Sr[r]) * gr[r] + (c.y - Sg[r]) * gg[r] +
                                        (c.z - Sb[r]) * gb[r]) -
-                               gT[r] * Tf[r] / (1.f - alpha);
+                               gT[r] * Tf[r] * inv;
           Sr[r] = alpha * c.x + (1.f - alpha) * Sr[r];
           Sg[r] = alpha * c.y + (1.f - alpha) * Sg[r];
           Sb[r] = alpha * c.z + (1.f - alpha) * Sb[r];
           if (ag < amax) {
-            g[5] += galpha * G;
+            g[5] += galpha * ag * iop;  // d alpha / d opacity = G
             // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy, dx = u - px; the
             // staged exponent holds A2 = -ca log2e / 2, B2 = -cb log2e,
             // C2 = -cc log2e / 2
-            const float gp = galpha * eb.y * G;
+            const float gp = galpha * ag;
             const float gl = gp * LN2F;
             g[0] += gl * (2.f * ea.z * dx + ea.w * dy);
             g[1] += gl * (2.f * eb.x * dy + ea.w * dx);
