@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gaussian-only", action="store_true")
+    ap.add_argument("--pmc-probe-step", action="store_true",
+                    help="for counter runs: one forward + loss + backward of the 16-camera "
+                         "step (one-wave backward, batch 128)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: every view of the headline workload once (plus one "
                          "extra blend), then 3 copies of a 256 MiB buffer (the scale of the byte "
@@ -82,6 +85,19 @@ def pmc_probe(torch, hr, scenes, dev):
         dst.copy_(src)
     torch.cuda.synchronize()
     log(f"pmc probe done: 32 views, copy bytes {src.numel() * 4}")
+
+
+def pmc_probe_step(torch, hr, scenes, dev):
+    s4 = scenes.config4()
+    g, m = hr.to_device(s4.gaussians, s4.mesh, device=dev)
+    r = hr.Renderer(g, m, s4.cameras)
+    r.settings.batch, r.settings.variant, r.settings.batch_bwd = 256, 8, 128
+    f = r.render_hybrid(sync_check=True)
+    target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
+    _, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target)
+    r.render_hybrid_backward(gi, gt, gm)
+    torch.cuda.synchronize()
+    log("pmc step probe done")
 
 
 def timed_frames(torch, r, frame, views, steps, warmup):
@@ -121,6 +137,9 @@ def main():
     dev = "cuda:0"
     if args.pmc_probe:
         pmc_probe(torch, hr, scenes, dev)
+        return
+    if args.pmc_probe_step:
+        pmc_probe_step(torch, hr, scenes, dev)
         return
 
     # ----------------------------------------------------- headline: 1080p
