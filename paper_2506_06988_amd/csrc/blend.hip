@@ -663,6 +663,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
   __shared__ Staged sh[BG];
   __shared__ uint32_t rk[BG];
   __shared__ uint32_t bitmap[WIN_WORDS];
+  __shared__ float rowsum[4][12];  // per row of 16 lanes: the 9 record gradients
   const int t = (int)tile_order[blockIdx.x];
   const int cam = find_cam_by_tile(cams, S.n_cams, t);
   const CamDev& C = cams[cam];
@@ -747,9 +748,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
         const float dx = ea.x - px;
         const float dxx = dx * dx;
         const float iop = __builtin_amdgcn_rcpf(eb.w);
-        float g[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) g[q] = 0.f;
+        // per lane, over its four pixels: colour gradients, and the sums
+        // s0 = sum gp, s1 = sum gp dy, s2 = sum gp dy^2 (gp = dL/dpower),
+        // from which the mean, conic and opacity gradients follow since dx
+        // is common to the lane's pixels
+        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
         bool any = false;
 #pragma unroll
         for (int r = 0; r < WPIX; ++r) {
@@ -767,9 +770,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
           const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
           T[r] = T[r] * inv;
           const float wgt = alpha * T[r];
-          g[6] += wgt * gr[r];
-          g[7] += wgt * gg[r];
-          g[8] += wgt * gb[r];
+          gc0 = __builtin_fmaf(wgt, gr[r], gc0);
+          gc1 = __builtin_fmaf(wgt, gg[r], gc1);
+          gc2 = __builtin_fmaf(wgt, gb[r], gc2);
           const float galpha = T[r] * ((c.x - Sr[r]) * gr[r] + (c.y - Sg[r]) * gg[r] +
                                        (c.z - Sb[r]) * gb[r]) -
                                gT[r] * Tf[r] * inv;
@@ -777,27 +780,40 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
           Sg[r] = alpha * c.y + (1.f - alpha) * Sg[r];
           Sb[r] = alpha * c.z + (1.f - alpha) * Sb[r];
           if (ag < amax) {
-            g[5] += galpha * ag * iop;  // d alpha / d opacity = G
-            // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy, dx = u - px; the
-            // staged exponent holds A2 = -ca log2e / 2, B2 = -cb log2e,
-            // C2 = -cc log2e / 2
             const float gp = galpha * ag;
-            const float gl = gp * LN2F;
-            g[0] += gl * (2.f * ea.z * dx + ea.w * dy);
-            g[1] += gl * (2.f * eb.x * dy + ea.w * dx);
-            g[2] += -0.5f * gp * dxx;
-            g[3] += -gp * dxy;
-            g[4] += -0.5f * gp * dyy;
+            s0 += gp;
+            s1 = __builtin_fmaf(gp, dy, s1);
+            s2 = __builtin_fmaf(gp, dyy, s2);
           }
         }
         if (__any(any)) {
+          // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy, dx = u - px; the
+          // staged exponent holds A2 = -ca log2e / 2, B2 = -cb log2e,
+          // C2 = -cc log2e / 2; d alpha / d opacity = G = gp / (alpha' opacity)
+          float g[9];
+          g[0] = LN2F * (2.f * ea.z * dx * s0 + ea.w * s1);
+          g[1] = LN2F * (2.f * eb.x * s1 + ea.w * dx * s0);
+          g[2] = -0.5f * dxx * s0;
+          g[3] = -dx * s1;
+          g[4] = -0.5f * s2;
+          g[5] = s0 * iop;
+          g[6] = gc0;
+          g[7] = gc1;
+          g[8] = gc2;
+          // rows of 16 lanes by DPP, then the 4 row sums through LDS; lanes
+          // 0-8 add one gradient each
 #pragma unroll
-          for (int q = 0; q < 9; ++q) g[q] = wave_sum_to_last(g[q]);
-          if (lane == 63) {
-            float* dst = gacc + (size_t)rk[k] * 9;
+          for (int q = 0; q < 9; ++q) g[q] = row_sum_to_last(g[q]);
+          if ((lane & 15) == 15) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) atomicAdd(dst + q, g[q]);
+            for (int q = 0; q < 9; ++q) rowsum[lane >> 4][q] = g[q];
           }
+          __syncthreads();
+          if (lane < 9) {
+            const float v = rowsum[0][lane] + rowsum[1][lane] + rowsum[2][lane] + rowsum[3][lane];
+            atomicAdd(gacc + (size_t)rk[k] * 9 + lane, v);
+          }
+          __syncthreads();
         }
       }
     }

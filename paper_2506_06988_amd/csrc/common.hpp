@@ -88,6 +88,15 @@ __device__ __forceinline__ float dpp_f(float v) {
 // Sum over the 64 lanes of a wave, complete in lane 63: shifts by 1, 2, 4, 8
 // within each row of 16 lanes, then row 0 -> row 1 and row 2 -> row 3
 // (broadcast of lane 15), then rows 0-1 -> rows 2-3 (broadcast of lane 31).
+// Sum over each row of 16 lanes, complete in the row's last lane (15, 31, 47, 63).
+__device__ __forceinline__ float row_sum_to_last(float v) {
+  v += dpp_f<0x111>(v);
+  v += dpp_f<0x112>(v);
+  v += dpp_f<0x114>(v);
+  v += dpp_f<0x118>(v);
+  return v;
+}
+
 __device__ __forceinline__ float wave_sum_to_last(float v) {
   v += dpp_f<0x111>(v);
   v += dpp_f<0x112>(v);
