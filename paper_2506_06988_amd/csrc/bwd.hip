@@ -20,15 +20,17 @@ __global__ __launch_bounds__(128) void k_project_bwd(
     float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
     float* __restrict__ g_logit, float* __restrict__ g_sh, float* __restrict__ m2d_norm,
     int32_t* __restrict__ m2d_count) {
+  // the 3K SH-coefficient gradients of this thread's Gaussian live in its own
+  // column of LDS (registers would cap the kernel at one wave per SIMD)
+  __shared__ float shacc[48 * 128];
+  float* gshr_col = shacc + threadIdx.x;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= S.n) return;
   float stat_norm = 0.f;
   int stat_cnt = 0;
   const int K = (S.sh_degree + 1) * (S.sh_degree + 1);
   double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glg = 0;
-  float gshr[48];
-#pragma unroll
-  for (int k = 0; k < 48; ++k) gshr[k] = 0.f;
+  for (int k = 0; k < 3 * K; ++k) gshr_col[k * 128] = 0.f;
   bool any = false;
   const float* shg = sh + (size_t)g * K * 3;
   for (int c = 0; c < S.n_cams; ++c) {
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(128) void k_project_bwd(
       if (P.clamped[ch]) continue;
       const double gc = G9[6 + ch];
       for (int k = 0; k < K; ++k) {
-        gshr[3 * k + ch] += (float)(Y[k] * gc);
+        gshr_col[(3 * k + ch) * 128] += (float)(Y[k] * gc);
         wdir[k] += (double)shg[3 * k + ch] * gc;
       }
     }
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(128) void k_project_bwd(
     for (int a = 0; a < 4; ++a) g_q[4 * g + a] += (float)gq[a];
   if (g_logit) g_logit[g] += (float)glg;
   if (g_sh)
-    for (int k = 0; k < 3 * K; ++k) g_sh[(size_t)g * K * 3 + k] += gshr[k];
+    for (int k = 0; k < 3 * K; ++k) g_sh[(size_t)g * K * 3 + k] += gshr_col[k * 128];
 }
 
 
@@ -204,7 +206,7 @@ __device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, 
   return lo;
 }
 
-constexpr int TEX_LDS = 4096;  // texels of one tile's footprint accumulated in LDS
+constexpr int TEX_LDS = 1024;  // texels of one tile's footprint accumulated in LDS
 
 // dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights.
 // One workgroup per tile: the texels the tile's pixels read from its most
