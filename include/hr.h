@@ -90,7 +90,7 @@ typedef struct {
  * ((i + 1/2)/W, (j + 1/2)/H), row 0 at V = 0, clamped at the edges. */
 typedef struct {
   int32_t n_verts, n_faces; /* n_faces = 0: no mesh (Gaussians over bg) */
-  int32_t n_tex, tex_h, tex_w;  /* texture sides below 32768 */
+  int32_t n_tex, tex_h, tex_w;
   const float* verts;      /* [n_verts,3] */
   const int32_t* faces;    /* [n_faces,3] vertex indices */
   const float* uvs;        /* [n_faces,3,2] */

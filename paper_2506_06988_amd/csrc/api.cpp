@@ -40,7 +40,7 @@ struct Plan {
   size_t cams, counters, tiles, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, tiles_s, item_s, pair_off, mat, tile_total,
       tile_start, tile_order, tile_dmax, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
-      mesh_rgb, taps, gacc, tune, scan_scratch, total;
+      mesh_rgb, gacc, tune, scan_scratch, total;
   std::vector<CamDev> camdev;
 };
 
@@ -65,8 +65,6 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
       return fail(HR_ERR_INVALID_ARGUMENT, "null mesh array");
     if (m->n_verts < 3 || m->n_tex < 1 || m->tex_h < 1 || m->tex_w < 1)
       return fail(HR_ERR_INVALID_ARGUMENT, "mesh needs >= 3 vertices and a texture");
-    if (m->tex_h > 32767 || m->tex_w > 32767)
-      return fail(HR_ERR_UNSUPPORTED, "texture sides must be below 32768 texels");
     if (m->n_faces > (1 << 30)) return fail(HR_ERR_INVALID_ARGUMENT, "too many faces");
   }
   if (key_cap < 0 || key_cap > (int64_t)0xffffffffll)
@@ -177,7 +175,6 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.final_T = L.take(4 * P);
   p.n_contrib = L.take(4 * P);
   p.mesh_rgb = L.take(12 * P);
-  p.taps = L.take(16 * P);
   p.gacc = L.take(36 * M);
   p.tune = L.take(16 * P + 256);
   int64_t longest =
@@ -229,7 +226,6 @@ Work make_work(const Plan& p, void* ws) {
   w.final_T = (float*)(b + p.final_T);
   w.n_contrib = (int32_t*)(b + p.n_contrib);
   w.mesh_rgb = (float*)(b + p.mesh_rgb);
-  w.taps = (uint4*)(b + p.taps);
   w.gacc = (float*)(b + p.gacc);
   w.scan_scratch = b + p.scan_scratch;
   return w;

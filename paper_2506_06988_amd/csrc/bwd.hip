@@ -215,7 +215,8 @@ constexpr int TEX_LDS = 1024;  // texels of one tile's footprint accumulated in 
 // to the gradient with one global atomic per non-zero texel channel. Pixels
 // on other textures, and tiles whose box is too large, add directly.
 __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restrict__ cams,
-                                                 const uint4* __restrict__ taps,
+                                                 const unsigned long long* __restrict__ zbuf,
+                                                 const TriRec* __restrict__ tris,
                                                  const float* __restrict__ T_ws,
                                                  const float* __restrict__ grad_image,
                                                  const float* __restrict__ grad_mesh,
@@ -235,12 +236,12 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
   }
   bool live = false;
   float gm[3] = {0.f, 0.f, 0.f};
-  Taps tp = {0, 0, 0, 0, 0.f, 0.f, 0, 0, 0, 0};
+  Taps tp = {0, 0, 0, 0, 0.f, 0.f};
   int tex = 0;
   if (i < C.W && j < C.H) {
     const int64_t p = C.pix_off + (int64_t)j * C.W + i;
-    const uint4 tq = taps[p];  // the forward's texel footprint
-    if (tq.y != 0xffffffffu) {
+    const unsigned long long key = zbuf[p];
+    if (key != ~0ull) {
       const int64_t hw = (int64_t)C.W * C.H;
       const int64_t pl = 3 * C.pix_off + (p - C.pix_off);
       const float Tf = T_ws[p];
@@ -250,8 +251,13 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
                  (grad_mesh ? grad_mesh[pl + ch * hw] : 0.f);
       live = gm[0] != 0.f || gm[1] != 0.f || gm[2] != 0.f;
       if (live) {
-        tp = unpack_taps(tq, S.tex_h, S.tex_w);
-        tex = (int)tq.y;
+        const TriRec& T = tris[(uint32_t)key];
+        int64_t e[3];
+        tri_cover(T, i, j, e);
+        double uv[2];
+        tri_interp(T, e, uv);
+        tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
+        tex = T.tex;
       }
     }
   }
@@ -264,10 +270,12 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
   int xa = 0, ya = 0, xb = 0, yb = 0;
   const bool mine = live && tex == rtex;
   if (mine) {
-    xa = tp.i0;
-    ya = tp.j0;
-    xb = tp.i1;
-    yb = tp.j1;
+    const int64_t b = (int64_t)rtex * plane;
+    const int64_t q00 = tp.o00 / 3 - b, q11 = tp.o11 / 3 - b;
+    ya = (int)(q00 / S.tex_w);
+    xa = (int)(q00 - (int64_t)ya * S.tex_w);
+    yb = (int)(q11 / S.tex_w);
+    xb = (int)(q11 - (int64_t)yb * S.tex_w);
     atomicMin(&box[1], xa);
     atomicMin(&box[2], ya);
     atomicMax(&box[3], xb);
@@ -440,8 +448,9 @@ void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,
                              hipStream_t st) {
   (void)m;
   if (S.n_faces == 0 || !grad_tex || S.n_pix == 0) return;
-  hipLaunchKernelGGL(k_tex_bwd, dim3((unsigned)S.n_tiles), dim3(256), 0, st, S, w.cams, w.taps,
-                     w.final_T, grad_image, grad_mesh_rgb, grad_tex);
+  hipLaunchKernelGGL(k_tex_bwd, dim3((unsigned)S.n_tiles), dim3(256), 0, st, S, w.cams,
+                     (const unsigned long long*)w.zbuf, w.tris, w.final_T, grad_image,
+                     grad_mesh_rgb, grad_tex);
 }
 
 void launch_loss(const float* image, const float* T, const float* mesh_rgb, const int32_t* tri,

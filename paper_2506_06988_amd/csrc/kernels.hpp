@@ -52,7 +52,6 @@ struct Work {
   float* final_T;        // [P]
   int32_t* n_contrib;    // [P]
   float* mesh_rgb;       // [3P]
-  uint4* taps;           // [P] bilinear footprint of the pixel's texel fetch (see mesh_math.hpp)
   // backward accumulators, [M][9] by rank: u, v, conic a b c, opacity, r g b
   float* gacc;
   // scratch of the scans

@@ -138,7 +138,6 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
                                                       const TriRec* __restrict__ tris,
                                                       const float* __restrict__ tex,
                                                       float* __restrict__ mesh_rgb_ws,
-                                                      uint4* __restrict__ taps,
                                                       float* __restrict__ mesh_rgb,
                                                       float* __restrict__ mesh_depth,
                                                       int32_t* __restrict__ tri_id) {
@@ -153,7 +152,6 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
   float rgb[3] = {0.f, 0.f, 0.f};
   float depth = __int_as_float(0x7f800000);
   int face = -1;
-  uint4 tq = make_uint4(0u, 0xffffffffu, 0u, 0u);
   if (key != ~0ull) {
     const TriRec& T = tris[(uint32_t)key];
     int64_t e[3];
@@ -170,9 +168,7 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
                 w11 * tex[tp.o11 + ch];
     depth = __uint_as_float((uint32_t)(key >> 32));
     face = T.face;
-    tq = pack_taps(T.tex, tp);
   }
-  taps[p] = tq;
   const int64_t pl = 3 * C.pix_off;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
@@ -262,7 +258,7 @@ void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* o
   }
   const float* tex = MF > 0 ? m.tex : nullptr;
   hipLaunchKernelGGL(k_mesh_resolve, dim3((unsigned)((S.n_pix + 255) / 256)), dim3(256), 0, st, S,
-                     w.cams, (const unsigned long long*)w.zbuf, w.tris, tex, w.mesh_rgb, w.taps,
+                     w.cams, (const unsigned long long*)w.zbuf, w.tris, tex, w.mesh_rgb,
                      out ? out->mesh_rgb : nullptr, out ? out->mesh_depth : nullptr,
                      out ? out->tri_id : nullptr);
 }

@@ -150,7 +150,6 @@ __device__ __forceinline__ double tri_interp(const TriRec& T, const int64_t e[3]
 struct Taps {
   int64_t o00, o10, o01, o11;  // element offsets of the 4 texels (RGB follows)
   float fx, fy;
-  int i0, i1, j0, j1;          // texel columns and rows after clamping
 };
 
 // bilinear footprint: texel (i, j) centred at ((i+1/2)/W, (j+1/2)/H), clamp to edge
@@ -169,31 +168,6 @@ __device__ __forceinline__ Taps bilinear_taps(int tex, int H, int W, const doubl
   t.o10 = (b + (int64_t)j0 * W + i1) * 3;
   t.o01 = (b + (int64_t)j1 * W + i0) * 3;
   t.o11 = (b + (int64_t)j1 * W + i1) * 3;
-  t.i0 = i0; t.i1 = i1; t.j0 = j0; t.j1 = j1;
-  return t;
-}
-
-// A pixel's texel footprint as the forward used it, for the texture backward:
-// x = i0 | (i1 - i0) << 15 | j0 << 16 | (j1 - j0) << 31, y = texture (all ones:
-// no face), z, w = the bilinear weights fx, fy.
-__device__ __forceinline__ uint4 pack_taps(int tex, const Taps& t) {
-  return make_uint4((uint32_t)t.i0 | ((uint32_t)(t.i1 - t.i0) << 15) | ((uint32_t)t.j0 << 16) |
-                        ((uint32_t)(t.j1 - t.j0) << 31),
-                    (uint32_t)tex, __float_as_uint(t.fx), __float_as_uint(t.fy));
-}
-
-__device__ __forceinline__ Taps unpack_taps(const uint4 v, int H, int W) {
-  const int i0 = (int)(v.x & 0x7fffu), i1 = i0 + (int)((v.x >> 15) & 1u);
-  const int j0 = (int)((v.x >> 16) & 0x7fffu), j1 = j0 + (int)(v.x >> 31);
-  const int64_t b = (int64_t)v.y * H * W;
-  Taps t;
-  t.o00 = (b + (int64_t)j0 * W + i0) * 3;
-  t.o10 = (b + (int64_t)j0 * W + i1) * 3;
-  t.o01 = (b + (int64_t)j1 * W + i0) * 3;
-  t.o11 = (b + (int64_t)j1 * W + i1) * 3;
-  t.fx = __uint_as_float(v.z);
-  t.fy = __uint_as_float(v.w);
-  t.i0 = i0; t.i1 = i1; t.j0 = j0; t.j1 = j1;
   return t;
 }
 
