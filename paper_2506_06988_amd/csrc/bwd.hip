@@ -294,10 +294,15 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
       const int l00 = (ya - by0) * bw + (xa - bx0), l11 = (yb - by0) * bw + (xb - bx0);
       const int l10 = (ya - by0) * bw + (xb - bx0), l01 = (yb - by0) * bw + (xa - bx0);
       const int ls[4] = {l00, l10, l01, l11};
+      // the four pixels of a 2x2 quad often read the same four texels: each
+      // starts at a different tap, so one atomic instruction hits four texels
+      const int rot = (threadIdx.x & 1) | ((threadIdx.x >> 3) & 2);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q0 = 0; q0 < 4; ++q0) {
+        const int q = (q0 + rot) & 3;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) atomicAdd(&acc[3 * ls[q] + ch], w4[q] * gm[ch]);
+      }
     }
   }
   if (live && !(use_lds && mine)) {
