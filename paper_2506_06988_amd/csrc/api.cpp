@@ -66,8 +66,6 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
     if (m->n_verts < 3 || m->n_tex < 1 || m->tex_h < 1 || m->tex_w < 1)
       return fail(HR_ERR_INVALID_ARGUMENT, "mesh needs >= 3 vertices and a texture");
     if (m->n_faces > (1 << 30)) return fail(HR_ERR_INVALID_ARGUMENT, "too many faces");
-    if ((int64_t)m->n_tex * m->tex_h * m->tex_w >= (int64_t)0xffffffffll)
-      return fail(HR_ERR_UNSUPPORTED, "more than 2^32 - 2 texels in all");
   }
   if (key_cap < 0 || key_cap > (int64_t)0xffffffffll)
     return fail(HR_ERR_INVALID_ARGUMENT, "key_capacity must be in [0, 2^32)");

@@ -206,15 +206,14 @@ __device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, 
   return lo;
 }
 
-constexpr int TEX_SLOTS = 2048;  // LDS hash slots: above the 4 x 256 texels one tile can read
-constexpr uint32_t TEX_EMPTY = 0xffffffffu;
+constexpr int TEX_LDS = 1024;  // texels of one tile's footprint accumulated in LDS
 
 // dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights.
-// One workgroup per tile. The tile's pixels read at most 4 x 256 distinct
-// texels (of any of the textures), so an LDS hash table of TEX_SLOTS slots,
-// keyed by the global texel index, holds all of them at most half full; the
-// pixels accumulate there, and each occupied slot is added to the gradient
-// with one global atomic per non-zero channel.
+// One workgroup per tile: the texels the tile's pixels read from its most
+// common texture (the lowest texture id present) usually form a small box;
+// when the box fits in LDS the pixels accumulate there and the box is added
+// to the gradient with one global atomic per non-zero texel channel. Pixels
+// on other textures, and tiles whose box is too large, add directly.
 __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restrict__ cams,
                                                  const unsigned long long* __restrict__ zbuf,
                                                  const TriRec* __restrict__ tris,
@@ -222,19 +221,23 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
                                                  const float* __restrict__ grad_image,
                                                  const float* __restrict__ grad_mesh,
                                                  float* __restrict__ grad_tex) {
-  __shared__ uint32_t keys[TEX_SLOTS];
-  __shared__ float vals[3 * TEX_SLOTS];
+  __shared__ float acc[3 * TEX_LDS];
+  __shared__ int box[5];  // tex, x0, y0, x1, y1
   const int t = blockIdx.x;
   const int c = find_cam_by_tile(cams, S.n_cams, t);
   const CamDev& C = cams[c];
   const int lt = t - C.tile_off;
   const int ty = lt / C.TX, tx = lt - (lt / C.TX) * C.TX;
   const int i = tx * TILE + (threadIdx.x & 15), j = ty * TILE + (threadIdx.x >> 4);
-  for (int k = threadIdx.x; k < TEX_SLOTS; k += 256) keys[k] = TEX_EMPTY;
-  for (int k = threadIdx.x; k < 3 * TEX_SLOTS; k += 256) vals[k] = 0.f;
+  if (threadIdx.x == 0) {
+    box[0] = 0x7fffffff;
+    box[1] = box[2] = 0x7fffffff;
+    box[3] = box[4] = -1;
+  }
   bool live = false;
   float gm[3] = {0.f, 0.f, 0.f};
   Taps tp = {0, 0, 0, 0, 0.f, 0.f};
+  int tex = 0;
   if (i < C.W && j < C.H) {
     const int64_t p = C.pix_off + (int64_t)j * C.W + i;
     const unsigned long long key = zbuf[p];
@@ -254,39 +257,71 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
         double uv[2];
         tri_interp(T, e, uv);
         tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
+        tex = T.tex;
       }
     }
   }
   __syncthreads();
-  if (live) {
-    const float wx = tp.fx, wy = tp.fy;
-    const float w4[4] = {(1.f - wx) * (1.f - wy), wx * (1.f - wy), (1.f - wx) * wy, wx * wy};
+  if (live) atomicMin(&box[0], tex);
+  __syncthreads();
+  const int rtex = box[0];
+  const int64_t plane = (int64_t)S.tex_h * S.tex_w;
+  // texel coordinates of the 4 taps relative to texture rtex
+  int xa = 0, ya = 0, xb = 0, yb = 0;
+  const bool mine = live && tex == rtex;
+  if (mine) {
+    const int64_t b = (int64_t)rtex * plane;
+    const int64_t q00 = tp.o00 / 3 - b, q11 = tp.o11 / 3 - b;
+    ya = (int)(q00 / S.tex_w);
+    xa = (int)(q00 - (int64_t)ya * S.tex_w);
+    yb = (int)(q11 / S.tex_w);
+    xb = (int)(q11 - (int64_t)yb * S.tex_w);
+    atomicMin(&box[1], xa);
+    atomicMin(&box[2], ya);
+    atomicMax(&box[3], xb);
+    atomicMax(&box[4], yb);
+  }
+  __syncthreads();
+  const int bx0 = box[1], by0 = box[2];
+  const int bw = box[3] - bx0 + 1, bh = box[4] - by0 + 1;
+  const bool use_lds = rtex != 0x7fffffff && bw > 0 && bh > 0 && bw * bh <= TEX_LDS;
+  const float wx = tp.fx, wy = tp.fy;
+  const float w4[4] = {(1.f - wx) * (1.f - wy), wx * (1.f - wy), (1.f - wx) * wy, wx * wy};
+  if (use_lds) {
+    for (int k = threadIdx.x; k < 3 * bw * bh; k += 256) acc[k] = 0.f;
+    __syncthreads();
+    if (mine) {
+      const int l00 = (ya - by0) * bw + (xa - bx0), l11 = (yb - by0) * bw + (xb - bx0);
+      const int l10 = (ya - by0) * bw + (xb - bx0), l01 = (yb - by0) * bw + (xa - bx0);
+      const int ls[4] = {l00, l10, l01, l11};
+      // the four pixels of a 2x2 quad often read the same four texels: each
+      // starts at a different tap, so one atomic instruction hits four texels
+      const int rot = (threadIdx.x & 1) | ((threadIdx.x >> 3) & 2);
+#pragma unroll
+      for (int q0 = 0; q0 < 4; ++q0) {
+        const int q = (q0 + rot) & 3;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) atomicAdd(&acc[3 * ls[q] + ch], w4[q] * gm[ch]);
+      }
+    }
+  }
+  if (live && !(use_lds && mine)) {
     const int64_t os[4] = {tp.o00, tp.o10, tp.o01, tp.o11};
-    // the four pixels of a 2x2 quad often read the same four texels: each
-    // starts at a different tap, so one atomic instruction hits four texels
-    const int rot = (threadIdx.x & 1) | ((threadIdx.x >> 3) & 2);
 #pragma unroll
-    for (int q0 = 0; q0 < 4; ++q0) {
-      const int q = (q0 + rot) & 3;
-      const uint32_t tk = (uint32_t)(os[q] / 3);
-      uint32_t h = (tk * 2654435761u) >> 21;  // 11 bits: TEX_SLOTS = 2048
-      for (int probe = 0; probe < TEX_SLOTS; ++probe) {
-        const uint32_t prev = atomicCAS(&keys[h], TEX_EMPTY, tk);
-        if (prev == TEX_EMPTY || prev == tk) break;
-        h = (h + 1) & (TEX_SLOTS - 1);
-      }
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) atomicAdd(&vals[3 * h + ch], w4[q] * gm[ch]);
-    }
+      for (int ch = 0; ch < 3; ++ch) atomicAdd(grad_tex + os[q] + ch, w4[q] * gm[ch]);
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < TEX_SLOTS; k += 256) {
-    const uint32_t tk = keys[k];
-    if (tk == TEX_EMPTY) continue;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      const float v = vals[3 * k + ch];
-      if (v != 0.f) atomicAdd(grad_tex + (int64_t)tk * 3 + ch, v);
+  if (use_lds) {
+    __syncthreads();
+    const int64_t base = (int64_t)rtex * plane;
+    for (int k = threadIdx.x; k < 3 * bw * bh; k += 256) {
+      const float v = acc[k];
+      if (v != 0.f) {
+        const int l = k / 3, ch = k - 3 * l;
+        const int yy = by0 + l / bw, xx = bx0 + l - (l / bw) * bw;
+        atomicAdd(grad_tex + (base + (int64_t)yy * S.tex_w + xx) * 3 + ch, v);
+      }
     }
   }
 }
