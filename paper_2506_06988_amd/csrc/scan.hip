@@ -54,36 +54,22 @@ __global__ __launch_bounds__(SB) void k_scan_reduce(const uint32_t* __restrict__
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-template <typename T>
-__global__ __launch_bounds__(SB) void k_scan_partials(T* __restrict__ partial, int64_t nb,
-                                                      T* __restrict__ total_out) {
-  __shared__ T lds[SB / 64];
-  T carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += SE) {
-    const int64_t base = b0 + (int64_t)threadIdx.x * SI;
-    T v[SI];
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-      v[i] = base + i < nb ? partial[base + i] : 0;
-      s += v[i];
-    }
-    T total;
-    T ex = block_excl_scan<T>(s, lds, total) + carry;
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-      if (base + i < nb) partial[base + i] = ex;
-      ex += v[i];
-    }
-    carry += total;
-  }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
+// Down-sweep: each block first sums the block totals before it (a few hundred
+// at most, read cooperatively), then scans its own elements; the last block
+// writes the grand total. With one block there is no partial array.
 template <typename T>
 __global__ __launch_bounds__(SB) void k_scan_down(const uint32_t* __restrict__ in, T* __restrict__ out,
-                                                  int64_t n, const T* __restrict__ partial) {
+                                                  int64_t n, const T* __restrict__ partial,
+                                                  T* __restrict__ total_out) {
   __shared__ T lds[SB / 64];
+  T pre = 0;
+  if (partial) {
+    T s = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SB) s += partial[b];
+    T tot;
+    block_excl_scan<T>(s, lds, tot);
+    pre = tot;
+  }
   const int64_t base = (int64_t)blockIdx.x * SE + (int64_t)threadIdx.x * SI;
   uint32_t v[SI];
   T s = 0;
@@ -93,23 +79,24 @@ __global__ __launch_bounds__(SB) void k_scan_down(const uint32_t* __restrict__ i
     s += v[i];
   }
   T total;
-  T ex = block_excl_scan<T>(s, lds, total) + partial[blockIdx.x];
+  T ex = block_excl_scan<T>(s, lds, total) + pre;
 #pragma unroll
   for (int i = 0; i < SI; ++i) {
     if (base + i < n) out[base + i] = ex;
     ex += v[i];
   }
+  if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = pre + total;
 }
 
 template <typename T>
 void scan_impl(const uint32_t* in, T* out, int64_t n, T* total, void* scratch, hipStream_t st) {
   if (n <= 0) return;
   const int64_t nb = (n + SE - 1) / SE;
-  T* partial = (T*)scratch;
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(SB), 0, st, in, n, partial);
-  hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(SB), 0, st, partial, nb, total);
+  T* partial = nb > 1 ? (T*)scratch : nullptr;
+  if (partial)
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(SB), 0, st, in, n, partial);
   hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)nb), dim3(SB), 0, st, in, out, n,
-                     (const T*)partial);
+                     (const T*)partial, total);
 }
 
 }  // namespace

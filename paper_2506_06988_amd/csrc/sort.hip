@@ -479,9 +479,15 @@ __global__ __launch_bounds__(256) void k_tile_schedule(int n_tiles, const uint32
   __shared__ uint32_t off[33];
   if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
   __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += 256) {
-    const uint32_t L = tile_total[t];
-    atomicAdd(&cnt[L ? 32 - __clz(L) : 0], 1u);
+  // lanes of a wave with the same bucket share one LDS atomic (the lowest adds)
+  const int n_rounds = (n_tiles + 255) / 256;
+  for (int rd = 0; rd < n_rounds; ++rd) {
+    const int t = rd * 256 + threadIdx.x;
+    const bool ok = t < n_tiles;
+    const uint32_t L = ok ? tile_total[t] : 0u;
+    const uint32_t b = L ? 32 - __clz(L) : 0;
+    const uint64_t m = match_digit(b, ok);
+    if (ok && (m & lanemask_lt()) == 0) atomicAdd(&cnt[b], (uint32_t)__popcll(m));
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -492,9 +498,17 @@ __global__ __launch_bounds__(256) void k_tile_schedule(int n_tiles, const uint32
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += 256) {
-    const uint32_t L = tile_total[t];
-    order[atomicAdd(&off[L ? 32 - __clz(L) : 0], 1u)] = (uint32_t)t;
+  for (int rd = 0; rd < n_rounds; ++rd) {
+    const int t = rd * 256 + threadIdx.x;
+    const bool ok = t < n_tiles;
+    const uint32_t L = ok ? tile_total[t] : 0u;
+    const uint32_t b = L ? 32 - __clz(L) : 0;
+    const uint64_t m = match_digit(b, ok);
+    const int lead = m ? __ffsll((unsigned long long)m) - 1 : 0;
+    uint32_t base = 0;
+    if (ok && __lane_id() == lead) base = atomicAdd(&off[b], (uint32_t)__popcll(m));
+    base = __shfl(base, lead, 64);
+    if (ok) order[base + (uint32_t)__popcll(m & lanemask_lt())] = (uint32_t)t;
   }
 }
 
