@@ -473,21 +473,15 @@ __global__ __launch_bounds__(256) void k_tile_order(const CamDev* __restrict__ c
 
 // Blend schedule: tiles by decreasing list length (buckets of log2 length),
 // so the longest lists start first and the short ones fill in at the end.
-__global__ __launch_bounds__(256) void k_tile_schedule(int n_tiles, const uint32_t* __restrict__ tile_total,
-                                                       uint32_t* __restrict__ order) {
+__global__ __launch_bounds__(1024) void k_tile_schedule(int n_tiles, const uint32_t* __restrict__ tile_total,
+                                                        uint32_t* __restrict__ order) {
   __shared__ uint32_t cnt[33];
   __shared__ uint32_t off[33];
   if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
   __syncthreads();
-  // lanes of a wave with the same bucket share one LDS atomic (the lowest adds)
-  const int n_rounds = (n_tiles + 255) / 256;
-  for (int rd = 0; rd < n_rounds; ++rd) {
-    const int t = rd * 256 + threadIdx.x;
-    const bool ok = t < n_tiles;
-    const uint32_t L = ok ? tile_total[t] : 0u;
-    const uint32_t b = L ? 32 - __clz(L) : 0;
-    const uint64_t m = match_digit(b, ok);
-    if (ok && (m & lanemask_lt()) == 0) atomicAdd(&cnt[b], (uint32_t)__popcll(m));
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const uint32_t L = tile_total[t];
+    atomicAdd(&cnt[L ? 32 - __clz(L) : 0], 1u);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -498,17 +492,9 @@ __global__ __launch_bounds__(256) void k_tile_schedule(int n_tiles, const uint32
     }
   }
   __syncthreads();
-  for (int rd = 0; rd < n_rounds; ++rd) {
-    const int t = rd * 256 + threadIdx.x;
-    const bool ok = t < n_tiles;
-    const uint32_t L = ok ? tile_total[t] : 0u;
-    const uint32_t b = L ? 32 - __clz(L) : 0;
-    const uint64_t m = match_digit(b, ok);
-    const int lead = m ? __ffsll((unsigned long long)m) - 1 : 0;
-    uint32_t base = 0;
-    if (ok && __lane_id() == lead) base = atomicAdd(&off[b], (uint32_t)__popcll(m));
-    base = __shfl(base, lead, 64);
-    if (ok) order[base + (uint32_t)__popcll(m & lanemask_lt())] = (uint32_t)t;
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const uint32_t L = tile_total[t];
+    order[atomicAdd(&off[L ? 32 - __clz(L) : 0], 1u)] = (uint32_t)t;
   }
 }
 
@@ -602,7 +588,7 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, hr_ou
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
   scan_u32(w.tile_total, w.tile_start, S.n_tiles, w.counters + 13, w.scan_scratch, st);
   hipLaunchKernelGGL(k_kept_total, dim3(1), dim3(1), 0, st, S.key_cap, w.counters);
-  hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(256), 0, st, S.n_tiles, w.tile_total,
+  hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(1024), 0, st, S.n_tiles, w.tile_total,
                      w.tile_order);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
