@@ -122,7 +122,15 @@ enum {
    * low_pass is the pixel filter variance (0.1 for that method) and the
    * opacity is scaled by sqrt(det Sigma' / det(Sigma' + low_pass I)), the
    * ratio floored at 2.5e-5. Forward and backward must agree on it. */
-  HR_FLAG_MIP_2D = 1u << 4
+  HR_FLAG_MIP_2D = 1u << 4,
+  /* forward: keep a (Gaussian, tile) pair only if the tile's pixel centres
+   * meet the ellipse where alpha = opacity * G can reach alpha_min (grown by
+   * a margin that covers FP32 evaluation), instead of the whole 3-sigma
+   * tile rectangle. The dropped pairs are skipped by every pixel anyway, so
+   * images, T and n_blended are unchanged; n_contrib and n_processed are
+   * positions in the kept lists; keys/ranges, n_keys and the capacity
+   * requirement count the kept pairs. */
+  HR_FLAG_TILE_ELLIPSE = 1u << 5
 };
 
 typedef struct {

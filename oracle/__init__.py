@@ -28,6 +28,7 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FP64_RECORDS = 1
+TILE_ELLIPSE = 8  # keep only the tiles the alpha >= alpha_min ellipse can reach
 MIP_2D = 4  # Mip-Splatting 2D filter: low_pass is the pixel filter, opacity compensated
 CULL_MESH = 2  # drop (Gaussian, tile) pairs at or behind the tile's largest mesh depth
 

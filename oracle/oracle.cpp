@@ -63,7 +63,7 @@ typedef struct {
   double amb_alpha, amb_t;  // relative slack under which a decision is tagged
 } or_params;
 
-enum { OR_FP64_RECORDS = 1, OR_CULL_MESH = 2, OR_MIP_2D = 4 };
+enum { OR_FP64_RECORDS = 1, OR_CULL_MESH = 2, OR_MIP_2D = 4, OR_TILE_ELLIPSE = 8 };
 
 // per-Gaussian record export
 typedef struct {
@@ -568,18 +568,52 @@ struct Cand {
   int32_t g;
 };
 
+// Tile-ellipse option: in tile row ty, the tiles whose pixel centres meet
+// the ellipse d^T Q d <= 2 ln(opacity / alpha_min) of the record (where
+// alpha = opacity G reaches alpha_min), grown to 1.01 R + 0.1 plus a term
+// for the magnitude of the form over the rectangle; outside it every pixel
+// skips the Gaussian (alpha < alpha_min). Returns false for an empty run.
+bool ellipse_run(const Rec& r, int ty, double ln_amin, int tile, int* x0, int* x1) {
+  *x0 = r.x0;
+  *x1 = r.x1;
+  const double a = r.bcon[0], b = r.bcon[1], c = r.bcon[2];
+  const double det = a * c - b * b;
+  if (!(a > 0.0 && c > 0.0 && det > 0.0)) return true;
+  const double rr = 2.0 * (std::log(r.bop) - ln_amin);
+  if (!(rr > 0.0)) return false;
+  const double ext = (double)tile * std::max(r.x1 - r.x0, r.y1 - r.y0);
+  const double rp = 1.01 * rr + 0.1 + 1e-5 * (a + c) * ext * ext;
+  const double dymax = std::sqrt(a * rp / det);
+  const double lo = std::max((double)ty * tile + 0.5 - r.bv, -dymax);
+  const double hi = std::min((double)ty * tile + (tile - 0.5) - r.bv, dymax);
+  if (lo > hi) return false;
+  const double sc = std::sqrt(rp / (c * det));
+  const double ys = std::min(std::max(-b * sc, lo), hi), yn = std::min(std::max(b * sc, lo), hi);
+  const double xmax = (-b * ys + std::sqrt(std::max(a * rp - det * ys * ys, 0.0))) / a;
+  const double xmin = (-b * yn - std::sqrt(std::max(a * rp - det * yn * yn, 0.0))) / a;
+  *x0 = std::max(*x0, (int)std::ceil((r.bu + xmin - (tile - 0.5)) / tile));
+  *x1 = std::min(*x1, (int)std::floor((r.bu + xmax - 0.5) / tile) + 1);
+  return *x1 > *x0;
+}
+
 // For every tile overlapping the window: all Gaussians whose tile rectangle
-// holds it, ordered by (fp32 depth bits, index).
-std::vector<std::vector<Cand>> tile_lists(const std::vector<Rec>& recs, int tx0, int ty0, int tx1,
-                                          int ty1) {
+// holds it (and, with OR_TILE_ELLIPSE, whose ellipse run holds it), ordered
+// by (fp32 depth bits, index).
+std::vector<std::vector<Cand>> tile_lists(const std::vector<Rec>& recs, const or_params& p,
+                                          int tx0, int ty0, int tx1, int ty1) {
   const int ntx = tx1 - tx0, nty = ty1 - ty0;
+  const bool ell = (p.flags & OR_TILE_ELLIPSE) != 0;
+  const double ln_amin = std::log(p.alpha_min);
   std::vector<std::vector<Cand>> lists((size_t)ntx * nty);
   for (int g = 0; g < (int)recs.size(); ++g) {
     const Rec& r = recs[g];
     if (!r.vis) continue;
-    for (int ty = std::max(r.y0, ty0); ty < std::min(r.y1, ty1); ++ty)
-      for (int tx = std::max(r.x0, tx0); tx < std::min(r.x1, tx1); ++tx)
+    for (int ty = std::max(r.y0, ty0); ty < std::min(r.y1, ty1); ++ty) {
+      int x0 = r.x0, x1 = r.x1;
+      if (ell && !ellipse_run(r, ty, ln_amin, p.tile, &x0, &x1)) continue;
+      for (int tx = std::max(x0, tx0); tx < std::min(x1, tx1); ++tx)
         lists[(size_t)(ty - ty0) * ntx + (tx - tx0)].push_back({r.dbits, g});
+    }
   }
 #pragma omp parallel for schedule(dynamic)
   for (int t = 0; t < ntx * nty; ++t)
@@ -699,7 +733,7 @@ Frame prepare(const or_scene& sc, const or_camera& cam, const or_params& p, int 
   f.ty0 = wy0 / p.tile;
   f.tx1 = (wx1 + p.tile - 1) / p.tile;
   f.ty1 = (wy1 + p.tile - 1) / p.tile;
-  f.lists = tile_lists(f.recs, f.tx0, f.ty0, f.tx1, f.ty1);
+  f.lists = tile_lists(f.recs, p, f.tx0, f.ty0, f.tx1, f.ty1);
   if (p.flags & OR_CULL_MESH) cull_behind_mesh(sc, cam, p, f.recs, f.tx0, f.ty0, f.tx1, f.ty1, f.lists);
   return f;
 }
@@ -780,7 +814,7 @@ int64_t or_keys(const or_scene* sc, const or_camera* cam, const or_params* p, ui
   if (!sc || !cam || !p || p->tile <= 0) return -1;
   std::vector<Rec> recs = project_all(*sc, *cam, *p);
   const int TX = tiles_x(*cam, *p), TY = tiles_y(*cam, *p);
-  auto lists = tile_lists(recs, 0, 0, TX, TY);
+  auto lists = tile_lists(recs, *p, 0, 0, TX, TY);
   if (p->flags & OR_CULL_MESH) cull_behind_mesh(*sc, *cam, *p, recs, 0, 0, TX, TY, lists);
   int64_t K = 0;
   for (auto& l : lists) K += (int64_t)l.size();

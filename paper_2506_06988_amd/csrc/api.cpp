@@ -289,7 +289,7 @@ void enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const hr_gau
   if (cull) launch_tile_dmax(S, w, st);
   launch_project(S, w.cams, *g, w, out->radii, st);
   launch_depth_sort(S, w, st);
-  launch_binning(S, w, (int)p.n_cams, cull, out, st);
+  launch_binning(S, w, (int)p.n_cams, cull, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, out, st);
   launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
   if (out->stats) launch_counters_to_stats(w.counters, out->stats, st);
 }

@@ -62,8 +62,8 @@ struct Work {
 void launch_project(const SetDev& S, const CamDev* cams, const hr_gaussians& g, const Work& w,
                     int32_t* radii, hipStream_t st);
 void launch_depth_sort(const SetDev& S, const Work& w, hipStream_t st);
-void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, hr_outputs* out,
-                    hipStream_t st);
+void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool ell,
+                    hr_outputs* out, hipStream_t st);
 void launch_tile_dmax(const SetDev& S, const Work& w, hipStream_t st);
 void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* out,
                  hipStream_t st);

@@ -24,6 +24,7 @@
 // kernels do in LDS for the windows they reach. The key traffic is one write
 // of a 4-byte rank per pair and one read per pair the blend reaches.
 #include <algorithm>
+#include <cmath>
 
 #include "kernels.hpp"
 #include "window.hpp"
@@ -260,6 +261,44 @@ __device__ __forceinline__ bool row_run(const uint2 rc, int y, int& x0, int& x1)
   return y >= (int)(rc.y & 0xffffu) && y < (int)(rc.y >> 16);
 }
 
+// With the tile-ellipse option, the run is cut to the tiles whose pixel
+// centres can reach alpha >= alpha_min: outside the ellipse
+// d^T Q d <= 2 ln(opacity / alpha_min) (conic Q of the record) every pixel
+// skips the Gaussian, so those pairs change no output. The ellipse is grown
+// (1.01 R + 0.1, plus a term for the magnitude of the quadratic form over the
+// rectangle) to cover the FP32 evaluation of the blend's test. An opacity at
+// or below alpha_min empties the row. FP64, the same steps in both passes.
+__device__ __forceinline__ bool ellipse_run(const GRec& R, const uint2 rc, int y, double ln_amin,
+                                            int& x0, int& x1) {
+  if (!row_run(rc, y, x0, x1)) return false;
+  const double a = R.ca, b = R.cb, c = R.cc;
+  const double det = a * c - b * b;
+  if (!(a > 0.0 && c > 0.0 && det > 0.0)) return true;  // keep the rectangle run
+  const double rr = 2.0 * (log((double)R.op) - ln_amin);
+  if (!(rr > 0.0)) return false;
+  const double ext = 16.0 * (double)max(x1 - x0, (int)(rc.y >> 16) - (int)(rc.y & 0xffffu));
+  const double rp = 1.01 * rr + 0.1 + 1e-5 * (a + c) * ext * ext;
+  const double dymax = sqrt(a * rp / det);
+  const double lo = fmax((double)y * TILE + 0.5 - (double)R.v, -dymax);
+  const double hi = fmin((double)y * TILE + (TILE - 0.5) - (double)R.v, dymax);
+  if (lo > hi) return false;
+  const double sc = sqrt(rp / (c * det));
+  const double ys = fmin(fmax(-b * sc, lo), hi), yn = fmin(fmax(b * sc, lo), hi);
+  const double xmax = (-b * ys + sqrt(fmax(a * rp - det * ys * ys, 0.0))) / a;
+  const double xmin = (-b * yn - sqrt(fmax(a * rp - det * yn * yn, 0.0))) / a;
+  const int ex0 = (int)ceil(((double)R.u + xmin - (TILE - 0.5)) / TILE);
+  const int ex1 = (int)floor(((double)R.u + xmax - 0.5) / TILE) + 1;
+  x0 = max(x0, ex0);
+  x1 = min(x1, ex1);
+  return x1 > x0;
+}
+
+__device__ __forceinline__ bool pair_run(const uint2* rect_s, const GRec* rec_s, int64_t k, int y,
+                                         bool ell, double ln_amin, int& x0, int& x1) {
+  return ell ? ellipse_run(rec_s[k], rect_s[k], y, ln_amin, x0, x1)
+             : row_run(rect_s[k], y, x0, x1);
+}
+
 // Count pass: per (chunk, tile row), the chunk's pair count of every tile of
 // the row, written to the chunk's row of the count matrix.
 __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ cams, int n_cams,
@@ -268,6 +307,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
                                                    const uint2* __restrict__ rect_s,
                                                    const GRec* __restrict__ rec_s,
                                                    const uint32_t* __restrict__ tile_dmax,
+                                                   int ell, double ln_amin,
                                                    uint32_t* __restrict__ mat) {
   __shared__ int32_t diff[MAX_TX + 1];
   __shared__ uint32_t red4[4];
@@ -280,7 +320,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
     const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off + B.y * B.TX : nullptr;
     for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
       int x0, x1;
-      if (!row_run(rect_s[k], B.y, x0, x1)) continue;
+      if (!pair_run(rect_s, rec_s, k, B.y, ell, ln_amin, x0, x1)) continue;
       if (!tdm) {
         atomicAdd(&diff[x0], 1);
         atomicSub(&diff[x1], 1);
@@ -328,6 +368,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
                                                      const uint2* __restrict__ rect_s,
                                                      const GRec* __restrict__ rec_s,
                                                      const uint32_t* __restrict__ tile_dmax,
+                                                     int ell, double ln_amin,
                                                      uint32_t* __restrict__ mat,
                                                      const uint32_t* __restrict__ tile_start,
                                                      int64_t key_cap, uint32_t* __restrict__ lists) {
@@ -355,7 +396,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
     // short runs by one lane; the others are sorted into the two lists
     for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
       int x0, x1;
-      if (!row_run(rect_s[k], B.y, x0, x1)) continue;
+      if (!pair_run(rect_s, rec_s, k, B.y, ell, ln_amin, x0, x1)) continue;
       const uint32_t packed = (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k - B.r0) << 21);
       const int w = x1 - x0;
       if (w > NARROW_RUN && w > half) {
@@ -572,9 +613,10 @@ void launch_depth_sort(const SetDev& S, const Work& w, hipStream_t st) {
                      w.tiles_s, w.item_s, w.rank_of);
 }
 
-void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, hr_outputs* out,
-                    hipStream_t st) {
+void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool ell,
+                    hr_outputs* out, hipStream_t st) {
   const uint32_t* tdm = cull ? w.tile_dmax : nullptr;
+  const double ln_amin = std::log((double)S.alpha_min);
   const int64_t M = (int64_t)S.n * S.n_cams;
   uint64_t* Ktot = reinterpret_cast<uint64_t*>(w.counters + 10);
   scan_u64(w.tiles_s, w.pair_off, M + 1, Ktot, w.scan_scratch, st);
@@ -583,7 +625,7 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, hr_ou
   hipLaunchKernelGGL(k_bin_items, dim3(1), dim3(64), 0, st, w.cams, n_cams, w.vis_off, w.item_off);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
-                       w.item_off, w.rect_s, w.rec_s, tdm, w.mat);
+                       w.item_off, w.rect_s, w.rec_s, tdm, ell ? 1 : 0, ln_amin, w.mat);
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
   scan_u32(w.tile_total, w.tile_start, S.n_tiles, w.counters + 13, w.scan_scratch, st);
@@ -592,8 +634,8 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, hr_ou
                      w.tile_order);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
-                       w.item_off, w.rect_s, w.rec_s, tdm, w.mat, w.tile_start, S.key_cap,
-                       w.lists);
+                       w.item_off, w.rect_s, w.rec_s, tdm, ell ? 1 : 0, ln_amin, w.mat,
+                       w.tile_start, S.key_cap, w.lists);
   if (out && out->ranges)
     hipLaunchKernelGGL(k_ranges, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, S.n_tiles,
                        w.tile_start, w.tile_total, out->ranges);

@@ -22,6 +22,7 @@ HR_FLAG_DETACH_MASK = 1 << 1
 HR_FLAG_EXPORT_KEYS = 1 << 2
 HR_FLAG_CULL_BEHIND_MESH = 1 << 3
 HR_FLAG_MIP_2D = 1 << 4
+HR_FLAG_TILE_ELLIPSE = 1 << 5
 
 P = C.c_void_p
 

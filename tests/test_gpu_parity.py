@@ -419,3 +419,39 @@ def test_mip_filters_forward_and_backward_match_oracle(hr, seed):
     ref = oracle.backward(sc.gaussians, sc.mesh, cam, gi, gt, None, params=pm, filter3d=f3)
     for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex"):
         _grad_compare(k, grads[k].cpu().numpy(), ref[k])
+
+
+def test_tile_ellipse_culling_matches_oracle(hr):
+    say("case: tile-ellipse culling, small room, 2 cameras, forward and backward")
+    sc = scenes.small_room(81, n=6000, faces=2000, tex=32)
+    rng = np.random.default_rng(81)
+    cams = [scenes.random_room_camera(rng, w, h) for (w, h) in ((96, 80), (70, 45))]
+    st = hr.default_settings(flags=hr.HR_FLAG_TILE_ELLIPSE)
+    pe = oracle.default_params(flags=oracle.TILE_ELLIPSE)
+    r, f = gpu_render(hr, sc, cams=cams, export_keys=True, settings=st)
+    ranges = f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    keys = f.keys.cpu().numpy().view(np.uint64)
+    vals = f.values.cpu().numpy().view(np.uint32)
+    key_base = tile_base = uncut = 0
+    for c, cam in enumerate(cams):
+        check_view(f, cams, c, oracle.render(sc.gaussians, sc.mesh, cam, params=pe))
+        k, v, rg = oracle.keys(sc.gaussians, cam, params=pe)
+        uncut += len(oracle.keys(sc.gaussians, cam)[0])
+        ntl = rg.shape[0]
+        np.testing.assert_array_equal(ranges[tile_base:tile_base + ntl] - key_base, rg)
+        np.testing.assert_array_equal(keys[key_base:key_base + len(k)] - (np.uint64(tile_base) << np.uint64(32)), k)
+        np.testing.assert_array_equal(vals[key_base:key_base + len(k)], v)
+        key_base += len(k)
+        tile_base += ntl
+    say(f"  kept pairs {key_base} of {uncut}")
+    assert f.stats_dict()["n_keys"] == key_base and key_base < 0.8 * uncut
+    # the same image and T as without culling, and the same gradients
+    r0, f0 = gpu_render(hr, sc, cams=cams)
+    assert torch.equal(f0.image, f.image) and torch.equal(f0.final_T, f.final_T)
+    assert torch.equal(f0.n_blended, f.n_blended)
+    gi = torch.randn(3 * r.P, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    ga, gb = r.render_hybrid_backward(gi), r0.render_hybrid_backward(gi)
+    torch.cuda.synchronize()
+    for k_ in ga:
+        x, y = ga[k_].double(), gb[k_].double()
+        assert float((x - y).norm()) <= 1e-5 * float(y.norm()) + 1e-12, k_

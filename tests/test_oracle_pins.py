@@ -844,3 +844,53 @@ def test_oracle_gradient_with_mip_filters_matches_finite_differences(seed):
     f3 = np.random.default_rng(seed).uniform(0.2, 1.0, g.n) * np.exp(2 * g.log_scales.astype(np.float64)).mean(1)
     pm = oracle.default_params(low_pass=0.1, flags=oracle.FP64_RECORDS | oracle.MIP_2D)
     _fd_check(seed, pm, f3)
+
+
+# ---------------------------------------------------- tile-ellipse culling --
+def _ellipse_scene(seed, n=120):
+    rng = np.random.default_rng(seed)
+    means = np.column_stack([rng.uniform(-1.2, 1.2, n), rng.uniform(-0.9, 0.9, n), rng.uniform(1.5, 4.0, n)])
+    ls = rng.uniform(-4.0, -1.8, (n, 3))
+    ls[:, 0] += rng.uniform(0, 1.5, n)  # elongated
+    g = scenes.make_gaussians(means, ls, rng.standard_normal((n, 4)), rng.normal(-1.0, 2.0, n),
+                              ((rng.uniform(0, 1, (n, 1, 3)) - 0.5) / scenes.Y00), 0)
+    cam = scenes.Camera(96, 80, 60.0, 60.0, 48.0, 40.0, np.eye(3), np.zeros(3))
+    return g, cam
+
+
+def test_tile_ellipse_keeps_every_pair_a_pixel_blends_and_the_image():
+    g, cam = _ellipse_scene(71)
+    pe = oracle.default_params(flags=oracle.TILE_ELLIPSE)
+    base = oracle.render(g, None, cam)
+    cut = oracle.render(g, None, cam, params=pe)
+    for k in ("image", "final_T", "n_blended"):
+        np.testing.assert_array_equal(cut[k], base[k])
+    # positions in the shorter lists
+    assert (cut["n_processed"] <= base["n_processed"]).all()
+    assert (cut["n_contrib"] <= base["n_contrib"]).all()
+    k0, v0, _ = oracle.keys(g, cam)
+    k1, v1, _ = oracle.keys(g, cam, params=pe)
+    assert len(k1) < 0.7 * len(k0)
+    kept = set(zip((k1 >> np.uint64(32)).tolist(), v1.tolist()))
+    assert kept <= set(zip((k0 >> np.uint64(32)).tolist(), v0.tolist()))
+    # brute force: every dropped (Gaussian, tile) pair has alpha < alpha_min
+    # at all of the tile's pixel centres (records as the blend reads them)
+    pr = oracle.project(g, cam)
+    amin = F32(1 / 255)
+    TX = 6
+    dropped = 0
+    for key, gi in zip(k0.tolist(), v0.tolist()):
+        t = key >> 32
+        if (t, gi) in kept:
+            continue
+        dropped += 1
+        tx, ty = t % TX, t // TX
+        xs = np.arange(tx * 16, min(tx * 16 + 16, cam.width)) + 0.5
+        ys = np.arange(ty * 16, min(ty * 16 + 16, cam.height)) + 0.5
+        dx = xs[None, :] - F32(pr["mean2d"][gi, 0])
+        dy = ys[:, None] - F32(pr["mean2d"][gi, 1])
+        a, b, c = (F32(x) for x in pr["conic"][gi])
+        power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+        alpha = F32(pr["opacity"][gi]) * np.exp(power)
+        assert alpha.max() < amin, (t, gi, alpha.max())
+    assert dropped > 100
