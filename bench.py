@@ -41,6 +41,9 @@ BLEND_OPS_BLENDED = 7
 # and WRITE_SIZE counter passes of `bench.py --pmc-probe` (scaled by a 256 MiB
 # copy: FETCH x2, WRITE x1), valid for the configuration they were taken with
 BLEND_TRAFFIC = {"batch": 256, "variant": 0, "bytes_per_launch": 202.9e6}
+# pairs outside the alpha >= alpha_min ellipse are skipped by every pixel:
+# binning only the tiles the ellipse reaches leaves every image unchanged
+PAIR_CULL = 0
 
 
 def log(*a):
@@ -55,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gaussian-only", action="store_true")
+    ap.add_argument("--rect-pairs", action="store_true",
+                    help="bin every tile of the 3-sigma rectangle (no tile-ellipse culling)")
     ap.add_argument("--pmc-probe-step", action="store_true",
                     help="for counter runs: one forward + loss + backward of the 16-camera "
                          "step (one-wave backward, batch 128)")
@@ -71,7 +76,7 @@ def pmc_probe(torch, hr, scenes, dev):
     byte counters are read over, and the copy that scales them."""
     sc = scenes.config5("hybrid")
     g, m = hr.to_device(sc.gaussians, sc.mesh, device=dev)
-    r = hr.Renderer(g, m, [sc.cameras[0]])
+    r = hr.Renderer(g, m, [sc.cameras[0]], settings=hr.default_settings(flags=PAIR_CULL))
     r.settings.batch, r.settings.variant = 256, 0
     frame = r.new_frame()
     for v in range(len(sc.cameras)):
@@ -90,7 +95,7 @@ def pmc_probe(torch, hr, scenes, dev):
 def pmc_probe_step(torch, hr, scenes, dev):
     s4 = scenes.config4()
     g, m = hr.to_device(s4.gaussians, s4.mesh, device=dev)
-    r = hr.Renderer(g, m, s4.cameras)
+    r = hr.Renderer(g, m, s4.cameras, settings=hr.default_settings(flags=PAIR_CULL))
     r.settings.batch, r.settings.variant, r.settings.batch_bwd = 256, 8, 128
     f = r.render_hybrid(sync_check=True)
     target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
@@ -135,6 +140,8 @@ def main():
     hr.load()
     assert torch.cuda.is_available()
     dev = "cuda:0"
+    global PAIR_CULL
+    PAIR_CULL = 0 if args.rect_pairs else hr.HR_FLAG_TILE_ELLIPSE
     if args.pmc_probe:
         pmc_probe(torch, hr, scenes, dev)
         return
@@ -148,7 +155,7 @@ def main():
     log(f"hybrid scene built in {time.perf_counter() - t:.1f}s: {sc.gaussians.n} Gaussians, "
         f"{sc.mesh.n_faces} faces, textures {sc.mesh.tex.shape}")
     g, m = hr.to_device(sc.gaussians, sc.mesh, device=dev)
-    r = hr.Renderer(g, m, [sc.cameras[0]])
+    r = hr.Renderer(g, m, [sc.cameras[0]], settings=hr.default_settings(flags=PAIR_CULL))
     frame = r.new_frame()
     # size the key capacity over all views
     for v in range(len(sc.cameras)):
@@ -158,7 +165,7 @@ def main():
     # tune the blend on 8 of the views rendered together (one call, the mix
     # of the workload), then use the choice for single-view frames
     tv = sc.cameras[::4]
-    rt = hr.Renderer(g, m, tv)
+    rt = hr.Renderer(g, m, tv, settings=hr.default_settings(flags=PAIR_CULL))
     ft = rt.render_hybrid(sync_check=True)
     rt.autotune(ft, repeats=3)
     r.settings.batch, r.settings.variant = rt.settings.batch, rt.settings.variant
@@ -220,7 +227,8 @@ def main():
         "config": {"workload": "config5 hybrid: 1920x1080, 600k Gaussians SH3, 200k-triangle room "
                                "mesh, 4x4096^2 textures, 32 views, forward",
                    "gaussians": 600000, "faces": int(sc.mesh.n_faces), "width": 1920,
-                   "height": 1080, "views": len(sc.cameras)},
+                   "height": 1080, "views": len(sc.cameras),
+                   "pair_binning": "3-sigma rectangle" if args.rect_pairs else "tile-ellipse"},
         "blend_pairs_per_s": blends_per_s,
         "blend_ms_per_launch": round(blend_s / launches * 1e3, 4),
         "blend_stats": hyb_stats,
@@ -241,7 +249,7 @@ def main():
     if not args.no_gaussian_only:
         sg = scenes.config5("gaussian_only")
         g, _ = hr.to_device(sg.gaussians, None, device=dev)
-        r = hr.Renderer(g, None, [sg.cameras[0]])
+        r = hr.Renderer(g, None, [sg.cameras[0]], settings=hr.default_settings(flags=PAIR_CULL))
         frame = r.new_frame()
         for v in range(len(sg.cameras)):
             r.set_cameras([sg.cameras[v]])
@@ -257,7 +265,7 @@ def main():
     if not args.no_batched:
         s4 = scenes.config4()
         g, m = hr.to_device(s4.gaussians, s4.mesh, device=dev)
-        r = hr.Renderer(g, m, s4.cameras)
+        r = hr.Renderer(g, m, s4.cameras, settings=hr.default_settings(flags=PAIR_CULL))
         f = r.render_hybrid(sync_check=True)
         torch.cuda.synchronize()
         target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
