@@ -194,6 +194,8 @@ Work make_work(const Plan& p, void* ws) {
   w.vis_scan = (uint32_t*)(b + p.vis_scan);
   w.dkey = (uint32_t*)(b + p.dkey);
   w.rec = (GRec*)(b + p.rec);
+  static_assert(sizeof(EllP) <= sizeof(GRec), "ellipse parameters must fit in a record slot");
+  w.ell_s = (EllP*)(b + p.rec);
   w.rect = (uint2*)(b + p.rect);
   w.rank_of = (int32_t*)(b + p.rank_of);
   w.skey[0] = (uint32_t*)(b + p.skey0);

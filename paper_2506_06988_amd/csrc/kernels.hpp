@@ -5,6 +5,13 @@
 
 namespace hr {
 
+// Per-rank part of the tile-ellipse test: determinant of the conic, grown
+// radius^2 rp (+inf keeps the rectangle, < 0 empties it), half-height of the
+// ellipse and the scale of its x-extreme points.
+struct EllP {
+  double det, rp, dymax, sc;
+};
+
 // Device pointers into the caller's workspace (see plan.cpp for the layout).
 struct Work {
   CamDev* cams;          // [n_cams]
@@ -27,6 +34,7 @@ struct Work {
   uint32_t* tiles_s;     // [M + 1] by rank
   uint32_t* item_s;      // [M] item of each rank
   uint64_t* pair_off;    // [M + 1]
+  EllP* ell_s;           // [M] by rank; shares the memory of rec, unused after the gather
   // tile binning
   uint32_t* mat;         // chunk x tile counts, then column prefixes
   int64_t chunk_rows;    // total chunk rows

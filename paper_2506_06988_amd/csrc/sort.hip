@@ -267,25 +267,50 @@ __device__ __forceinline__ bool row_run(const uint2 rc, int y, int& x0, int& x1)
 // skips the Gaussian, so those pairs change no output. The ellipse is grown
 // (1.01 R + 0.1, plus a term for the magnitude of the quadratic form over the
 // rectangle) to cover the FP32 evaluation of the blend's test. An opacity at
-// or below alpha_min empties the row. FP64, the same steps in both passes.
-__device__ __forceinline__ bool ellipse_run(const GRec& R, const uint2 rc, int y, double ln_amin,
+// or below alpha_min empties the row. FP64; the per-rank part is computed
+// once (k_ell_params), the per-row part in both passes by the same steps.
+__global__ __launch_bounds__(256) void k_ell_params(const uint32_t* __restrict__ counters,
+                                                    const GRec* __restrict__ rec_s,
+                                                    const uint2* __restrict__ rect_s,
+                                                    double ln_amin, EllP* __restrict__ ell) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)counters[0]) return;
+  const GRec R = rec_s[r];
+  const uint2 rc = rect_s[r];
+  const double a = R.ca, b = R.cb, c = R.cc;
+  EllP e;
+  e.det = a * c - b * b;
+  e.dymax = e.sc = 0.0;
+  if (!(a > 0.0 && c > 0.0 && e.det > 0.0)) {
+    e.rp = INFINITY;  // keep the rectangle run
+  } else {
+    const double rr = 2.0 * (log((double)R.op) - ln_amin);
+    if (!(rr > 0.0)) {
+      e.rp = -1.0;  // alpha never reaches alpha_min
+    } else {
+      const int w = (int)(rc.x >> 16) - (int)(rc.x & 0xffffu);
+      const int h = (int)(rc.y >> 16) - (int)(rc.y & 0xffffu);
+      const double ext = 16.0 * (double)max(w, h);
+      e.rp = 1.01 * rr + 0.1 + 1e-5 * (a + c) * ext * ext;
+      e.dymax = sqrt(a * e.rp / e.det);
+      e.sc = sqrt(e.rp / (c * e.det));
+    }
+  }
+  ell[r] = e;
+}
+
+__device__ __forceinline__ bool ellipse_run(const GRec& R, const uint2 rc, const EllP& e, int y,
                                             int& x0, int& x1) {
   if (!row_run(rc, y, x0, x1)) return false;
-  const double a = R.ca, b = R.cb, c = R.cc;
-  const double det = a * c - b * b;
-  if (!(a > 0.0 && c > 0.0 && det > 0.0)) return true;  // keep the rectangle run
-  const double rr = 2.0 * (log((double)R.op) - ln_amin);
-  if (!(rr > 0.0)) return false;
-  const double ext = 16.0 * (double)max(x1 - x0, (int)(rc.y >> 16) - (int)(rc.y & 0xffffu));
-  const double rp = 1.01 * rr + 0.1 + 1e-5 * (a + c) * ext * ext;
-  const double dymax = sqrt(a * rp / det);
-  const double lo = fmax((double)y * TILE + 0.5 - (double)R.v, -dymax);
-  const double hi = fmin((double)y * TILE + (TILE - 0.5) - (double)R.v, dymax);
+  if (e.rp < 0.0) return false;
+  if (isinf(e.rp)) return true;
+  const double a = R.ca, b = R.cb;
+  const double lo = fmax((double)y * TILE + 0.5 - (double)R.v, -e.dymax);
+  const double hi = fmin((double)y * TILE + (TILE - 0.5) - (double)R.v, e.dymax);
   if (lo > hi) return false;
-  const double sc = sqrt(rp / (c * det));
-  const double ys = fmin(fmax(-b * sc, lo), hi), yn = fmin(fmax(b * sc, lo), hi);
-  const double xmax = (-b * ys + sqrt(fmax(a * rp - det * ys * ys, 0.0))) / a;
-  const double xmin = (-b * yn - sqrt(fmax(a * rp - det * yn * yn, 0.0))) / a;
+  const double ys = fmin(fmax(-b * e.sc, lo), hi), yn = fmin(fmax(b * e.sc, lo), hi);
+  const double xmax = (-b * ys + sqrt(fmax(a * e.rp - e.det * ys * ys, 0.0))) / a;
+  const double xmin = (-b * yn - sqrt(fmax(a * e.rp - e.det * yn * yn, 0.0))) / a;
   const int ex0 = (int)ceil(((double)R.u + xmin - (TILE - 0.5)) / TILE);
   const int ex1 = (int)floor(((double)R.u + xmax - 0.5) / TILE) + 1;
   x0 = max(x0, ex0);
@@ -293,9 +318,9 @@ __device__ __forceinline__ bool ellipse_run(const GRec& R, const uint2 rc, int y
   return x1 > x0;
 }
 
-__device__ __forceinline__ bool pair_run(const uint2* rect_s, const GRec* rec_s, int64_t k, int y,
-                                         bool ell, double ln_amin, int& x0, int& x1) {
-  return ell ? ellipse_run(rec_s[k], rect_s[k], y, ln_amin, x0, x1)
+__device__ __forceinline__ bool pair_run(const uint2* rect_s, const GRec* rec_s, const EllP* ell,
+                                         int64_t k, int y, int& x0, int& x1) {
+  return ell ? ellipse_run(rec_s[k], rect_s[k], ell[k], y, x0, x1)
              : row_run(rect_s[k], y, x0, x1);
 }
 
@@ -307,7 +332,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
                                                    const uint2* __restrict__ rect_s,
                                                    const GRec* __restrict__ rec_s,
                                                    const uint32_t* __restrict__ tile_dmax,
-                                                   int ell, double ln_amin,
+                                                   const EllP* __restrict__ ell,
                                                    uint32_t* __restrict__ mat) {
   __shared__ int32_t diff[MAX_TX + 1];
   __shared__ uint32_t red4[4];
@@ -320,7 +345,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
     const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off + B.y * B.TX : nullptr;
     for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
       int x0, x1;
-      if (!pair_run(rect_s, rec_s, k, B.y, ell, ln_amin, x0, x1)) continue;
+      if (!pair_run(rect_s, rec_s, ell, k, B.y, x0, x1)) continue;
       if (!tdm) {
         atomicAdd(&diff[x0], 1);
         atomicSub(&diff[x1], 1);
@@ -368,7 +393,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
                                                      const uint2* __restrict__ rect_s,
                                                      const GRec* __restrict__ rec_s,
                                                      const uint32_t* __restrict__ tile_dmax,
-                                                     int ell, double ln_amin,
+                                                     const EllP* __restrict__ ell,
                                                      uint32_t* __restrict__ mat,
                                                      const uint32_t* __restrict__ tile_start,
                                                      int64_t key_cap, uint32_t* __restrict__ lists) {
@@ -396,7 +421,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
     // short runs by one lane; the others are sorted into the two lists
     for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
       int x0, x1;
-      if (!pair_run(rect_s, rec_s, k, B.y, ell, ln_amin, x0, x1)) continue;
+      if (!pair_run(rect_s, rec_s, ell, k, B.y, x0, x1)) continue;
       const uint32_t packed = (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k - B.r0) << 21);
       const int w = x1 - x0;
       if (w > NARROW_RUN && w > half) {
@@ -617,7 +642,11 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
                     hr_outputs* out, hipStream_t st) {
   const uint32_t* tdm = cull ? w.tile_dmax : nullptr;
   const double ln_amin = std::log((double)S.alpha_min);
+  const EllP* ellp = ell ? w.ell_s : nullptr;
   const int64_t M = (int64_t)S.n * S.n_cams;
+  if (ell && M > 0)
+    hipLaunchKernelGGL(k_ell_params, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                       w.counters, w.rec_s, w.rect_s, ln_amin, w.ell_s);
   uint64_t* Ktot = reinterpret_cast<uint64_t*>(w.counters + 10);
   scan_u64(w.tiles_s, w.pair_off, M + 1, Ktot, w.scan_scratch, st);
   hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, Ktot, S.key_cap, w.counters);
@@ -625,7 +654,7 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
   hipLaunchKernelGGL(k_bin_items, dim3(1), dim3(64), 0, st, w.cams, n_cams, w.vis_off, w.item_off);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
-                       w.item_off, w.rect_s, w.rec_s, tdm, ell ? 1 : 0, ln_amin, w.mat);
+                       w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat);
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
   scan_u32(w.tile_total, w.tile_start, S.n_tiles, w.counters + 13, w.scan_scratch, st);
@@ -634,8 +663,8 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
                      w.tile_order);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
-                       w.item_off, w.rect_s, w.rec_s, tdm, ell ? 1 : 0, ln_amin, w.mat,
-                       w.tile_start, S.key_cap, w.lists);
+                       w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat, w.tile_start,
+                       S.key_cap, w.lists);
   if (out && out->ranges)
     hipLaunchKernelGGL(k_ranges, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, S.n_tiles,
                        w.tile_start, w.tile_total, out->ranges);
