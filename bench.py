@@ -37,10 +37,17 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # addressing and loop control are not counted.
 BLEND_OPS_EXAMINED = 11
 BLEND_OPS_BLENDED = 7
-# HBM bytes per blend launch over the 32 headline views, from the FETCH_SIZE
-# and WRITE_SIZE counter passes of `bench.py --pmc-probe` (scaled by a 256 MiB
-# copy: FETCH x2, WRITE x1), valid for the configuration they were taken with
-BLEND_TRAFFIC = {"batch": 256, "variant": 0, "bytes_per_launch": 202.9e6}
+# HBM bytes per blend launch over the 32 headline views, by (batch, variant),
+# from the FETCH_SIZE and WRITE_SIZE counter passes of `bench.py --pmc-probe`
+# (scaled by a 256 MiB copy: FETCH x2, WRITE x1), tile-ellipse binning; valid
+# for the blend kernels they were taken with
+BLEND_TRAFFIC = {(32, 0): 166.1e6, (32, 1): 166.5e6, (32, 2): 161.4e6, (32, 3): 161.6e6,
+                 (64, 0): 166.4e6, (64, 1): 167.0e6, (64, 2): 161.4e6, (64, 3): 161.9e6,
+                 (64, 4): 166.6e6, (128, 0): 166.8e6, (128, 1): 167.9e6, (128, 2): 161.7e6,
+                 (128, 3): 162.8e6, (128, 4): 167.1e6, (256, 0): 167.7e6, (256, 1): 169.3e6,
+                 (256, 2): 162.6e6, (256, 3): 164.1e6}
+# every configuration the forward autotuner may choose
+BLEND_CONFIGS = [(b, v) for v in range(4) for b in (32, 64, 128, 256)] + [(64, 4), (128, 4)]
 # pairs outside the alpha >= alpha_min ellipse are skipped by every pixel:
 # binning only the tiles the ellipse reaches leaves every image unchanged
 PAIR_CULL = 0
@@ -71,25 +78,29 @@ def parse():
 
 
 def pmc_probe(torch, hr, scenes, dev):
-    """One forward and one extra blend (batch 256, variant 0) of each of the
-    32 headline views, then 3 copies of a 256 MiB buffer: the dispatches the
-    byte counters are read over, and the copy that scales them."""
+    """One forward of each of the 32 headline views, each followed by one
+    blend in every configuration the autotuner may choose, then 3 copies of a
+    256 MiB buffer: the dispatches the byte counters are read over, and the
+    copy that scales them."""
     sc = scenes.config5("hybrid")
     g, m = hr.to_device(sc.gaussians, sc.mesh, device=dev)
     r = hr.Renderer(g, m, [sc.cameras[0]], settings=hr.default_settings(flags=PAIR_CULL))
-    r.settings.batch, r.settings.variant = 256, 0
     frame = r.new_frame()
     for v in range(len(sc.cameras)):
         r.set_cameras([sc.cameras[v]])
+        r.settings.batch, r.settings.variant = 256, 0
         r.render_hybrid(frame, sync_check=True)
-        r.blend_forward(frame)
+        for b, var in BLEND_CONFIGS:
+            r.settings.batch, r.settings.variant = b, var
+            r.blend_forward(frame)
     torch.cuda.synchronize()
     src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    log(f"pmc probe done: 32 views, copy bytes {src.numel() * 4}")
+    log(f"pmc probe done: 32 views x {len(BLEND_CONFIGS)} blend configurations, "
+        f"copy bytes {src.numel() * 4}")
 
 
 def pmc_probe_step(torch, hr, scenes, dev):
@@ -235,9 +246,7 @@ def main():
         "blend_tuning": tuning,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": (BLEND_TRAFFIC["bytes_per_launch"]
-                                 if (tuning["batch"], tuning["variant"]) ==
-                                 (BLEND_TRAFFIC["batch"], BLEND_TRAFFIC["variant"]) else None),
+                     "traffic": BLEND_TRAFFIC.get((tuning["batch"], tuning["variant"])),
                      "traffic_unit": "HBM bytes per launch",
                      "kernel": "k_blend_fwd", "ops_per_examined": BLEND_OPS_EXAMINED,
                      "ops_per_blended": BLEND_OPS_BLENDED, "ops_per_launch": ops // launches,

@@ -39,7 +39,7 @@ struct Plan {
       bin_items;
   size_t cams, counters, tiles, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, tiles_s, item_s, pair_off, mat, tile_total,
-      tile_start, tile_order, tile_dmax, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
+      tile_start, tile_order, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, gacc, tune, scan_scratch, total;
   std::vector<CamDev> camdev;
 };
@@ -164,6 +164,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.tile_start = L.take(4 * p.n_tiles);
   p.tile_order = L.take(4 * p.n_tiles);
   p.tile_dmax = L.take(4 * p.n_tiles);
+  p.tile_np = L.take(16 * p.n_tiles);
   p.item_off = L.take(4 * (p.n_cams + 1));
   p.lists = L.take(4 * key_cap);
   p.zbuf = L.take(8 * P);
@@ -216,6 +217,7 @@ Work make_work(const Plan& p, void* ws) {
   w.tile_start = (uint32_t*)(b + p.tile_start);
   w.tile_order = (uint32_t*)(b + p.tile_order);
   w.tile_dmax = (uint32_t*)(b + p.tile_dmax);
+  w.tile_np = (uint64_t*)(b + p.tile_np);
   w.item_off = (uint32_t*)(b + p.item_off);
   w.bin_items_max = p.bin_items;
   w.lists = (uint32_t*)(b + p.lists);
@@ -293,7 +295,7 @@ void enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const hr_gau
   launch_depth_sort(S, w, st);
   launch_binning(S, w, (int)p.n_cams, cull, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, out, st);
   launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
-  if (out->stats) launch_counters_to_stats(w.counters, out->stats, st);
+  if (out->stats) launch_counters_to_stats(w.counters, w.tile_np, (int)S.n_tiles, out->stats, st);
 }
 
 void enqueue_backward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,

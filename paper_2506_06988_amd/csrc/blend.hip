@@ -144,7 +144,7 @@ struct FwdArgs {
   int32_t* nc_out;
   int32_t* nb_out;
   int32_t* np_out;
-  uint32_t* counters;
+  unsigned long long* tile_np;  // [2 * n_tiles] examined, blended pairs of each tile
 };
 
 template <int BG, int DEPTH>
@@ -164,7 +164,6 @@ __device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH
   const uint32_t* __restrict__ lists = A.lists;
   const GRec* __restrict__ rec_s = A.rec_s;
   const float* __restrict__ mesh_rgb = A.mesh_rgb;
-  uint32_t* __restrict__ counters = A.counters;
   auto& sh = L.sh;
   auto& rk = L.rk;
   auto& bitmap = L.bitmap;
@@ -274,9 +273,11 @@ __device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH
     atomicAdd(&red[1], sb);
   }
   __syncthreads();
+  // per-tile sums (one plain store each); the stats export adds the tiles up,
+  // which keeps thousands of same-address atomics out of the blend
   if (threadIdx.x == 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(counters + 6), red[0]);
-    atomicAdd(reinterpret_cast<unsigned long long*>(counters + 8), red[1]);
+    A.tile_np[2 * t] = red[0];
+    A.tile_np[2 * t + 1] = red[1];
   }
   __syncthreads();  // LDS is reused by the next tile of a persistent group
 }
@@ -645,8 +646,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
     sb += __shfl_xor(sb, o, 64);
   }
   if (lane == 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(A.counters + 6), sp);
-    atomicAdd(reinterpret_cast<unsigned long long*>(A.counters + 8), sb);
+    A.tile_np[2 * t] = sp;
+    A.tile_np[2 * t + 1] = sb;
   }
 }
 
@@ -847,7 +848,7 @@ void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int b
   FwdArgs A{S, w.cams, w.vis_off, w.mat, w.tile_start, w.tile_total, w.tile_order, w.lists,
             w.rec_s, (const unsigned long long*)w.zbuf, w.mesh_rgb, out->image, w.final_T,
             w.n_contrib, out->final_T, out->n_contrib, out->n_blended, out->n_processed,
-            w.counters};
+            (unsigned long long*)w.tile_np};
   const bool d2 = (variant & 1) != 0, pers = (variant & 2) != 0;
   uint32_t* queue = w.counters + 14;
   if (variant & 4) {

@@ -44,10 +44,10 @@ struct Work {
   uint32_t* tile_start;  // [n_tiles]
   uint32_t* tile_order;  // [n_tiles] blend schedule, longest lists first
   uint32_t* tile_dmax;   // [n_tiles] largest mesh depth bits over the tile (culling)
+  uint64_t* tile_np;     // [2 * n_tiles] examined and blended pairs of each tile (forward)
   uint32_t* lists;       // [key_cap] ranks grouped by tile, chunk sub-segments in chunk order
   // counters: [0] n_vis, [1] overflow, [2..3] K (u64), [4] n_tris, [5] n_blocks,
-  // [6..7] sum n_processed (u64), [8..9] sum n_blended (u64), [10..11] K scan total,
-  // [13] pairs kept in the tile lists
+  // [10..11] K scan total, [13] pairs kept in the tile lists, [14] tile queue
   uint32_t* counters;
   // mesh
   uint64_t* zbuf;        // [P] fp32 depth bits << 32 | triangle index
@@ -107,7 +107,8 @@ static_assert(sizeof(CamUpload) + 8 <= 4096, "camera upload must fit in kernel a
 void launch_upload_cams(const CamUpload& u, CamDev* dst, hipStream_t st);
 void launch_mip_filter3d(const float* means, int n, const CamDev* cams, int n_cams, float near,
                          double scale, float* f3, hipStream_t st);
-void launch_counters_to_stats(const uint32_t* counters, hr_stats* stats, hipStream_t st);
+void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,
+                              hr_stats* stats, hipStream_t st);
 void launch_zero_gacc(float* gacc, const uint32_t* counters, hipStream_t st);
 void launch_count_mismatch(const float* a, const float* b, int64_t n, uint32_t* out,
                            hipStream_t st);

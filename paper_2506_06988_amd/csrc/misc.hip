@@ -11,14 +11,42 @@ __global__ void k_upload_cams(CamUpload u, CamDev* dst) {
   if (k < u.count) dst[u.first + k] = u.c[k];
 }
 
-__global__ void k_counters_to_stats(const uint32_t* __restrict__ c, hr_stats* __restrict__ s) {
+// one group of 1024 threads: the counters, and the examined / blended pairs
+// summed over the per-tile sums of the blend
+__global__ __launch_bounds__(1024) void k_counters_to_stats(const uint32_t* __restrict__ c,
+                                                            const uint64_t* __restrict__ tile_np,
+                                                            int n_tiles,
+                                                            hr_stats* __restrict__ s) {
+  __shared__ unsigned long long part[2][16];
+  unsigned long long sp = 0, sb = 0;
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    sp += tile_np[2 * t];
+    sb += tile_np[2 * t + 1];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sp += __shfl_xor(sp, o, 64);
+    sb += __shfl_xor(sb, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if (__lane_id() == 0) {
+    part[0][w] = sp;
+    part[1][w] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  sp = sb = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    sp += part[0][k];
+    sb += part[1][k];
+  }
   s->n_visible = c[0];
   s->overflow = c[1];
   const uint64_t K = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
   s->n_keys = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
   s->n_tris = c[4];
-  s->n_processed = (uint64_t)c[6] | ((uint64_t)c[7] << 32);
-  s->n_blended = (uint64_t)c[8] | ((uint64_t)c[9] << 32);
+  s->n_processed = sp;
+  s->n_blended = sb;
 }
 
 // clears the [n_visible][9] gradient accumulators
@@ -44,8 +72,10 @@ void launch_upload_cams(const CamUpload& u, CamDev* dst, hipStream_t st) {
   hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(64), 0, st, u, dst);
 }
 
-void launch_counters_to_stats(const uint32_t* counters, hr_stats* stats, hipStream_t st) {
-  hipLaunchKernelGGL(k_counters_to_stats, dim3(1), dim3(1), 0, st, counters, stats);
+void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,
+                              hr_stats* stats, hipStream_t st) {
+  hipLaunchKernelGGL(k_counters_to_stats, dim3(1), dim3(1024), 0, st, counters, tile_np, n_tiles,
+                     stats);
 }
 
 void launch_zero_gacc(float* gacc, const uint32_t* counters, hipStream_t st) {
