@@ -35,7 +35,6 @@ namespace {
 constexpr int RS_B = 256;             // radix-sort threads per block
 constexpr int RS_ROUNDS = 8;          // striped rounds per block
 constexpr int RS_KPB = RS_B * RS_ROUNDS;
-constexpr int BIN_GRID = 2048;        // persistent binning workgroups (8 per CU)
 constexpr int MAX_TX = MAX_TILE_COLS; // widest tile row of a camera
 constexpr int NARROW_RUN = 4;         // runs up to this wide are written by one lane
 constexpr int GROUP = 16;             // lanes that share one medium run in the scatter
@@ -650,7 +649,9 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
   uint64_t* Ktot = reinterpret_cast<uint64_t*>(w.counters + 10);
   scan_u64(w.tiles_s, w.pair_off, M + 1, Ktot, w.scan_scratch, st);
   hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, Ktot, S.key_cap, w.counters);
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(BIN_GRID, w.bin_items_max));
+  // one workgroup per (chunk, tile row) the cameras could use (the unused ones
+  // exit at once): the dispatcher balances the uneven rows, nearest chunks first
+  const unsigned grid = (unsigned)std::max<int64_t>(1, w.bin_items_max);
   hipLaunchKernelGGL(k_bin_items, dim3(1), dim3(64), 0, st, w.cams, n_cams, w.vis_off, w.item_off);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
