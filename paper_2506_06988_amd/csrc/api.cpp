@@ -37,8 +37,8 @@ struct Layout {
 struct Plan {
   int64_t n, n_cams, M, F, MF, P, n_tiles, key_cap, rs_blocks, chunk_rows, mat_entries,
       bin_items;
-  size_t cams, counters, tiles, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
-      sval1, rs_hist, vis_off, rec_s, rect_s, tiles_s, item_s, pair_off, mat, tile_total,
+  size_t cams, counters, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
+      sval1, rs_hist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
       tile_start, tile_order, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, gacc, tune, scan_scratch, total;
   std::vector<CamDev> camdev;
@@ -141,7 +141,6 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   const int64_t M = p.M;
   p.cams = L.take(sizeof(CamDev) * n_cams);
   p.counters = L.take(64 * 4);
-  p.tiles = L.take(4 * M);
   p.vis = L.take(4 * M);
   p.vis_scan = L.take(4 * M);
   p.dkey = L.take(4 * M);
@@ -156,9 +155,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.vis_off = L.take(4 * (n_cams + 1));
   p.rec_s = L.take(sizeof(GRec) * M);
   p.rect_s = L.take(8 * M);
-  p.tiles_s = L.take(4 * (M + 1));
   p.item_s = L.take(4 * M);
-  p.pair_off = L.take(8 * (M + 1));
   p.mat = L.take(4 * p.mat_entries);
   p.tile_total = L.take(4 * p.n_tiles);
   p.tile_start = L.take(4 * p.n_tiles);
@@ -190,13 +187,10 @@ Work make_work(const Plan& p, void* ws) {
   Work w;
   w.cams = (CamDev*)(b + p.cams);
   w.counters = (uint32_t*)(b + p.counters);
-  w.tiles = (uint32_t*)(b + p.tiles);
   w.vis = (uint32_t*)(b + p.vis);
   w.vis_scan = (uint32_t*)(b + p.vis_scan);
   w.dkey = (uint32_t*)(b + p.dkey);
   w.rec = (GRec*)(b + p.rec);
-  static_assert(sizeof(EllP) <= sizeof(GRec), "ellipse parameters must fit in a record slot");
-  w.ell_s = (EllP*)(b + p.rec);
   w.rect = (uint2*)(b + p.rect);
   w.rank_of = (int32_t*)(b + p.rank_of);
   w.skey[0] = (uint32_t*)(b + p.skey0);
@@ -208,9 +202,7 @@ Work make_work(const Plan& p, void* ws) {
   w.vis_off = (uint32_t*)(b + p.vis_off);
   w.rec_s = (GRec*)(b + p.rec_s);
   w.rect_s = (uint2*)(b + p.rect_s);
-  w.tiles_s = (uint32_t*)(b + p.tiles_s);
   w.item_s = (uint32_t*)(b + p.item_s);
-  w.pair_off = (uint64_t*)(b + p.pair_off);
   w.mat = (uint32_t*)(b + p.mat);
   w.chunk_rows = p.chunk_rows;
   w.tile_total = (uint32_t*)(b + p.tile_total);
@@ -231,6 +223,10 @@ Work make_work(const Plan& p, void* ws) {
   w.n_contrib = (int32_t*)(b + p.n_contrib);
   w.mesh_rgb = (float*)(b + p.mesh_rgb);
   w.gacc = (float*)(b + p.gacc);
+  // the backward clears gacc before it accumulates; the forward's binning
+  // uses the same memory for the per-rank ellipse constants
+  static_assert(sizeof(EllP) <= 36, "ellipse constants must fit in a gradient slot");
+  w.ell_s = (EllP*)(b + p.gacc);
   w.scan_scratch = b + p.scan_scratch;
   return w;
 }
@@ -269,14 +265,14 @@ hr_status hip_check(const char* what) {
   return HR_OK;
 }
 
-void upload_cams(const Plan& p, const Work& w, hipStream_t st) {
+void upload_cams(const Plan& p, const Work& w, bool clear_counters, hipStream_t st) {
   for (int64_t c0 = 0; c0 < p.n_cams; c0 += CAMS_PER_UPLOAD) {
     CamUpload u;
     std::memset(&u, 0, sizeof(u));
     u.first = (int32_t)c0;
     u.count = (int32_t)std::min<int64_t>(CAMS_PER_UPLOAD, p.n_cams - c0);
     for (int k = 0; k < u.count; ++k) u.c[k] = p.camdev[c0 + k];
-    launch_upload_cams(u, w.cams, st);
+    launch_upload_cams(u, w.cams, clear_counters && c0 == 0 ? w.counters : nullptr, st);
   }
 }
 
@@ -286,13 +282,12 @@ int pick_batch_bwd(const hr_settings* s) { return s->batch_bwd == 0 ? pick_batch
 // enqueue the whole forward
 void enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
                      const hr_mesh* m, const hr_settings* s, hr_outputs* out, hipStream_t st) {
-  launch_fill_u32(w.counters, 0u, 64, st);
-  upload_cams(p, w, st);
+  upload_cams(p, w, true, st);
   launch_mesh(S, *m, w, out, st);
   const bool cull = (s->flags & HR_FLAG_CULL_BEHIND_MESH) && S.n_faces > 0;
   if (cull) launch_tile_dmax(S, w, st);
   launch_project(S, w.cams, *g, w, out->radii, st);
-  launch_depth_sort(S, w, st);
+  launch_depth_sort(S, w, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, st);
   launch_binning(S, w, (int)p.n_cams, cull, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, out, st);
   launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
   if (out->stats) launch_counters_to_stats(w.counters, w.tile_np, (int)S.n_tiles, out->stats, st);

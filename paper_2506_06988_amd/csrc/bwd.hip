@@ -206,7 +206,7 @@ __device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, 
   return lo;
 }
 
-constexpr int TEX_LDS = 1024;  // texels of one tile's footprint accumulated in LDS
+constexpr int TEX_LDS = 2048;  // texels of one tile's footprint accumulated in LDS
 
 // dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights.
 // One workgroup per tile: the texels the tile's pixels read from its most

@@ -16,7 +16,6 @@ struct EllP {
 struct Work {
   CamDev* cams;          // [n_cams]
   // per (camera, Gaussian) item, M = n_cams * n
-  uint32_t* tiles;       // [M] tiles touched, 0 = culled
   uint32_t* vis;         // [M] 1 = visible
   uint32_t* vis_scan;    // [M] exclusive scan of vis
   uint32_t* dkey;        // [M] fp32 depth bits
@@ -31,10 +30,8 @@ struct Work {
   uint32_t* vis_off;     // [n_cams + 1] first rank of each camera
   GRec* rec_s;           // [M] by rank
   uint2* rect_s;         // [M] by rank
-  uint32_t* tiles_s;     // [M + 1] by rank
   uint32_t* item_s;      // [M] item of each rank
-  uint64_t* pair_off;    // [M + 1]
-  EllP* ell_s;           // [M] by rank; shares the memory of rec, unused after the gather
+  EllP* ell_s;           // [M] by rank; shares the memory of gacc (forward only)
   // tile binning
   uint32_t* mat;         // chunk x tile counts, then column prefixes
   int64_t chunk_rows;    // total chunk rows
@@ -46,8 +43,8 @@ struct Work {
   uint32_t* tile_dmax;   // [n_tiles] largest mesh depth bits over the tile (culling)
   uint64_t* tile_np;     // [2 * n_tiles] examined and blended pairs of each tile (forward)
   uint32_t* lists;       // [key_cap] ranks grouped by tile, chunk sub-segments in chunk order
-  // counters: [0] n_vis, [1] overflow, [2..3] K (u64), [4] n_tris, [5] n_blocks,
-  // [10..11] K scan total, [13] pairs kept in the tile lists, [14] tile queue
+  // counters: [0] n_vis, [1] overflow, [2..3] K = pairs in the tile lists (u64),
+  // [4] n_tris, [5] n_blocks, [14] tile queue
   uint32_t* counters;
   // mesh
   uint64_t* zbuf;        // [P] fp32 depth bits << 32 | triangle index
@@ -69,7 +66,7 @@ struct Work {
 // host launch wrappers (all asynchronous on `st`)
 void launch_project(const SetDev& S, const CamDev* cams, const hr_gaussians& g, const Work& w,
                     int32_t* radii, hipStream_t st);
-void launch_depth_sort(const SetDev& S, const Work& w, hipStream_t st);
+void launch_depth_sort(const SetDev& S, const Work& w, bool ell, hipStream_t st);
 void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool ell,
                     hr_outputs* out, hipStream_t st);
 void launch_tile_dmax(const SetDev& S, const Work& w, hipStream_t st);
@@ -104,7 +101,7 @@ struct CamUpload {
   int32_t first, count;
 };
 static_assert(sizeof(CamUpload) + 8 <= 4096, "camera upload must fit in kernel arguments");
-void launch_upload_cams(const CamUpload& u, CamDev* dst, hipStream_t st);
+void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, hipStream_t st);
 void launch_mip_filter3d(const float* means, int n, const CamDev* cams, int n_cams, float near,
                          double scale, float* f3, hipStream_t st);
 void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,

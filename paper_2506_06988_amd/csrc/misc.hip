@@ -6,9 +6,11 @@ namespace hr {
 
 namespace {
 
-__global__ void k_upload_cams(CamUpload u, CamDev* dst) {
+// also clears the 64 forward counters when `clear` is given
+__global__ void k_upload_cams(CamUpload u, CamDev* dst, uint32_t* clear) {
   const int k = threadIdx.x;
   if (k < u.count) dst[u.first + k] = u.c[k];
+  if (clear && k < 64) clear[k] = 0u;
 }
 
 // one group of 1024 threads: the counters, and the examined / blended pairs
@@ -68,8 +70,8 @@ __global__ void k_count_mismatch(const float* __restrict__ a, const float* __res
 
 }  // namespace
 
-void launch_upload_cams(const CamUpload& u, CamDev* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(64), 0, st, u, dst);
+void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, hipStream_t st) {
+  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(64), 0, st, u, dst, clear);
 }
 
 void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,

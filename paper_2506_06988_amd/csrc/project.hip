@@ -13,8 +13,7 @@ namespace {
 __global__ __launch_bounds__(256) void k_project(
     SetDev S, const CamDev* __restrict__ cams, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float* __restrict__ quats,
-    const float* __restrict__ logits, const float* __restrict__ sh, uint32_t* __restrict__ tiles,
-    uint32_t* __restrict__ vis, uint32_t* __restrict__ dkey, GRec* __restrict__ rec,
+    const float* __restrict__ logits, const float* __restrict__ sh, uint32_t* __restrict__ vis, uint32_t* __restrict__ dkey, GRec* __restrict__ rec,
     uint2* __restrict__ rect, int32_t* __restrict__ rank_of, int32_t* __restrict__ radii) {
   const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t M = (int64_t)S.n * S.n_cams;
@@ -26,11 +25,9 @@ __global__ __launch_bounds__(256) void k_project(
   rank_of[item] = -1;
   if (radii) radii[item] = P.vis ? P.r : 0;
   if (!P.vis) {
-    tiles[item] = 0;
     vis[item] = 0;
     return;
   }
-  tiles[item] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
   vis[item] = 1;
   dkey[item] = __float_as_uint(P.zf);
   GRec R;
@@ -116,7 +113,7 @@ void launch_project(const SetDev& S, const CamDev* cams, const hr_gaussians& g, 
   const int64_t M = (int64_t)S.n * S.n_cams;
   if (M == 0) return;
   hipLaunchKernelGGL(k_project, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, S, cams,
-                     g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, w.tiles, w.vis,
+                     g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, w.vis,
                      w.dkey, w.rec, w.rect, w.rank_of, radii);
 }
 

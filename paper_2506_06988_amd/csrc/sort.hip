@@ -56,28 +56,24 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return valid ? m : 0ull;
 }
 
-__global__ void k_vis_offsets(const uint32_t* __restrict__ vis_scan, const uint32_t* __restrict__ vis,
-                              int n, int n_cams, uint32_t* __restrict__ vis_off,
-                              uint32_t* __restrict__ counters) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c > n_cams) return;
-  const int64_t M = (int64_t)n * n_cams;
-  uint32_t v;
-  if (c < n_cams) {
-    v = n > 0 ? vis_scan[(int64_t)c * n] : 0u;
-  } else {
-    v = M > 0 ? vis_scan[M - 1] + vis[M - 1] : 0u;
-    counters[0] = v;
-  }
-  vis_off[c] = v;
-}
-
+// Compaction of the visible items into the first radix-sort buffers; the
+// first n_cams + 1 threads also write each camera's first rank and the total.
 __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ vis,
                                                  const uint32_t* __restrict__ vis_scan,
-                                                 const uint32_t* __restrict__ dkey, int64_t M,
-                                                 uint32_t* __restrict__ skey,
-                                                 uint32_t* __restrict__ sval) {
+                                                 const uint32_t* __restrict__ dkey, int n,
+                                                 int n_cams, uint32_t* __restrict__ skey,
+                                                 uint32_t* __restrict__ sval,
+                                                 uint32_t* __restrict__ vis_off,
+                                                 uint32_t* __restrict__ counters) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t M = (int64_t)n * n_cams;
+  if (i < n_cams) {
+    vis_off[i] = vis_scan[i * n];
+  } else if (i == n_cams) {
+    const uint32_t v = vis_scan[M - 1] + vis[M - 1];
+    vis_off[i] = v;
+    counters[0] = v;
+  }
   if (i >= M || !vis[i]) return;
   const uint32_t p = vis_scan[i];
   skey[p] = dkey[i];
@@ -154,28 +150,48 @@ __global__ __launch_bounds__(RS_B) void k_rs_scatter(const uint32_t* __restrict_
   }
 }
 
+// The per-rank part of the tile-ellipse test (see ellipse_run), FP64.
+__device__ __forceinline__ EllP ell_params(const GRec& R, const uint2 rc, double ln_amin) {
+  const double a = R.ca, b = R.cb, c = R.cc;
+  EllP e;
+  e.det = a * c - b * b;
+  e.dymax = e.sc = 0.0;
+  if (!(a > 0.0 && c > 0.0 && e.det > 0.0)) {
+    e.rp = INFINITY;  // keep the rectangle run
+  } else {
+    const double rr = 2.0 * (log((double)R.op) - ln_amin);
+    if (!(rr > 0.0)) {
+      e.rp = -1.0;  // alpha never reaches alpha_min
+    } else {
+      const int w = (int)(rc.x >> 16) - (int)(rc.x & 0xffffu);
+      const int h = (int)(rc.y >> 16) - (int)(rc.y & 0xffffu);
+      const double ext = 16.0 * (double)max(w, h);
+      e.rp = 1.01 * rr + 0.1 + 1e-5 * (a + c) * ext * ext;
+      e.dymax = sqrt(a * e.rp / e.det);
+      e.sc = sqrt(e.rp / (c * e.det));
+    }
+  }
+  return e;
+}
+
 __global__ __launch_bounds__(256) void k_gather(const uint32_t* __restrict__ sval,
                                                 const uint32_t* __restrict__ counters, int64_t M,
                                                 const GRec* __restrict__ rec,
                                                 const uint2* __restrict__ rect,
-                                                const uint32_t* __restrict__ tiles,
                                                 GRec* __restrict__ rec_s, uint2* __restrict__ rect_s,
-                                                uint32_t* __restrict__ tiles_s,
                                                 uint32_t* __restrict__ item_s,
-                                                int32_t* __restrict__ rank_of) {
+                                                int32_t* __restrict__ rank_of, double ln_amin,
+                                                EllP* __restrict__ ell) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r > M) return;
-  const uint32_t nv = counters[0];
-  if (r >= nv) {
-    tiles_s[r] = 0;
-    return;
-  }
+  if (r >= M || r >= (int64_t)counters[0]) return;
   const uint32_t it = sval[r];
-  rec_s[r] = rec[it];
-  rect_s[r] = rect[it];
-  tiles_s[r] = tiles[it];
+  const GRec R = rec[it];
+  const uint2 rc = rect[it];
+  rec_s[r] = R;
+  rect_s[r] = rc;
   item_s[r] = it;
   rank_of[it] = (int32_t)r;
+  if (ell) ell[r] = ell_params(R, rc, ln_amin);
 }
 
 __device__ __forceinline__ int find_cam_by_row(const CamDev* cams, int n_cams, int64_t row) {
@@ -268,36 +284,6 @@ __device__ __forceinline__ bool row_run(const uint2 rc, int y, int& x0, int& x1)
 // rectangle) to cover the FP32 evaluation of the blend's test. An opacity at
 // or below alpha_min empties the row. FP64; the per-rank part is computed
 // once (k_ell_params), the per-row part in both passes by the same steps.
-__global__ __launch_bounds__(256) void k_ell_params(const uint32_t* __restrict__ counters,
-                                                    const GRec* __restrict__ rec_s,
-                                                    const uint2* __restrict__ rect_s,
-                                                    double ln_amin, EllP* __restrict__ ell) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= (int64_t)counters[0]) return;
-  const GRec R = rec_s[r];
-  const uint2 rc = rect_s[r];
-  const double a = R.ca, b = R.cb, c = R.cc;
-  EllP e;
-  e.det = a * c - b * b;
-  e.dymax = e.sc = 0.0;
-  if (!(a > 0.0 && c > 0.0 && e.det > 0.0)) {
-    e.rp = INFINITY;  // keep the rectangle run
-  } else {
-    const double rr = 2.0 * (log((double)R.op) - ln_amin);
-    if (!(rr > 0.0)) {
-      e.rp = -1.0;  // alpha never reaches alpha_min
-    } else {
-      const int w = (int)(rc.x >> 16) - (int)(rc.x & 0xffffu);
-      const int h = (int)(rc.y >> 16) - (int)(rc.y & 0xffffu);
-      const double ext = 16.0 * (double)max(w, h);
-      e.rp = 1.01 * rr + 0.1 + 1e-5 * (a + c) * ext * ext;
-      e.dymax = sqrt(a * e.rp / e.det);
-      e.sc = sqrt(e.rp / (c * e.det));
-    }
-  }
-  ell[r] = e;
-}
-
 __device__ __forceinline__ bool ellipse_run(const GRec& R, const uint2 rc, const EllP& e, int y,
                                             int& x0, int& x1) {
   if (!row_run(rc, y, x0, x1)) return false;
@@ -538,16 +524,26 @@ __global__ __launch_bounds__(256) void k_tile_order(const CamDev* __restrict__ c
 
 // Blend schedule: tiles by decreasing list length (buckets of log2 length),
 // so the longest lists start first and the short ones fill in at the end.
+// The same workgroup adds up the pairs of every tile (64-bit): the key count
+// and the capacity check.
 __global__ __launch_bounds__(1024) void k_tile_schedule(int n_tiles, const uint32_t* __restrict__ tile_total,
-                                                        uint32_t* __restrict__ order) {
+                                                        uint32_t* __restrict__ order,
+                                                        int64_t key_cap,
+                                                        uint32_t* __restrict__ counters) {
   __shared__ uint32_t cnt[33];
   __shared__ uint32_t off[33];
+  __shared__ unsigned long long part[16];
   if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
   __syncthreads();
+  unsigned long long K = 0;
   for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
     const uint32_t L = tile_total[t];
+    K += L;
     atomicAdd(&cnt[L ? 32 - __clz(L) : 0], 1u);
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) K += __shfl_xor(K, o, 64);
+  if (__lane_id() == 0) part[threadIdx.x >> 6] = K;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
@@ -555,32 +551,17 @@ __global__ __launch_bounds__(1024) void k_tile_schedule(int n_tiles, const uint3
       off[b] = acc;
       acc += cnt[b];
     }
+    K = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) K += part[w];
+    counters[2] = (uint32_t)K;
+    counters[3] = (uint32_t)(K >> 32);
+    counters[1] = K > (unsigned long long)key_cap ? 1u : 0u;
   }
   __syncthreads();
   for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
     const uint32_t L = tile_total[t];
     order[atomicAdd(&off[L ? 32 - __clz(L) : 0], 1u)] = (uint32_t)t;
   }
-}
-
-__global__ __launch_bounds__(256) void k_pair_total(const uint64_t* __restrict__ total,
-                                                    int64_t key_cap, uint32_t* __restrict__ counters) {
-  const uint64_t K = *total;
-  counters[2] = (uint32_t)K;
-  counters[3] = (uint32_t)(K >> 32);
-  counters[1] = K > (uint64_t)key_cap ? 1u : 0u;
-}
-
-// After culling: the lists hold counters[13] pairs (exact while the uncut
-// total K fits 32 bits, which every valid capacity implies); the capacity
-// check and the reported key count use it.
-__global__ __launch_bounds__(256) void k_kept_total(int64_t key_cap, uint32_t* __restrict__ counters) {
-  const uint64_t K = (uint64_t)counters[2] | ((uint64_t)counters[3] << 32);
-  if (K > 0xffffffffull) return;  // overflow already flagged by k_pair_total
-  const uint32_t kept = counters[13];
-  counters[2] = kept;
-  counters[3] = 0;
-  counters[1] = (int64_t)kept > key_cap ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(256) void k_export_keys(const CamDev* __restrict__ cams, int n_cams,
@@ -605,20 +586,17 @@ __global__ __launch_bounds__(256) void k_export_keys(const CamDev* __restrict__ 
 
 }  // namespace
 
-void launch_depth_sort(const SetDev& S, const Work& w, hipStream_t st) {
+void launch_depth_sort(const SetDev& S, const Work& w, bool ell, hipStream_t st) {
   const int64_t M = (int64_t)S.n * S.n_cams;
   if (M == 0) {
     launch_fill_u32(w.counters, 0u, 1, st);
     launch_fill_u32(w.vis_off, 0u, S.n_cams + 1, st);
-    launch_fill_u32(w.tiles_s, 0u, 1, st);
     return;
   }
   scan_u32(w.vis, w.vis_scan, M, nullptr, w.scan_scratch, st);
-  hipLaunchKernelGGL(k_vis_offsets, dim3((S.n_cams + 1 + 255) / 256), dim3(256), 0, st, w.vis_scan,
-                     w.vis, S.n, S.n_cams, w.vis_off, w.counters);
-  const unsigned gb = (unsigned)((M + 255) / 256);
-  hipLaunchKernelGGL(k_compact, dim3(gb), dim3(256), 0, st, w.vis, w.vis_scan, w.dkey, M,
-                     w.skey[0], w.sval[0]);
+  const unsigned gb = (unsigned)((std::max<int64_t>(M, S.n_cams + 1) + 255) / 256);
+  hipLaunchKernelGGL(k_compact, dim3(gb), dim3(256), 0, st, w.vis, w.vis_scan, w.dkey, S.n,
+                     S.n_cams, w.skey[0], w.sval[0], w.vis_off, w.counters);
   int passes = 4;
   if (S.n_cams > 1) passes = S.n_cams > 256 ? 6 : 5;
   const int64_t nb = w.rs_blocks;
@@ -632,23 +610,16 @@ void launch_depth_sort(const SetDev& S, const Work& w, hipStream_t st) {
                        w.rs_hist);
     cur ^= 1;
   }
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)((M + 1 + 255) / 256)), dim3(256), 0, st,
-                     w.sval[cur], w.counters, M, w.rec, w.rect, w.tiles, w.rec_s, w.rect_s,
-                     w.tiles_s, w.item_s, w.rank_of);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                     w.sval[cur], w.counters, M, w.rec, w.rect, w.rec_s, w.rect_s,
+                     w.item_s, w.rank_of, std::log((double)S.alpha_min),
+                     ell ? w.ell_s : nullptr);
 }
 
 void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool ell,
                     hr_outputs* out, hipStream_t st) {
   const uint32_t* tdm = cull ? w.tile_dmax : nullptr;
-  const double ln_amin = std::log((double)S.alpha_min);
   const EllP* ellp = ell ? w.ell_s : nullptr;
-  const int64_t M = (int64_t)S.n * S.n_cams;
-  if (ell && M > 0)
-    hipLaunchKernelGGL(k_ell_params, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
-                       w.counters, w.rec_s, w.rect_s, ln_amin, w.ell_s);
-  uint64_t* Ktot = reinterpret_cast<uint64_t*>(w.counters + 10);
-  scan_u64(w.tiles_s, w.pair_off, M + 1, Ktot, w.scan_scratch, st);
-  hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, st, Ktot, S.key_cap, w.counters);
   // one workgroup per (chunk, tile row) the cameras could use (the unused ones
   // exit at once): the dispatcher balances the uneven rows, nearest chunks first
   const unsigned grid = (unsigned)std::max<int64_t>(1, w.bin_items_max);
@@ -658,10 +629,9 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
                        w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat);
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
-  scan_u32(w.tile_total, w.tile_start, S.n_tiles, w.counters + 13, w.scan_scratch, st);
-  hipLaunchKernelGGL(k_kept_total, dim3(1), dim3(1), 0, st, S.key_cap, w.counters);
+  scan_u32(w.tile_total, w.tile_start, S.n_tiles, nullptr, w.scan_scratch, st);
   hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(1024), 0, st, S.n_tiles, w.tile_total,
-                     w.tile_order);
+                     w.tile_order, S.key_cap, w.counters);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
                        w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat, w.tile_start,
