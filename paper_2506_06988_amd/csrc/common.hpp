@@ -61,7 +61,7 @@ struct alignas(16) GRec {
 // Clipped, snapped triangle of one camera.
 struct alignas(16) TriRec {
   int32_t X[3], Y[3];   // vertices in 1/256 px, counter-clockwise (positive area)
-  double z[3];          // view depth of each vertex
+  double iz[3];         // 1 / view depth of each vertex
   double uv[3][2];
   int32_t face, tex, cam, pad;
   int32_t bx0, by0, bx1, by1;  // 8x8 pixel blocks covered by the bbox (inclusive)

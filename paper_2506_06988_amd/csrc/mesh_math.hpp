@@ -98,7 +98,7 @@ __device__ __forceinline__ bool setup_tri(const CamDev& cam, const CV poly[4], i
   for (int k = 0; k < 3; ++k) {
     T.X[k] = (int32_t)X[ord[k]];
     T.Y[k] = (int32_t)Y[ord[k]];
-    T.z[k] = tv[ord[k]]->p[2];
+    T.iz[k] = 1.0 / tv[ord[k]]->p[2];
     T.uv[k][0] = tv[ord[k]]->uv[0];
     T.uv[k][1] = tv[ord[k]]->uv[1];
   }
@@ -118,31 +118,38 @@ __device__ __forceinline__ int tri_blocks(const TriRec& T) {
   return (T.bx1 - T.bx0 + 1) * (T.by1 - T.by0 + 1);
 }
 
-// Coverage of pixel (i, j): edge values e[k] (the weight of vertex k).
+// Coverage of pixel (i, j): edge values e[k] (the weight of vertex k). The
+// vertices are within 2^29 in fixed point, so every difference fits 32 bits
+// and each edge value is two 32 x 32 -> 64-bit products.
+__device__ __forceinline__ int64_t edge_at(int32_t ax, int32_t ay, int32_t bx, int32_t by,
+                                           int32_t px, int32_t py) {
+  return (int64_t)(bx - ax) * (int64_t)(py - ay) - (int64_t)(by - ay) * (int64_t)(px - ax);
+}
+
 __device__ __forceinline__ bool tri_cover(const TriRec& T, int i, int j, int64_t e[3]) {
-  const int64_t px = (int64_t)SUBPIX * i + SUBPIX / 2, py = (int64_t)SUBPIX * j + SUBPIX / 2;
-  const int64_t X0 = T.X[0], Y0 = T.Y[0], X1 = T.X[1], Y1 = T.Y[1], X2 = T.X[2], Y2 = T.Y[2];
-  e[0] = edge_i64(X1, Y1, X2, Y2, px, py);
-  e[1] = edge_i64(X2, Y2, X0, Y0, px, py);
-  e[2] = edge_i64(X0, Y0, X1, Y1, px, py);
+  const int32_t px = SUBPIX * i + SUBPIX / 2, py = SUBPIX * j + SUBPIX / 2;
+  const int32_t X0 = T.X[0], Y0 = T.Y[0], X1 = T.X[1], Y1 = T.Y[1], X2 = T.X[2], Y2 = T.Y[2];
+  e[0] = edge_at(X1, Y1, X2, Y2, px, py);
+  e[1] = edge_at(X2, Y2, X0, Y0, px, py);
+  e[2] = edge_at(X0, Y0, X1, Y1, px, py);
   const bool in0 = e[0] > 0 || (e[0] == 0 && edge_owns(X1, Y1, X2, Y2));
   const bool in1 = e[1] > 0 || (e[1] == 0 && edge_owns(X2, Y2, X0, Y0));
   const bool in2 = e[2] > 0 || (e[2] == 0 && edge_owns(X0, Y0, X1, Y1));
   return in0 && in1 && in2;
 }
 
-// perspective-correct depth and UV from the edge values
+// Perspective-correct depth and UV from the edge values: with s_k = e_k / z_k,
+// the depth is (e_0 + e_1 + e_2) / (s_0 + s_1 + s_2) and the perspective
+// weights are s_k / (s_0 + s_1 + s_2). One FP64 reciprocal per pixel.
 __device__ __forceinline__ double tri_interp(const TriRec& T, const int64_t e[3], double uv[2]) {
-  const int64_t A64 = e[0] + e[1] + e[2];
-  const double A = (double)A64;
-  const double q0 = ((double)e[0] / A) / T.z[0];
-  const double q1 = ((double)e[1] / A) / T.z[1];
-  const double q2 = ((double)e[2] / A) / T.z[2];
-  const double z = 1.0 / (q0 + q1 + q2);
+  const double s0 = (double)e[0] * T.iz[0];
+  const double s1 = (double)e[1] * T.iz[1];
+  const double s2 = (double)e[2] * T.iz[2];
+  const double inv = 1.0 / (s0 + s1 + s2);
+  const double z = (double)(e[0] + e[1] + e[2]) * inv;
   if (uv) {
-    const double w0 = q0 * z, w1 = q1 * z, w2 = q2 * z;
-    uv[0] = w0 * T.uv[0][0] + w1 * T.uv[1][0] + w2 * T.uv[2][0];
-    uv[1] = w0 * T.uv[0][1] + w1 * T.uv[1][1] + w2 * T.uv[2][1];
+    uv[0] = (s0 * T.uv[0][0] + s1 * T.uv[1][0] + s2 * T.uv[2][0]) * inv;
+    uv[1] = (s0 * T.uv[0][1] + s1 * T.uv[1][1] + s2 * T.uv[2][1]) * inv;
   }
   return z;
 }
