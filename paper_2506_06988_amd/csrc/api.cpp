@@ -41,6 +41,7 @@ struct Plan {
       sval1, rs_hist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
       tile_start, tile_order, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, gacc, tune, scan_scratch, total;
+  int64_t scan_words;
   std::vector<CamDev> camdev;
 };
 
@@ -178,6 +179,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   int64_t longest =
       std::max<int64_t>({M + 1, 256 * p.rs_blocks, p.n_tiles, p.MF + 1, p.chunk_rows + 1, 1});
   p.scan_scratch = L.take(scan_scratch_bytes(longest) + 4096);
+  p.scan_words = (int64_t)scan_state_words(longest);
   p.total = L.off;
   return HR_OK;
 }
@@ -228,6 +230,7 @@ Work make_work(const Plan& p, void* ws) {
   static_assert(sizeof(EllP) <= 36, "ellipse constants must fit in a gradient slot");
   w.ell_s = (EllP*)(b + p.gacc);
   w.scan_scratch = b + p.scan_scratch;
+  w.scan_words = p.scan_words;
   return w;
 }
 
@@ -272,7 +275,9 @@ void upload_cams(const Plan& p, const Work& w, bool clear_counters, hipStream_t 
     u.first = (int32_t)c0;
     u.count = (int32_t)std::min<int64_t>(CAMS_PER_UPLOAD, p.n_cams - c0);
     for (int k = 0; k < u.count; ++k) u.c[k] = p.camdev[c0 + k];
-    launch_upload_cams(u, w.cams, clear_counters && c0 == 0 ? w.counters : nullptr, st);
+    const bool clr = clear_counters && c0 == 0;
+    launch_upload_cams(u, w.cams, clr ? w.counters : nullptr, (uint32_t*)w.scan_scratch,
+                       w.scan_words, st);
   }
 }
 

@@ -112,11 +112,12 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
 // Launch wrappers implemented in the .hip files (host side).
 namespace hr {
 
-// generic exclusive scans over n elements (n may exceed what is used; the tail must be 0)
+// generic exclusive scan over n elements (n may exceed what is used; the tail
+// must be 0); the scratch holds its state, which must be zero before the first
+// scan (the forward's camera upload clears scan_state_words of it)
 size_t scan_scratch_bytes(int64_t n);
+size_t scan_state_words(int64_t n);
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* scratch,
-              hipStream_t st);
-void scan_u64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* total, void* scratch,
               hipStream_t st);
 
 }  // namespace hr

@@ -59,8 +59,9 @@ struct Work {
   float* mesh_rgb;       // [3P]
   // backward accumulators, [M][9] by rank: u, v, conic a b c, opacity, r g b
   float* gacc;
-  // scratch of the scans
+  // scratch of the scans (its first scan_words words are the scan state)
   void* scan_scratch;
+  int64_t scan_words;
 };
 
 // host launch wrappers (all asynchronous on `st`)
@@ -101,7 +102,8 @@ struct CamUpload {
   int32_t first, count;
 };
 static_assert(sizeof(CamUpload) + 8 <= 4096, "camera upload must fit in kernel arguments");
-void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, hipStream_t st);
+void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
+                        int64_t n2, hipStream_t st);
 void launch_mip_filter3d(const float* means, int n, const CamDev* cams, int n_cams, float near,
                          double scale, float* f3, hipStream_t st);
 void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,
