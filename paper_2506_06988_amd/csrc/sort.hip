@@ -150,7 +150,7 @@ __global__ __launch_bounds__(RS_B) void k_rs_scatter(const uint32_t* __restrict_
   }
 }
 
-// The per-rank part of the tile-ellipse test (see ellipse_run), FP64.
+// The per-rank part of the tile-ellipse test (see ellipse_cut), FP64.
 __device__ __forceinline__ EllP ell_params(const GRec& R, const uint2 rc, double ln_amin) {
   const double a = R.ca, b = R.cb, c = R.cc;
   EllP e;
@@ -283,30 +283,62 @@ __device__ __forceinline__ bool row_run(const uint2 rc, int y, int& x0, int& x1)
 // (1.01 R + 0.1, plus a term for the magnitude of the quadratic form over the
 // rectangle) to cover the FP32 evaluation of the blend's test. An opacity at
 // or below alpha_min empties the row. FP64; the per-rank part is computed
-// once (k_ell_params), the per-row part in both passes by the same steps.
-__device__ __forceinline__ bool ellipse_run(const GRec& R, const uint2 rc, const EllP& e, int y,
-                                            int& x0, int& x1) {
-  if (!row_run(rc, y, x0, x1)) return false;
+// once (ell_params, in the gather), the per-row part in both passes by the
+// same steps.
+// g = (u, v, conic a, conic b), the first 16 bytes of the record
+__device__ __forceinline__ bool ellipse_cut(const float4 g, const EllP& e, int y, int& x0,
+                                            int& x1) {
   if (e.rp < 0.0) return false;
   if (isinf(e.rp)) return true;
-  const double a = R.ca, b = R.cb;
-  const double lo = fmax((double)y * TILE + 0.5 - (double)R.v, -e.dymax);
-  const double hi = fmin((double)y * TILE + (TILE - 0.5) - (double)R.v, e.dymax);
+  const double a = g.z, b = g.w;
+  const double lo = fmax((double)y * TILE + 0.5 - (double)g.y, -e.dymax);
+  const double hi = fmin((double)y * TILE + (TILE - 0.5) - (double)g.y, e.dymax);
   if (lo > hi) return false;
   const double ys = fmin(fmax(-b * e.sc, lo), hi), yn = fmin(fmax(b * e.sc, lo), hi);
   const double xmax = (-b * ys + sqrt(fmax(a * e.rp - e.det * ys * ys, 0.0))) / a;
   const double xmin = (-b * yn - sqrt(fmax(a * e.rp - e.det * yn * yn, 0.0))) / a;
-  const int ex0 = (int)ceil(((double)R.u + xmin - (TILE - 0.5)) / TILE);
-  const int ex1 = (int)floor(((double)R.u + xmax - 0.5) / TILE) + 1;
+  const int ex0 = (int)ceil(((double)g.x + xmin - (TILE - 0.5)) / TILE);
+  const int ex1 = (int)floor(((double)g.x + xmax - 0.5) / TILE) + 1;
   x0 = max(x0, ex0);
   x1 = min(x1, ex1);
   return x1 > x0;
 }
 
-__device__ __forceinline__ bool pair_run(const uint2* rect_s, const GRec* rec_s, const EllP* ell,
-                                         int64_t k, int y, int& x0, int& x1) {
-  return ell ? ellipse_run(rec_s[k], rect_s[k], ell[k], y, x0, x1)
-             : row_run(rect_s[k], y, x0, x1);
+// The runs in row B.y of this thread's ranks k0 + 256 j, j < RUNS (x1 <= x0:
+// none). All rectangles are loaded first, then the ellipse data of the ranks
+// whose rectangle spans the row, so the loads of a thread overlap.
+constexpr int RUNS = 4;
+__device__ __forceinline__ void item_runs(const BinItem& B, int64_t k0,
+                                          const uint2* __restrict__ rect_s,
+                                          const GRec* __restrict__ rec_s,
+                                          const EllP* __restrict__ ell, int x0[RUNS],
+                                          int x1[RUNS]) {
+  uint2 rc[RUNS];
+#pragma unroll
+  for (int j = 0; j < RUNS; ++j) {
+    const int64_t k = k0 + 256 * j;
+    rc[j] = k < B.r1 ? rect_s[k] : make_uint2(0u, 0u);  // rows [0, 0): no run
+  }
+  bool on[RUNS];
+#pragma unroll
+  for (int j = 0; j < RUNS; ++j) on[j] = row_run(rc[j], B.y, x0[j], x1[j]);
+  if (ell) {
+    float4 g[RUNS];
+    EllP e[RUNS];
+#pragma unroll
+    for (int j = 0; j < RUNS; ++j)
+      if (on[j]) {
+        const int64_t k = k0 + 256 * j;
+        g[j] = *reinterpret_cast<const float4*>(rec_s + k);
+        e[j] = ell[k];
+      }
+#pragma unroll
+    for (int j = 0; j < RUNS; ++j)
+      if (on[j]) on[j] = ellipse_cut(g[j], e[j], B.y, x0[j], x1[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < RUNS; ++j)
+    if (!on[j]) x1[j] = x0[j];
 }
 
 // Count pass: per (chunk, tile row), the chunk's pair count of every tile of
@@ -328,19 +360,24 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
     for (int x = threadIdx.x; x <= B.TX; x += 256) diff[x] = 0;
     __syncthreads();
     const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off + B.y * B.TX : nullptr;
-    for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
-      int x0, x1;
-      if (!pair_run(rect_s, rec_s, ell, k, B.y, x0, x1)) continue;
-      if (!tdm) {
-        atomicAdd(&diff[x0], 1);
-        atomicSub(&diff[x1], 1);
-      } else {
-        const uint32_t dep = __float_as_uint(rec_s[k].depth);
-        for (int x = x0; x < x1; ++x)
-          if (dep < tdm[x]) {
-            atomicAdd(&diff[x], 1);
-            atomicSub(&diff[x + 1], 1);
-          }
+    for (int64_t k0 = B.r0 + threadIdx.x; k0 < B.r1; k0 += 256 * RUNS) {
+      int rx0[RUNS], rx1[RUNS];
+      item_runs(B, k0, rect_s, rec_s, ell, rx0, rx1);
+#pragma unroll
+      for (int j = 0; j < RUNS; ++j) {
+        const int x0 = rx0[j], x1 = rx1[j];
+        if (x1 <= x0) continue;
+        if (!tdm) {
+          atomicAdd(&diff[x0], 1);
+          atomicSub(&diff[x1], 1);
+        } else {
+          const uint32_t dep = __float_as_uint(rec_s[k0 + 256 * j].depth);
+          for (int x = x0; x < x1; ++x)
+            if (dep < tdm[x]) {
+              atomicAdd(&diff[x], 1);
+              atomicSub(&diff[x + 1], 1);
+            }
+        }
       }
     }
     __syncthreads();
@@ -404,21 +441,28 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
     };
     const int half = B.TX / 2;
     // short runs by one lane; the others are sorted into the two lists
-    for (int64_t k = B.r0 + threadIdx.x; k < B.r1; k += 256) {
-      int x0, x1;
-      if (!pair_run(rect_s, rec_s, ell, k, B.y, x0, x1)) continue;
-      const uint32_t packed = (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k - B.r0) << 21);
-      const int w = x1 - x0;
-      if (w > NARROW_RUN && w > half) {
-        const uint32_t q = atomicAdd(&nwide, 1u);
-        wide[q] = packed;
-        if (tdm) wide_dep[q] = __float_as_uint(rec_s[k].depth);
-      } else if (w > NARROW_RUN) {
-        mid[atomicAdd(&nmid, 1u)] = packed;
-      } else {
-        const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
-        for (int x = x0; x < x1; ++x)
-          if (!tdm || dep < tdm[x]) put((uint32_t)k, x);
+    for (int64_t k0 = B.r0 + threadIdx.x; k0 < B.r1; k0 += 256 * RUNS) {
+      int rx0[RUNS], rx1[RUNS];
+      item_runs(B, k0, rect_s, rec_s, ell, rx0, rx1);
+#pragma unroll
+      for (int j = 0; j < RUNS; ++j) {
+        const int x0 = rx0[j], x1 = rx1[j];
+        if (x1 <= x0) continue;
+        const int64_t k = k0 + 256 * j;
+        const uint32_t packed =
+            (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k - B.r0) << 21);
+        const int w = x1 - x0;
+        if (w > NARROW_RUN && w > half) {
+          const uint32_t q = atomicAdd(&nwide, 1u);
+          wide[q] = packed;
+          if (tdm) wide_dep[q] = __float_as_uint(rec_s[k].depth);
+        } else if (w > NARROW_RUN) {
+          mid[atomicAdd(&nmid, 1u)] = packed;
+        } else {
+          const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
+          for (int x = x0; x < x1; ++x)
+            if (!tdm || dep < tdm[x]) put((uint32_t)k, x);
+        }
       }
     }
     __syncthreads();
