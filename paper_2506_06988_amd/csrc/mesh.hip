@@ -162,10 +162,15 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
     const float wx = tp.fx, wy = tp.fy;
     const float w00 = (1.f - wx) * (1.f - wy), w10 = wx * (1.f - wy), w01 = (1.f - wx) * wy,
                 w11 = wx * wy;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch)
-      rgb[ch] = w00 * tex[tp.o00 + ch] + w10 * tex[tp.o10 + ch] + w01 * tex[tp.o01 + ch] +
-                w11 * tex[tp.o11 + ch];
+    // one 12-byte load per texel
+    float3 t00, t10, t01, t11;
+    __builtin_memcpy(&t00, tex + tp.o00, 12);
+    __builtin_memcpy(&t10, tex + tp.o10, 12);
+    __builtin_memcpy(&t01, tex + tp.o01, 12);
+    __builtin_memcpy(&t11, tex + tp.o11, 12);
+    rgb[0] = w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x;
+    rgb[1] = w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y;
+    rgb[2] = w00 * t00.z + w10 * t10.z + w01 * t01.z + w11 * t11.z;
     depth = __uint_as_float((uint32_t)(key >> 32));
     face = T.face;
   }

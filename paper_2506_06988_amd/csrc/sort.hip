@@ -120,15 +120,20 @@ __global__ __launch_bounds__(RS_B) void k_rs_scatter(const uint32_t* __restrict_
   const uint32_t nv = counters[0];
   const int64_t base = (int64_t)blockIdx.x * RS_KPB;
   if (base >= nv) return;
+  // every round's keys are loaded up front, so the loads overlap
+  uint32_t kr[RS_ROUNDS], vr[RS_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t i = base + r * RS_B + tid;
+    kr[r] = i < nv ? key[i] : 0u;
+    vr[r] = i < nv ? val[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t i = base + r * RS_B + tid;
     const bool valid = i < nv;
-    uint32_t kk = 0, vv = 0, d = 0;
-    if (valid) {
-      kk = key[i];
-      vv = val[i];
-      d = rs_digit(kk, vv, pass, n);
-    }
+    const uint32_t kk = kr[r], vv = vr[r];
+    const uint32_t d = valid ? rs_digit(kk, vv, pass, n) : 0u;
     const uint64_t m = match_digit(d, valid);
     const uint32_t below = (uint32_t)__popcll(m & lanemask_lt());
     if (valid && below == 0) wcnt[w][d] = (uint32_t)__popcll(m);
