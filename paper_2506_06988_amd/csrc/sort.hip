@@ -518,10 +518,16 @@ __global__ __launch_bounds__(256) void k_colscan(const CamDev* __restrict__ cams
   const int64_t rows = (nvc + CHUNK - 1) / CHUNK;
   uint32_t acc = 0;
   uint32_t* col = mat + cam.mat_off + tl;
-  for (int64_t r = 0; r < rows; ++r) {
-    const uint32_t v = col[r * ntl];
-    col[r * ntl] = acc;
-    acc += v;
+  // 8 rows at a time: the loads of a group are in flight together
+  for (int64_t r0 = 0; r0 < rows; r0 += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = r0 + q < rows ? col[(r0 + q) * ntl] : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (r0 + q < rows) col[(r0 + q) * ntl] = acc;
+      acc += v[q];
+    }
   }
   tile_total[t] = acc;
 }
