@@ -44,8 +44,9 @@ __device__ __forceinline__ float gauss_p2(const float4& a, const float4& b, floa
                                           float& dx, float& dy) {
   dx = a.x - px;
   dy = a.y - py;
-  const float dxx = dx * dx, dyy = dy * dy, dxy = dx * dy;
-  return __builtin_fmaf(a.z, dxx, __builtin_fmaf(b.x, dyy, __builtin_fmaf(a.w, dxy, b.y)));
+  // A2 dx^2 + B2 dx dy + C2 dy^2 + log2(op) as dx (A2 dx + B2 dy) + (C2 dy dy + log2(op))
+  const float t = __builtin_fmaf(a.w, dy, a.z * dx);
+  return __builtin_fmaf(dx, t, __builtin_fmaf(b.x * dy, dy, b.y));
 }
 
 struct TileCtx {
@@ -575,7 +576,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
         if (lane_done()) continue;
         const float4 ea = e->a, eb = e->b;
         const float dx = ea.x - px;
-        const float dxx = dx * dx;
+        const float adx = ea.z * dx;  // the factored form of gauss_p2, A2 dx shared
         const int pos = pos0 + k;
 #pragma unroll
         for (int r = 0; r < WPIX; ++r) {
@@ -586,9 +587,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
             continue;
           }
           const float dy = ea.y - py[r];
-          const float dyy = dy * dy, dxy = dx * dy;
-          const float p2 =
-              __builtin_fmaf(ea.z, dxx, __builtin_fmaf(eb.x, dyy, __builtin_fmaf(ea.w, dxy, eb.y)));
+          const float p2 = __builtin_fmaf(dx, __builtin_fmaf(ea.w, dy, adx),
+                                          __builtin_fmaf(eb.x * dy, dy, eb.y));
           if (p2 >= lthr) {
             const float alpha = fminf(amax, __builtin_amdgcn_exp2f(p2));
             const float Tn = T[r] * (1.f - alpha);
@@ -748,6 +748,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
         const float4 ea = sh[k].a, eb = sh[k].b;
         const float dx = ea.x - px;
         const float dxx = dx * dx;
+        const float adx = ea.z * dx;  // the factored form of gauss_p2, A2 dx shared
         const float iop = __builtin_amdgcn_rcpf(eb.w);
         // per lane, over its four pixels: colour gradients, and the sums
         // s0 = sum gp, s1 = sum gp dy, s2 = sum gp dy^2 (gp = dL/dpower),
@@ -759,9 +760,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
         for (int r = 0; r < WPIX; ++r) {
           if (idx > nc[r]) continue;
           const float dy = ea.y - py[r];
-          const float dyy = dy * dy, dxy = dx * dy;
-          const float p2 =
-              __builtin_fmaf(ea.z, dxx, __builtin_fmaf(eb.x, dyy, __builtin_fmaf(ea.w, dxy, eb.y)));
+          const float dyy = dy * dy;
+          const float p2 = __builtin_fmaf(dx, __builtin_fmaf(ea.w, dy, adx),
+                                          __builtin_fmaf(eb.x * dy, dy, eb.y));
           if (!(p2 >= lthr)) continue;  // the forward's skip decision
           any = true;
           const float ag = __builtin_amdgcn_exp2f(p2);  // opacity * G

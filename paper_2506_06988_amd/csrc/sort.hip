@@ -591,10 +591,23 @@ __global__ __launch_bounds__(1024) void k_tile_schedule(int n_tiles, const uint3
   if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
   __syncthreads();
   unsigned long long K = 0;
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-    const uint32_t L = tile_total[t];
+  // the loops are uniform over the group; the lanes of a wave that share a
+  // bucket add to it with one LDS atomic (few distinct buckets per wave)
+  const int lane = __lane_id();
+  for (int t0 = threadIdx.x - lane; t0 < n_tiles; t0 += blockDim.x) {
+    const int t = t0 + lane;
+    const bool ok = t < n_tiles;
+    const uint32_t L = ok ? tile_total[t] : 0u;
     K += L;
-    atomicAdd(&cnt[L ? 32 - __clz(L) : 0], 1u);
+    const uint32_t b = L ? 32 - __clz(L) : 0;
+    uint64_t todo = __ballot(ok);
+    while (todo) {
+      const int lead = __ffsll((long long)todo) - 1;
+      const uint32_t lb = __shfl(b, lead, 64);
+      const uint64_t m = __ballot(ok && b == lb);
+      if (lane == lead) atomicAdd(&cnt[lb], (uint32_t)__popcll(m));
+      todo &= ~m;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) K += __shfl_xor(K, o, 64);
@@ -613,9 +626,24 @@ __global__ __launch_bounds__(1024) void k_tile_schedule(int n_tiles, const uint3
     counters[1] = K > (unsigned long long)key_cap ? 1u : 0u;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-    const uint32_t L = tile_total[t];
-    order[atomicAdd(&off[L ? 32 - __clz(L) : 0], 1u)] = (uint32_t)t;
+  for (int t0 = threadIdx.x - lane; t0 < n_tiles; t0 += blockDim.x) {
+    const int t = t0 + lane;
+    const bool ok = t < n_tiles;
+    const uint32_t L = ok ? tile_total[t] : 0u;
+    const uint32_t b = L ? 32 - __clz(L) : 0;
+    uint64_t todo = __ballot(ok);
+    uint32_t pos = 0;
+    while (todo) {
+      const int lead = __ffsll((long long)todo) - 1;
+      const uint32_t lb = __shfl(b, lead, 64);
+      const uint64_t m = __ballot(ok && b == lb);
+      uint32_t base = 0;
+      if (lane == lead) base = atomicAdd(&off[lb], (uint32_t)__popcll(m));
+      base = __shfl(base, lead, 64);
+      if (ok && b == lb) pos = base + (uint32_t)__popcll(m & lanemask_lt());
+      todo &= ~m;
+    }
+    if (ok) order[pos] = (uint32_t)t;
   }
 }
 
