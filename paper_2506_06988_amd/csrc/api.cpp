@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -40,7 +41,7 @@ struct Plan {
   size_t cams, counters, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
       tile_start, tile_order, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
-      mesh_rgb, gacc, tune, scan_scratch, total;
+      mesh_rgb, gacc, tune, scan_scratch, scan_scratch2, total;
   int64_t scan_words;
   std::vector<CamDev> camdev;
 };
@@ -179,6 +180,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   int64_t longest =
       std::max<int64_t>({M + 1, 256 * p.rs_blocks, p.n_tiles, p.MF + 1, p.chunk_rows + 1, 1});
   p.scan_scratch = L.take(scan_scratch_bytes(longest) + 4096);
+  p.scan_scratch2 = L.take(scan_scratch_bytes(longest) + 4096);  // the mesh stream's scans
   p.scan_words = (int64_t)scan_state_words(longest);
   p.total = L.off;
   return HR_OK;
@@ -230,6 +232,7 @@ Work make_work(const Plan& p, void* ws) {
   static_assert(sizeof(EllP) <= 36, "ellipse constants must fit in a gradient slot");
   w.ell_s = (EllP*)(b + p.gacc);
   w.scan_scratch = b + p.scan_scratch;
+  w.scan_scratch2 = b + p.scan_scratch2;
   w.scan_words = p.scan_words;
   return w;
 }
@@ -277,25 +280,63 @@ void upload_cams(const Plan& p, const Work& w, bool clear_counters, hipStream_t 
     for (int k = 0; k < u.count; ++k) u.c[k] = p.camdev[c0 + k];
     const bool clr = clear_counters && c0 == 0;
     launch_upload_cams(u, w.cams, clr ? w.counters : nullptr, (uint32_t*)w.scan_scratch,
-                       w.scan_words, st);
+                       (uint32_t*)w.scan_scratch2, w.scan_words, st);
   }
 }
 
 int pick_batch(const hr_settings* s) { return s->batch == 0 ? 64 : s->batch; }
 int pick_batch_bwd(const hr_settings* s) { return s->batch_bwd == 0 ? pick_batch(s) : s->batch_bwd; }
 
+// The mesh pass and the Gaussian passes share nothing until the blend (the
+// mesh-depth culling reads the z-buffer before binning): the mesh runs on a
+// second stream of the library, forked from and joined back into the
+// caller's stream with events (a graph capture follows the fork and join).
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+hr_status side_stream(SideStream*& out) {
+  static std::mutex mu;
+  static SideStream per_dev[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    return fail(HR_ERR_HIP, "no current device");
+  std::lock_guard<std::mutex> lock(mu);
+  SideStream& ss = per_dev[dev];
+  if (!ss.st) {
+    if (hipStreamCreateWithFlags(&ss.st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess)
+      return fail(HR_ERR_HIP, "side stream creation failed");
+  }
+  out = &ss;
+  return HR_OK;
+}
+
 // enqueue the whole forward
-void enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
-                     const hr_mesh* m, const hr_settings* s, hr_outputs* out, hipStream_t st) {
+hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
+                          const hr_mesh* m, const hr_settings* s, hr_outputs* out,
+                          hipStream_t st) {
+  SideStream* ss = nullptr;
+  hr_status rc = side_stream(ss);
+  if (rc != HR_OK) return rc;
   upload_cams(p, w, true, st);
-  launch_mesh(S, *m, w, out, st);
+  Work wm = w;  // the mesh's scans use their own scratch
+  wm.scan_scratch = w.scan_scratch2;
+  if (hipEventRecord(ss->fork, st) != hipSuccess || hipStreamWaitEvent(ss->st, ss->fork, 0) != hipSuccess)
+    return fail(HR_ERR_HIP, "stream fork failed");
+  launch_mesh(S, *m, wm, out, ss->st);
+  if (hipEventRecord(ss->join, ss->st) != hipSuccess) return fail(HR_ERR_HIP, "stream join failed");
   const bool cull = (s->flags & HR_FLAG_CULL_BEHIND_MESH) && S.n_faces > 0;
-  if (cull) launch_tile_dmax(S, w, st);
   launch_project(S, w.cams, *g, w, out->radii, st);
   launch_depth_sort(S, w, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, st);
+  if (hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return fail(HR_ERR_HIP, "stream join failed");
+  if (cull) launch_tile_dmax(S, w, st);
   launch_binning(S, w, (int)p.n_cams, cull, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, out, st);
   launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
   if (out->stats) launch_counters_to_stats(w.counters, w.tile_np, (int)S.n_tiles, out->stats, st);
+  return HR_OK;
 }
 
 void enqueue_backward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
@@ -362,7 +403,7 @@ hr_status hr_render_hybrid(const hr_gaussians* g, const hr_mesh* mesh, const hr_
   Work w = make_work(p, workspace);
   SetDev S = make_setdev(p, g, mesh, s);
   hipGetLastError();
-  enqueue_forward(p, w, S, g, mesh, s, out, st);
+  if ((rc = enqueue_forward(p, w, S, g, mesh, s, out, st)) != HR_OK) return rc;
   if ((rc = hip_check("forward launch")) != HR_OK) return rc;
   if (!(s->flags & HR_FLAG_NO_SYNC)) {
     uint32_t c[4];
@@ -673,7 +714,13 @@ hr_status hr_batch_create(const hr_gaussians* g, const hr_mesh* mesh, const hr_c
     delete b;
     return fail(HR_ERR_HIP, "hipStreamBeginCapture failed");
   }
-  enqueue_forward(p, w, S, g, mesh, s, out, st);
+  if (enqueue_forward(p, w, S, g, mesh, s, out, st) != HR_OK) {
+    hipGraph_t broken = nullptr;
+    hipStreamEndCapture(st, &broken);
+    if (broken) hipGraphDestroy(broken);
+    delete b;
+    return HR_ERR_HIP;
+  }
   launch_loss(out->image, out->final_T, out->mesh_rgb, out->tri_id, target, p.P, lambda_t, k,
               (s->flags & HR_FLAG_DETACH_MASK) != 0, loss_out, grad_image, grad_final_T,
               grad_mesh_rgb, loss_scratch, st);

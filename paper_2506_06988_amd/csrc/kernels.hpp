@@ -61,6 +61,7 @@ struct Work {
   float* gacc;
   // scratch of the scans (its first scan_words words are the scan state)
   void* scan_scratch;
+  void* scan_scratch2;  // the same for the mesh pass on the second stream
   int64_t scan_words;
 };
 
@@ -103,7 +104,7 @@ struct CamUpload {
 };
 static_assert(sizeof(CamUpload) + 8 <= 4096, "camera upload must fit in kernel arguments");
 void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
-                        int64_t n2, hipStream_t st);
+                        uint32_t* clear3, int64_t n2, hipStream_t st);
 void launch_mip_filter3d(const float* means, int n, const CamDev* cams, int n_cams, float near,
                          double scale, float* f3, hipStream_t st);
 void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,

@@ -6,15 +6,18 @@ namespace hr {
 
 namespace {
 
-// also clears the 64 forward counters and `n2` words of scan state when
-// `clear` is given
+// also clears the 64 forward counters and `n2` words of each of the two scan
+// states when `clear` is given
 __global__ void k_upload_cams(CamUpload u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
-                              int64_t n2) {
+                              uint32_t* clear3, int64_t n2) {
   const int k = threadIdx.x;
   if (k < u.count) dst[u.first + k] = u.c[k];
   if (!clear) return;
   if (k < 64) clear[k] = 0u;
-  for (int64_t i = k; i < n2; i += blockDim.x) clear2[i] = 0u;
+  for (int64_t i = k; i < n2; i += blockDim.x) {
+    clear2[i] = 0u;
+    clear3[i] = 0u;
+  }
 }
 
 // one group of 1024 threads: the counters, and the examined / blended pairs
@@ -75,8 +78,8 @@ __global__ void k_count_mismatch(const float* __restrict__ a, const float* __res
 }  // namespace
 
 void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
-                        int64_t n2, hipStream_t st) {
-  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(256), 0, st, u, dst, clear, clear2, n2);
+                        uint32_t* clear3, int64_t n2, hipStream_t st) {
+  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(256), 0, st, u, dst, clear, clear2, clear3, n2);
 }
 
 void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,
