@@ -339,15 +339,26 @@ hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const h
   return HR_OK;
 }
 
-void enqueue_backward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
-                      const hr_mesh* m, const hr_settings* s, const float* grad_image,
-                      const float* grad_T, const float* grad_mesh, hr_grads* grads,
-                      hipStream_t st) {
+// The texture backward reads only forward outputs and writes only the texture
+// gradient: it runs on the second stream beside the blend and projection
+// backward.
+hr_status enqueue_backward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
+                           const hr_mesh* m, const hr_settings* s, const float* grad_image,
+                           const float* grad_T, const float* grad_mesh, hr_grads* grads,
+                           hipStream_t st) {
   (void)p;
+  SideStream* ss = nullptr;
+  hr_status rc = side_stream(ss);
+  if (rc != HR_OK) return rc;
+  if (hipEventRecord(ss->fork, st) != hipSuccess || hipStreamWaitEvent(ss->st, ss->fork, 0) != hipSuccess)
+    return fail(HR_ERR_HIP, "stream fork failed");
+  launch_texture_backward(S, *m, w, grad_image, grad_mesh, grads->tex, ss->st);
+  if (hipEventRecord(ss->join, ss->st) != hipSuccess) return fail(HR_ERR_HIP, "stream join failed");
   launch_zero_gacc(w.gacc, w.counters, st);
   launch_blend_backward(S, w, grad_image, grad_T, pick_batch_bwd(s), s->variant, st);
   launch_project_backward(S, w.cams, *g, w, grads, st);
-  launch_texture_backward(S, *m, w, grad_image, grad_mesh, grads->tex, st);
+  if (hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return fail(HR_ERR_HIP, "stream join failed");
+  return HR_OK;
 }
 
 hr_status check_outputs(const hr_outputs* out) {
@@ -435,7 +446,9 @@ hr_status hr_render_hybrid_backward(const hr_gaussians* g, const hr_mesh* mesh,
   Work w = make_work(p, workspace);
   SetDev S = make_setdev(p, g, mesh, s);
   hipGetLastError();
-  enqueue_backward(p, w, S, g, mesh, s, grad_image, grad_final_T, grad_mesh_rgb, grads, st);
+  if ((rc = enqueue_backward(p, w, S, g, mesh, s, grad_image, grad_final_T, grad_mesh_rgb, grads,
+                             st)) != HR_OK)
+    return rc;
   return hip_check("backward launch");
 }
 
@@ -733,8 +746,14 @@ hr_status hr_batch_create(const hr_gaussians* g, const hr_mesh* mesh, const hr_c
   if (grads->sh) launch_fill_u32((uint32_t*)grads->sh, 0u, 3 * K * p.n, st);
   if (grads->tex && mesh->n_faces > 0)
     launch_fill_u32((uint32_t*)grads->tex, 0u, (int64_t)3 * mesh->n_tex * mesh->tex_h * mesh->tex_w, st);
-  enqueue_backward(p, w, S, g, mesh, s, grad_image, grad_final_T, grad_mesh_rgb, grads, st);
+  const hr_status brc =
+      enqueue_backward(p, w, S, g, mesh, s, grad_image, grad_final_T, grad_mesh_rgb, grads, st);
   hipError_t e = hipStreamEndCapture(st, &b->graph);
+  if (brc != HR_OK) {
+    if (b->graph) hipGraphDestroy(b->graph);
+    delete b;
+    return brc;
+  }
   if (e != hipSuccess) {
     delete b;
     return fail(HR_ERR_HIP, std::string("capture failed: ") + hipGetErrorString(e));
