@@ -28,11 +28,19 @@
  *     hr_camera array, which is host memory read during the call.
  *   - The library never allocates or frees device memory except inside
  *     hr_batch_create/hr_batch_destroy (documented there), and keeps no state
- *     between calls. All intermediate state lives in the caller's workspace,
- *     sized by hr_query_workspace. The forward's workspace contents are the
- *     saved context of the matching backward call.
- *   - All work is enqueued on the given stream (hipStream_t passed as void*;
- *     NULL = the null stream); calls return before the GPU finishes.
+ *     between calls other than one internal stream and two events per device,
+ *     created on first use and kept until the process ends. All intermediate
+ *     state lives in the caller's workspace, sized by hr_query_workspace. The
+ *     forward's workspace contents are the saved context of the matching
+ *     backward call.
+ *   - All work is ordered on the given stream (hipStream_t passed as void*;
+ *     NULL = the null stream); calls return before the GPU finishes. The
+ *     forward and backward fork independent parts onto the internal stream
+ *     (after an event recorded on the given stream) and join them back (the
+ *     given stream waits on an event) before their last kernels, so work
+ *     enqueued later on the given stream sees every result; a graph capture
+ *     of the given stream includes both branches. Calls that share a device
+ *     share the internal stream, which serialises their forked parts.
  *   - Several cameras are rendered by one call. Their pixels are packed one
  *     camera after another: camera c starts at pixel offset
  *     P_c = sum_{c'<c} W_c' H_c'; images are planar [3, H_c, W_c] at 3 P_c.
