@@ -291,9 +291,20 @@ int pick_batch_bwd(const hr_settings* s) { return s->batch_bwd == 0 ? pick_batch
 // mesh-depth culling reads the z-buffer before binning): the mesh runs on a
 // second stream of the library, forked from and joined back into the
 // caller's stream with events (a graph capture follows the fork and join).
+// The counters are shared: the mesh's scans write only entries 4 and 5.
 struct SideStream {
   hipStream_t st = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  std::mutex mu;  // an event's record and the wait on it stay together
+
+  bool fork_from(hipStream_t main) {
+    std::lock_guard<std::mutex> lock(mu);
+    return hipEventRecord(fork, main) == hipSuccess && hipStreamWaitEvent(st, fork, 0) == hipSuccess;
+  }
+  bool join_into(hipStream_t main) {
+    std::lock_guard<std::mutex> lock(mu);
+    return hipEventRecord(join, st) == hipSuccess && hipStreamWaitEvent(main, join, 0) == hipSuccess;
+  }
 };
 
 hr_status side_stream(SideStream*& out) {
@@ -324,16 +335,18 @@ hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const h
   upload_cams(p, w, true, st);
   Work wm = w;  // the mesh's scans use their own scratch
   wm.scan_scratch = w.scan_scratch2;
-  if (hipEventRecord(ss->fork, st) != hipSuccess || hipStreamWaitEvent(ss->st, ss->fork, 0) != hipSuccess)
-    return fail(HR_ERR_HIP, "stream fork failed");
+  if (!ss->fork_from(st)) return fail(HR_ERR_HIP, "stream fork failed");
   launch_mesh(S, *m, wm, out, ss->st);
-  if (hipEventRecord(ss->join, ss->st) != hipSuccess) return fail(HR_ERR_HIP, "stream join failed");
   const bool cull = (s->flags & HR_FLAG_CULL_BEHIND_MESH) && S.n_faces > 0;
   launch_project(S, w.cams, *g, w, out->radii, st);
   launch_depth_sort(S, w, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, st);
-  if (hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return fail(HR_ERR_HIP, "stream join failed");
-  if (cull) launch_tile_dmax(S, w, st);
+  // the mesh-depth culling needs the z-buffer before binning, the blend after
+  if (cull) {
+    if (!ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
+    launch_tile_dmax(S, w, st);
+  }
   launch_binning(S, w, (int)p.n_cams, cull, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, out, st);
+  if (!cull && !ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
   launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
   if (out->stats) launch_counters_to_stats(w.counters, w.tile_np, (int)S.n_tiles, out->stats, st);
   return HR_OK;
@@ -350,14 +363,12 @@ hr_status enqueue_backward(const Plan& p, const Work& w, const SetDev& S, const 
   SideStream* ss = nullptr;
   hr_status rc = side_stream(ss);
   if (rc != HR_OK) return rc;
-  if (hipEventRecord(ss->fork, st) != hipSuccess || hipStreamWaitEvent(ss->st, ss->fork, 0) != hipSuccess)
-    return fail(HR_ERR_HIP, "stream fork failed");
+  if (!ss->fork_from(st)) return fail(HR_ERR_HIP, "stream fork failed");
   launch_texture_backward(S, *m, w, grad_image, grad_mesh, grads->tex, ss->st);
-  if (hipEventRecord(ss->join, ss->st) != hipSuccess) return fail(HR_ERR_HIP, "stream join failed");
   launch_zero_gacc(w.gacc, w.counters, st);
   launch_blend_backward(S, w, grad_image, grad_T, pick_batch_bwd(s), s->variant, st);
   launch_project_backward(S, w.cams, *g, w, grads, st);
-  if (hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return fail(HR_ERR_HIP, "stream join failed");
+  if (!ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
   return HR_OK;
 }
 

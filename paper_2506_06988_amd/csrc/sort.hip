@@ -57,13 +57,17 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 }
 
 // Compaction of the visible items into the first radix-sort buffers; the
-// first n_cams + 1 threads also write each camera's first rank and the total.
+// first n_cams + 1 threads also write each camera's first rank and the total,
+// and thread n_cams the binning items of every camera: (used chunk row, tile
+// row) pairs, item_off[c] the first of camera c, item_off[n_cams] the total.
 __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ vis,
                                                  const uint32_t* __restrict__ vis_scan,
                                                  const uint32_t* __restrict__ dkey, int n,
-                                                 int n_cams, uint32_t* __restrict__ skey,
+                                                 int n_cams, const CamDev* __restrict__ cams,
+                                                 uint32_t* __restrict__ skey,
                                                  uint32_t* __restrict__ sval,
                                                  uint32_t* __restrict__ vis_off,
+                                                 uint32_t* __restrict__ item_off,
                                                  uint32_t* __restrict__ counters) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t M = (int64_t)n * n_cams;
@@ -73,6 +77,14 @@ __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ vi
     const uint32_t v = vis_scan[M - 1] + vis[M - 1];
     vis_off[i] = v;
     counters[0] = v;
+    uint32_t acc = 0;
+    for (int c = 0; c < n_cams; ++c) {
+      item_off[c] = acc;
+      const uint32_t end = c + 1 < n_cams ? vis_scan[(int64_t)(c + 1) * n] : v;
+      const uint32_t rows = (end - vis_scan[(int64_t)c * n] + CHUNK - 1) / CHUNK;
+      acc += rows * (uint32_t)cams[c].TY;
+    }
+    item_off[n_cams] = acc;
   }
   if (i >= M || !vis[i]) return;
   const uint32_t p = vis_scan[i];
@@ -231,20 +243,6 @@ __device__ __forceinline__ ChunkInfo chunk_info(const CamDev* cams, int n_cams,
   const int64_t e = (int64_t)vis_off[ci.cam + 1];
   ci.r1 = ci.r0 + CHUNK < e ? ci.r0 + CHUNK : e;
   return ci;
-}
-
-// Binning items of every camera: (used chunk row, tile row) pairs, item_off[c]
-// the first of camera c and item_off[n_cams] the total.
-__global__ void k_bin_items(const CamDev* __restrict__ cams, int n_cams,
-                            const uint32_t* __restrict__ vis_off, uint32_t* __restrict__ item_off) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  uint32_t acc = 0;
-  for (int c = 0; c < n_cams; ++c) {
-    item_off[c] = acc;
-    const uint32_t rows = (vis_off[c + 1] - vis_off[c] + CHUNK - 1) / CHUNK;
-    acc += rows * (uint32_t)cams[c].TY;
-  }
-  item_off[n_cams] = acc;
 }
 
 struct BinItem {
@@ -581,14 +579,43 @@ __global__ __launch_bounds__(256) void k_tile_order(const CamDev* __restrict__ c
 // so the longest lists start first and the short ones fill in at the end.
 // The same workgroup adds up the pairs of every tile (64-bit): the key count
 // and the capacity check.
+// With `tile_start` given (short tile arrays) it also writes the exclusive
+// prefix of the tile totals, 1024 tiles at a time.
 __global__ __launch_bounds__(1024) void k_tile_schedule(int n_tiles, const uint32_t* __restrict__ tile_total,
                                                         uint32_t* __restrict__ order,
                                                         int64_t key_cap,
-                                                        uint32_t* __restrict__ counters) {
+                                                        uint32_t* __restrict__ counters,
+                                                        uint32_t* __restrict__ tile_start) {
   __shared__ uint32_t cnt[33];
   __shared__ uint32_t off[33];
   __shared__ unsigned long long part[16];
+  __shared__ uint32_t wsum[16];
   if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
+  if (tile_start) {
+    const int w = threadIdx.x >> 6, l = __lane_id();
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < n_tiles; c0 += blockDim.x) {
+      const int t = c0 + (int)threadIdx.x;
+      const uint32_t v = t < n_tiles ? tile_total[t] : 0u;
+      uint32_t inc = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o, 64);
+        if (l >= o) inc += u;
+      }
+      if (l == 63) wsum[w] = inc;
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+        const uint32_t q = wsum[k];
+        if (k < w) before += q;
+        total += q;
+      }
+      if (t < n_tiles) tile_start[t] = carry + before + inc - v;
+      carry += total;
+      __syncthreads();
+    }
+  }
   __syncthreads();
   unsigned long long K = 0;
   // the loops are uniform over the group; the lanes of a wave that share a
@@ -674,12 +701,13 @@ void launch_depth_sort(const SetDev& S, const Work& w, bool ell, hipStream_t st)
   if (M == 0) {
     launch_fill_u32(w.counters, 0u, 1, st);
     launch_fill_u32(w.vis_off, 0u, S.n_cams + 1, st);
+    launch_fill_u32(w.item_off, 0u, S.n_cams + 1, st);
     return;
   }
   scan_u32(w.vis, w.vis_scan, M, nullptr, w.scan_scratch, st);
   const unsigned gb = (unsigned)((std::max<int64_t>(M, S.n_cams + 1) + 255) / 256);
   hipLaunchKernelGGL(k_compact, dim3(gb), dim3(256), 0, st, w.vis, w.vis_scan, w.dkey, S.n,
-                     S.n_cams, w.skey[0], w.sval[0], w.vis_off, w.counters);
+                     S.n_cams, w.cams, w.skey[0], w.sval[0], w.vis_off, w.item_off, w.counters);
   int passes = 4;
   if (S.n_cams > 1) passes = S.n_cams > 256 ? 6 : 5;
   const int64_t nb = w.rs_blocks;
@@ -706,15 +734,16 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
   // one workgroup per (chunk, tile row) the cameras could use (the unused ones
   // exit at once): the dispatcher balances the uneven rows, nearest chunks first
   const unsigned grid = (unsigned)std::max<int64_t>(1, w.bin_items_max);
-  hipLaunchKernelGGL(k_bin_items, dim3(1), dim3(64), 0, st, w.cams, n_cams, w.vis_off, w.item_off);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
                        w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat);
   hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
                      S.n_tiles, w.vis_off, w.mat, w.tile_total);
-  scan_u32(w.tile_total, w.tile_start, S.n_tiles, nullptr, w.scan_scratch, st);
+  // the list starts: inside the schedule's workgroup for short tile arrays
+  const bool starts_inline = S.n_tiles <= 16384;
+  if (!starts_inline) scan_u32(w.tile_total, w.tile_start, S.n_tiles, nullptr, w.scan_scratch, st);
   hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(1024), 0, st, S.n_tiles, w.tile_total,
-                     w.tile_order, S.key_cap, w.counters);
+                     w.tile_order, S.key_cap, w.counters, starts_inline ? w.tile_start : nullptr);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
                        w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat, w.tile_start,
