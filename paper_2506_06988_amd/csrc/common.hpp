@@ -11,6 +11,7 @@ namespace hr {
 constexpr int TILE = 16;        // pixels per tile side
 constexpr int TILE_PIX = 256;   // pixels per tile = threads per blend workgroup
 constexpr int CHUNK = 2048;     // depth ranks per binning chunk
+constexpr int RS_KEYS = 1024;   // keys per radix-sort workgroup (its histogram column)
 constexpr int SORT_WIN = 8192;  // ranks one workgroup sorts in LDS at once
 constexpr int SUBPIX = 256;     // fixed-point steps per pixel for mesh vertices
 constexpr int64_t GUARD = (int64_t)1 << 29;  // |vertex| bound in fixed point (2^21 px)

@@ -33,11 +33,12 @@ namespace hr {
 namespace {
 
 constexpr int RS_B = 256;             // radix-sort threads per block
-constexpr int RS_ROUNDS = 8;          // striped rounds per block
-constexpr int RS_KPB = RS_B * RS_ROUNDS;
+constexpr int RS_ROUNDS = RS_KEYS / RS_B;  // striped rounds per block
+constexpr int RS_KPB = RS_KEYS;
+static_assert(RS_ROUNDS * RS_B == RS_KEYS, "whole rounds per radix-sort block");
 constexpr int MAX_TX = MAX_TILE_COLS; // widest tile row of a camera
 constexpr int NARROW_RUN = 4;         // runs up to this wide are written by one lane
-constexpr int GROUP = 16;             // lanes that share one medium run in the scatter
+constexpr int GROUP = 4;              // lanes that share one medium run in the scatter
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = __lane_id();
@@ -310,7 +311,7 @@ __device__ __forceinline__ bool ellipse_cut(const float4 g, const EllP& e, int y
 // The runs in row B.y of this thread's ranks k0 + 256 j, j < RUNS (x1 <= x0:
 // none). All rectangles are loaded first, then the ellipse data of the ranks
 // whose rectangle spans the row, so the loads of a thread overlap.
-constexpr int RUNS = 4;
+constexpr int RUNS = 2;
 __device__ __forceinline__ void item_runs(const BinItem& B, int64_t k0,
                                           const uint2* __restrict__ rect_s,
                                           const GRec* __restrict__ rec_s,
