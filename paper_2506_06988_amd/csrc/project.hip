@@ -112,7 +112,7 @@ void launch_project(const SetDev& S, const CamDev* cams, const hr_gaussians& g, 
                     int32_t* radii, hipStream_t st) {
   const int64_t M = (int64_t)S.n * S.n_cams;
   if (M == 0) return;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, S, cams,
+  hipLaunchKernelGGL(k_project, dim3((unsigned)((M + 127) / 128)), dim3(128), 0, st, S, cams,
                      g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, w.vis,
                      w.dkey, w.rec, w.rect, w.rank_of, radii);
 }
