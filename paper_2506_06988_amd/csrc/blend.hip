@@ -574,38 +574,34 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
       const Staged* e = sh;
       for (int k = 0; k < n; ++k, ++e) {
         if (lane_done()) continue;
-        const float4 ea = e->a, eb = e->b;
+        const float4 ea = e->a, eb = e->b, c = e->c;
         const float dx = ea.x - px;
         const float adx = ea.z * dx;  // the factored form of gauss_p2, A2 dx shared
         const int pos = pos0 + k;
+        // the four pixels without branches: every step is computed and the
+        // selects keep what a pixel that is done, skips or stops must keep
+        // (a zero weight leaves the non-negative colour sums unchanged)
 #pragma unroll
         for (int r = 0; r < WPIX; ++r) {
-          if (done[r]) continue;
-          if (eb.z >= Dm[r]) {  // at or behind the mesh: the pixel ends (Sec. 3.4)
-            done[r] = true;
-            npro[r] = pos;
-            continue;
-          }
+          const bool front = eb.z < Dm[r];  // at or behind the mesh the pixel ends (Sec. 3.4)
           const float dy = ea.y - py[r];
           const float p2 = __builtin_fmaf(dx, __builtin_fmaf(ea.w, dy, adx),
                                           __builtin_fmaf(eb.x * dy, dy, eb.y));
-          if (p2 >= lthr) {
-            const float alpha = fminf(amax, __builtin_amdgcn_exp2f(p2));
-            const float Tn = T[r] * (1.f - alpha);
-            if (Tn < tmin) {
-              done[r] = true;
-              npro[r] = pos;
-            } else {
-              const float4 c = e->c;
-              const float wgt = alpha * T[r];
-              cr[r] = __builtin_fmaf(c.x, wgt, cr[r]);
-              cg[r] = __builtin_fmaf(c.y, wgt, cg[r]);
-              cb[r] = __builtin_fmaf(c.z, wgt, cb[r]);
-              T[r] = Tn;
-              nc[r] = pos;
-              ++nbl[r];
-            }
-          }
+          const float alpha = fminf(amax, __builtin_amdgcn_exp2f(p2));
+          const float Tn = T[r] * (1.f - alpha);
+          const bool hit = !done[r] && front && p2 >= lthr;
+          const bool tstop = hit && Tn < tmin;
+          const bool blend = hit && !(Tn < tmin);
+          const bool ends = (!done[r] && !front) || tstop;
+          const float wgt = blend ? alpha * T[r] : 0.f;
+          cr[r] = __builtin_fmaf(c.x, wgt, cr[r]);
+          cg[r] = __builtin_fmaf(c.y, wgt, cg[r]);
+          cb[r] = __builtin_fmaf(c.z, wgt, cb[r]);
+          T[r] = blend ? Tn : T[r];
+          nc[r] = blend ? pos : nc[r];
+          nbl[r] += blend ? 1 : 0;
+          npro[r] = ends ? pos : npro[r];
+          done[r] = done[r] || ends;
         }
       }
     }
