@@ -40,7 +40,7 @@ struct Plan {
       bin_items;
   size_t cams, counters, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
-      tile_start, tile_order, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
+      tile_start, tile_order, sched_cnt, sched_sum, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, gacc, tune, scan_scratch, scan_scratch2, total;
   int64_t scan_words;
   std::vector<CamDev> camdev;
@@ -162,6 +162,8 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.tile_total = L.take(4 * p.n_tiles);
   p.tile_start = L.take(4 * p.n_tiles);
   p.tile_order = L.take(4 * p.n_tiles);
+  p.sched_cnt = L.take(4 * 33 * ((p.n_tiles + 255) / 256));
+  p.sched_sum = L.take(8 * ((p.n_tiles + 255) / 256));
   p.tile_dmax = L.take(4 * p.n_tiles);
   p.tile_np = L.take(16 * p.n_tiles);
   p.item_off = L.take(4 * (p.n_cams + 1));
@@ -212,6 +214,8 @@ Work make_work(const Plan& p, void* ws) {
   w.tile_total = (uint32_t*)(b + p.tile_total);
   w.tile_start = (uint32_t*)(b + p.tile_start);
   w.tile_order = (uint32_t*)(b + p.tile_order);
+  w.sched_cnt = (uint32_t*)(b + p.sched_cnt);
+  w.sched_sum = (unsigned long long*)(b + p.sched_sum);
   w.tile_dmax = (uint32_t*)(b + p.tile_dmax);
   w.tile_np = (uint64_t*)(b + p.tile_np);
   w.item_off = (uint32_t*)(b + p.item_off);

@@ -40,6 +40,8 @@ struct Work {
   uint32_t* tile_total;  // [n_tiles]
   uint32_t* tile_start;  // [n_tiles]
   uint32_t* tile_order;  // [n_tiles] blend schedule, longest lists first
+  uint32_t* sched_cnt;   // [ceil(n_tiles / 256)][33] schedule bucket counts per block of tiles
+  unsigned long long* sched_sum;  // [ceil(n_tiles / 256)] pairs per block of tiles
   uint32_t* tile_dmax;   // [n_tiles] largest mesh depth bits over the tile (culling)
   uint64_t* tile_np;     // [2 * n_tiles] examined and blended pairs of each tile (forward)
   uint32_t* lists;       // [key_cap] ranks grouped by tile, chunk sub-segments in chunk order

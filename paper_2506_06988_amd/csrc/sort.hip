@@ -39,6 +39,7 @@ static_assert(RS_ROUNDS * RS_B == RS_KEYS, "whole rounds per radix-sort block");
 constexpr int MAX_TX = MAX_TILE_COLS; // widest tile row of a camera
 constexpr int NARROW_RUN = 4;         // runs up to this wide are written by one lane
 constexpr int GROUP = 4;              // lanes that share one medium run in the scatter
+constexpr int SCHED_BUCKETS = 33;     // schedule buckets: list length 0, then by bit length
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = __lane_id();
@@ -502,33 +503,124 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
   }
 }
 
-// per global tile: exclusive prefix over its camera's used chunk rows, and the tile total
+// per global tile: exclusive prefix over its camera's used chunk rows, and the
+// tile total; per block of 256 tiles: the schedule bucket counts, the pairs,
+// and the block-local part of the list starts
 __global__ __launch_bounds__(256) void k_colscan(const CamDev* __restrict__ cams, int n_cams,
                                                  int n_tiles, const uint32_t* __restrict__ vis_off,
                                                  uint32_t* __restrict__ mat,
-                                                 uint32_t* __restrict__ tile_total) {
+                                                 uint32_t* __restrict__ tile_total,
+                                                 uint32_t* __restrict__ tile_start,
+                                                 uint32_t* __restrict__ sched_cnt,
+                                                 unsigned long long* __restrict__ sched_sum) {
+  __shared__ uint32_t hist[SCHED_BUCKETS];
+  __shared__ uint32_t wsum[4];
+  if (threadIdx.x < SCHED_BUCKETS) hist[threadIdx.x] = 0;
+  __syncthreads();
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int c = find_cam_by_tile(cams, n_cams, t);
-  const CamDev& cam = cams[c];
-  const int ntl = cam.TX * cam.TY;
-  const int tl = t - cam.tile_off;
-  const int64_t nvc = (int64_t)vis_off[c + 1] - vis_off[c];
-  const int64_t rows = (nvc + CHUNK - 1) / CHUNK;
   uint32_t acc = 0;
-  uint32_t* col = mat + cam.mat_off + tl;
-  // 8 rows at a time: the loads of a group are in flight together
-  for (int64_t r0 = 0; r0 < rows; r0 += 8) {
-    uint32_t v[8];
+  if (t < n_tiles) {
+    const int c = find_cam_by_tile(cams, n_cams, t);
+    const CamDev& cam = cams[c];
+    const int ntl = cam.TX * cam.TY;
+    const int tl = t - cam.tile_off;
+    const int64_t nvc = (int64_t)vis_off[c + 1] - vis_off[c];
+    const int64_t rows = (nvc + CHUNK - 1) / CHUNK;
+    uint32_t* col = mat + cam.mat_off + tl;
+    // 8 rows at a time: the loads of a group are in flight together
+    for (int64_t r0 = 0; r0 < rows; r0 += 8) {
+      uint32_t v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = r0 + q < rows ? col[(r0 + q) * ntl] : 0u;
+      for (int q = 0; q < 8; ++q) v[q] = r0 + q < rows ? col[(r0 + q) * ntl] : 0u;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      if (r0 + q < rows) col[(r0 + q) * ntl] = acc;
-      acc += v[q];
+      for (int q = 0; q < 8; ++q) {
+        if (r0 + q < rows) col[(r0 + q) * ntl] = acc;
+        acc += v[q];
+      }
+    }
+    tile_total[t] = acc;
+    atomicAdd(&hist[acc ? 32 - __clz(acc) : 0], 1u);
+  }
+  // the block's part of the list starts (the schedule adds the blocks before)
+  uint32_t total;
+  const uint32_t ex = group_excl_scan(acc, wsum, total);
+  if (t < n_tiles) tile_start[t] = ex;
+  __syncthreads();
+  if (threadIdx.x < SCHED_BUCKETS) sched_cnt[blockIdx.x * SCHED_BUCKETS + threadIdx.x] = hist[threadIdx.x];
+  if (threadIdx.x == 0) sched_sum[blockIdx.x] = total;
+}
+
+// Blend schedule: tiles by decreasing list length (buckets of log2 length),
+// so the longest lists start first and the short ones fill in at the end.
+// Each block of 256 tiles places its tiles after every tile of a longer
+// bucket and after its bucket's tiles in earlier blocks; it also finishes
+// the list starts, and block 0 the key count and the capacity check.
+__global__ __launch_bounds__(256) void k_tile_schedule(int n_tiles, int64_t key_cap,
+                                                       const uint32_t* __restrict__ tile_total,
+                                                       const uint32_t* __restrict__ sched_cnt,
+                                                       const unsigned long long* __restrict__ sched_sum,
+                                                       uint32_t* __restrict__ tile_start,
+                                                       uint32_t* __restrict__ order,
+                                                       uint32_t* __restrict__ counters) {
+  __shared__ uint32_t tot[SCHED_BUCKETS];
+  __shared__ uint32_t off[SCHED_BUCKETS];
+  __shared__ unsigned long long red[4];
+  const int b = blockIdx.x;
+  const int nb = gridDim.x;
+  // sums over blocks: before this one (list starts), all (block 0: key count)
+  unsigned long long pre = 0, all = 0;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+    const unsigned long long v = sched_sum[q];
+    if (q < b) pre += v;
+    all += v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    pre += __shfl_xor(pre, o, 64);
+    all += __shfl_xor(all, o, 64);
+  }
+  if (__lane_id() == 0) red[threadIdx.x >> 6] = pre;
+  __syncthreads();
+  pre = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  if (b == 0) {
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = all;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long K = red[0] + red[1] + red[2] + red[3];
+      counters[2] = (uint32_t)K;
+      counters[3] = (uint32_t)(K >> 32);
+      counters[1] = K > (unsigned long long)key_cap ? 1u : 0u;
     }
   }
-  tile_total[t] = acc;
+  // bucket k: tiles of every block, and of the blocks before this one (a
+  // thread per block of tiles, its 33 counts loaded together)
+  if (threadIdx.x < SCHED_BUCKETS) tot[threadIdx.x] = off[threadIdx.x] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+    uint32_t v[SCHED_BUCKETS];
+#pragma unroll
+    for (int k = 0; k < SCHED_BUCKETS; ++k) v[k] = sched_cnt[q * SCHED_BUCKETS + k];
+#pragma unroll
+    for (int k = 0; k < SCHED_BUCKETS; ++k)
+      if (v[k]) {
+        atomicAdd(&tot[k], v[k]);
+        if (q < b) atomicAdd(&off[k], v[k]);
+      }
+  }
+  __syncthreads();
+  if (threadIdx.x < SCHED_BUCKETS) {
+    uint32_t longer = 0;
+    for (int k2 = threadIdx.x + 1; k2 < SCHED_BUCKETS; ++k2) longer += tot[k2];
+    off[threadIdx.x] += longer;
+  }
+  __syncthreads();
+  const int t = b * blockDim.x + threadIdx.x;
+  if (t < n_tiles) {
+    tile_start[t] += (uint32_t)pre;
+    const uint32_t L = tile_total[t];
+    order[atomicAdd(&off[L ? 32 - __clz(L) : 0], 1u)] = (uint32_t)t;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_ranges(int n_tiles, const uint32_t* __restrict__ tile_start,
@@ -573,105 +665,6 @@ __global__ __launch_bounds__(256) void k_tile_order(const CamDev* __restrict__ c
       ++idx;
     }
     __syncthreads();
-  }
-}
-
-// Blend schedule: tiles by decreasing list length (buckets of log2 length),
-// so the longest lists start first and the short ones fill in at the end.
-// The same workgroup adds up the pairs of every tile (64-bit): the key count
-// and the capacity check.
-// With `tile_start` given (short tile arrays) it also writes the exclusive
-// prefix of the tile totals, 1024 tiles at a time.
-__global__ __launch_bounds__(1024) void k_tile_schedule(int n_tiles, const uint32_t* __restrict__ tile_total,
-                                                        uint32_t* __restrict__ order,
-                                                        int64_t key_cap,
-                                                        uint32_t* __restrict__ counters,
-                                                        uint32_t* __restrict__ tile_start) {
-  __shared__ uint32_t cnt[33];
-  __shared__ uint32_t off[33];
-  __shared__ unsigned long long part[16];
-  __shared__ uint32_t wsum[16];
-  if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
-  if (tile_start) {
-    const int w = threadIdx.x >> 6, l = __lane_id();
-    uint32_t carry = 0;
-    for (int c0 = 0; c0 < n_tiles; c0 += blockDim.x) {
-      const int t = c0 + (int)threadIdx.x;
-      const uint32_t v = t < n_tiles ? tile_total[t] : 0u;
-      uint32_t inc = v;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t u = __shfl_up(inc, o, 64);
-        if (l >= o) inc += u;
-      }
-      if (l == 63) wsum[w] = inc;
-      __syncthreads();
-      uint32_t before = 0, total = 0;
-      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
-        const uint32_t q = wsum[k];
-        if (k < w) before += q;
-        total += q;
-      }
-      if (t < n_tiles) tile_start[t] = carry + before + inc - v;
-      carry += total;
-      __syncthreads();
-    }
-  }
-  __syncthreads();
-  unsigned long long K = 0;
-  // the loops are uniform over the group; the lanes of a wave that share a
-  // bucket add to it with one LDS atomic (few distinct buckets per wave)
-  const int lane = __lane_id();
-  for (int t0 = threadIdx.x - lane; t0 < n_tiles; t0 += blockDim.x) {
-    const int t = t0 + lane;
-    const bool ok = t < n_tiles;
-    const uint32_t L = ok ? tile_total[t] : 0u;
-    K += L;
-    const uint32_t b = L ? 32 - __clz(L) : 0;
-    uint64_t todo = __ballot(ok);
-    while (todo) {
-      const int lead = __ffsll((long long)todo) - 1;
-      const uint32_t lb = __shfl(b, lead, 64);
-      const uint64_t m = __ballot(ok && b == lb);
-      if (lane == lead) atomicAdd(&cnt[lb], (uint32_t)__popcll(m));
-      todo &= ~m;
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) K += __shfl_xor(K, o, 64);
-  if (__lane_id() == 0) part[threadIdx.x >> 6] = K;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int b = 32; b >= 0; --b) {
-      off[b] = acc;
-      acc += cnt[b];
-    }
-    K = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) K += part[w];
-    counters[2] = (uint32_t)K;
-    counters[3] = (uint32_t)(K >> 32);
-    counters[1] = K > (unsigned long long)key_cap ? 1u : 0u;
-  }
-  __syncthreads();
-  for (int t0 = threadIdx.x - lane; t0 < n_tiles; t0 += blockDim.x) {
-    const int t = t0 + lane;
-    const bool ok = t < n_tiles;
-    const uint32_t L = ok ? tile_total[t] : 0u;
-    const uint32_t b = L ? 32 - __clz(L) : 0;
-    uint64_t todo = __ballot(ok);
-    uint32_t pos = 0;
-    while (todo) {
-      const int lead = __ffsll((long long)todo) - 1;
-      const uint32_t lb = __shfl(b, lead, 64);
-      const uint64_t m = __ballot(ok && b == lb);
-      uint32_t base = 0;
-      if (lane == lead) base = atomicAdd(&off[lb], (uint32_t)__popcll(m));
-      base = __shfl(base, lead, 64);
-      if (ok && b == lb) pos = base + (uint32_t)__popcll(m & lanemask_lt());
-      todo &= ~m;
-    }
-    if (ok) order[pos] = (uint32_t)t;
   }
 }
 
@@ -738,13 +731,12 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
                        w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat);
-  hipLaunchKernelGGL(k_colscan, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, w.cams, n_cams,
-                     S.n_tiles, w.vis_off, w.mat, w.tile_total);
-  // the list starts: inside the schedule's workgroup for short tile arrays
-  const bool starts_inline = S.n_tiles <= 16384;
-  if (!starts_inline) scan_u32(w.tile_total, w.tile_start, S.n_tiles, nullptr, w.scan_scratch, st);
-  hipLaunchKernelGGL(k_tile_schedule, dim3(1), dim3(1024), 0, st, S.n_tiles, w.tile_total,
-                     w.tile_order, S.key_cap, w.counters, starts_inline ? w.tile_start : nullptr);
+  const unsigned tb = (unsigned)((S.n_tiles + 255) / 256);
+  hipLaunchKernelGGL(k_colscan, dim3(tb), dim3(256), 0, st, w.cams, n_cams, S.n_tiles, w.vis_off,
+                     w.mat, w.tile_total, w.tile_start, w.sched_cnt, w.sched_sum);
+  hipLaunchKernelGGL(k_tile_schedule, dim3(tb), dim3(256), 0, st, S.n_tiles, S.key_cap,
+                     w.tile_total, w.sched_cnt, w.sched_sum, w.tile_start, w.tile_order,
+                     w.counters);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
                        w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat, w.tile_start,
