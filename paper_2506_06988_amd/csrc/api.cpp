@@ -339,10 +339,12 @@ hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const h
   upload_cams(p, w, true, st);
   Work wm = w;  // the mesh's scans use their own scratch
   wm.scan_scratch = w.scan_scratch2;
+  const bool cull = (s->flags & HR_FLAG_CULL_BEHIND_MESH) && S.n_faces > 0;
+  // the projection first: it is memory-bound and the mesh would slow it; the
+  // latency-bound sort and binning leave room for the mesh
+  launch_project(S, w.cams, *g, w, out->radii, st);
   if (!ss->fork_from(st)) return fail(HR_ERR_HIP, "stream fork failed");
   launch_mesh(S, *m, wm, out, ss->st);
-  const bool cull = (s->flags & HR_FLAG_CULL_BEHIND_MESH) && S.n_faces > 0;
-  launch_project(S, w.cams, *g, w, out->radii, st);
   launch_depth_sort(S, w, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, st);
   // the mesh-depth culling needs the z-buffer before binning, the blend after
   if (cull) {
