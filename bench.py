@@ -41,11 +41,11 @@ BLEND_OPS_BLENDED = 7
 # from the FETCH_SIZE and WRITE_SIZE counter passes of `bench.py --pmc-probe`
 # (scaled by a 256 MiB copy: FETCH x2, WRITE x1), tile-ellipse binning; valid
 # for the blend kernels they were taken with
-BLEND_TRAFFIC = {(32, 0): 165.8e6, (32, 1): 166.2e6, (32, 2): 161.5e6, (32, 3): 161.7e6,
-                 (64, 0): 166.1e6, (64, 1): 166.7e6, (64, 2): 161.6e6, (64, 3): 162.2e6,
-                 (64, 4): 166.4e6, (128, 0): 166.5e6, (128, 1): 167.5e6, (128, 2): 162.0e6,
-                 (128, 3): 163.0e6, (128, 4): 166.8e6, (256, 0): 167.3e6, (256, 1): 168.8e6,
-                 (256, 2): 162.6e6, (256, 3): 164.0e6}
+BLEND_TRAFFIC = {(32, 0): 165.9e6, (32, 1): 166.2e6, (32, 2): 161.0e6, (32, 3): 161.4e6,
+                 (64, 0): 166.1e6, (64, 1): 166.8e6, (64, 2): 161.3e6, (64, 3): 162.0e6,
+                 (64, 4): 166.4e6, (128, 0): 166.5e6, (128, 1): 167.5e6, (128, 2): 161.7e6,
+                 (128, 3): 162.7e6, (128, 4): 166.9e6, (256, 0): 167.3e6, (256, 1): 168.8e6,
+                 (256, 2): 162.2e6, (256, 3): 163.8e6}
 # every configuration the forward autotuner may choose
 BLEND_CONFIGS = [(b, v) for v in range(4) for b in (32, 64, 128, 256)] + [(64, 4), (128, 4)]
 # pairs outside the alpha >= alpha_min ellipse are skipped by every pixel:
@@ -316,16 +316,16 @@ def main():
         t_frames = 0.0
         t_spent = 0.0
         for cam in views:
-            # a 16x16 and a 384x384 window at the centre give the per-call
+            # a 16x16 and a 480x480 window at the centre give the per-call
             # and the per-pixel cost of this view, extrapolated to 1920x1080
             cx, cy = cam.width // 2, cam.height // 2
             t0 = time.perf_counter()
             oracle.render(sc.gaussians, sc.mesh, cam, window=(cx - 8, cy - 8, cx + 8, cy + 8))
             t_small = time.perf_counter() - t0
             t0 = time.perf_counter()
-            oracle.render(sc.gaussians, sc.mesh, cam, window=(cx - 192, cy - 192, cx + 192, cy + 192))
+            oracle.render(sc.gaussians, sc.mesh, cam, window=(cx - 240, cy - 240, cx + 240, cy + 240))
             t_big = time.perf_counter() - t0
-            per_px = max(t_big - t_small, 1e-9) / (384 * 384 - 256)
+            per_px = max(t_big - t_small, 1e-9) / (480 * 480 - 256)
             t_frames += t_small + per_px * (cam.width * cam.height - 256)
             t_spent += t_small + t_big
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -333,7 +333,7 @@ def main():
             "value": round(len(views) / t_frames, 5), "unit": "frames/s", "cores": cores,
             "kind": "oracle",
             "sample": (f"oracle (FP64, OpenMP) on all {len(views)} headline views: per view a "
-                       f"16x16 and a 384x384 window at the centre ({t_spent:.1f}s in all) give the "
+                       f"16x16 and a 480x480 window at the centre ({t_spent:.1f}s in all) give the "
                        f"per-call and per-pixel cost, extrapolated to the 1920x1080 frame")}
         log(f"cpu oracle: {t_spent:.1f}s of samples -> {len(views) / t_frames:.4f} frames/s extrapolated")
 
