@@ -12,7 +12,10 @@ namespace {
 
 // One thread per Gaussian; loops over cameras, recomputes the projection in
 // FP64 and accumulates every parameter gradient before one write per array.
-__global__ __launch_bounds__(128) void k_project_bwd(
+// Capping the architectural VGPRs at 128 (the rest spills to AGPRs and a
+// little scratch) gives two waves per SIMD instead of one: faster on the
+// 16-camera step.
+__global__ __launch_bounds__(128) __attribute__((amdgpu_num_vgpr(128))) void k_project_bwd(
     SetDev S, const CamDev* __restrict__ cams, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ logits, const float* __restrict__ sh,
