@@ -137,7 +137,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   if (items > 0xffffffffll) return fail(HR_ERR_UNSUPPORTED, "too many binning items");
   p.bin_items = items;
   p.mat_entries = mat;
-  p.rs_blocks = (p.M + RS_KEYS - 1) / RS_KEYS;
+  p.rs_blocks = (p.M + rs_keys_for(p.M) - 1) / rs_keys_for(p.M);
 
   Layout L;
   const int64_t M = p.M;

@@ -11,7 +11,9 @@ namespace hr {
 constexpr int TILE = 16;        // pixels per tile side
 constexpr int TILE_PIX = 256;   // pixels per tile = threads per blend workgroup
 constexpr int CHUNK = 2048;     // depth ranks per binning chunk
-constexpr int RS_KEYS = 1024;   // keys per radix-sort workgroup (its histogram column)
+// keys per radix-sort workgroup (its histogram column): short sorts gain from
+// more workgroups, long ones (several cameras) from fewer histogram columns
+inline int rs_keys_for(int64_t n_items) { return n_items <= (int64_t)2 << 20 ? 1024 : 4096; }
 constexpr int SORT_WIN = 8192;  // ranks one workgroup sorts in LDS at once
 constexpr int SUBPIX = 256;     // fixed-point steps per pixel for mesh vertices
 constexpr int64_t GUARD = (int64_t)1 << 29;  // |vertex| bound in fixed point (2^21 px)

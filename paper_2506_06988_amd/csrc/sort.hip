@@ -33,9 +33,6 @@ namespace hr {
 namespace {
 
 constexpr int RS_B = 256;             // radix-sort threads per block
-constexpr int RS_ROUNDS = RS_KEYS / RS_B;  // striped rounds per block
-constexpr int RS_KPB = RS_KEYS;
-static_assert(RS_ROUNDS * RS_B == RS_KEYS, "whole rounds per radix-sort block");
 constexpr int MAX_TX = MAX_TILE_COLS; // widest tile row of a camera
 constexpr int NARROW_RUN = 4;         // runs up to this wide are written by one lane
 constexpr int GROUP = 4;              // lanes that share one medium run in the scatter
@@ -100,6 +97,8 @@ __device__ __forceinline__ uint32_t rs_digit(uint32_t key, uint32_t val, int pas
   return (cam >> (8 * (pass - 4))) & 255u;
 }
 
+// RS_ROUNDS striped rounds of RS_B keys per workgroup (4 or 16, rs_keys_for)
+template <int RS_ROUNDS>
 __global__ __launch_bounds__(RS_B) void k_rs_hist(const uint32_t* __restrict__ key,
                                                   const uint32_t* __restrict__ val,
                                                   const uint32_t* __restrict__ counters, int pass,
@@ -108,7 +107,7 @@ __global__ __launch_bounds__(RS_B) void k_rs_hist(const uint32_t* __restrict__ k
   h[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t nv = counters[0];
-  const int64_t base = (int64_t)blockIdx.x * RS_KPB;
+  const int64_t base = (int64_t)blockIdx.x * (RS_ROUNDS * RS_B);
   for (int k = 0; k < RS_ROUNDS; ++k) {
     const int64_t i = base + k * RS_B + threadIdx.x;
     if (i < nv) atomicAdd(&h[rs_digit(key[i], val[i], pass, n)], 1u);
@@ -118,6 +117,7 @@ __global__ __launch_bounds__(RS_B) void k_rs_hist(const uint32_t* __restrict__ k
 }
 
 // stable scatter: keys keep their input order within a digit
+template <int RS_ROUNDS>
 __global__ __launch_bounds__(RS_B) void k_rs_scatter(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ val,
                                                      uint32_t* __restrict__ key_out,
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(RS_B) void k_rs_scatter(const uint32_t* __restrict_
   for (int k = 0; k < RS_B / 64; ++k) wcnt[k][tid] = 0;
   __syncthreads();
   const uint32_t nv = counters[0];
-  const int64_t base = (int64_t)blockIdx.x * RS_KPB;
+  const int64_t base = (int64_t)blockIdx.x * (RS_ROUNDS * RS_B);
   if (base >= nv) return;
   // every round's keys are loaded up front, so the loads overlap
   uint32_t kr[RS_ROUNDS], vr[RS_ROUNDS];
@@ -705,12 +705,15 @@ void launch_depth_sort(const SetDev& S, const Work& w, bool ell, hipStream_t st)
   int passes = 4;
   if (S.n_cams > 1) passes = S.n_cams > 256 ? 6 : 5;
   const int64_t nb = w.rs_blocks;
+  const bool long_sort = rs_keys_for(M) > 1024;
+  auto hist = long_sort ? k_rs_hist<16> : k_rs_hist<4>;
+  auto scat = long_sort ? k_rs_scatter<16> : k_rs_scatter<4>;
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_B), 0, st, w.skey[cur], w.sval[cur],
+    hipLaunchKernelGGL(hist, dim3((unsigned)nb), dim3(RS_B), 0, st, w.skey[cur], w.sval[cur],
                        w.counters, p, S.n, nb, w.rs_hist);
     scan_u32(w.rs_hist, w.rs_hist, 256 * nb, nullptr, w.scan_scratch, st);
-    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(RS_B), 0, st, w.skey[cur],
+    hipLaunchKernelGGL(scat, dim3((unsigned)nb), dim3(RS_B), 0, st, w.skey[cur],
                        w.sval[cur], w.skey[cur ^ 1], w.sval[cur ^ 1], w.counters, p, S.n, nb,
                        w.rs_hist);
     cur ^= 1;
