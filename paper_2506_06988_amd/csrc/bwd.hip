@@ -11,7 +11,9 @@ namespace hr {
 namespace {
 
 // One thread per Gaussian; loops over cameras, recomputes the projection in
-// FP64 and accumulates every parameter gradient before one write per array.
+// FP64 (so that every decision is the forward's), applies the chain rule in
+// FP32 and accumulates every parameter gradient in FP64 before one write per
+// array.
 // Capping the architectural VGPRs at 128 (the rest spills to AGPRs and a
 // little scratch) gives two waves per SIMD instead of one: faster on the
 // 16-camera step.
@@ -55,135 +57,154 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_num_vgpr(128))) void k_p
     Proj P;
     project_gaussian(S, cam, means, log_scales, quats, logits, sh, g, P, true);
     if (!P.vis) continue;
+    // the chain rule in FP32 (the projection and its decisions stay FP64;
+    // FP32 values here halve the registers of the FP64 chain)
+    const float op = (float)P.op, c3 = (float)P.c3, c2 = (float)P.c2, f3 = (float)P.f3;
+    const float G5 = (float)G9[5];
     // opacity: the record holds op c3 c2 (Mip-Splatting factors, 1 otherwise)
-    glg += G9[5] * P.c3 * P.c2 * P.op * (1.0 - P.op);
+    glg += G5 * c3 * c2 * op * (1.f - op);
     // d c3 / d log s_i = c3 f3 / (s_i^2 + f3)
-    if (P.f3 > 0.0)
+    float sc[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        gls[i] += G9[5] * P.op * P.c2 * P.c3 * P.f3 / (P.s[i] * P.s[i] + P.f3);
+    for (int i = 0; i < 3; ++i) sc[i] = (float)P.s[i];
+    if (f3 > 0.f)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) gls[i] += G5 * op * c2 * c3 * f3 / (sc[i] * sc[i] + f3);
     // c2 = sqrt(D0 / D1), D1 = det Sigma', D0 = det(Sigma' - lp I):
     // d c2 = c2 / 2 (dD0 / D0 - dD1 / D1) on the entries (a, b, c) of Sigma'
-    double gma = 0.0, gmb = 0.0, gmc = 0.0;
+    float gma = 0.f, gmb = 0.f, gmc = 0.f;
     if (S.mip2d && !P.c2lo) {
-      const double a = P.cov[0], b = P.cov[1], c = P.cov[2], lp = (double)S.low_pass;
-      const double D1 = a * c - b * b, D0 = (a - lp) * (c - lp) - b * b;
-      const double gc2 = G9[5] * P.op * P.c3 * 0.5 * P.c2;
+      const float a = (float)P.cov[0], b = (float)P.cov[1], c = (float)P.cov[2], lp = S.low_pass;
+      const float D1 = a * c - b * b, D0 = (a - lp) * (c - lp) - b * b;
+      const float gc2 = G5 * op * c3 * 0.5f * c2;
       gma = gc2 * ((c - lp) / D0 - c / D1);
-      gmb = gc2 * (2.0 * b / D1 - 2.0 * b / D0);
+      gmb = gc2 * (2.f * b / D1 - 2.f * b / D0);
       gmc = gc2 * ((a - lp) / D0 - a / D1);
     }
     // colour: SH coefficients and the view direction
-    double Y[16];
-    sh_eval(P.dir, S.sh_degree, Y);
-    double wdir[16];
-    for (int k = 0; k < K; ++k) wdir[k] = 0.0;
+    const float dir[3] = {(float)P.dir[0], (float)P.dir[1], (float)P.dir[2]};
+    float Y[16];
+    sh_eval(dir, S.sh_degree, Y);
+    float wdir[16];
+    for (int k = 0; k < K; ++k) wdir[k] = 0.f;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       if (P.clamped[ch]) continue;
-      const double gc = G9[6 + ch];
+      const float gc = (float)G9[6 + ch];
       for (int k = 0; k < K; ++k) {
-        gshr_col[(3 * k + ch) * 128] += (float)(Y[k] * gc);
-        wdir[k] += (double)shg[3 * k + ch] * gc;
+        gshr_col[(3 * k + ch) * 128] += Y[k] * gc;
+        wdir[k] += shg[3 * k + ch] * gc;
       }
     }
-    double gdir[3] = {0, 0, 0};
-    sh_grad_acc(P.dir, S.sh_degree, wdir, gdir);
-    const double dd = gdir[0] * P.dir[0] + gdir[1] * P.dir[1] + gdir[2] * P.dir[2];
+    float gdir[3] = {0.f, 0.f, 0.f};
+    sh_grad_acc(dir, S.sh_degree, wdir, gdir);
+    const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+    const float idn = 1.f / (float)P.dnorm;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - P.dir[a] * dd) / P.dnorm;
+    for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dd) * idn;
     // conic -> Sigma': H = -Q G Q with G the symmetric gradient of the conic
-    const double q00 = P.con[0], q01 = P.con[1], q11 = P.con[2];
-    const double G00 = G9[2], G01 = 0.5 * G9[3], G11 = G9[4];
-    const double a00 = q00 * G00 + q01 * G01, a01 = q00 * G01 + q01 * G11;
-    const double a10 = q01 * G00 + q11 * G01, a11 = q01 * G01 + q11 * G11;
+    const float q00 = (float)P.con[0], q01 = (float)P.con[1], q11 = (float)P.con[2];
+    const float G00 = (float)G9[2], G01 = 0.5f * (float)G9[3], G11 = (float)G9[4];
+    const float a00 = q00 * G00 + q01 * G01, a01 = q00 * G01 + q01 * G11;
+    const float a10 = q01 * G00 + q11 * G01, a11 = q01 * G01 + q11 * G11;
     // plus the 2D filter's factor; b sits in both off-diagonal entries
-    const double H00 = -(a00 * q00 + a01 * q01) + gma;
-    const double H01 = -(a00 * q01 + a01 * q11) + 0.5 * gmb;
-    const double H11 = -(a10 * q01 + a11 * q11) + gmc;
+    const float H00 = -(a00 * q00 + a01 * q01) + gma;
+    const float H01 = -(a00 * q01 + a01 * q11) + 0.5f * gmb;
+    const float H11 = -(a10 * q01 + a11 * q11) + gmc;
     // Sigma' = J Sc J^T + lp:  gSc = J^T H J,  gJ = 2 H J Sc
-    const double j00 = P.J[0], j02 = P.J[1], j11 = P.J[2], j12 = P.J[3];
+    const float j00 = (float)P.J[0], j02 = (float)P.J[1], j11 = (float)P.J[2], j12 = (float)P.J[3];
     // HJ (2x3): row a = H[a][0] J[0][:] + H[a][1] J[1][:], J rows (j00,0,j02), (0,j11,j12)
-    const double hj00 = H00 * j00, hj01 = H01 * j11, hj02 = H00 * j02 + H01 * j12;
-    const double hj10 = H01 * j00, hj11 = H11 * j11, hj12 = H01 * j02 + H11 * j12;
+    const float hj00 = H00 * j00, hj01 = H01 * j11, hj02 = H00 * j02 + H01 * j12;
+    const float hj10 = H01 * j00, hj11 = H11 * j11, hj12 = H01 * j02 + H11 * j12;
     // gSc[k][l] = J[0][k] HJ[0][l] + J[1][k] HJ[1][l]
-    double gSc[9];
-    const double J0[3] = {j00, 0.0, j02}, J1[3] = {0.0, j11, j12};
-    const double HJ0[3] = {hj00, hj01, hj02}, HJ1[3] = {hj10, hj11, hj12};
+    float gSc[9];
+    const float J0[3] = {j00, 0.f, j02}, J1[3] = {0.f, j11, j12};
+    const float HJ0[3] = {hj00, hj01, hj02}, HJ1[3] = {hj10, hj11, hj12};
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
       for (int l = 0; l < 3; ++l) gSc[3 * k + l] = J0[k] * HJ0[l] + J1[k] * HJ1[l];
-    const double Sc[9] = {P.Sc[0], P.Sc[1], P.Sc[2], P.Sc[1], P.Sc[3], P.Sc[4],
-                          P.Sc[2], P.Sc[4], P.Sc[5]};
-    auto gJ = [&](const double* HJr, int col) {
-      return 2.0 * (HJr[0] * Sc[col] + HJr[1] * Sc[3 + col] + HJr[2] * Sc[6 + col]);
+    const float Sc[9] = {(float)P.Sc[0], (float)P.Sc[1], (float)P.Sc[2],
+                         (float)P.Sc[1], (float)P.Sc[3], (float)P.Sc[4],
+                         (float)P.Sc[2], (float)P.Sc[4], (float)P.Sc[5]};
+    auto gJ = [&](const float* HJr, int col) {
+      return 2.f * (HJr[0] * Sc[col] + HJr[1] * Sc[3 + col] + HJr[2] * Sc[6 + col]);
     };
-    const double gj00 = gJ(HJ0, 0), gj02 = gJ(HJ0, 2), gj11 = gJ(HJ1, 1), gj12 = gJ(HJ1, 2);
-    const double x = P.pc[0], y = P.pc[1], z = P.pc[2];
-    const double fx = cam.fx, fy = cam.fy, iz = 1.0 / z, iz2 = iz * iz;
-    double gpc[3] = {0, 0, 0};
+    const float gj00 = gJ(HJ0, 0), gj02 = gJ(HJ0, 2), gj11 = gJ(HJ1, 1), gj12 = gJ(HJ1, 2);
+    const float x = (float)P.pc[0], y = (float)P.pc[1];
+    const float fx = (float)cam.fx, fy = (float)cam.fy, iz = (float)(1.0 / P.pc[2]), iz2 = iz * iz;
+    float gpc[3] = {0.f, 0.f, 0.f};
     gpc[2] += gj00 * (-fx * iz2) + gj11 * (-fy * iz2);
     if (P.clx) {
-      gpc[2] += gj02 * (fx * P.xc * iz2);
+      gpc[2] += gj02 * (fx * (float)P.xc * iz2);
     } else {
       gpc[0] += gj02 * (-fx * iz2);
-      gpc[2] += gj02 * (2.0 * fx * x * iz2 * iz);
+      gpc[2] += gj02 * (2.f * fx * x * iz2 * iz);
     }
     if (P.cly) {
-      gpc[2] += gj12 * (fy * P.yc * iz2);
+      gpc[2] += gj12 * (fy * (float)P.yc * iz2);
     } else {
       gpc[1] += gj12 * (-fy * iz2);
-      gpc[2] += gj12 * (2.0 * fy * y * iz2 * iz);
+      gpc[2] += gj12 * (2.f * fy * y * iz2 * iz);
     }
     // mean2D
-    gpc[0] += G9[0] * fx * iz;
-    gpc[1] += G9[1] * fy * iz;
-    gpc[2] += -(G9[0] * fx * x + G9[1] * fy * y) * iz2;
+    const float G0 = (float)G9[0], G1 = (float)G9[1];
+    gpc[0] += G0 * fx * iz;
+    gpc[1] += G1 * fy * iz;
+    gpc[2] += -(G0 * fx * x + G1 * fy * y) * iz2;
+    float cR[9];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-      gmu[a] += cam.R[a] * gpc[0] + cam.R[3 + a] * gpc[1] + cam.R[6 + a] * gpc[2];
+    for (int q = 0; q < 9; ++q) cR[q] = (float)cam.R[q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gmu[a] += cR[a] * gpc[0] + cR[3 + a] * gpc[1] + cR[6 + a] * gpc[2];
     // Sigma_cam = N N^T, N = W Rq S:  gN = 2 gSc N (gSc symmetric)
-    double gN[9];
+    float N[9], Rq[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      N[q] = (float)P.N[q];
+      Rq[q] = (float)P.Rq[q];
+    }
+    float gN[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
-        gN[3 * i + j] = (gSc[3 * i] + gSc[i]) * P.N[j] + (gSc[3 * i + 1] + gSc[3 + i]) * P.N[3 + j] +
-                        (gSc[3 * i + 2] + gSc[6 + i]) * P.N[6 + j];
+        gN[3 * i + j] = (gSc[3 * i] + gSc[i]) * N[j] + (gSc[3 * i + 1] + gSc[3 + i]) * N[3 + j] +
+                        (gSc[3 * i + 2] + gSc[6 + i]) * N[6 + j];
     // N[i][j] = (W Rq)[i][j] s_j
-    double gWR[9];
+    float gWR[9];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double gs = 0.0;
+      float gs = 0.f;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double wr = cam.R[3 * i] * P.Rq[j] + cam.R[3 * i + 1] * P.Rq[3 + j] +
-                          cam.R[3 * i + 2] * P.Rq[6 + j];
+        const float wr = cR[3 * i] * Rq[j] + cR[3 * i + 1] * Rq[3 + j] + cR[3 * i + 2] * Rq[6 + j];
         gs += gN[3 * i + j] * wr;
-        gWR[3 * i + j] = gN[3 * i + j] * P.s[j];
+        gWR[3 * i + j] = gN[3 * i + j] * sc[j];
       }
-      gls[j] += gs * P.s[j];
+      gls[j] += gs * sc[j];
     }
     // gRq = W^T gWR
-    double gR[9];
+    float gR[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
-        gR[3 * i + j] = cam.R[i] * gWR[j] + cam.R[3 + i] * gWR[3 + j] + cam.R[6 + i] * gWR[6 + j];
-    const double w = P.qn[0], qa = P.qn[1], qb = P.qn[2], qc = P.qn[3];
-    double gqn[4];
-    gqn[0] = 2.0 * (-qc * gR[1] + qb * gR[2] + qc * gR[3] - qa * gR[5] - qb * gR[6] + qa * gR[7]);
-    gqn[1] = 2.0 * (qb * gR[1] + qc * gR[2] + qb * gR[3] - 2.0 * qa * gR[4] - w * gR[5] +
-                    qc * gR[6] + w * gR[7] - 2.0 * qa * gR[8]);
-    gqn[2] = 2.0 * (-2.0 * qb * gR[0] + qa * gR[1] + w * gR[2] + qa * gR[3] + qc * gR[5] -
-                    w * gR[6] + qc * gR[7] - 2.0 * qb * gR[8]);
-    gqn[3] = 2.0 * (-2.0 * qc * gR[0] - w * gR[1] + qa * gR[2] + w * gR[3] - 2.0 * qc * gR[4] +
+        gR[3 * i + j] = cR[i] * gWR[j] + cR[3 + i] * gWR[3 + j] + cR[6 + i] * gWR[6 + j];
+    const float w = (float)P.qn[0], qa = (float)P.qn[1], qb = (float)P.qn[2], qc = (float)P.qn[3];
+    float gqn[4];
+    gqn[0] = 2.f * (-qc * gR[1] + qb * gR[2] + qc * gR[3] - qa * gR[5] - qb * gR[6] + qa * gR[7]);
+    gqn[1] = 2.f * (qb * gR[1] + qc * gR[2] + qb * gR[3] - 2.f * qa * gR[4] - w * gR[5] +
+                    qc * gR[6] + w * gR[7] - 2.f * qa * gR[8]);
+    gqn[2] = 2.f * (-2.f * qb * gR[0] + qa * gR[1] + w * gR[2] + qa * gR[3] + qc * gR[5] -
+                    w * gR[6] + qc * gR[7] - 2.f * qb * gR[8]);
+    gqn[3] = 2.f * (-2.f * qc * gR[0] - w * gR[1] + qa * gR[2] + w * gR[3] - 2.f * qc * gR[4] +
                     qb * gR[5] + qa * gR[6] + qb * gR[7]);
-    const double dq = gqn[0] * w + gqn[1] * qa + gqn[2] * qb + gqn[3] * qc;
+    const float dq = gqn[0] * w + gqn[1] * qa + gqn[2] * qb + gqn[3] * qc;
+    const float qn4[4] = {w, qa, qb, qc};
+    const float iqn = (float)(1.0 / P.qnorm);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) gq[a] += (gqn[a] - P.qn[a] * dq) / P.qnorm;
+    for (int a = 0; a < 4; ++a) gq[a] += (gqn[a] - qn4[a] * dq) * iqn;
   }
   if (m2d_norm && stat_cnt) m2d_norm[g] += stat_norm;
   if (m2d_count && stat_cnt) m2d_count[g] += stat_cnt;

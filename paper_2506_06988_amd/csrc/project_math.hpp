@@ -37,64 +37,68 @@ struct Proj {
 
 // Real spherical harmonics without the Condon-Shortley phase, orthonormal on
 // the sphere, index l*l + l + m. Constants are sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!)
-// times the normalisation of the cos/sin combination, written out in closed form.
-__device__ __forceinline__ void sh_eval(const double d[3], int deg, double* Y) {
+// times the normalisation of the cos/sin combination, written out in closed
+// form (computed in FP64, then rounded to T).
+template <typename T>
+__device__ __forceinline__ void sh_eval(const T d[3], int deg, T* Y) {
   constexpr double PI = 3.14159265358979323846;
-  const double x = d[0], y = d[1], z = d[2];
-  Y[0] = 0.5 * sqrt(1.0 / PI);
+  const T x = d[0], y = d[1], z = d[2];
+  Y[0] = T(0.5 * sqrt(1.0 / PI));
   if (deg < 1) return;
-  const double c1 = sqrt(3.0 / (4.0 * PI));
+  const T c1 = T(sqrt(3.0 / (4.0 * PI)));
   Y[1] = c1 * y;
   Y[2] = c1 * z;
   Y[3] = c1 * x;
   if (deg < 2) return;
-  const double a2 = 0.5 * sqrt(15.0 / PI), b2 = 0.25 * sqrt(5.0 / PI), d2 = 0.25 * sqrt(15.0 / PI);
-  const double xx = x * x, yy = y * y, zz = z * z;
+  const T a2 = T(0.5 * sqrt(15.0 / PI)), b2 = T(0.25 * sqrt(5.0 / PI)),
+          d2 = T(0.25 * sqrt(15.0 / PI));
+  const T xx = x * x, yy = y * y, zz = z * z;
   Y[4] = a2 * x * y;
   Y[5] = a2 * y * z;
-  Y[6] = b2 * (3.0 * zz - 1.0);
+  Y[6] = b2 * (T(3) * zz - T(1));
   Y[7] = a2 * x * z;
   Y[8] = d2 * (xx - yy);
   if (deg < 3) return;
-  const double e3 = 0.25 * sqrt(35.0 / (2.0 * PI)), f3 = 0.5 * sqrt(105.0 / PI),
-               g3 = 0.25 * sqrt(21.0 / (2.0 * PI)), h3 = 0.25 * sqrt(7.0 / PI),
-               k3 = 0.25 * sqrt(105.0 / PI);
-  Y[9] = e3 * y * (3.0 * xx - yy);
+  const T e3 = T(0.25 * sqrt(35.0 / (2.0 * PI))), f3 = T(0.5 * sqrt(105.0 / PI)),
+          g3 = T(0.25 * sqrt(21.0 / (2.0 * PI))), h3 = T(0.25 * sqrt(7.0 / PI)),
+          k3 = T(0.25 * sqrt(105.0 / PI));
+  Y[9] = e3 * y * (T(3) * xx - yy);
   Y[10] = f3 * x * y * z;
-  Y[11] = g3 * y * (5.0 * zz - 1.0);
-  Y[12] = h3 * z * (5.0 * zz - 3.0);
-  Y[13] = g3 * x * (5.0 * zz - 1.0);
+  Y[11] = g3 * y * (T(5) * zz - T(1));
+  Y[12] = h3 * z * (T(5) * zz - T(3));
+  Y[13] = g3 * x * (T(5) * zz - T(1));
   Y[14] = k3 * z * (xx - yy);
-  Y[15] = e3 * x * (xx - 3.0 * yy);
+  Y[15] = e3 * x * (xx - T(3) * yy);
 }
 
 // d/d(x,y,z) of each polynomial of sh_eval, accumulated against weights w[k]:
 // g += sum_k w[k] grad Y_k
-__device__ __forceinline__ void sh_grad_acc(const double d[3], int deg, const double* w,
-                                            double g[3]) {
+template <typename T>
+__device__ __forceinline__ void sh_grad_acc(const T d[3], int deg, const T* w, T g[3]) {
   constexpr double PI = 3.14159265358979323846;
-  const double x = d[0], y = d[1], z = d[2];
+  const T x = d[0], y = d[1], z = d[2];
   if (deg < 1) return;
-  const double c1 = sqrt(3.0 / (4.0 * PI));
+  const T c1 = T(sqrt(3.0 / (4.0 * PI)));
   g[1] += c1 * w[1];
   g[2] += c1 * w[2];
   g[0] += c1 * w[3];
   if (deg < 2) return;
-  const double a2 = 0.5 * sqrt(15.0 / PI), b2 = 0.25 * sqrt(5.0 / PI), d2 = 0.25 * sqrt(15.0 / PI);
-  g[0] += a2 * (y * w[4] + z * w[7]) + 2.0 * d2 * x * w[8];
-  g[1] += a2 * (x * w[4] + z * w[5]) - 2.0 * d2 * y * w[8];
-  g[2] += a2 * (y * w[5] + x * w[7]) + 6.0 * b2 * z * w[6];
+  const T a2 = T(0.5 * sqrt(15.0 / PI)), b2 = T(0.25 * sqrt(5.0 / PI)),
+          d2 = T(0.25 * sqrt(15.0 / PI));
+  g[0] += a2 * (y * w[4] + z * w[7]) + T(2) * d2 * x * w[8];
+  g[1] += a2 * (x * w[4] + z * w[5]) - T(2) * d2 * y * w[8];
+  g[2] += a2 * (y * w[5] + x * w[7]) + T(6) * b2 * z * w[6];
   if (deg < 3) return;
-  const double e3 = 0.25 * sqrt(35.0 / (2.0 * PI)), f3 = 0.5 * sqrt(105.0 / PI),
-               g3 = 0.25 * sqrt(21.0 / (2.0 * PI)), h3 = 0.25 * sqrt(7.0 / PI),
-               k3 = 0.25 * sqrt(105.0 / PI);
-  const double xx = x * x, yy = y * y, zz = z * z;
-  g[0] += e3 * 6.0 * x * y * w[9] + f3 * y * z * w[10] + g3 * (5.0 * zz - 1.0) * w[13] +
-          2.0 * k3 * x * z * w[14] + e3 * 3.0 * (xx - yy) * w[15];
-  g[1] += e3 * 3.0 * (xx - yy) * w[9] + f3 * x * z * w[10] + g3 * (5.0 * zz - 1.0) * w[11] -
-          2.0 * k3 * y * z * w[14] - e3 * 6.0 * x * y * w[15];
-  g[2] += f3 * x * y * w[10] + 10.0 * g3 * y * z * w[11] + h3 * (15.0 * zz - 3.0) * w[12] +
-          10.0 * g3 * x * z * w[13] + k3 * (xx - yy) * w[14];
+  const T e3 = T(0.25 * sqrt(35.0 / (2.0 * PI))), f3 = T(0.5 * sqrt(105.0 / PI)),
+          g3 = T(0.25 * sqrt(21.0 / (2.0 * PI))), h3 = T(0.25 * sqrt(7.0 / PI)),
+          k3 = T(0.25 * sqrt(105.0 / PI));
+  const T xx = x * x, yy = y * y, zz = z * z;
+  g[0] += e3 * T(6) * x * y * w[9] + f3 * y * z * w[10] + g3 * (T(5) * zz - T(1)) * w[13] +
+          T(2) * k3 * x * z * w[14] + e3 * T(3) * (xx - yy) * w[15];
+  g[1] += e3 * T(3) * (xx - yy) * w[9] + f3 * x * z * w[10] + g3 * (T(5) * zz - T(1)) * w[11] -
+          T(2) * k3 * y * z * w[14] - e3 * T(6) * x * y * w[15];
+  g[2] += f3 * x * y * w[10] + T(10) * g3 * y * z * w[11] + h3 * (T(15) * zz - T(3)) * w[12] +
+          T(10) * g3 * x * z * w[13] + k3 * (xx - yy) * w[14];
 }
 
 __device__ __forceinline__ int clamp_tile(double v, int hi) {
