@@ -593,20 +593,25 @@ __global__ __launch_bounds__(256) void k_tile_schedule(int n_tiles, int64_t key_
       counters[1] = K > (unsigned long long)key_cap ? 1u : 0u;
     }
   }
-  // bucket k: tiles of every block, and of the blocks before this one (a
-  // thread per block of tiles, its 33 counts loaded together)
-  if (threadIdx.x < SCHED_BUCKETS) tot[threadIdx.x] = off[threadIdx.x] = 0;
-  __syncthreads();
-  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-    uint32_t v[SCHED_BUCKETS];
+  // bucket k: tiles of every block, and of the blocks before this one (wave
+  // w sums buckets w, w + 4, ..., a lane per block of tiles)
+  const int wv = threadIdx.x >> 6, ln = __lane_id();
+  for (int k = wv; k < SCHED_BUCKETS; k += 4) {
+    uint32_t s_all = 0, s_pre = 0;
+    for (int q = ln; q < nb; q += 64) {
+      const uint32_t v = sched_cnt[q * SCHED_BUCKETS + k];
+      s_all += v;
+      if (q < b) s_pre += v;
+    }
 #pragma unroll
-    for (int k = 0; k < SCHED_BUCKETS; ++k) v[k] = sched_cnt[q * SCHED_BUCKETS + k];
-#pragma unroll
-    for (int k = 0; k < SCHED_BUCKETS; ++k)
-      if (v[k]) {
-        atomicAdd(&tot[k], v[k]);
-        if (q < b) atomicAdd(&off[k], v[k]);
-      }
+    for (int o = 32; o > 0; o >>= 1) {
+      s_all += __shfl_xor(s_all, o, 64);
+      s_pre += __shfl_xor(s_pre, o, 64);
+    }
+    if (ln == 0) {
+      tot[k] = s_all;
+      off[k] = s_pre;
+    }
   }
   __syncthreads();
   if (threadIdx.x < SCHED_BUCKETS) {
