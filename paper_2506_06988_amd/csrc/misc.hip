@@ -27,10 +27,25 @@ __global__ __launch_bounds__(1024) void k_counters_to_stats(const uint32_t* __re
                                                             int n_tiles,
                                                             hr_stats* __restrict__ s) {
   __shared__ unsigned long long part[2][16];
+  // one 16-byte load per tile, four tiles in flight per thread
+  const ulonglong2* __restrict__ np2 = reinterpret_cast<const ulonglong2*>(tile_np);
   unsigned long long sp = 0, sb = 0;
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-    sp += tile_np[2 * t];
-    sb += tile_np[2 * t + 1];
+  const int step = (int)blockDim.x;
+  int t = threadIdx.x;
+  for (; t + 3 * step < n_tiles; t += 4 * step) {
+    ulonglong2 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = np2[t + q * step];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sp += v[q].x;
+      sb += v[q].y;
+    }
+  }
+  for (; t < n_tiles; t += step) {
+    const ulonglong2 v = np2[t];
+    sp += v.x;
+    sb += v.y;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
