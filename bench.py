@@ -139,8 +139,9 @@ def timed_frames(torch, r, frame, views, steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
-              f"(asked for {args.gpus}); views shard across GPUs as described in DESIGN.md.",
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path "
+              f"(asked for {args.gpus}); with several GPUs each would render its own share "
+              f"of the views, so the one-GPU figure is the per-GPU rate.",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
