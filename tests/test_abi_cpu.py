@@ -100,3 +100,16 @@ def test_status_strings():
     for k in range(6):
         assert L.hr_status_string(k)
     assert L.hr_status_string(hr.HR_ERR_CAPACITY) == b"key capacity too small"
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_bench_refuses_several_gpus(n):
+    """The benchmark measures one GPU: asked for more it exits with status 2
+    and a message, before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and f"asked for {n}" in r.stderr
+    assert r.stdout == ""
