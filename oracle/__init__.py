@@ -90,7 +90,11 @@ class ProjOut_(C.Structure):
 class RenderOut_(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("image", "final_T", "n_contrib", "n_blended",
                                           "n_processed", "amb", "tri_id", "mesh_depth",
-                                          "mesh_rgb", "trace")]
+                                          "mesh_rgb", "trace", "n_alt", "alts")]
+
+
+MAX_ALT = 16  # outcomes kept per pixel by render(..., alts=True)
+AMB_ALPHA, AMB_T, AMB_PROJ, AMB_MESH, AMB_MANY = 1, 2, 4, 16, 32  # bits of render()["amb"]
 
 
 class Grads_(C.Structure):
@@ -230,8 +234,15 @@ def keys(gaussians, cam, params=None, mesh=None, filter3d=None):
     return k, v, r
 
 
-def render(gaussians, mesh, cam, params=None, window=None, overrides=None, filter3d=None):
-    """Forward render; `window` = (x0, y0, x1, y1) restricts the pixels computed."""
+def render(gaussians, mesh, cam, params=None, window=None, overrides=None, filter3d=None,
+           alts=False):
+    """Forward render; `window` = (x0, y0, x1, y1) restricts the pixels computed.
+
+    With alts=True, also `n_alt` [h,w] and `alts` [h,w,MAX_ALT,7]: for a pixel
+    whose alpha-skip or transmittance-stop decision lies inside the ambiguity
+    slack (FP32 cannot be sure of it), the outcome (r, g, b, T, n_contrib,
+    n_blended, n_processed) of every path through those decisions taken
+    either way; alts[..., 0, :] is the FP64 outcome itself."""
     P = _params(params or default_params())
     sa = _SceneArrays(gaussians, mesh, overrides, filter3d)
     x0, y0, x1, y1 = window or (0, 0, cam.width, cam.height)
@@ -241,6 +252,9 @@ def render(gaussians, mesh, cam, params=None, window=None, overrides=None, filte
                n_processed=np.zeros((h, w), np.int32), amb=np.zeros((h, w), np.uint8),
                tri_id=np.zeros((h, w), np.int32), mesh_depth=np.zeros((h, w), np.float32),
                mesh_rgb=np.zeros((3, h, w)), trace=np.zeros(1, np.uint64))
+    if alts:
+        out["n_alt"] = np.zeros((h, w), np.int32)
+        out["alts"] = np.zeros((h, w, MAX_ALT, 7))
     o = RenderOut_(**{k: _p(v) for k, v in out.items()})
     c = _camera(cam)
     rc = lib().or_render(C.byref(sa.s), C.byref(c), C.byref(P), x0, y0, x1, y1, C.byref(o))

@@ -20,6 +20,12 @@
 // plane, 1.3 x FOV clamp of the Jacobian, SH colour + 0.5 clamped at 0) are
 // inputs (or_params), not constants.
 //
+// Decisions of the blend that an FP32 evaluation cannot be sure of (alpha
+// within a relative slack of alpha_min, T(1 - alpha) within one of t_min) are
+// tagged; or_render can also list the outcome of every path through them,
+// taken either way, so that a kernel's result can be matched against one of
+// them instead of being left unchecked.
+//
 // Everything is FP64 except where the method's definition rounds: the sort key
 // and the depth test use fp32(z); the blend reads the projected record rounded
 // to FP32 (the record precision of the kernel) unless OR_FP64_RECORDS is set,
@@ -91,7 +97,16 @@ typedef struct {
   float* mesh_depth;    // [h,w]
   double* mesh_rgb;     // [3,h,w]
   uint64_t* trace;      // [1] hash of every decision taken
+  // Every pixel with an alpha-skip or T-stop decision inside the ambiguity
+  // slack (amb bits 0-1) gets the outcome of each path through its ambiguous
+  // decisions, either way at each: n_alt[h,w] paths (1 elsewhere, at most
+  // OR_MAX_ALT; amb bit 5 set when more exist), alts[h,w,OR_MAX_ALT,7] =
+  // (r, g, b, T, n_contrib, n_blended, n_processed). Both nullable.
+  int32_t* n_alt;
+  double* alts;
 } or_render_out;
+
+#define OR_MAX_ALT 16
 
 typedef struct {
   double* means;     // [n,3]
@@ -634,15 +649,30 @@ struct Step {
   bool clamped;
 };
 
+// A floating-point decision of the blend taken too close to its threshold for
+// an FP32 evaluation to be sure of it: the alpha-skip (kind 0) or the
+// transmittance stop (kind 1) at list entry k.
+struct Decision {
+  int k, kind;
+  bool operator<(const Decision& o) const { return k != o.k ? k < o.k : kind < o.kind; }
+  bool operator==(const Decision& o) const { return k == o.k && kind == o.kind; }
+};
+
 // Sec. 3.1 Eq. 2 with the joint-rasterization depth stop of Sec. 3.4.
 // Returns the steps that blended (the tape) and fills the pixel outputs.
+// `flip` lists decisions to take the other way; `near` (nullable) receives
+// every decision met within the ambiguity slack, in list order.
 void blend_pixel(const std::vector<Rec>& recs, const std::vector<Cand>& list, const or_params& p,
                  double px, double py, float Dm, std::vector<Step>* tape, double C[3], double* Tout,
-                 int* nc, int* nb, int* npro, uint8_t* amb, uint64_t* hash) {
+                 int* nc, int* nb, int* npro, uint8_t* amb, uint64_t* hash,
+                 const std::vector<Decision>* flip = nullptr, std::vector<Decision>* near = nullptr) {
   double T = 1.0;
   C[0] = C[1] = C[2] = 0.0;
   *nc = 0; *nb = 0; *npro = (int)list.size();
   uint64_t h = 0;
+  auto flipped = [&](int k, int kind) {
+    return flip && std::find(flip->begin(), flip->end(), Decision{k, kind}) != flip->end();
+  };
   for (size_t k = 0; k < list.size(); ++k) {
     const Rec& r = recs[list[k].g];
     if (r.amb) *amb |= 4;
@@ -657,14 +687,20 @@ void blend_pixel(const std::vector<Rec>& recs, const std::vector<Cand>& list, co
     const double a = r.bop * G;
     const bool clamped = a >= p.alpha_max;
     const double alpha = clamped ? p.alpha_max : a;
-    if (std::fabs(alpha - p.alpha_min) <= p.amb_alpha * p.alpha_min) *amb |= 1;
-    if (alpha < p.alpha_min) {
+    if (std::fabs(alpha - p.alpha_min) <= p.amb_alpha * p.alpha_min) {
+      *amb |= 1;
+      if (near) near->push_back({(int)k, 0});
+    }
+    if ((alpha < p.alpha_min) != flipped((int)k, 0)) {
       h = mix(h, 1);
       continue;
     }
     const double Tn = T * (1.0 - alpha);
-    if (std::fabs(Tn - p.t_min) <= p.amb_t * p.t_min) *amb |= 2;
-    if (Tn < p.t_min) {
+    if (std::fabs(Tn - p.t_min) <= p.amb_t * p.t_min) {
+      *amb |= 2;
+      if (near) near->push_back({(int)k, 1});
+    }
+    if ((Tn < p.t_min) != flipped((int)k, 1)) {
       *npro = (int)k + 1;
       h = mix(h, 2);
       break;
@@ -864,12 +900,54 @@ int or_render(const or_scene* sc, const or_camera* cam, const or_params* p, int 
     int nc, nb, npro;
     uint8_t amb = has && mp.amb ? 16 : 0;
     uint64_t h;
-    blend_pixel(f.recs, list, *p, i + 0.5, j + 0.5, Dm, nullptr, C, &T, &nc, &nb, &npro, &amb, &h);
+    std::vector<Decision> near;
+    blend_pixel(f.recs, list, *p, i + 0.5, j + 0.5, Dm, nullptr, C, &T, &nc, &nb, &npro, &amb, &h,
+                nullptr, &near);
     const size_t hw = (size_t)ww * wh;
+    double B[3];
     for (int c = 0; c < 3; ++c) {
-      const double B = has ? Im[c] : p->bg[c];
-      if (o->image) o->image[c * hw + idx] = C[c] + T * B;
+      B[c] = has ? Im[c] : p->bg[c];
+      if (o->image) o->image[c * hw + idx] = C[c] + T * B[c];
       if (o->mesh_rgb) o->mesh_rgb[c * hw + idx] = Im[c];
+    }
+    if (o->n_alt && o->alts) {
+      // depth-first over the ambiguous decisions: a path flips a set of them,
+      // each later in the list than the previous flip and met (within the
+      // slack) on the path so far; every path is one possible FP32 outcome
+      double* al = o->alts + (size_t)idx * OR_MAX_ALT * 7;
+      int n_alt = 0;
+      auto put = [&](const double* Cc, double Tt, int a, int b, int c) {
+        double* q = al + (size_t)n_alt * 7;
+        for (int ch = 0; ch < 3; ++ch) q[ch] = Cc[ch] + Tt * B[ch];
+        q[3] = Tt; q[4] = a; q[5] = b; q[6] = c;
+        ++n_alt;
+      };
+      put(C, T, nc, nb, npro);
+      std::vector<std::pair<std::vector<Decision>, std::vector<Decision>>> stack;
+      stack.push_back({{}, near});
+      while (!stack.empty()) {
+        auto [flips, met] = stack.back();
+        stack.pop_back();
+        for (const Decision& d : met) {
+          if (!flips.empty() && !(flips.back() < d)) continue;
+          if (n_alt == OR_MAX_ALT) {
+            amb |= 32;
+            break;
+          }
+          std::vector<Decision> f2 = flips;
+          f2.push_back(d);
+          std::vector<Decision> met2;
+          double C2[3], T2;
+          int nc2, nb2, np2;
+          uint8_t amb2 = 0;
+          uint64_t h2;
+          blend_pixel(f.recs, list, *p, i + 0.5, j + 0.5, Dm, nullptr, C2, &T2, &nc2, &nb2, &np2,
+                      &amb2, &h2, &f2, &met2);
+          put(C2, T2, nc2, nb2, np2);
+          stack.push_back({f2, met2});
+        }
+      }
+      o->n_alt[idx] = n_alt;
     }
     if (o->final_T) o->final_T[idx] = T;
     if (o->n_contrib) o->n_contrib[idx] = nc;

@@ -43,6 +43,25 @@ MUTANTS = [
     ("tile rectangle one tile short",
      "r.x1 = clampi(std::floor(ex1) + 1, TX);", "r.x1 = clampi(std::floor(ex1), TX);",
      "test_rect_is_the_tile_cover_of_the_3sigma_box or test_keys_match_brute_force_lexsort"),
+    ("transmittance stop removed",
+     "if ((Tn < p.t_min) != flipped((int)k, 1)) {", "if (false) {",
+     "stack or n_contrib_is"),
+    ("the Gaussian that crosses t_min blended before the stop",
+     "      *npro = (int)k + 1;\n      h = mix(h, 2);\n      break;",
+     "      for (int c = 0; c < 3; ++c) C[c] += r.brgb[c] * alpha * T;\n"
+     "      T = Tn; *nc = (int)k + 1; *nb += 1;\n"
+     "      *npro = (int)k + 1;\n      h = mix(h, 2);\n      break;",
+     "stack"),
+    ("n_contrib counted from 0",
+     "*nc = (int)k + 1;", "*nc = (int)k;",
+     "stack or n_contrib_is or strict"),
+    ("tile-ellipse cut without its FP32 growth margin",
+     "const double rp = 1.01 * rr + 0.1 + 1e-5 * (a + c) * ext * ext;", "const double rp = rr;",
+     "tile_ellipse_key_set"),
+    ("tile-ellipse run one tile short on the right",
+     "*x1 = std::min(*x1, (int)std::floor((r.bu + xmax - 0.5) / tile) + 1);",
+     "*x1 = std::min(*x1, (int)std::floor((r.bu + xmax - 0.5) / tile));",
+     "tile_ellipse_key_set"),
     ("SH degree-2 constant off",
      "const double a2 = 0.5 * std::sqrt(15.0 / PI), b2 = 0.25 * std::sqrt(5.0 / PI),\n               d2 = 0.25 * std::sqrt(15.0 / PI);\n  Y[4]",
      "const double a2 = 0.5 * std::sqrt(15.0 / PI), b2 = 0.25 * std::sqrt(3.0 / PI),\n               d2 = 0.25 * std::sqrt(15.0 / PI);\n  Y[4]",

@@ -362,6 +362,119 @@ def test_two_gaussians_front_to_back():
     np.testing.assert_allclose(out["image"], expect, atol=1e-6)
 
 
+# ------------------------------------- transmittance stop and pixel counts --
+# A stack of Gaussians on the optical axis of a camera whose principal point
+# is the centre of pixel (16, 16): there every Gaussian has G = 1, so its
+# alpha is its record opacity (clamped at 0.99) whatever its depth and size,
+# and the list of that pixel's tile is the stack in depth order.
+def _axis_stack(logits, depths, colours=None, mesh=None):
+    cam = scenes.Camera(32, 32, 32.0, 32.0, 16.5, 16.5, np.eye(3), np.zeros(3))
+    n = len(logits)
+    means = np.column_stack([np.zeros(n), np.zeros(n), np.asarray(depths, np.float64)])
+    col = np.tile([0.8, 0.4, 0.2], (n, 1)) if colours is None else colours
+    g = gauss(means, log_scales=[[-2.5] * 3] * n, logits=logits, colours=col)
+    out = oracle.render(g, mesh, cam)
+    return out, g
+
+
+def _record_alpha(logit):
+    """alpha of a Gaussian seen at its centre: the FP32 record opacity
+    sigmoid(logit), clamped at alpha_max"""
+    o = F32(1.0 / (1.0 + math.exp(-float(np.float32(logit)))))
+    return min(o, F32(0.99))
+
+
+@pytest.mark.parametrize("offset", [+1e-3, -1e-3])
+def test_identical_stack_stops_where_transmittance_would_cross_t_min(offset):
+    # k identical Gaussians of alpha a leave T_n = (1 - a)^n after n blends. A
+    # pixel stops before the first Gaussian that would take T under t_min:
+    # n* = floor(ln t_min / ln(1 - a)) + 1 is that Gaussian's 1-based index,
+    # n* - 1 Gaussians blend and T = (1 - a)^(n* - 1). Here (1 - a)^4 sits
+    # 1e-3 above (4 blend, the 5th stops) or below (3 blend, the 4th stops)
+    # t_min.
+    t_min = F32(1e-4)
+    a_want = 1.0 - (t_min * (1.0 + offset)) ** 0.25
+    logit = math.log(a_want / (1.0 - a_want))
+    a = _record_alpha(logit)
+    k = 8
+    out, g = _axis_stack([logit] * k, 2.0 + 0.25 * np.arange(k))
+    n_star = math.floor(math.log(t_min) / math.log(1.0 - a)) + 1
+    assert n_star == (5 if offset > 0 else 4)
+    j = i = 16
+    assert out["n_blended"][j, i] == n_star - 1
+    assert out["n_contrib"][j, i] == n_star - 1
+    assert out["n_processed"][j, i] == n_star
+    T = (1.0 - a) ** (n_star - 1)
+    assert T >= t_min and T * (1.0 - a) < t_min
+    np.testing.assert_allclose(out["final_T"][j, i], T, rtol=1e-12)
+    # the colour of a stack of identical colours c: c (1 - T), no mesh: bg = 0
+    col = np.float32([0.8, 0.4, 0.2]).astype(np.float64)
+    np.testing.assert_allclose(out["image"][:, j, i], col * (1.0 - T), rtol=1e-6)
+
+
+def test_clamped_stack_stops_at_the_second_gaussian():
+    # alpha clamps at fp32(0.99): (1 - 0.99)^2 is just under fp32(1e-4), so
+    # the second Gaussian stops the pixel after one blend
+    a = _record_alpha(8.0)
+    assert a == F32(0.99)
+    assert (1.0 - a) ** 2 < F32(1e-4) <= 1.0 - a
+    out, _ = _axis_stack([8.0] * 5, [2.0, 2.5, 3.0, 3.5, 4.0])
+    assert (out["n_blended"][16, 16], out["n_contrib"][16, 16], out["n_processed"][16, 16]) == (1, 1, 2)
+    np.testing.assert_allclose(out["final_T"][16, 16], 1.0 - a, rtol=1e-12)
+    # the decision is within the FP32 slack of t_min: tagged ambiguous
+    assert out["amb"][16, 16] & oracle.AMB_T
+
+
+def test_n_contrib_is_the_list_index_of_the_last_blended_gaussian():
+    # entries with alpha < 1/255 are skipped but still take a list position:
+    # stack [A s A s s A s s] (A: alpha 0.5, s: alpha ~1e-3): blended
+    # positions 1, 3, 6, so n_contrib = 6, n_blended = 3, and the list runs
+    # out without a stop, so n_processed = 8 and T = 0.5^3
+    A, s_ = 0.0, -7.0
+    out, _ = _axis_stack([A, s_, A, s_, s_, A, s_, s_], 2.0 + 0.25 * np.arange(8))
+    a = _record_alpha(A)
+    assert a == 0.5 and _record_alpha(s_) < F32(1 / 255)
+    assert (out["n_contrib"][16, 16], out["n_blended"][16, 16], out["n_processed"][16, 16]) == (6, 3, 8)
+    np.testing.assert_allclose(out["final_T"][16, 16], 0.125, rtol=1e-14)
+
+
+def test_mesh_depth_stop_is_strict_and_counts_the_stopping_entry():
+    # Sec. 3.4: Gaussians blend only while D_gs < D_m. A quad at z = 5 has
+    # D_m = 5 exactly; a Gaussian at exactly 5 stops the pixel (and is the
+    # n_processed-th entry), one at the next smaller FP32 depth blends.
+    mesh = quad(z=5.0, half=3.0, rng=np.random.default_rng(4))
+    below = float(np.nextafter(np.float32(5.0), np.float32(0.0)))
+    a = _record_alpha(0.0)
+    for z2, nb, npro in ((5.0, 1, 2), (below, 2, 3)):
+        out, _ = _axis_stack([0.0, 0.0, 0.0], [4.0, z2, 6.0], mesh=mesh)
+        assert out["mesh_depth"][16, 16] == 5.0
+        assert (out["n_blended"][16, 16], out["n_contrib"][16, 16], out["n_processed"][16, 16]) == (nb, nb, npro)
+        T = (1.0 - a) ** nb
+        np.testing.assert_allclose(out["final_T"][16, 16], T, rtol=1e-14)
+        Im = out["mesh_rgb"][:, 16, 16]
+        col = np.float32([0.8, 0.4, 0.2]).astype(np.float64)
+        np.testing.assert_allclose(out["image"][:, 16, 16], col * (1.0 - T) + T * Im, rtol=1e-6)
+
+
+def test_ambiguous_decisions_enumerate_both_outcomes():
+    # the clamped stack's stop is within the slack: the alternative outcome is
+    # the second Gaussian blended (T = (1 - a)^2, 2e-6 under t_min), after
+    # which the third stops the pixel far from the threshold
+    a = _record_alpha(8.0)
+    cam = scenes.Camera(32, 32, 32.0, 32.0, 16.5, 16.5, np.eye(3), np.zeros(3))
+    g = gauss(np.column_stack([np.zeros(5), np.zeros(5), [2.0, 2.5, 3.0, 3.5, 4.0]]),
+              log_scales=[[-2.5] * 3] * 5, logits=[8.0] * 5)
+    out = oracle.render(g, None, cam, alts=True)
+    assert out["n_alt"][16, 16] == 2
+    first, second = out["alts"][16, 16, 0], out["alts"][16, 16, 1]
+    np.testing.assert_array_equal(first[3:], [1.0 - a, 1, 1, 2])
+    np.testing.assert_allclose(second[3], (1.0 - a) ** 2, rtol=1e-14)
+    np.testing.assert_array_equal(second[4:], [2, 2, 3])
+    # a pixel without ambiguous decisions has one outcome, the render itself
+    assert out["n_alt"][0, 0] == 1
+    np.testing.assert_array_equal(out["alts"][0, 0, 0, :3], out["image"][:, 0, 0])
+
+
 def test_permuting_gaussians_with_distinct_depths():
     sc = scenes.config1()
     g = sc.gaussians
@@ -894,3 +1007,100 @@ def test_tile_ellipse_keeps_every_pair_a_pixel_blends_and_the_image():
         alpha = F32(pr["opacity"][gi]) * np.exp(power)
         assert alpha.max() < amin, (t, gi, alpha.max())
     assert dropped > 100
+
+
+def _box_min_quadratic(a, b, c, x0, x1, y0, y1):
+    """min of a x^2 + 2 b x y + c y^2 (positive definite) over [x0,x1] x [y0,y1]:
+    0 when the origin is inside, else the least of the four edge minima (each
+    a 1-D quadratic minimised at its clamped vertex)."""
+    if x0 <= 0.0 <= x1 and y0 <= 0.0 <= y1:
+        return 0.0
+    f = lambda x, y: a * x * x + 2 * b * x * y + c * y * y
+    best = math.inf
+    for x in (x0, x1):
+        y = min(max(-b * x / c, y0), y1)
+        best = min(best, f(x, y))
+    for y in (y0, y1):
+        x = min(max(-b * y / a, x0), x1)
+        best = min(best, f(x, y))
+    return best
+
+
+def test_tile_ellipse_key_set_is_the_grown_ellipse_meeting_the_tile():
+    # The cut keeps a (Gaussian, tile) pair of the 3-sigma rectangle exactly
+    # when the tile's 16x16 pixel-centre box meets the ellipse d^T Q d <= R'
+    # around the record's mean (Q its conic), R' = 1.01 R + 0.1 + 1e-5 (a+c)
+    # ext^2 grown from R = 2 ln(opacity / alpha_min) (ext: the rectangle's
+    # longer side in pixels). Recomputed here by minimising the quadratic form
+    # over each box, independent of the oracle's row-by-row x-extent method.
+    g, cam = _ellipse_scene(72, n=160)
+    pe = oracle.default_params(flags=oracle.TILE_ELLIPSE)
+    k0, v0, _ = oracle.keys(g, cam)
+    k1, v1, _ = oracle.keys(g, cam, params=pe)
+    kept = set(zip((k1 >> np.uint64(32)).tolist(), v1.tolist()))
+    pr = oracle.project(g, cam)
+    TX = 6
+    amin = F32(1 / 255)
+    n_keep = n_drop = 0
+    for key, gi in zip(k0.tolist(), v0.tolist()):
+        t = key >> 32
+        tx, ty = t % TX, t // TX
+        a, b, c = (F32(x) for x in pr["conic"][gi])
+        u, v = (F32(x) for x in pr["mean2d"][gi])
+        o = F32(pr["opacity"][gi])
+        x0r, x1r, y0r, y1r = pr["rect"][gi]
+        if not (a > 0 and c > 0 and a * c - b * b > 0):
+            want = True
+        elif o <= amin:
+            want = False
+        else:
+            R = 2.0 * (math.log(o) - math.log(amin))
+            ext = 16.0 * max(x1r - x0r, y1r - y0r)
+            Rp = 1.01 * R + 0.1 + 1e-5 * (a + c) * ext * ext
+            m = _box_min_quadratic(a, b, c, 16 * tx + 0.5 - u, 16 * tx + 15.5 - u,
+                                   16 * ty + 0.5 - v, 16 * ty + 15.5 - v)
+            if abs(m - Rp) <= 1e-9 * Rp:
+                continue  # on the boundary: either answer is right
+            want = m <= Rp
+        assert ((t, gi) in kept) == want, (t, gi)
+        n_keep += want
+        n_drop += not want
+    assert n_keep > 100 and n_drop > 100
+    # nothing outside the rectangle's pairs is kept
+    assert kept <= set(zip((k0 >> np.uint64(32)).tolist(), v0.tolist()))
+
+
+def test_tile_ellipse_counts_are_positions_in_the_cut_lists():
+    # Every pair the cut drops is skipped by every pixel of its tile, so a
+    # pixel of the cut render blends the same Gaussians as the uncut one and
+    # stops at the same entry, or - when that entry (a mesh-depth stop) was
+    # dropped - at the next kept one, which lies behind the mesh too. Hence
+    # n_contrib = kept entries among the first n_contrib of the uncut list;
+    # n_processed = kept entries among the first n_processed, plus one when the
+    # terminating entry was dropped and kept entries follow it.
+    rng = np.random.default_rng(73)
+    g, cam = _ellipse_scene(73, n=140)
+    mesh = scenes.quad_mesh(rng, z=2.9, half=3.0, tex_size=8)  # stops some pixels
+    pe = oracle.default_params(flags=oracle.TILE_ELLIPSE)
+    base = oracle.render(g, mesh, cam)
+    cut = oracle.render(g, mesh, cam, params=pe)
+    for k in ("image", "final_T", "n_blended"):
+        np.testing.assert_array_equal(cut[k], base[k])
+    k0, v0, r0 = oracle.keys(g, cam)
+    k1, v1, _ = oracle.keys(g, cam, params=pe)
+    kept = set(zip((k1 >> np.uint64(32)).tolist(), v1.tolist()))
+    TX = 6
+    stopped_on_dropped = 0
+    for t in range(r0.shape[0]):
+        lst = v0[r0[t, 0]:r0[t, 1]].tolist()
+        keep = np.array([(t, gi) in kept for gi in lst], bool)
+        csum = np.concatenate([[0], np.cumsum(keep)])
+        tx, ty = t % TX, t // TX
+        for j in range(16 * ty, min(16 * ty + 16, cam.height)):
+            for i in range(16 * tx, min(16 * tx + 16, cam.width)):
+                nc, npro = base["n_contrib"][j, i], base["n_processed"][j, i]
+                assert cut["n_contrib"][j, i] == csum[nc]
+                extra = int(npro > 0 and not keep[npro - 1] and csum[-1] > csum[npro])
+                stopped_on_dropped += extra
+                assert cut["n_processed"][j, i] == csum[npro] + extra, (t, j, i)
+    assert stopped_on_dropped > 0
