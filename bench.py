@@ -110,7 +110,7 @@ def pmc_probe_step(torch, hr, scenes, dev):
     r.settings.batch, r.settings.variant, r.settings.batch_bwd = 256, 8, 128
     f = r.render_hybrid(sync_check=True)
     target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
-    _, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target)
+    _, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target, r.sizes)
     r.render_hybrid_backward(gi, gt, gm)
     torch.cuda.synchronize()
     log("pmc step probe done")
@@ -280,7 +280,8 @@ def main():
         torch.cuda.synchronize()
         target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
         r.autotune(f, repeats=2)
-        L0, gi0, gt0, _ = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target)
+        L0, gi0, gt0, _ = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target,
+                                          r.sizes)
         r.autotune_backward(gi0, gt0, repeats=2)
         log(f"batched tuning: forward batch {r.settings.batch}, backward batch "
             f"{r.settings.batch_bwd}, variant {r.settings.variant}")

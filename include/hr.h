@@ -9,7 +9,7 @@
  *   - an opaque textured mesh rendered with barycentric UVs           (Sec. 3.1 "Textured mesh")
  *   - joint rasterization: the mesh gives I_m and D_m, only Gaussians
  *     with D_gs < D_m are blended and the residual transmittance T
- *     weights I_m (or the background)                                  (Sec. 3.4 "Joint rasterization")
+ *     weights I_m (or the background)                                  (Sec. 3.4 "Joint optimization", paragraph "Joint rasterization")
  *   - gradients to every Gaussian parameter and to the texture map,
  *     none to mesh vertices                                            (Sec. 3.4)
  *   - the loss L1 + lambda * M_T * ||I~ - I~_m||^2                     (Sec. 3.4, transmittance-aware supervision)
@@ -51,9 +51,13 @@
  *     HR_ERR_INVALID_ARGUMENT nothing is written. hr_last_error() returns a
  *     thread-local description of the last failure.
  *   - When the pair count exceeds the workspace's key capacity the outputs
- *     are undefined, hr_stats.overflow is set on the device and, unless
- *     HR_FLAG_NO_SYNC is given, the call synchronises the stream once and
- *     returns HR_ERR_CAPACITY with hr_stats.n_keys holding the needed count.
+ *     are undefined (no write leaves the workspace or the outputs), the
+ *     device flag hr_stats.overflow is set and, unless HR_FLAG_NO_SYNC is
+ *     given, the call synchronises the stream once and returns
+ *     HR_ERR_CAPACITY with hr_stats.n_keys holding the needed count. The same
+ *     synchronisation reports HR_ERR_INTERNAL when hr_stats.wait_limit is set.
+ *     A replayed graph (hr_batch_launch) never synchronises: hr_batch_status
+ *     reads both flags after the replay.
  *   - Non-finite Gaussian parameters cull that Gaussian; degenerate triangles
  *     are skipped; n = 0 and n_faces = 0 are legal.
  */
@@ -67,7 +71,7 @@
 extern "C" {
 #endif
 
-#define HR_ABI_VERSION 1
+#define HR_ABI_VERSION 2
 
 typedef enum {
   HR_OK = 0,
@@ -169,6 +173,10 @@ typedef struct {
   uint32_t n_tris;     /* visible clipped triangles */
   uint64_t n_processed;/* sum over pixels of list entries examined */
   uint64_t n_blended;  /* sum over pixels of Gaussians blended */
+  uint32_t wait_limit; /* 1 when a one-pass prefix sum gave up waiting for another
+                          workgroup (a bounded wait that should never end this way):
+                          the outputs are undefined; reported as HR_ERR_INTERNAL */
+  uint32_t reserved;   /* 0 */
 } hr_stats;
 
 /* Outputs of the forward; every pointer is device memory, sized over the
@@ -245,19 +253,26 @@ hr_status hr_blend_forward(const hr_gaussians* g, const hr_mesh* mesh, const hr_
                            void* workspace, size_t workspace_bytes, hr_outputs* out,
                            void* stream);
 
-/* Loss of Sec. 3.4 over n_pix packed pixels:
+/* Loss of Sec. 3.4 ("transmittance-aware supervision") over n_images images
+ * packed like the renderer's outputs: image i is sizes[2i] wide and
+ * sizes[2i+1] high (`sizes` is host memory), its pixels start at
+ * P_i = sum_{i'<i} W_i' H_i' in final_T and tri_id and its planar [3, H_i, W_i]
+ * colours at 3 P_i in image, mesh_rgb and target. With P = sum W_i H_i:
  *   L = mean_{p,c} |I_h - I| + lambda_t * mean_{p,c} M_T(p) (I~ - I~_m)^2,
  *   M_T = 1 / (1 + exp(-k (T - 1/2))), I~ = I and I~_m = I_m where
- *   tri_id >= 0, else 0 (the means run over 3 n_pix values).
+ *   tri_id >= 0, else 0 (the means run over 3P values).
  * Writes the loss (device scalar, deterministic reduction) and dL/dI_h,
- * dL/dT (0 with HR_FLAG_DETACH_MASK) and dL/dI_m. `scratch` holds
- * hr_loss_scratch_bytes(n_pix) bytes. Images are planar [3, n_pix]. */
-size_t hr_loss_scratch_bytes(int64_t n_pix);
+ * dL/dT (0 with HR_FLAG_DETACH_MASK) and dL/dI_m, laid out like their inputs.
+ * One image of n pixels may be given as sizes = {n, 1}. `scratch` holds
+ * hr_loss_scratch_bytes(sizes, n_images) bytes of device memory (0 = invalid
+ * sizes); its contents need no clearing. Errors: HR_ERR_INVALID_ARGUMENT
+ * (null pointer, n_images < 1, a size < 1, more than 2^40 pixels). */
+size_t hr_loss_scratch_bytes(const int32_t* sizes, int32_t n_images);
 hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* mesh_rgb,
-                         const int32_t* tri_id, const float* target, int64_t n_pix,
-                         float lambda_t, float k, uint32_t flags, float* loss_out,
-                         float* grad_image, float* grad_final_T, float* grad_mesh_rgb,
-                         void* scratch, void* stream);
+                         const int32_t* tri_id, const float* target, const int32_t* sizes,
+                         int32_t n_images, float lambda_t, float k, uint32_t flags,
+                         float* loss_out, float* grad_image, float* grad_final_T,
+                         float* grad_mesh_rgb, void* scratch, void* stream);
 
 /* Mip-Splatting 3D smoothing variance of every Gaussian for a set of
  * training views: scale / nu^2, nu the highest sampling rate fx / z over the
@@ -340,7 +355,8 @@ hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camer
  * loss against `target` (planar, packed like the image), backward into
  * `grads`. The graph is recorded once for fixed shapes and pointers; every
  * hr_batch_launch replays it. hr_batch_create allocates nothing on the
- * device; the graph object itself is host state freed by hr_batch_destroy. */
+ * device; the graph object itself is host state freed by hr_batch_destroy.
+ * loss_scratch holds hr_loss_scratch_bytes() of the cameras' sizes. */
 typedef struct hr_batch hr_batch;
 hr_status hr_batch_create(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
                           int32_t n_cams, const hr_settings* s, int64_t key_capacity,
@@ -349,6 +365,15 @@ hr_status hr_batch_create(const hr_gaussians* g, const hr_mesh* mesh, const hr_c
                           float* grad_image, float* grad_final_T, float* grad_mesh_rgb,
                           void* loss_scratch, hr_grads* grads, void* stream, hr_batch** batch);
 hr_status hr_batch_launch(hr_batch* batch, void* stream);
+/* Outcome of the replays enqueued so far: synchronises `stream` (the one the
+ * graph was launched on), then reads the forward's device flags. Returns
+ * HR_ERR_CAPACITY when the pair count exceeded the key capacity (the step's
+ * outputs and gradients are undefined; stats->n_keys is the needed count:
+ * create the batch again over a workspace with that capacity),
+ * HR_ERR_INTERNAL when a prefix sum's bounded wait gave up, else HR_OK.
+ * `stats` (host memory, nullable) receives the counters of the last replay
+ * (n_processed and n_blended are 0: they are not summed by a replay). */
+hr_status hr_batch_status(hr_batch* batch, hr_stats* stats, void* stream);
 void hr_batch_destroy(hr_batch* batch);
 
 const char* hr_status_string(hr_status s);

@@ -12,7 +12,7 @@
 //   * textured mesh rendered by barycentric UV interpolation     (Sec. 3.1 "Textured mesh")
 //   * joint rasterization: mesh gives I_m and D_m; only Gaussians with
 //     D_gs < D_m are blended; the residual transmittance T weights the mesh
-//     colour, else the background colour                         (Sec. 3.4 "Joint rasterization")
+//     colour, else the background colour                         (Sec. 3.4 "Joint optimization", paragraph "Joint rasterization")
 //   * gradients to Gaussians and texture (texture optimisable, no vertex
 //     optimisation)                                              (Sec. 3.4)
 // Conventions the paper leaves to its 3DGS code base (16 px tiles, 3 sigma

@@ -275,6 +275,35 @@ hr_status hip_check(const char* what) {
   return HR_OK;
 }
 
+// Synchronises `st` and reads the forward's device flags: the key overflow
+// (HR_ERR_CAPACITY, with the needed count) and the scans' wait limit
+// (HR_ERR_INTERNAL). `stats` (host, nullable) receives the counters.
+hr_status read_flags(const Work& w, hipStream_t st, hr_stats* stats) {
+  uint32_t c[6] = {0, 0, 0, 0, 0, 0};
+  uint32_t lim[2] = {0, 0};
+  if (hipMemcpyAsync(c, w.counters, sizeof(c), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&lim[0], (const uint32_t*)w.scan_scratch + 2, 4, hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(&lim[1], (const uint32_t*)w.scan_scratch2 + 2, 4, hipMemcpyDeviceToHost,
+                     st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(HR_ERR_HIP, "flag read-back failed");
+  const uint64_t K = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->n_visible = c[0];
+    stats->n_keys = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
+    stats->overflow = c[1];
+    stats->n_tris = c[4];
+    stats->wait_limit = (lim[0] | lim[1]) ? 1u : 0u;
+  }
+  if (lim[0] | lim[1])
+    return fail(HR_ERR_INTERNAL, "a one-pass prefix sum gave up waiting (bounded wait)");
+  if (c[1])
+    return fail(HR_ERR_CAPACITY, "key capacity too small: " + std::to_string(K) + " pairs");
+  return HR_OK;
+}
+
 void upload_cams(const Plan& p, const Work& w, bool clear_counters, hipStream_t st) {
   for (int64_t c0 = 0; c0 < p.n_cams; c0 += CAMS_PER_UPLOAD) {
     CamUpload u;
@@ -354,7 +383,9 @@ hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const h
   launch_binning(S, w, (int)p.n_cams, cull, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, out, st);
   if (!cull && !ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
   launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
-  if (out->stats) launch_counters_to_stats(w.counters, w.tile_np, (int)S.n_tiles, out->stats, st);
+  if (out->stats)
+    launch_counters_to_stats(w.counters, w.tile_np, (int)S.n_tiles, (const uint32_t*)w.scan_scratch,
+                             (const uint32_t*)w.scan_scratch2, out->stats, st);
   return HR_OK;
 }
 
@@ -433,17 +464,7 @@ hr_status hr_render_hybrid(const hr_gaussians* g, const hr_mesh* mesh, const hr_
   hipGetLastError();
   if ((rc = enqueue_forward(p, w, S, g, mesh, s, out, st)) != HR_OK) return rc;
   if ((rc = hip_check("forward launch")) != HR_OK) return rc;
-  if (!(s->flags & HR_FLAG_NO_SYNC)) {
-    uint32_t c[4];
-    if (hipMemcpyAsync(c, w.counters, sizeof(c), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return fail(HR_ERR_HIP, "capacity check copy failed");
-    if (c[1]) {
-      const uint64_t K = (uint64_t)c[2] | ((uint64_t)c[3] << 32);
-      return fail(HR_ERR_CAPACITY, "key capacity " + std::to_string(key_capacity) +
-                                       " too small: " + std::to_string(K) + " pairs");
-    }
-  }
+  if (!(s->flags & HR_FLAG_NO_SYNC)) return read_flags(w, st, nullptr);
   return HR_OK;
 }
 
@@ -488,21 +509,42 @@ hr_status hr_blend_forward(const hr_gaussians* g, const hr_mesh* mesh, const hr_
   return hip_check("blend launch");
 }
 
-size_t hr_loss_scratch_bytes(int64_t n_pix) {
-  return (size_t)((n_pix + 255) / 256 + 1) * sizeof(double);
+// pixels per image of a loss call; false on invalid sizes
+static bool loss_image_pixels(const int32_t* sizes, int32_t n_images, std::vector<int64_t>& pix,
+                       int64_t& total) {
+  if (!sizes || n_images < 1) return false;
+  pix.resize(n_images);
+  total = 0;
+  for (int i = 0; i < n_images; ++i) {
+    if (sizes[2 * i] < 1 || sizes[2 * i + 1] < 1) return false;
+    pix[i] = (int64_t)sizes[2 * i] * sizes[2 * i + 1];
+    total += pix[i];
+    if (total > ((int64_t)1 << 40)) return false;
+  }
+  return true;
+}
+
+size_t hr_loss_scratch_bytes(const int32_t* sizes, int32_t n_images) {
+  std::vector<int64_t> pix;
+  int64_t total = 0;
+  if (!loss_image_pixels(sizes, n_images, pix, total)) return 0;
+  return loss_scratch_bytes(total, n_images);
 }
 
 hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* mesh_rgb,
-                         const int32_t* tri_id, const float* target, int64_t n_pix,
-                         float lambda_t, float k, uint32_t flags, float* loss_out,
-                         float* grad_image, float* grad_final_T, float* grad_mesh_rgb,
-                         void* scratch, void* stream) {
-  if (n_pix < 1) return fail(HR_ERR_INVALID_ARGUMENT, "n_pix must be >= 1");
+                         const int32_t* tri_id, const float* target, const int32_t* sizes,
+                         int32_t n_images, float lambda_t, float k, uint32_t flags,
+                         float* loss_out, float* grad_image, float* grad_final_T,
+                         float* grad_mesh_rgb, void* scratch, void* stream) {
+  std::vector<int64_t> pix;
+  int64_t total = 0;
+  if (!loss_image_pixels(sizes, n_images, pix, total))
+    return fail(HR_ERR_INVALID_ARGUMENT, "need n_images >= 1 positive image sizes");
   if (!image || !final_T || !mesh_rgb || !tri_id || !target || !loss_out || !grad_image ||
       !grad_final_T || !grad_mesh_rgb || !scratch)
     return fail(HR_ERR_INVALID_ARGUMENT, "null loss argument");
   hipGetLastError();
-  launch_loss(image, final_T, mesh_rgb, tri_id, target, n_pix, lambda_t, k,
+  launch_loss(image, final_T, mesh_rgb, tri_id, target, pix.data(), n_images, lambda_t, k,
               (flags & HR_FLAG_DETACH_MASK) != 0, loss_out, grad_image, grad_final_T,
               grad_mesh_rgb, scratch, (hipStream_t)stream);
   return hip_check("loss launch");
@@ -713,6 +755,7 @@ hr_status hr_autotune_backward(const hr_gaussians* g, const hr_mesh* mesh, const
 struct hr_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  Work w;  // the captured workspace (its counters and scan states hold the flags)
 };
 
 hr_status hr_batch_create(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
@@ -740,6 +783,7 @@ hr_status hr_batch_create(const hr_gaussians* g, const hr_mesh* mesh, const hr_c
   SetDev S = make_setdev(p, g, mesh, s);
   hipGetLastError();
   hr_batch* b = new hr_batch();
+  b->w = w;
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     delete b;
     return fail(HR_ERR_HIP, "hipStreamBeginCapture failed");
@@ -751,9 +795,11 @@ hr_status hr_batch_create(const hr_gaussians* g, const hr_mesh* mesh, const hr_c
     delete b;
     return HR_ERR_HIP;
   }
-  launch_loss(out->image, out->final_T, out->mesh_rgb, out->tri_id, target, p.P, lambda_t, k,
-              (s->flags & HR_FLAG_DETACH_MASK) != 0, loss_out, grad_image, grad_final_T,
-              grad_mesh_rgb, loss_scratch, st);
+  std::vector<int64_t> cam_pix(n_cams);
+  for (int c = 0; c < n_cams; ++c) cam_pix[c] = (int64_t)cams[c].width * cams[c].height;
+  launch_loss(out->image, out->final_T, out->mesh_rgb, out->tri_id, target, cam_pix.data(),
+              n_cams, lambda_t, k, (s->flags & HR_FLAG_DETACH_MASK) != 0, loss_out, grad_image,
+              grad_final_T, grad_mesh_rgb, loss_scratch, st);
   // the step starts from zero gradients
   const int64_t K = (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
   if (grads->means) launch_fill_u32((uint32_t*)grads->means, 0u, 3 * p.n, st);
@@ -790,6 +836,11 @@ hr_status hr_batch_launch(hr_batch* batch, void* stream) {
   hipError_t e = hipGraphLaunch(batch->exec, (hipStream_t)stream);
   if (e != hipSuccess) return fail(HR_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
   return HR_OK;
+}
+
+hr_status hr_batch_status(hr_batch* batch, hr_stats* stats, void* stream) {
+  if (!batch || !batch->exec) return fail(HR_ERR_INVALID_ARGUMENT, "invalid batch");
+  return read_flags(batch->w, (hipStream_t)stream, stats);
 }
 
 void hr_batch_destroy(hr_batch* batch) {

@@ -1,5 +1,5 @@
 // Per-tile front-to-back blending with the mesh depth stop (Sec. 3.1 Eq. 2,
-// Sec. 3.4 "Joint rasterization") and its reverse-order backward.
+// Sec. 3.4 "Joint optimization", paragraph "Joint rasterization") and its reverse-order backward.
 //
 // One 256-thread workgroup (4 waves of 64) per 16x16 tile, one pixel per
 // thread. The tile's depth-ordered list is streamed through LDS in batches of

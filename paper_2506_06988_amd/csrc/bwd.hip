@@ -353,7 +353,11 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
 // ------------------------------------------------------------------ loss --
 constexpr int LB = 256;
 
-__global__ __launch_bounds__(LB) void k_loss(const float* __restrict__ image,
+// Pixel p of the packed images belongs to image i with off[i] <= p < off[i+1];
+// that image's planes are [3, hw_i] starting at float 3 off[i], so channel ch
+// of p sits at 2 off[i] + ch hw_i + p.
+__global__ __launch_bounds__(LB) void k_loss(const int64_t* __restrict__ off, int n_img,
+                                             const float* __restrict__ image,
                                              const float* __restrict__ T,
                                              const float* __restrict__ mesh,
                                              const int32_t* __restrict__ tri,
@@ -366,13 +370,19 @@ __global__ __launch_bounds__(LB) void k_loss(const float* __restrict__ image,
   const int64_t p = (int64_t)blockIdx.x * LB + threadIdx.x;
   double acc = 0.0;
   if (p < n_pix) {
+    int lo = 0, hi = n_img - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    const int64_t o = off[lo], hw = off[lo + 1] - o;
     const float inv = 1.0f / (3.0f * (float)n_pix);
     const bool has = tri[p] >= 0;
     const float t = T[p];
     const float mt = 1.f / (1.f + __expf(-k * (t - 0.5f)));
     float sq = 0.f;
     for (int ch = 0; ch < 3; ++ch) {
-      const int64_t q = ch * n_pix + p;
+      const int64_t q = 2 * o + ch * hw + p;
       const float d = image[q] - target[q];
       acc += fabs((double)d);
       g_image[q] = (d > 0.f ? inv : (d < 0.f ? -inv : 0.f));
@@ -395,6 +405,18 @@ __global__ __launch_bounds__(LB) void k_loss(const float* __restrict__ image,
     for (int w = 0; w < LB / 64; ++w) s += red[w];
     partial[blockIdx.x] = s;
   }
+}
+
+// image offset table by kernel argument (graph-capturable)
+constexpr int OFFS_PER_UPLOAD = 480;
+struct OffUpload {
+  int64_t v[OFFS_PER_UPLOAD];
+  int32_t first, count;
+};
+static_assert(sizeof(OffUpload) + 8 <= 4096, "offset upload must fit in kernel arguments");
+
+__global__ void k_upload_offs(OffUpload u, int64_t* __restrict__ dst) {
+  for (int i = threadIdx.x; i < u.count; i += blockDim.x) dst[u.first + i] = u.v[i];
 }
 
 __global__ __launch_bounds__(LB) void k_loss_final(const double* __restrict__ partial, int64_t nb,
@@ -482,15 +504,37 @@ void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,
                      grad_mesh_rgb, grad_tex);
 }
 
+size_t loss_scratch_bytes(int64_t n_pix, int32_t n_img) {
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  return al(8 * ((size_t)n_img + 1)) + ((size_t)(n_pix + LB - 1) / LB + 1) * sizeof(double);
+}
+
 void launch_loss(const float* image, const float* T, const float* mesh_rgb, const int32_t* tri,
-                 const float* target, int64_t n_pix, float lambda_t, float k, bool detach,
-                 float* loss, float* g_image, float* g_T, float* g_mesh, void* scratch,
-                 hipStream_t st) {
+                 const float* target, const int64_t* img_pix, int32_t n_img, float lambda_t,
+                 float k, bool detach, float* loss, float* g_image, float* g_T, float* g_mesh,
+                 void* scratch, hipStream_t st) {
+  // scratch: image pixel offsets [n_img + 1] | per-workgroup partial sums
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  int64_t* off = (int64_t*)scratch;
+  double* partial = (double*)((char*)scratch + al(8 * ((size_t)n_img + 1)));
+  int64_t n_pix = 0;
+  OffUpload u;
+  u.first = 0;
+  u.count = 0;
+  for (int i = 0; i <= n_img; ++i) {
+    u.v[u.count++] = n_pix;
+    if (i < n_img) n_pix += img_pix[i];
+    if (u.count == OFFS_PER_UPLOAD || i == n_img) {
+      hipLaunchKernelGGL(k_upload_offs, dim3(1), dim3(256), 0, st, u, off);
+      u.first += u.count;
+      u.count = 0;
+    }
+  }
   const int64_t nb = (n_pix + LB - 1) / LB;
-  double* partial = (double*)scratch;
   if (nb > 0)
-    hipLaunchKernelGGL(k_loss, dim3((unsigned)nb), dim3(LB), 0, st, image, T, mesh_rgb, tri, target,
-                       n_pix, lambda_t, k, detach ? 1 : 0, g_image, g_T, g_mesh, partial);
+    hipLaunchKernelGGL(k_loss, dim3((unsigned)nb), dim3(LB), 0, st, (const int64_t*)off, n_img,
+                       image, T, mesh_rgb, tri, target, n_pix, lambda_t, k, detach ? 1 : 0,
+                       g_image, g_T, g_mesh, partial);
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LB), 0, st, partial, nb, n_pix, loss);
 }
 

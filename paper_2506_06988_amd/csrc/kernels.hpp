@@ -85,10 +85,12 @@ void launch_project_backward(const SetDev& S, const CamDev* cams, const hr_gauss
 void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,
                              const float* grad_image, const float* grad_mesh_rgb, float* grad_tex,
                              hipStream_t st);
+// loss over n_img packed planar images of img_pix[i] pixels each (host array)
+size_t loss_scratch_bytes(int64_t n_pix, int32_t n_img);
 void launch_loss(const float* image, const float* T, const float* mesh_rgb, const int32_t* tri,
-                 const float* target, int64_t n_pix, float lambda_t, float k, bool detach,
-                 float* loss, float* g_image, float* g_T, float* g_mesh, void* scratch,
-                 hipStream_t st);
+                 const float* target, const int64_t* img_pix, int32_t n_img, float lambda_t,
+                 float k, bool detach, float* loss, float* g_image, float* g_T, float* g_mesh,
+                 void* scratch, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void launch_adam(const hr_adam_group* groups, int n_groups, double b1, double b2, double eps,
                  int step, hipStream_t st);
@@ -109,8 +111,10 @@ void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32
                         uint32_t* clear3, int64_t n2, hipStream_t st);
 void launch_mip_filter3d(const float* means, int n, const CamDev* cams, int n_cams, float near,
                          double scale, float* f3, hipStream_t st);
+// scan1, scan2: the two scan scratch states (word 2 = bounded wait gave up)
 void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,
-                              hr_stats* stats, hipStream_t st);
+                              const uint32_t* scan1, const uint32_t* scan2, hr_stats* stats,
+                              hipStream_t st);
 void launch_zero_gacc(float* gacc, const uint32_t* counters, hipStream_t st);
 void launch_count_mismatch(const float* a, const float* b, int64_t n, uint32_t* out,
                            hipStream_t st);

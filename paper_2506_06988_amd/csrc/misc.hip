@@ -25,6 +25,8 @@ __global__ void k_upload_cams(CamUpload u, CamDev* dst, uint32_t* clear, uint32_
 __global__ __launch_bounds__(1024) void k_counters_to_stats(const uint32_t* __restrict__ c,
                                                             const uint64_t* __restrict__ tile_np,
                                                             int n_tiles,
+                                                            const uint32_t* __restrict__ scan1,
+                                                            const uint32_t* __restrict__ scan2,
                                                             hr_stats* __restrict__ s) {
   __shared__ unsigned long long part[2][16];
   // one 16-byte load per tile, four tiles in flight per thread
@@ -71,6 +73,8 @@ __global__ __launch_bounds__(1024) void k_counters_to_stats(const uint32_t* __re
   s->n_tris = c[4];
   s->n_processed = sp;
   s->n_blended = sb;
+  s->wait_limit = (scan1[2] | scan2[2]) != 0u ? 1u : 0u;
+  s->reserved = 0u;
 }
 
 // clears the [n_visible][9] gradient accumulators
@@ -98,9 +102,10 @@ void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32
 }
 
 void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,
-                              hr_stats* stats, hipStream_t st) {
+                              const uint32_t* scan1, const uint32_t* scan2, hr_stats* stats,
+                              hipStream_t st) {
   hipLaunchKernelGGL(k_counters_to_stats, dim3(1), dim3(1024), 0, st, counters, tile_np, n_tiles,
-                     stats);
+                     scan1, scan2, stats);
 }
 
 void launch_zero_gacc(float* gacc, const uint32_t* counters, hipStream_t st) {

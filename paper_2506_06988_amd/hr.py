@@ -70,7 +70,8 @@ class hr_adam_group(C.Structure):
 EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid",
             "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
             "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_mip_filter3d", "hr_autotune", "hr_autotune_backward",
-            "hr_batch_create", "hr_batch_launch", "hr_batch_destroy", "hr_status_string",
+            "hr_batch_create", "hr_batch_launch", "hr_batch_status", "hr_batch_destroy",
+            "hr_status_string",
             "hr_last_error", "hr_abi_version"]
 
 _lib = None
@@ -96,10 +97,10 @@ def load(path: str = LIB_PATH):
     L.hr_blend_forward.restype = C.c_int
     L.hr_blend_forward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P]
     L.hr_loss_scratch_bytes.restype = C.c_size_t
-    L.hr_loss_scratch_bytes.argtypes = [C.c_int64]
+    L.hr_loss_scratch_bytes.argtypes = [P, C.c_int32]
     L.hr_hybrid_loss.restype = C.c_int
-    L.hr_hybrid_loss.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_uint32, P, P,
-                                 P, P, P, P]
+    L.hr_hybrid_loss.argtypes = [P, P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_uint32, P,
+                                 P, P, P, P, P]
     L.hr_mip_filter3d.restype = C.c_int
     L.hr_mip_filter3d.argtypes = [P, P, C.c_int32, P, C.c_double, P, P]
     L.hr_adam_step.restype = C.c_int
@@ -119,6 +120,8 @@ def load(path: str = LIB_PATH):
                                   C.c_float, P, P, P, P, P, P, P, P]
     L.hr_batch_launch.restype = C.c_int
     L.hr_batch_launch.argtypes = [P, P]
+    L.hr_batch_status.restype = C.c_int
+    L.hr_batch_status.argtypes = [P, P, P]
     L.hr_batch_destroy.restype = None
     L.hr_batch_destroy.argtypes = [P]
     L.hr_status_string.restype = C.c_char_p
@@ -287,17 +290,44 @@ class Frame:
                 sl(self.n_blended), sl(self.n_processed))
 
     def stats_dict(self):
-        s = self.stats.cpu().numpy().view(np.uint32)
-        return dict(n_visible=int(s[0]), n_keys=int(s[1]), overflow=int(s[2]), n_tris=int(s[3]),
-                    n_processed=int(s[4]) | (int(s[5]) << 32), n_blended=int(s[6]) | (int(s[7]) << 32))
+        return stats_to_dict(self.stats.cpu().numpy())
+
+
+class hr_stats(C.Structure):
+    _fields_ = [("n_visible", C.c_uint32), ("n_keys", C.c_uint32), ("overflow", C.c_uint32),
+                ("n_tris", C.c_uint32), ("n_processed", C.c_uint64), ("n_blended", C.c_uint64),
+                ("wait_limit", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+STATS_WORDS = C.sizeof(hr_stats) // 8
+
+
+def stats_to_dict(raw) -> dict:
+    st = hr_stats.from_buffer_copy(np.ascontiguousarray(raw).tobytes()[:C.sizeof(hr_stats)])
+    return {k: int(getattr(st, k)) for k, _ in hr_stats._fields_ if k != "reserved"}
+
+
+@dataclasses.dataclass
+class Context:
+    """What one forward leaves for its backward: the Gaussian and texture
+    tensors it read, its workspace (the library's saved context), the key
+    capacity and settings that workspace was laid out for, and the cameras."""
+    g: DevGaussians
+    tex: Optional["torch.Tensor"]
+    ws: "torch.Tensor"
+    key_capacity: int
+    settings: hr_settings
+    cam_arr: "C.Array"
+    n_cams: int
 
 
 class Renderer:
-    """Owns the workspace of one scene/camera configuration."""
+    """One scene/camera configuration: its Gaussians, mesh, cameras, settings and
+    a reusable workspace. The autograd path (`forward_context`) gives every
+    forward a workspace of its own instead."""
 
     def __init__(self, gaussians: DevGaussians, mesh: Optional[DevMesh], cams, settings=None,
                  key_capacity: Optional[int] = None):
-        import torch
         self.L = load()
         self.g = gaussians
         self.mesh = mesh
@@ -314,23 +344,36 @@ class Renderer:
         self.ws = None
         self._alloc_ws()
 
-    def _structs(self, tex=None):
-        gs = self.g.struct()
+    @property
+    def sizes(self):
+        return [(int(c.width), int(c.height)) for c in self.cams]
+
+    def _structs(self, tex=None, g=None):
+        gs = (self.g if g is None else g).struct()
         ms = self.mesh.struct(tex) if self.mesh is not None else empty_mesh_struct()
         return gs, ms
 
-    def _alloc_ws(self):
-        import torch
-        gs, ms = self._structs()
-        nbytes = self.L.hr_query_workspace(C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams),
-                                           C.byref(self.settings), self.key_capacity)
+    def workspace_bytes(self, key_capacity=None, g=None) -> int:
+        gs, ms = self._structs(g=g)
+        cap = self.key_capacity if key_capacity is None else int(key_capacity)
+        nbytes = int(self.L.hr_query_workspace(C.byref(gs), C.byref(ms), self.cam_arr,
+                                               len(self.cams), C.byref(self.settings), cap))
         if nbytes == 0:
             raise HRError(HR_ERR_INVALID_ARGUMENT, self.L.hr_last_error().decode())
+        return nbytes
+
+    def _alloc_ws(self):
+        import torch
+        nbytes = self.workspace_bytes()
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = None
-            torch.cuda.empty_cache() if self.ws is not None else None
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.ws_bytes = int(self.ws.numel())
+
+    def grow_capacity(self, needed: int):
+        """Key capacity for `needed` pairs plus a quarter; regrows the workspace."""
+        self.key_capacity = int(min(0xffffffff, int(needed) * 5 // 4 + 1024))
+        self._alloc_ws()
 
     def new_frame(self, export_keys=False) -> Frame:
         import torch
@@ -345,7 +388,7 @@ class Renderer:
                   n_blended=torch.empty(P, dtype=torch.int32, device=d),
                   n_processed=torch.empty(P, dtype=torch.int32, device=d),
                   radii=torch.empty(max(1, n * len(self.cams)), dtype=torch.int32, device=d),
-                  stats=torch.zeros(4, dtype=torch.int64, device=d), offsets=self.offsets)
+                  stats=torch.zeros(STATS_WORDS, dtype=torch.int64, device=d), offsets=self.offsets)
         if export_keys:
             f.keys = torch.empty(self.key_capacity, dtype=torch.int64, device=d)
             f.values = torch.empty(self.key_capacity, dtype=torch.int32, device=d)
@@ -361,53 +404,88 @@ class Renderer:
         o.stats = _ptr(f.stats)
         return o
 
+    def _forward(self, f: Frame, g: DevGaussians, tex, ws, cap: int, sync_check: bool):
+        gs, ms = self._structs(tex, g)
+        o = self.outputs_struct(f)
+        s = hr_settings.from_buffer_copy(self.settings)
+        if not sync_check:
+            s.flags |= HR_FLAG_NO_SYNC
+        return self.L.hr_render_hybrid(C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams),
+                                       C.byref(s), int(cap), _ptr(ws), int(ws.numel()), C.byref(o),
+                                       _stream())
+
     def render_hybrid(self, frame: Optional[Frame] = None, export_keys=False, tex=None,
                       sync_check=True) -> Frame:
-        """hr_render_hybrid; grows the key capacity and retries on HR_ERR_CAPACITY."""
+        """hr_render_hybrid into the renderer's workspace; grows the key capacity
+        and retries on HR_ERR_CAPACITY."""
         f = frame if frame is not None else self.new_frame(export_keys)
         for _ in range(3):
-            gs, ms = self._structs(tex)
-            o = self.outputs_struct(f)
-            s = hr_settings.from_buffer_copy(self.settings)
-            if not sync_check:
-                s.flags |= HR_FLAG_NO_SYNC
-            rc = self.L.hr_render_hybrid(C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams),
-                                         C.byref(s), self.key_capacity, _ptr(self.ws),
-                                         self.ws_bytes, C.byref(o), _stream())
+            rc = self._forward(f, self.g, tex, self.ws, self.key_capacity, sync_check)
             if rc != HR_ERR_CAPACITY:
                 check(rc)
                 return f
-            need = f.stats_dict()["n_keys"]
-            self.key_capacity = int(min(0xffffffff, need * 5 // 4 + 1024))
-            self._alloc_ws()
+            self.grow_capacity(f.stats_dict()["n_keys"])
             if export_keys:
                 f = self.new_frame(export_keys)
         raise HRError(HR_ERR_CAPACITY, "key capacity did not converge")
 
-    def render_hybrid_backward(self, grad_image, grad_final_T=None, grad_mesh_rgb=None, grads=None,
-                               tex=None):
-        """hr_render_hybrid_backward; returns a dict of gradient tensors (accumulated into `grads`)."""
+    def forward_context(self, g: DevGaussians, tex=None):
+        """hr_render_hybrid of Gaussians `g` (and texture `tex`) into a workspace
+        of its own; the renderer's Gaussians and workspace are left as they are.
+        Returns (frame, Context) for backward_context."""
         import torch
-        d = self.device
-        if grads is None:
-            grads = dict(means=torch.zeros_like(self.g.means), log_scales=torch.zeros_like(self.g.log_scales),
-                         quats=torch.zeros_like(self.g.quats),
-                         opacity_logits=torch.zeros_like(self.g.opacity_logits),
-                         sh=torch.zeros_like(self.g.sh))
-            if self.mesh is not None:
-                grads["tex"] = torch.zeros_like(self.mesh.tex if tex is None else tex)
+        f = self.new_frame()
+        cap = self.key_capacity
+        for _ in range(3):
+            ws = torch.empty(self.workspace_bytes(cap, g), dtype=torch.uint8, device=self.device)
+            rc = self._forward(f, g, tex, ws, cap, True)
+            if rc != HR_ERR_CAPACITY:
+                check(rc)
+                ctx = Context(g, tex, ws, cap, hr_settings.from_buffer_copy(self.settings),
+                              self.cam_arr, len(self.cams))
+                return f, ctx
+            cap = int(min(0xffffffff, f.stats_dict()["n_keys"] * 5 // 4 + 1024))
+            self.key_capacity = max(self.key_capacity, cap)  # a hint for later forwards
+        raise HRError(HR_ERR_CAPACITY, "key capacity did not converge")
+
+    def _zero_grads(self, g: DevGaussians, tex=None):
+        import torch
+        grads = dict(means=torch.zeros_like(g.means), log_scales=torch.zeros_like(g.log_scales),
+                     quats=torch.zeros_like(g.quats),
+                     opacity_logits=torch.zeros_like(g.opacity_logits), sh=torch.zeros_like(g.sh))
+        if self.mesh is not None:
+            grads["tex"] = torch.zeros_like(self.mesh.tex if tex is None else tex)
+        return grads
+
+    def _backward(self, g, tex, ws, cap, settings, cam_arr, n_cams, grad_image, grad_final_T,
+                  grad_mesh_rgb, grads):
         gr = hr_grads()
         for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex", "mean2d_norm",
                   "mean2d_count"):
             setattr(gr, k, _ptr(grads.get(k)))
-        gs, ms = self._structs(tex)
+        gs, ms = self._structs(tex, g)
         check(self.L.hr_render_hybrid_backward(
-            C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams), C.byref(self.settings),
-            self.key_capacity, _ptr(self.ws), self.ws_bytes, _ptr(grad_image.contiguous()),
+            C.byref(gs), C.byref(ms), cam_arr, n_cams, C.byref(settings), int(cap), _ptr(ws),
+            int(ws.numel()), _ptr(grad_image.contiguous()),
             _ptr(None if grad_final_T is None else grad_final_T.contiguous()),
             _ptr(None if grad_mesh_rgb is None else grad_mesh_rgb.contiguous()), C.byref(gr),
             _stream()))
         return grads
+
+    def render_hybrid_backward(self, grad_image, grad_final_T=None, grad_mesh_rgb=None, grads=None,
+                               tex=None):
+        """hr_render_hybrid_backward of the last render_hybrid; returns a dict of
+        gradient tensors (accumulated into `grads`)."""
+        grads = self._zero_grads(self.g, tex) if grads is None else grads
+        return self._backward(self.g, tex, self.ws, self.key_capacity, self.settings, self.cam_arr,
+                              len(self.cams), grad_image, grad_final_T, grad_mesh_rgb, grads)
+
+    def backward_context(self, ctx: Context, grad_image, grad_final_T=None, grad_mesh_rgb=None,
+                         grads=None):
+        """hr_render_hybrid_backward of the forward that produced `ctx`."""
+        grads = self._zero_grads(ctx.g, ctx.tex) if grads is None else grads
+        return self._backward(ctx.g, ctx.tex, ctx.ws, ctx.key_capacity, ctx.settings, ctx.cam_arr,
+                              ctx.n_cams, grad_image, grad_final_T, grad_mesh_rgb, grads)
 
     def set_cameras(self, cams):
         """Switch to other cameras of the same sizes (the workspace is reused)."""
@@ -443,19 +521,36 @@ class Renderer:
         return int(self.settings.batch_bwd), int(self.settings.variant)
 
 
-def hybrid_loss(image, final_T, mesh_rgb, tri_id, target, lambda_t=0.1, k=20.0, detach_mask=False):
-    """hr_hybrid_loss over packed planar buffers; returns (loss, g_image, g_T, g_mesh_rgb)."""
+def _sizes_array(sizes):
+    return (C.c_int32 * (2 * len(sizes)))(*[int(v) for wh in sizes for v in wh])
+
+
+def loss_scratch_bytes(sizes) -> int:
+    nb = int(load().hr_loss_scratch_bytes(_sizes_array(sizes), len(sizes)))
+    if nb == 0:
+        raise HRError(HR_ERR_INVALID_ARGUMENT, "invalid image sizes")
+    return nb
+
+
+def hybrid_loss(image, final_T, mesh_rgb, tri_id, target, sizes=None, lambda_t=0.1, k=20.0,
+                detach_mask=False):
+    """hr_hybrid_loss over images packed like the renderer's outputs; `sizes` is
+    the (width, height) of each image (default: one planar image of all pixels).
+    Returns (loss, g_image, g_T, g_mesh_rgb)."""
     import torch
     L = load()
     n_pix = int(final_T.numel())
+    sizes = [(n_pix, 1)] if sizes is None else [(int(w), int(h)) for (w, h) in sizes]
+    assert sum(w * h for w, h in sizes) == n_pix, "sizes do not cover the pixels"
     d = image.device
     loss = torch.zeros(1, dtype=torch.float32, device=d)
     gi = torch.empty_like(image)
     gt = torch.empty_like(final_T)
     gm = torch.empty_like(mesh_rgb)
-    scratch = torch.empty(int(L.hr_loss_scratch_bytes(n_pix)), dtype=torch.uint8, device=d)
+    scratch = torch.empty(loss_scratch_bytes(sizes), dtype=torch.uint8, device=d)
+    sz = _sizes_array(sizes)
     check(L.hr_hybrid_loss(_ptr(image), _ptr(final_T), _ptr(mesh_rgb), _ptr(tri_id), _ptr(target),
-                           n_pix, float(lambda_t), float(k),
+                           sz, len(sizes), float(lambda_t), float(k),
                            HR_FLAG_DETACH_MASK if detach_mask else 0, _ptr(loss), _ptr(gi), _ptr(gt),
                            _ptr(gm), _ptr(scratch), _stream()))
     return loss, gi, gt, gm
@@ -498,7 +593,7 @@ def full_loss(image, final_T, mesh_rgb, tri_id, target, sizes, lambda_c=0.2, lam
     given (width, height) sizes; returns (loss, g_image, g_T, g_mesh_rgb)."""
     import torch
     L = load()
-    sz = (C.c_int32 * (2 * len(sizes)))(*[int(v) for wh in sizes for v in wh])
+    sz = _sizes_array(sizes)
     d = image.device
     loss = torch.zeros(1, dtype=torch.float32, device=d)
     gi = torch.empty_like(image)
@@ -520,37 +615,70 @@ def _autograd_fn():
     import torch
 
     class HybridRenderFn(torch.autograd.Function):
-        """(means, log_scales, quats, opacity_logits, sh, tex) -> (image, final_T, mesh_rgb).
+        """(renderer, means, log_scales, quats, opacity_logits, sh, tex)
+        -> (image, final_T, mesh_rgb, tri_id), packed over the renderer's cameras.
 
-        All three outputs are differentiable: T through the transmittance-aware
-        loss, I_m into the texture. Counters and mesh buffers stay in the Frame.
-        """
+        image, final_T and mesh_rgb are differentiable (T through the
+        transmittance-aware loss, I_m into the texture); tri_id is not. Each
+        call renders into a workspace of its own, kept in ctx with the tensors
+        it read, so several forwards may precede their backwards. The renderer
+        supplies the mesh, cameras and settings and is not modified (except
+        for its key-capacity hint)."""
 
         @staticmethod
         def forward(ctx, renderer, means, log_scales, quats, opacity_logits, sh, tex):
-            renderer.g = DevGaussians(means.detach().contiguous(), log_scales.detach().contiguous(),
-                                      quats.detach().contiguous(), opacity_logits.detach().contiguous(),
-                                      sh.detach().contiguous(), renderer.g.sh_degree,
-                                      renderer.g.filter3d)
+            g = DevGaussians(means.detach().contiguous(), log_scales.detach().contiguous(),
+                             quats.detach().contiguous(), opacity_logits.detach().contiguous(),
+                             sh.detach().contiguous(), renderer.g.sh_degree, renderer.g.filter3d)
             t = None if tex is None else tex.detach().contiguous()
-            f = renderer.render_hybrid(tex=t)
+            f, c = renderer.forward_context(g, t)
             ctx.renderer = renderer
-            ctx.tex = t
-            ctx.frame = f
-            return f.image, f.final_T, f.mesh_rgb
+            ctx.hr_ctx = c
+            ctx.mark_non_differentiable(f.tri_id)
+            return f.image, f.final_T, f.mesh_rgb, f.tri_id
 
         @staticmethod
-        def backward(ctx, g_image, g_T, g_mesh):
-            r = ctx.renderer
-            z = lambda g, like: torch.zeros_like(like) if g is None else g
-            grads = r.render_hybrid_backward(z(g_image, ctx.frame.image), g_T, g_mesh, tex=ctx.tex)
+        def backward(ctx, g_image, g_T, g_mesh, g_tri):
+            c = ctx.hr_ctx
+            if g_image is None:
+                g_image = torch.zeros(3 * ctx.renderer.P, dtype=torch.float32,
+                                      device=c.g.means.device)
+            grads = ctx.renderer.backward_context(c, g_image, g_T, g_mesh)
+            ctx.hr_ctx = None  # the workspace is released with the graph
             return (None, grads["means"], grads["log_scales"], grads["quats"],
                     grads["opacity_logits"], grads["sh"], grads.get("tex"))
 
     return HybridRenderFn
 
 
+def _loss_fn():
+    import torch
+
+    class HybridLossFn(torch.autograd.Function):
+        """(image, final_T, mesh_rgb, tri_id, target, sizes, lambda_t, k, detach_mask)
+        -> loss [1]: hr_hybrid_loss; its backward scales the kernel's dL/dI_h,
+        dL/dT and dL/dI_m by the incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, image, final_T, mesh_rgb, tri_id, target, sizes=None, lambda_t=0.1,
+                    k=20.0, detach_mask=False):
+            L, gi, gt, gm = hybrid_loss(image.detach().contiguous(), final_T.detach().contiguous(),
+                                        mesh_rgb.detach().contiguous(), tri_id.contiguous(),
+                                        target.detach().contiguous(), sizes, lambda_t, k,
+                                        detach_mask)
+            ctx.save_for_backward(gi, gt, gm)
+            return L
+
+        @staticmethod
+        def backward(ctx, g):
+            gi, gt, gm = ctx.saved_tensors
+            return (gi * g, gt * g, gm * g, None, None, None, None, None, None)
+
+    return HybridLossFn
+
+
 _HybridRenderFn = None
+_HybridLossFn = None
 
 
 def HybridRenderFn():
@@ -560,9 +688,22 @@ def HybridRenderFn():
     return _HybridRenderFn
 
 
+def HybridLossFn():
+    global _HybridLossFn
+    if _HybridLossFn is None:
+        _HybridLossFn = _loss_fn()
+    return _HybridLossFn
+
+
 # ---------------------------------------------------------- batched graph --
 class BatchedStep:
-    """hr_batch_create / hr_batch_launch: forward + loss + backward in one hipGraph."""
+    """hr_batch_create / hr_batch_launch / hr_batch_status: forward + loss +
+    backward of all the renderer's cameras in one hipGraph.
+
+    `launch()` replays the graph; `check()` waits for it and reads the
+    forward's device flags; `step()` does both and, when the pair count
+    outgrew the key capacity, regrows the renderer's workspace, captures the
+    graph again and replays it."""
 
     def __init__(self, renderer: Renderer, target, lambda_t=0.1, k=20.0, stream=None):
         import torch
@@ -570,20 +711,23 @@ class BatchedStep:
         self.r = r
         self.L = load()
         d = r.device
+        self.lambda_t, self.k = float(lambda_t), float(k)
         self.frame = r.new_frame()
         self.target = target.contiguous()
         self.loss = torch.zeros(1, dtype=torch.float32, device=d)
         self.g_image = torch.empty(3 * r.P, dtype=torch.float32, device=d)
         self.g_T = torch.empty(r.P, dtype=torch.float32, device=d)
         self.g_mesh = torch.empty(3 * r.P, dtype=torch.float32, device=d)
-        self.scratch = torch.empty(int(self.L.hr_loss_scratch_bytes(r.P)), dtype=torch.uint8, device=d)
-        self.grads = dict(means=torch.zeros_like(r.g.means), log_scales=torch.zeros_like(r.g.log_scales),
-                          quats=torch.zeros_like(r.g.quats),
-                          opacity_logits=torch.zeros_like(r.g.opacity_logits),
-                          sh=torch.zeros_like(r.g.sh))
-        if r.mesh is not None:
-            self.grads["tex"] = torch.zeros_like(r.mesh.tex)
+        self.scratch = torch.empty(loss_scratch_bytes(r.sizes), dtype=torch.uint8, device=d)
+        self.grads = r._zero_grads(r.g)
         self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.recaptures = 0
+        self.handle = None
+        self._capture()
+
+    def _capture(self):
+        import torch
+        r = self.r
         gr = hr_grads()
         for k_ in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex"):
             setattr(gr, k_, _ptr(self.grads.get(k_)))
@@ -596,7 +740,7 @@ class BatchedStep:
         torch.cuda.synchronize()
         check(self.L.hr_batch_create(C.byref(gs), C.byref(ms), r.cam_arr, len(r.cams), C.byref(s),
                                      r.key_capacity, _ptr(r.ws), r.ws_bytes, C.byref(o),
-                                     _ptr(self.target), float(lambda_t), float(k), _ptr(self.loss),
+                                     _ptr(self.target), self.lambda_t, self.k, _ptr(self.loss),
                                      _ptr(self.g_image), _ptr(self.g_T), _ptr(self.g_mesh),
                                      _ptr(self.scratch), C.byref(gr),
                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
@@ -604,6 +748,29 @@ class BatchedStep:
 
     def launch(self):
         check(self.L.hr_batch_launch(self.handle, C.c_void_p(self.stream.cuda_stream)))
+
+    def check(self) -> dict:
+        """hr_batch_status: waits for the replays and raises HRError on a flag."""
+        st = hr_stats()
+        rc = self.L.hr_batch_status(self.handle, C.byref(st), C.c_void_p(self.stream.cuda_stream))
+        self.last_stats = {k: int(getattr(st, k)) for k, _ in hr_stats._fields_ if k != "reserved"}
+        check(rc)
+        return self.last_stats
+
+    def step(self, max_recaptures=3):
+        """One checked replay; on HR_ERR_CAPACITY regrow, re-capture and replay."""
+        for _ in range(max_recaptures + 1):
+            self.launch()
+            try:
+                return self.check()
+            except HRError as e:
+                if e.status != HR_ERR_CAPACITY:
+                    raise
+                self.close()
+                self.r.grow_capacity(self.last_stats["n_keys"])
+                self._capture()
+                self.recaptures += 1
+        raise HRError(HR_ERR_CAPACITY, "key capacity did not converge")
 
     def close(self):
         if self.handle:

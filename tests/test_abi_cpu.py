@@ -22,7 +22,8 @@ def test_library_exports_every_declared_function():
     assert "hr_render_hybrid" in names and "hr_render_hybrid_backward" in names
     for n in names:
         assert hasattr(L, n), n
-    assert L.hr_abi_version() == 1
+    assert L.hr_abi_version() == 2
+    assert set(names) <= set(hr.EXPORTED) | {"hr_default_settings"}
 
 
 def _structs(n=10, deg=0, faces=0):
@@ -113,3 +114,37 @@ def test_bench_refuses_several_gpus(n):
     assert r.returncode == 2
     assert "one GPU only" in r.stderr and f"asked for {n}" in r.stderr
     assert r.stdout == ""
+
+
+def test_loss_sizes_and_arguments_are_checked_on_the_host():
+    """hr_loss_scratch_bytes / hr_hybrid_loss: image sizes per packed image,
+    rejected before any launch when invalid."""
+    L = hr.load()
+    sz = hr._sizes_array([(37, 29), (64, 48)])
+    nb = L.hr_loss_scratch_bytes(sz, 2)
+    P = 37 * 29 + 64 * 48
+    # the image table (3 offsets) plus one double per 256-pixel workgroup and one more
+    assert nb >= 3 * 8 + ((P + 255) // 256 + 1) * 8
+    assert L.hr_loss_scratch_bytes(hr._sizes_array([(0, 5)]), 1) == 0
+    assert L.hr_loss_scratch_bytes(sz, 0) == 0
+    assert L.hr_loss_scratch_bytes(None, 1) == 0
+    rc = L.hr_hybrid_loss(4096, 4096, 4096, 4096, 4096, hr._sizes_array([(5, -1)]), 1, 0.1, 20.0,
+                          0, 4096, 4096, 4096, 4096, 4096, None)
+    assert rc == hr.HR_ERR_INVALID_ARGUMENT and b"size" in L.hr_last_error()
+    rc = L.hr_hybrid_loss(4096, None, 4096, 4096, 4096, sz, 2, 0.1, 20.0, 0, 4096, 4096, 4096,
+                          4096, 4096, None)
+    assert rc == hr.HR_ERR_INVALID_ARGUMENT and b"null" in L.hr_last_error()
+
+
+def test_stats_layout_and_batch_status_argument_check():
+    L = hr.load()
+    assert C.sizeof(hr.hr_stats) == 40 and hr.STATS_WORDS == 5
+    raw = np.zeros(5, np.int64)
+    raw.view(np.uint32)[[0, 1, 2, 3]] = (7, 9, 1, 4)
+    raw[2], raw[3] = 123, 45
+    raw.view(np.uint32)[8] = 1
+    d = hr.stats_to_dict(raw)
+    assert d == dict(n_visible=7, n_keys=9, overflow=1, n_tris=4, n_processed=123, n_blended=45,
+                     wait_limit=1)
+    st = hr.hr_stats()
+    assert L.hr_batch_status(None, C.byref(st), None) == hr.HR_ERR_INVALID_ARGUMENT

@@ -1,27 +1,22 @@
 """Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
 
 Bars: integers (tile keys, ranges, triangle ids, per-pixel counts) bit-exact;
-images and T within 1e-4 absolute; gradients within 1e-3 relative. Pixels
+images and T within 1e-4 absolute; gradients within 1e-3 relative. A pixel
 where the oracle finds a floating-point decision (alpha vs 1/255, T vs 1e-4)
-closer than the FP32 kernel can resolve are tagged ambiguous, excluded from
-the exact checks and counted.
+closer than the FP32 kernel can resolve must equal one of the oracle's
+outcomes of that decision taken either way; pixels next to a projection or
+mesh-depth rounding boundary are left out of the blend checks and counted.
 """
-import sys
-
 import numpy as np
 import pytest
 
 import oracle
+from helpers import check_pixels, grad_compare, say
 from paper_2506_06988_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def gpu_render(hr, scene, cams=None, export_keys=False, settings=None, key_capacity=None):
@@ -34,36 +29,26 @@ def gpu_render(hr, scene, cams=None, export_keys=False, settings=None, key_capac
 
 
 def check_view(f, cams, c, orc, amb_frac_max=None, img_tol=1e-4):
-    im, T, mr, md, tri, nc, nb, npro = [x.cpu().numpy() for x in f.view(c, cams)]
-    amb = orc["amb"] != 0
-    mesh_amb = (orc["amb"] & 16) != 0
-    frac = amb.mean()
-    say(f"view {c}: {cams[c].width}x{cams[c].height} ambiguous px {amb.sum()} ({frac:.2e})")
+    """Every pixel of camera c against the oracle (see helpers.check_pixels):
+    FP64-path pixels exactly, pixels with an ambiguous alpha-skip or T-stop
+    decision against the oracle's outcomes of those decisions taken either
+    way; only pixels near a projection or mesh rounding boundary are left out
+    of the blend checks, and those must stay rare."""
+    view = [x.cpu().numpy() for x in f.view(c, cams)]
+    hard, soft = check_pixels(view, orc, img_tol)
+    n = orc["amb"].size
+    say(f"view {c}: {cams[c].width}x{cams[c].height} ambiguous px: {soft} checked by paths, "
+        f"{hard} left out ({hard / n:.2e})")
     if amb_frac_max is None:
-        # each examined pair lands in an alpha slack band of relative width
-        # 2e-5 with probability ~0.17 * 2e-5; add the T-stop band
-        amb_frac_max = 1e-3 + 1e-5 * float(orc["n_processed"].mean())
-    assert frac <= amb_frac_max
-    np.testing.assert_array_equal(tri, orc["tri_id"])
-    ok = ~mesh_amb
-    np.testing.assert_array_equal(md[ok], orc["mesh_depth"][ok])
-    np.testing.assert_allclose(mr, orc["mesh_rgb"], atol=1e-5)
-    good = ~amb
-    d_img = np.abs(im - orc["image"])[:, good]
-    d_T = np.abs(T - orc["final_T"])[good]
-    say(f"  max |image| diff {d_img.max() if d_img.size else 0:.2e}, max |T| diff {d_T.max() if d_T.size else 0:.2e}")
-    assert d_img.size == 0 or d_img.max() <= img_tol
-    assert d_T.size == 0 or d_T.max() <= img_tol
-    np.testing.assert_array_equal(nc[good], orc["n_contrib"][good])
-    np.testing.assert_array_equal(nb[good], orc["n_blended"][good])
-    np.testing.assert_array_equal(npro[good], orc["n_processed"][good])
+        amb_frac_max = 1e-3
+    assert hard <= amb_frac_max * n
 
 
 def test_config1_forward_matches_oracle(hr):
     say("case: config1 forward")
     sc = scenes.config1()
     r, f = gpu_render(hr, sc)
-    orc = oracle.render(sc.gaussians, sc.mesh, sc.cameras[0])
+    orc = oracle.render(sc.gaussians, sc.mesh, sc.cameras[0], alts=True)
     check_view(f, sc.cameras, 0, orc)
     st = f.stats_dict()
     say("stats", st)
@@ -101,7 +86,7 @@ def test_small_room_three_uneven_cameras_in_one_call(hr, seed, variant):
     keys = f.keys.cpu().numpy().view(np.uint64)
     vals = f.values.cpu().numpy().view(np.uint32)
     for c, cam in enumerate(cams):
-        orc = oracle.render(sc.gaussians, sc.mesh, cam)
+        orc = oracle.render(sc.gaussians, sc.mesh, cam, alts=True)
         check_view(f, cams, c, orc)
         k, v, rg = oracle.keys(sc.gaussians, cam)
         ntl = rg.shape[0]
@@ -125,7 +110,7 @@ def test_many_rank_windows_and_pair_slices(hr):
     st = f.stats_dict()
     say("stats", st)
     assert st["n_visible"] > 8192 and st["n_keys"] > 4 * 8192
-    check_view(f, sc.cameras, 0, oracle.render(sc.gaussians, sc.mesh, sc.cameras[0]))
+    check_view(f, sc.cameras, 0, oracle.render(sc.gaussians, sc.mesh, sc.cameras[0], alts=True))
     k, v, rg = oracle.keys(sc.gaussians, sc.cameras[0])
     K = len(k)
     np.testing.assert_array_equal(f.keys[:K].cpu().numpy().view(np.uint64), k)
@@ -155,7 +140,7 @@ def test_ragged_sizes_and_edge_cases(hr):
     for (w, h) in ((1, 1), (17, 15), (33, 1)):
         cam = scenes.random_room_camera(np.random.default_rng(w * 100 + h), w, h)
         r, f = gpu_render(hr, sc, cams=[cam])
-        check_view(f, [cam], 0, oracle.render(sc.gaussians, sc.mesh, cam), amb_frac_max=1.0)
+        check_view(f, [cam], 0, oracle.render(sc.gaussians, sc.mesh, cam, alts=True), amb_frac_max=1.0)
     # no Gaussians: the image is the mesh
     g0 = sc.gaussians.subset(np.zeros(sc.gaussians.n, bool))
     sc0 = scenes.Scene("empty", g0, sc.mesh, sc.cameras)
@@ -166,7 +151,8 @@ def test_ragged_sizes_and_edge_cases(hr):
     # no mesh: Gaussians over the background
     sc1 = scenes.Scene("nomesh", sc.gaussians, None, sc.cameras)
     r, f = gpu_render(hr, sc1, settings=hr.default_settings(bg=(0.2, 0.4, 0.6)))
-    orc = oracle.render(sc.gaussians, None, sc.cameras[0], params=oracle.default_params(bg=(0.2, 0.4, 0.6)))
+    orc = oracle.render(sc.gaussians, None, sc.cameras[0], params=oracle.default_params(bg=(0.2, 0.4, 0.6)),
+                        alts=True)
     check_view(f, sc.cameras, 0, orc)
 
 
@@ -209,19 +195,7 @@ def test_loss_kernel_matches_oracle_loss(hr):
     np.testing.assert_allclose(gM.cpu().numpy().reshape(3, H, W), gm, rtol=1e-4, atol=1e-10)
 
 
-def _grad_compare(name, got, ref, rel=1e-3):
-    got = np.asarray(got, np.float64).reshape(-1)
-    ref = np.asarray(ref, np.float64).reshape(-1)
-    nr = np.linalg.norm(ref)
-    err = np.linalg.norm(got - ref)
-    say(f"  grad {name}: |ref| {nr:.3e} rel err {err / max(nr, 1e-30):.2e}")
-    if nr == 0:
-        assert np.abs(got).max() <= 1e-6
-        return
-    assert err <= rel * nr, name
-    m = np.abs(ref).max()
-    bad = np.abs(got - ref) > 2e-3 * (np.abs(ref) + 1e-2 * m)
-    assert bad.mean() <= 1e-3, (name, bad.sum())
+_grad_compare = grad_compare
 
 
 def tiny(seed, n=30, deg=3, w=48, h=40):
@@ -242,7 +216,7 @@ def test_backward_matches_oracle_gradient(hr, seed, variant):
     sc = tiny(seed)
     cam = sc.cameras[0]
     r, f = gpu_render(hr, sc, settings=hr.default_settings(variant=variant))
-    orc = oracle.render(sc.gaussians, sc.mesh, cam)
+    orc = oracle.render(sc.gaussians, sc.mesh, cam, alts=True)
     amb = orc["amb"] != 0
     rng = np.random.default_rng(seed)
     H, W = cam.height, cam.width
@@ -270,7 +244,7 @@ def test_multicamera_backward_sums_over_cameras(hr):
     rng = np.random.default_rng(5)
     ups, refs = [], []
     for c, cam in enumerate(cams):
-        orc = oracle.render(sc.gaussians, sc.mesh, cam)
+        orc = oracle.render(sc.gaussians, sc.mesh, cam, alts=True)
         amb = orc["amb"] != 0
         gi = rng.normal(size=(3, cam.height, cam.width)).astype(np.float32)
         gi[:, amb] = 0
@@ -292,7 +266,7 @@ def test_graph_step_matches_eager(hr):
     r = hr.Renderer(g, m, cams)
     f = r.render_hybrid()
     target = torch.rand(3 * r.P, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
-    L, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target)
+    L, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target, r.sizes)
     ref = r.render_hybrid_backward(gi, gt, gm)
     torch.cuda.synchronize()
     step = hr.BatchedStep(r, target)
@@ -350,7 +324,7 @@ def test_mesh_depth_culling_matches_oracle(hr):
     vals = f.values.cpu().numpy().view(np.uint32)
     key_base = tile_base = uncut = 0
     for c, cam in enumerate(cams):
-        orc = oracle.render(g, sc.mesh, cam, params=pc)
+        orc = oracle.render(g, sc.mesh, cam, params=pc, alts=True)
         check_view(f, cams, c, orc)
         k, v, rg = oracle.keys(g, cam, params=pc, mesh=sc.mesh)
         uncut += len(oracle.keys(g, cam)[0])
@@ -402,10 +376,10 @@ def test_mip_filters_forward_and_backward_match_oracle(hr, seed):
     r = hr.Renderer(g, m, [cam], st)
     f = r.render_hybrid()
     torch.cuda.synchronize()
-    orc = oracle.render(sc.gaussians, sc.mesh, cam, params=pm, filter3d=f3)
+    orc = oracle.render(sc.gaussians, sc.mesh, cam, params=pm, filter3d=f3, alts=True)
     check_view(f, [cam], 0, orc)
     # the filters change the image
-    plain = oracle.render(sc.gaussians, sc.mesh, cam)
+    plain = oracle.render(sc.gaussians, sc.mesh, cam, alts=True)
     assert np.abs(plain["image"] - orc["image"]).max() > 1e-2
     amb = orc["amb"] != 0
     H, W = cam.height, cam.width
@@ -434,7 +408,7 @@ def test_tile_ellipse_culling_matches_oracle(hr):
     vals = f.values.cpu().numpy().view(np.uint32)
     key_base = tile_base = uncut = 0
     for c, cam in enumerate(cams):
-        check_view(f, cams, c, oracle.render(sc.gaussians, sc.mesh, cam, params=pe))
+        check_view(f, cams, c, oracle.render(sc.gaussians, sc.mesh, cam, params=pe, alts=True))
         k, v, rg = oracle.keys(sc.gaussians, cam, params=pe)
         uncut += len(oracle.keys(sc.gaussians, cam)[0])
         ntl = rg.shape[0]
