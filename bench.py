@@ -65,11 +65,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gaussian-only", action="store_true")
+    ap.add_argument("--no-720p", action="store_true")
     ap.add_argument("--rect-pairs", action="store_true",
                     help="bin every tile of the 3-sigma rectangle (no tile-ellipse culling)")
     ap.add_argument("--pmc-probe-step", action="store_true",
                     help="for counter runs: one forward + loss + backward of the 16-camera "
-                         "step (one-wave backward, batch 128)")
+                         "step (one-wave backward, batch 128), then 3 copies of a 256 MiB "
+                         "buffer (the scale of the byte counters)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: every view of the headline workload once (plus one "
                          "extra blend), then 3 copies of a 256 MiB buffer (the scale of the byte "
@@ -113,7 +115,12 @@ def pmc_probe_step(torch, hr, scenes, dev):
     _, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target, r.sizes)
     r.render_hybrid_backward(gi, gt, gm)
     torch.cuda.synchronize()
-    log("pmc step probe done")
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"pmc step probe done (then 3 copies of {src.numel() * 4} bytes)")
 
 
 def timed_frames(torch, r, frame, views, steps, warmup):
@@ -134,6 +141,164 @@ def timed_frames(torch, r, frame, views, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / 1e3 / steps, wall / steps
+
+
+HBM_BYTES_PER_S = 8.0e12
+
+
+def frame_roofline(stage_ms, counts, blend_stats, n_gauss, sh_degree, faces, blend_ms):
+    """Per stage of a 1080p frame: the algorithmic bytes (or VALU lane-ops)
+    the method must move (or compute), the time that takes at the HBM (VALU)
+    peak, and that time as a fraction of the measured stage time; the frame's
+    roofline time is their sum (the mesh pass counted although it runs
+    concurrently on its own stream)."""
+    K = (sh_degree + 1) ** 2
+    nv, nk = counts["n_visible"], counts["n_keys"]
+    ex, bl = blend_stats["pairs_examined_per_view"], blend_stats["pairs_blended_per_view"]
+    work = {
+        # read every Gaussian's parameters; write a 48-byte record per visible one
+        "projection": ("hbm", n_gauss * 4 * (11 + 3 * K) + nv * 48),
+        # 4 LSD passes over the visible (depth key, index) pairs, each read and written
+        "depth_sort": ("hbm", nv * 8 * 2 * 4),
+        # one 4-byte rank per kept (tile, Gaussian) pair
+        "binning": ("hbm", nk * 4),
+        "blend": ("alu", ex * BLEND_OPS_EXAMINED + bl * BLEND_OPS_BLENDED),
+        # 4 texels (48 bytes) and 20 bytes of outputs per mesh pixel, 80 bytes per face
+        "mesh": ("hbm", counts["mesh_pixels"] * 68 + faces * 80),
+    }
+    out, total_roof = {}, 0.0
+    for k, (bound, amount) in work.items():
+        peak = HBM_BYTES_PER_S if bound == "hbm" else VALU_PEAK_TOPS * 1e12
+        roof_ms = amount / peak * 1e3
+        meas = blend_ms if k == "blend" else stage_ms[k]
+        total_roof += roof_ms
+        out[k] = {"bound": bound, "work": int(amount), "unit": "bytes" if bound == "hbm" else "lane-ops",
+                  "roof_ms": round(roof_ms, 5), "measured_ms": round(meas, 5),
+                  "frac": round(roof_ms / meas, 4) if meas > 0 else None}
+        if bound == "hbm" and meas > 0:
+            out[k]["GB_per_s"] = round(amount / (meas * 1e-3) / 1e9, 1)
+    out["frame"] = {"roof_ms": round(total_roof, 5), "measured_ms": round(stage_ms["forward"], 5),
+                    "frac": round(total_roof / stage_ms["forward"], 4)}
+    return out
+
+
+def single_view_steps(torch, hr, s4, g, m, settings, target_parts, dev, reps=2):
+    """The plain single-view path: each of the 16 cameras rendered, its loss
+    taken and its backward run on its own (eager calls, one camera per call),
+    with the batched step's settings. Returns milliseconds per 16 views."""
+    sizes = sorted({(c.width, c.height) for c in s4.cameras})
+    rs, bufs = {}, {}
+    for wh in sizes:
+        cam0 = next(c for c in s4.cameras if (c.width, c.height) == wh)
+        rr = hr.Renderer(g, m, [cam0], settings=hr.hr_settings.from_buffer_copy(settings))
+        rs[wh] = (rr, rr.new_frame())
+        P = wh[0] * wh[1]
+        bufs[wh] = (torch.zeros(1, device=dev), torch.empty(3 * P, device=dev),
+                    torch.empty(P, device=dev), torch.empty(3 * P, device=dev),
+                    torch.empty(hr.loss_scratch_bytes([wh]), dtype=torch.uint8, device=dev))
+    grads = rs[sizes[0]][0]._zero_grads(g)
+
+    def one_pass():
+        for c, cam in enumerate(s4.cameras):
+            rr, f = rs[(cam.width, cam.height)]
+            rr.set_cameras([cam])
+            rr.render_hybrid(f, sync_check=False)
+            _, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target_parts[c],
+                                           out=bufs[(cam.width, cam.height)])
+            for t in grads.values():
+                t.zero_()
+            rr.render_hybrid_backward(gi, gt, gm, grads=grads)
+
+    # size every capacity first (the eager capacity check may regrow)
+    for c, cam in enumerate(s4.cameras):
+        rr, f = rs[(cam.width, cam.height)]
+        rr.set_cameras([cam])
+        rr.render_hybrid(f, sync_check=True)
+        rs[(cam.width, cam.height)] = (rr, rr.new_frame() if f.image.numel() != 3 * rr.P else f)
+    one_pass()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        one_pass()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_frame_rate(oracle, sc, views, half):
+    """Seconds of oracle work and the extrapolated 1920x1080 frames/s over
+    `views`: per view a 16x16 and a (2 half)^2 window at the centre give the
+    per-call and the per-pixel cost."""
+    t_frames = t_spent = 0.0
+    for cam in views:
+        cx, cy = cam.width // 2, cam.height // 2
+        t0 = time.perf_counter()
+        oracle.render(sc.gaussians, sc.mesh, cam, window=(cx - 8, cy - 8, cx + 8, cy + 8))
+        t_small = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.render(sc.gaussians, sc.mesh, cam, window=(cx - half, cy - half, cx + half, cy + half))
+        t_big = time.perf_counter() - t0
+        per_px = max(t_big - t_small, 1e-9) / ((2 * half) ** 2 - 256)
+        t_frames += t_small + per_px * (cam.width * cam.height - 256)
+        t_spent += t_small + t_big
+    return t_spent, len(views) / t_frames
+
+
+SINGLE_THREAD_SAMPLE = """
+import json, os, sys
+sys.path.insert(0, {root!r})
+import bench, oracle
+from paper_2506_06988_amd import scenes
+sc = scenes.config5("hybrid")
+spent, fps = bench.oracle_frame_rate(oracle, sc, sc.cameras[:2], 96)
+print(json.dumps({{"spent": spent, "fps": fps, "threads": oracle.threads()}}))
+"""
+
+
+def cpu_baseline(scenes):
+    """The CPU FP64 oracle on a bounded sample of the headline workload, on all
+    the host's cores (median of 3 runs over 16 of the 32 views) and on one
+    thread (2 views, in a child process started with OMP_NUM_THREADS=1)."""
+    import subprocess
+    import oracle
+    sc = scenes.config5("hybrid")
+    runs, spent = [], 0.0
+    for rep in range(3):
+        sp, fps = oracle_frame_rate(oracle, sc, sc.cameras[rep % 2::2], 160)
+        runs.append(fps)
+        spent += sp
+    runs.sort()
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    child = subprocess.run([sys.executable, "-c", SINGLE_THREAD_SAMPLE.format(root=ROOT)],
+                           capture_output=True, text=True, env=env, timeout=600)
+    one = json.loads(child.stdout.strip().splitlines()[-1]) if child.returncode == 0 else None
+    threads = oracle.threads()
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    log(f"cpu oracle: runs {[round(x, 4) for x in runs]} frames/s on {threads} threads "
+        f"({spent:.1f}s); one thread: {one}")
+    out = {"value": round(runs[1], 5), "unit": "frames/s", "cores": threads, "kind": "oracle",
+           "sample": (f"FP64 oracle (OpenMP, {threads} threads) on the headline workload: per view "
+                      f"a 16x16 and a 320x320 window at the centre give the per-call and "
+                      f"per-pixel cost, extrapolated to 1920x1080; median of 3 runs over 16 of the "
+                      f"32 views ({spent:.1f}s in all)"),
+           "runs_frames_per_s": [round(x, 5) for x in runs], "nproc": nproc, "cpu_model": cpu_model()}
+    if one is not None:
+        out["single_thread"] = {"value": round(one["fps"], 6), "unit": "frames/s",
+                                "threads": one["threads"],
+                                "sample": "2 views, 16x16 and 192x192 windows, extrapolated"}
+    return out
 
 
 def main():
@@ -220,6 +385,29 @@ def main():
     hyb_stats = dict(pairs_examined_per_view=pairs // launches,
                      pairs_blended_per_view=blended // launches)
     tuning = {"batch": int(r.settings.batch), "variant": int(r.settings.variant)}
+
+    # stage times (events between the stages, hr_render_hybrid_timed) and the
+    # forward without the mesh pass (the mesh of the same view kept in the
+    # workspace, HR_FLAG_MESH_REUSED), over all 32 views
+    stage_sum = {k: 0.0 for k in hr.STAGES}
+    no_mesh_ms = 0.0
+    counts = dict(n_visible=0, n_keys=0, mesh_pixels=0)
+    for v in range(len(sc.cameras)):
+        r.set_cameras([sc.cameras[v]])
+        t = r.render_hybrid_timed(frame)
+        for k in stage_sum:
+            stage_sum[k] += t[k] / len(sc.cameras)
+        st_v = frame.stats_dict()
+        counts["n_visible"] += st_v["n_visible"] / len(sc.cameras)
+        counts["n_keys"] += st_v["n_keys"] / len(sc.cameras)
+        counts["mesh_pixels"] += float((frame.tri_id >= 0).sum().item()) / len(sc.cameras)
+        no_mesh_ms += r.render_hybrid_timed(frame, mesh_reused=True)["forward"] / len(sc.cameras)
+    log("stage ms per 1080p view: " + ", ".join(f"{k} {v:.4f}" for k, v in stage_sum.items()) +
+        f"; forward without the mesh pass {no_mesh_ms:.4f} ms")
+    roof = frame_roofline(stage_sum, counts, hyb_stats, n_gauss=sc.gaussians.n,
+                          sh_degree=sc.gaussians.sh_degree, faces=sc.mesh.n_faces,
+                          blend_ms=blend_s / launches * 1e3)
+    log("frame roofline: " + json.dumps(roof))
     del r, frame, g, m
     torch.cuda.empty_cache()
 
@@ -252,6 +440,11 @@ def main():
                      "kernel": "k_blend_fwd", "ops_per_examined": BLEND_OPS_EXAMINED,
                      "ops_per_blended": BLEND_OPS_BLENDED, "ops_per_launch": ops // launches,
                      "avg_launch_ms": round(blend_s / launches * 1e3, 4)},
+        "n_keys_per_view": int(counts["n_keys"]),
+        "n_visible_per_view": int(counts["n_visible"]),
+        "stage_ms_per_view": {k: round(v, 4) for k, v in stage_sum.items()},
+        "frames_per_s_without_mesh_pass": round(1e3 / no_mesh_ms, 2),
+        "frame_roofline": roof,
     }
     del sc
 
@@ -269,6 +462,27 @@ def main():
         log(f"1080p Gaussian-only (3M): {sec_g * 1e3:.3f} ms/frame ({1 / sec_g:.1f} frames/s)")
         result["gaussian_only_frames_per_s"] = round(1.0 / sec_g, 2)
         del r, frame, g, sg
+        torch.cuda.empty_cache()
+
+    # ------------------------------------------------------- 720p, config 2
+    if not args.no_720p:
+        s2 = scenes.config2()
+        g, m = hr.to_device(s2.gaussians, s2.mesh, device=dev)
+        rt = hr.Renderer(g, m, s2.cameras, settings=hr.default_settings(flags=PAIR_CULL))
+        ft = rt.render_hybrid(sync_check=True)
+        rt.autotune(ft, repeats=3)
+        r = hr.Renderer(g, m, [s2.cameras[0]], settings=hr.default_settings(flags=PAIR_CULL))
+        r.settings.batch, r.settings.variant = rt.settings.batch, rt.settings.variant
+        del rt, ft
+        frame = r.new_frame()
+        for v in range(len(s2.cameras)):
+            r.set_cameras([s2.cameras[v]])
+            r.render_hybrid(frame, sync_check=True)
+        sec2, _ = timed_frames(torch, r, frame, s2.cameras, max(8, args.steps // 2), 2)
+        log(f"720p hybrid (300k Gaussians, 50k faces): {sec2 * 1e3:.3f} ms/frame "
+            f"({1 / sec2:.1f} frames/s)")
+        result["config2_720p_frames_per_s"] = round(1.0 / sec2, 2)
+        del r, frame, g, m, s2
         torch.cuda.empty_cache()
 
     # --------------------------------------------------- batched fwd + bwd
@@ -307,37 +521,19 @@ def main():
                                     "variant": int(r.settings.variant)}
         result["batched_ms_per_step"] = round(bsec * 1e3, 3)
         step.close()
-        del step, r, f, g, m, s4
+        # the plain single-view path on the same GPU: the 16 cameras one by one
+        parts = [torch.as_tensor(t.reshape(-1)).to(dev) for t in s4.target]
+        sv_ms = single_view_steps(torch, hr, s4, g, m, r.settings, parts, dev)
+        log(f"single-view fwd+bwd of the 16 cameras one by one: {sv_ms:.2f} ms "
+            f"({len(s4.cameras) / sv_ms * 1e3:.1f} views/s)")
+        result["single_view_fwd_bwd_views_per_s"] = round(len(s4.cameras) / sv_ms * 1e3, 2)
+        result["batched_vs_single_view"] = round(sv_ms / (bsec * 1e3), 3)
+        del step, r, f, g, m, s4, parts
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------- CPU baseline
     if not args.no_cpu_baseline:
-        import oracle
-        sc = scenes.config5("hybrid")
-        views = sc.cameras
-        t_frames = 0.0
-        t_spent = 0.0
-        for cam in views:
-            # a 16x16 and a 480x480 window at the centre give the per-call
-            # and the per-pixel cost of this view, extrapolated to 1920x1080
-            cx, cy = cam.width // 2, cam.height // 2
-            t0 = time.perf_counter()
-            oracle.render(sc.gaussians, sc.mesh, cam, window=(cx - 8, cy - 8, cx + 8, cy + 8))
-            t_small = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            oracle.render(sc.gaussians, sc.mesh, cam, window=(cx - 240, cy - 240, cx + 240, cy + 240))
-            t_big = time.perf_counter() - t0
-            per_px = max(t_big - t_small, 1e-9) / (480 * 480 - 256)
-            t_frames += t_small + per_px * (cam.width * cam.height - 256)
-            t_spent += t_small + t_big
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        result["cpu_baseline"] = {
-            "value": round(len(views) / t_frames, 5), "unit": "frames/s", "cores": cores,
-            "kind": "oracle",
-            "sample": (f"oracle (FP64, OpenMP) on all {len(views)} headline views: per view a "
-                       f"16x16 and a 480x480 window at the centre ({t_spent:.1f}s in all) give the "
-                       f"per-call and per-pixel cost, extrapolated to the 1920x1080 frame")}
-        log(f"cpu oracle: {t_spent:.1f}s of samples -> {len(views) / t_frames:.4f} frames/s extrapolated")
+        result["cpu_baseline"] = cpu_baseline(scenes)
 
     print(json.dumps(result), flush=True)
 

@@ -142,7 +142,13 @@ enum {
    * images, T and n_blended are unchanged; n_contrib and n_processed are
    * positions in the kept lists; keys/ranges, n_keys and the capacity
    * requirement count the kept pairs. */
-  HR_FLAG_TILE_ELLIPSE = 1u << 5
+  HR_FLAG_TILE_ELLIPSE = 1u << 5,
+  /* forward: skip the mesh pass and use the z-buffer, mesh colour and texel
+   * footprints the workspace already holds from a forward of the same
+   * cameras and mesh (for renders of the Gaussians alone over an unchanged
+   * mesh view). The outputs mesh_rgb, mesh_depth and tri_id are not written
+   * and hr_stats.n_tris is 0. */
+  HR_FLAG_MESH_REUSED = 1u << 6
 };
 
 typedef struct {
@@ -232,6 +238,21 @@ hr_status hr_render_hybrid(const hr_gaussians* g, const hr_mesh* mesh, const hr_
                            int32_t n_cams, const hr_settings* s, int64_t key_capacity,
                            void* workspace, size_t workspace_bytes, hr_outputs* out,
                            void* stream);
+
+/* hr_render_hybrid that also times its stages with events, synchronising the
+ * stream before it returns (not for graph capture). stage_ms (host,
+ * HR_N_STAGES floats) receives milliseconds: on the given stream 0 camera
+ * upload and projection, 1 depth sort (visibility scan, compaction, radix
+ * passes, gather), 2 tile binning (with the mesh-depth bound when culling,
+ * which waits for the mesh), 3 blend, 4 statistics export; 5 the mesh pass on
+ * the internal stream (concurrent with 1-2; 0 with HR_FLAG_MESH_REUSED); 6 the
+ * whole forward on the given stream. Errors as hr_render_hybrid (the capacity
+ * check is always made). */
+#define HR_N_STAGES 7
+hr_status hr_render_hybrid_timed(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                                 int32_t n_cams, const hr_settings* s, int64_t key_capacity,
+                                 void* workspace, size_t workspace_bytes, hr_outputs* out,
+                                 void* stream, float* stage_ms);
 
 /* Backward of hr_render_hybrid given upstream gradients of I_h, T and I_m
  * (grad_final_T and grad_mesh_rgb nullable). Blends in reverse order,
@@ -335,8 +356,11 @@ hr_status hr_full_loss(const float* image, const float* final_T, const float* me
 /* Backward autotuner: with the workspace of a forward just run on the same
  * arguments, times the backward blend (256-thread and one-wave kernels, LDS
  * batch 64 and 128) on the given upstream gradients and writes the fastest
- * choice to s->batch_bwd and bit 3 of s->variant. No gradient output is
- * touched. Synchronises the stream. */
+ * choice to s->batch_bwd and bit 3 of s->variant. Every candidate's
+ * accumulated record gradients must match those of the 256-thread kernel at
+ * batch 64 to 1e-4 relative (2-norm; float atomics sum in any order), else
+ * HR_ERR_INTERNAL. No gradient output is touched. Synchronises the stream.
+ * HR_AUTOTUNE_CACHE is honoured as by hr_autotune. */
 hr_status hr_autotune_backward(const hr_gaussians* gaussians, const hr_mesh* mesh,
                                const hr_camera* cams, int32_t n_cams, hr_settings* s,
                                int64_t key_capacity, void* workspace, size_t workspace_bytes,
@@ -345,11 +369,41 @@ hr_status hr_autotune_backward(const hr_gaussians* gaussians, const hr_mesh* mes
 
 /* Autotuner: times the blend variants (LDS batch size and staging depth) on
  * the inputs of a forward that has just run with this workspace, checks that
- * every variant's outputs are bit-identical, and writes the fastest choice to
- * s->batch and s->variant. Synchronises the stream. */
+ * every variant's outputs (image, T, n_contrib and, when exported, n_blended
+ * and n_processed) are bit-identical, and writes the fastest choice to
+ * s->batch and s->variant (HR_ERR_INTERNAL if a variant differs).
+ * Synchronises the stream.
+ * With the environment variable HR_AUTOTUNE_CACHE naming a file, a choice
+ * cached there for the same workload class (hr_autotune_key) is used without
+ * timing, and a newly timed choice is added to the file. HR_LOG (not "" or
+ * "0") prints the decisions and every failure to stderr. */
 hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
                       int32_t n_cams, hr_settings* s, int64_t key_capacity, void* workspace,
                       size_t workspace_bytes, hr_outputs* out, int32_t repeats, void* stream);
+
+/* Autotuner cache. A tuned choice is kept for a workload class: the key
+ * "fwd|" or "bwd|" (backward != 0), the architecture name and compute-unit
+ * count of the device, then the powers of two at or below the total pixel
+ * count, the Gaussian count and the camera count, the SH degree, whether a
+ * mesh is present, and the flags that change the lists (CULL_BEHIND_MESH,
+ * MIP_2D, TILE_ELLIPSE), e.g. "fwd|gfx950|cu256|px2^20|n2^19|cams2^0|sh3|mesh1|flags32".
+ * hr_autotune_key writes it to buf (cap bytes, truncated, NUL-terminated) and
+ * returns the bytes it needs (0 on invalid arguments); host only.
+ * The cache file is a JSON object {"hr_autotune_cache": 1, "entries": {key:
+ * [batch, variant], ...}} with one entry per line.
+ * hr_autotune_cache_lookup returns 1 and fills batch and variant when the file
+ * holds the key, else 0. hr_autotune_cache_store adds or replaces the key
+ * (written to a temporary file, then renamed over the cache);
+ * HR_ERR_INVALID_ARGUMENT for a null path, a key not starting with "fwd|" or
+ * "bwd|" or holding a quote, backslash or newline; HR_ERR_INTERNAL when the
+ * file cannot be written. Both are host only. */
+size_t hr_autotune_key(const char* arch, int32_t compute_units, const hr_gaussians* g,
+                       const hr_mesh* mesh, const hr_camera* cams, int32_t n_cams,
+                       const hr_settings* s, int32_t backward, char* buf, size_t cap);
+int32_t hr_autotune_cache_lookup(const char* path, const char* key, int32_t* batch,
+                                 int32_t* variant);
+hr_status hr_autotune_cache_store(const char* path, const char* key, int32_t batch,
+                                  int32_t variant);
 
 /* Batched training step captured in a hipGraph: forward of all cameras,
  * loss against `target` (planar, packed like the image), backward into

@@ -118,6 +118,13 @@ def _setup(L):
     L.or_quat_to_rot.restype = None
     L.or_mip_filter3d.argtypes = [P, P, C.c_int, P, C.c_double, P]
     L.or_mip_filter3d.restype = C.c_int
+    L.or_max_threads.argtypes = []
+    L.or_max_threads.restype = C.c_int
+
+
+def threads():
+    """Threads the oracle's parallel loops run on (OpenMP)."""
+    return int(lib().or_max_threads())
 
 
 def _p(a):

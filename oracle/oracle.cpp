@@ -37,6 +37,8 @@
 #include <limits>
 #include <vector>
 
+#include <omp.h>
+
 extern "C" {
 
 typedef struct {
@@ -779,6 +781,17 @@ Frame prepare(const or_scene& sc, const or_camera& cam, const or_params& p, int 
 extern "C" {
 
 int or_abi_version(void) { return 1; }
+
+// Threads an OpenMP loop of the oracle runs on (the timing harness reports it).
+int or_max_threads(void) {
+  int n = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    n = omp_get_num_threads();
+  }
+  return n;
+}
 
 // Per-Gaussian projected records for one camera.
 int or_project(const or_scene* sc, const or_camera* cam, const or_params* p, or_proj_out* o) {

@@ -15,8 +15,12 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["api.cpp", "scan.hip", "project.hip", "sort.hip", "mesh.hip", "blend.hip", "bwd.hip",
            "misc.hip",
            "ssim.hip"]
+# Atomics on one address with per-lane values (LDS bounding boxes, per-tile
+# sums) are combined across the wave with DPP before the one atomic, instead of
+# the default iterative scan (a scalar loop over every active lane).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
          "-I" + os.path.join(ROOT, "include")]
 
 

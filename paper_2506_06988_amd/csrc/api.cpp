@@ -1,11 +1,16 @@
 // Host runtime of libhybrid_raster: argument checks, workspace layout, launch
 // order, capacity check, autotuner and hipGraph capture of a training step.
 #include <hip/hip_runtime.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -18,8 +23,23 @@ namespace {
 
 thread_local std::string g_err;
 
+// HR_LOG set to anything but "" or "0": failures and autotuner decisions are
+// also printed to stderr
+bool log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("HR_LOG");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+void log_line(const std::string& msg) {
+  if (log_on()) std::fprintf(stderr, "[libhybrid_raster] %s\n", msg.c_str());
+}
+
 hr_status fail(hr_status s, const std::string& msg) {
   g_err = msg;
+  log_line("error: " + msg);
   return s;
 }
 
@@ -41,12 +61,90 @@ struct Plan {
   size_t cams, counters, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs_hist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
       tile_start, tile_order, sched_cnt, sched_sum, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
-      mesh_rgb, gacc, tune, scan_scratch, scan_scratch2, total;
+      mesh_rgb, taps, gacc, tune, scan_scratch, scan_scratch2, total;
   int64_t scan_words;
   std::vector<CamDev> camdev;
 };
 
 bool valid_ptr(const void* p) { return p != nullptr; }
+
+// ------------------------------------------------------ autotuner cache --
+// A JSON object whose "entries" map a workload key to [batch, variant]; one
+// entry per line, so reading needs no general JSON parser. Written whole to a
+// temporary file, then renamed over the old one.
+using TuneMap = std::map<std::string, std::pair<int, int>>;
+
+bool cache_read(const char* path, TuneMap& m) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t q0 = line.find('"');
+    if (q0 == std::string::npos) continue;
+    const size_t q1 = line.find('"', q0 + 1);
+    if (q1 == std::string::npos) continue;
+    const std::string key = line.substr(q0 + 1, q1 - q0 - 1);
+    if (key.rfind("fwd|", 0) != 0 && key.rfind("bwd|", 0) != 0) continue;
+    const size_t br = line.find('[', q1);
+    int b = 0, v = 0;
+    if (br == std::string::npos || std::sscanf(line.c_str() + br, "[%d , %d]", &b, &v) != 2)
+      continue;
+    m[key] = {b, v};
+  }
+  return true;
+}
+
+bool cache_write(const char* path, const TuneMap& m) {
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream f(tmp);
+    if (!f) return false;
+    f << "{\n  \"hr_autotune_cache\": 1,\n  \"entries\": {\n";
+    size_t i = 0;
+    for (const auto& e : m) {
+      f << "    \"" << e.first << "\": [" << e.second.first << ", " << e.second.second << "]"
+        << (++i < m.size() ? "," : "") << "\n";
+    }
+    f << "  }\n}\n";
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+int log2_bucket(int64_t v) {
+  int b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+// the workload class a tuned choice is kept for
+std::string tune_key(bool backward, const char* arch, int cus, int64_t pixels, int64_t n,
+                     int32_t n_cams, int32_t sh_degree, bool mesh, uint32_t flags) {
+  const uint32_t fl = flags & (HR_FLAG_CULL_BEHIND_MESH | HR_FLAG_MIP_2D | HR_FLAG_TILE_ELLIPSE);
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s|%s|cu%d|px2^%d|n2^%d|cams2^%d|sh%d|mesh%d|flags%u",
+                backward ? "bwd" : "fwd", arch, cus, log2_bucket(pixels), log2_bucket(n),
+                log2_bucket(n_cams), sh_degree, mesh ? 1 : 0, fl);
+  // the key is written between quotes: keep it printable
+  for (char* c = buf; *c; ++c)
+    if (*c == '"' || *c == '\\' || (unsigned char)*c < 32) *c = '_';
+  return buf;
+}
+
+bool device_arch(std::string& arch, int& cus) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return false;
+  arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  cus = prop.multiProcessorCount;
+  return true;
+}
 
 // Checks every argument that can be checked on the host and fills the plan.
 hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* cams,
@@ -68,6 +166,8 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
     if (m->n_verts < 3 || m->n_tex < 1 || m->tex_h < 1 || m->tex_w < 1)
       return fail(HR_ERR_INVALID_ARGUMENT, "mesh needs >= 3 vertices and a texture");
     if (m->n_faces > (1 << 30)) return fail(HR_ERR_INVALID_ARGUMENT, "too many faces");
+    if (m->tex_w > 65535 || m->tex_h > 65535 || m->n_tex >= (1 << 30))
+      return fail(HR_ERR_UNSUPPORTED, "textures are at most 65535 x 65535, fewer than 2^30");
   }
   if (key_cap < 0 || key_cap > (int64_t)0xffffffffll)
     return fail(HR_ERR_INVALID_ARGUMENT, "key_capacity must be in [0, 2^32)");
@@ -177,8 +277,9 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.final_T = L.take(4 * P);
   p.n_contrib = L.take(4 * P);
   p.mesh_rgb = L.take(12 * P);
+  p.taps = L.take(16 * P);
   p.gacc = L.take(36 * M);
-  p.tune = L.take(16 * P + 256);
+  p.tune = L.take((28 * P + 255) / 256 * 256 + 256);
   int64_t longest =
       std::max<int64_t>({M + 1, 256 * p.rs_blocks, p.n_tiles, p.MF + 1, p.chunk_rows + 1, 1});
   p.scan_scratch = L.take(scan_scratch_bytes(longest) + 4096);
@@ -230,6 +331,7 @@ Work make_work(const Plan& p, void* ws) {
   w.final_T = (float*)(b + p.final_T);
   w.n_contrib = (int32_t*)(b + p.n_contrib);
   w.mesh_rgb = (float*)(b + p.mesh_rgb);
+  w.taps = (uint4*)(b + p.taps);
   w.gacc = (float*)(b + p.gacc);
   // the backward clears gacc before it accumulates; the forward's binning
   // uses the same memory for the per-rank ellipse constants
@@ -359,12 +461,17 @@ hr_status side_stream(SideStream*& out) {
 }
 
 // enqueue the whole forward
+// ev (nullable): 8 timing events - main stream: start, after the projection,
+// the depth sort, the binning, the blend, the statistics; mesh stream: start,
+// end of the mesh pass
 hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
                           const hr_mesh* m, const hr_settings* s, hr_outputs* out,
-                          hipStream_t st) {
+                          hipStream_t st, hipEvent_t* ev = nullptr) {
   SideStream* ss = nullptr;
   hr_status rc = side_stream(ss);
   if (rc != HR_OK) return rc;
+  const bool reuse = (s->flags & HR_FLAG_MESH_REUSED) != 0;
+  if (ev) hipEventRecord(ev[0], st);
   upload_cams(p, w, true, st);
   Work wm = w;  // the mesh's scans use their own scratch
   wm.scan_scratch = w.scan_scratch2;
@@ -372,20 +479,32 @@ hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const h
   // the projection first: it is memory-bound and the mesh would slow it; the
   // latency-bound sort and binning leave room for the mesh
   launch_project(S, w.cams, *g, w, out->radii, st);
-  if (!ss->fork_from(st)) return fail(HR_ERR_HIP, "stream fork failed");
-  launch_mesh(S, *m, wm, out, ss->st);
+  if (ev) hipEventRecord(ev[1], st);
+  if (!reuse) {
+    if (!ss->fork_from(st)) return fail(HR_ERR_HIP, "stream fork failed");
+    if (ev) hipEventRecord(ev[6], ss->st);
+    launch_mesh(S, *m, wm, out, ss->st);
+    if (ev) hipEventRecord(ev[7], ss->st);
+  } else if (ev) {
+    hipEventRecord(ev[6], st);
+    hipEventRecord(ev[7], st);
+  }
   launch_depth_sort(S, w, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, st);
+  if (ev) hipEventRecord(ev[2], st);
   // the mesh-depth culling needs the z-buffer before binning, the blend after
   if (cull) {
-    if (!ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
+    if (!reuse && !ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
     launch_tile_dmax(S, w, st);
   }
   launch_binning(S, w, (int)p.n_cams, cull, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, out, st);
-  if (!cull && !ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
+  if (ev) hipEventRecord(ev[3], st);
+  if (!cull && !reuse && !ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
   launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
+  if (ev) hipEventRecord(ev[4], st);
   if (out->stats)
     launch_counters_to_stats(w.counters, w.tile_np, (int)S.n_tiles, (const uint32_t*)w.scan_scratch,
                              (const uint32_t*)w.scan_scratch2, out->stats, st);
+  if (ev) hipEventRecord(ev[5], st);
   return HR_OK;
 }
 
@@ -466,6 +585,47 @@ hr_status hr_render_hybrid(const hr_gaussians* g, const hr_mesh* mesh, const hr_
   if ((rc = hip_check("forward launch")) != HR_OK) return rc;
   if (!(s->flags & HR_FLAG_NO_SYNC)) return read_flags(w, st, nullptr);
   return HR_OK;
+}
+
+hr_status hr_render_hybrid_timed(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
+                                 int32_t n_cams, const hr_settings* s, int64_t key_capacity,
+                                 void* workspace, size_t workspace_bytes, hr_outputs* out,
+                                 void* stream, float* stage_ms) {
+  if (!stage_ms) return fail(HR_ERR_INVALID_ARGUMENT, "stage_ms is required");
+  Plan p;
+  hr_status rc = make_plan(g, mesh, cams, n_cams, s, key_capacity, p);
+  if (rc != HR_OK) return rc;
+  if ((rc = check_outputs(out)) != HR_OK) return rc;
+  if (!workspace || workspace_bytes < p.total)
+    return fail(HR_ERR_INVALID_ARGUMENT, "workspace smaller than hr_query_workspace()");
+  if ((uintptr_t)workspace % ALIGN) return fail(HR_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[8];
+  int made = 0;
+  for (; made < 8; ++made)
+    if (hipEventCreate(&ev[made]) != hipSuccess) break;
+  if (made < 8) {
+    for (int k = 0; k < made; ++k) hipEventDestroy(ev[k]);
+    return fail(HR_ERR_HIP, "event create failed");
+  }
+  Work w = make_work(p, workspace);
+  SetDev S = make_setdev(p, g, mesh, s);
+  hipGetLastError();
+  rc = enqueue_forward(p, w, S, g, mesh, s, out, st, ev);
+  if (rc == HR_OK) rc = hip_check("forward launch");
+  if (rc == HR_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(HR_ERR_HIP, "synchronize failed");
+  if (rc == HR_OK) {
+    const int a[HR_N_STAGES] = {0, 1, 2, 3, 4, 6, 0};
+    const int b[HR_N_STAGES] = {1, 2, 3, 4, 5, 7, 5};
+    for (int k = 0; k < HR_N_STAGES; ++k) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[a[k]], ev[b[k]]);
+      stage_ms[k] = ms;
+    }
+  }
+  for (int k = 0; k < 8; ++k) hipEventDestroy(ev[k]);
+  if (rc == HR_OK) rc = read_flags(w, st, nullptr);
+  return rc;
 }
 
 hr_status hr_render_hybrid_backward(const hr_gaussians* g, const hr_mesh* mesh,
@@ -627,6 +787,58 @@ hr_status hr_full_loss(const float* image, const float* final_T, const float* me
   return hip_check("full loss launch");
 }
 
+size_t hr_autotune_key(const char* arch, int32_t compute_units, const hr_gaussians* g,
+                       const hr_mesh* mesh, const hr_camera* cams, int32_t n_cams,
+                       const hr_settings* s, int32_t backward, char* buf, size_t cap) {
+  if (!arch || !g || !mesh || !cams || !s || n_cams < 1 || g->n < 0) return 0;
+  int64_t P = 0;
+  for (int c = 0; c < n_cams; ++c) P += (int64_t)cams[c].width * cams[c].height;
+  const std::string k = tune_key(backward != 0, arch, compute_units, P, g->n, n_cams,
+                                 g->sh_degree, mesh->n_faces > 0, s->flags);
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, k.size());
+    std::memcpy(buf, k.data(), n);
+    buf[n] = 0;
+  }
+  return k.size() + 1;
+}
+
+int32_t hr_autotune_cache_lookup(const char* path, const char* key, int32_t* batch,
+                                 int32_t* variant) {
+  if (!path || !key || !batch || !variant) return 0;
+  TuneMap m;
+  if (!cache_read(path, m)) return 0;
+  const auto it = m.find(key);
+  if (it == m.end()) return 0;
+  *batch = it->second.first;
+  *variant = it->second.second;
+  return 1;
+}
+
+hr_status hr_autotune_cache_store(const char* path, const char* key, int32_t batch,
+                                  int32_t variant) {
+  if (!path || !*path || !key) return fail(HR_ERR_INVALID_ARGUMENT, "null cache path or key");
+  if (std::strncmp(key, "fwd|", 4) != 0 && std::strncmp(key, "bwd|", 4) != 0)
+    return fail(HR_ERR_INVALID_ARGUMENT, "cache keys start with fwd| or bwd|");
+  for (const char* c = key; *c; ++c)
+    if (*c == '"' || *c == '\\' || *c == '\n')
+      return fail(HR_ERR_INVALID_ARGUMENT, "cache key with a quote, backslash or newline");
+  TuneMap m;
+  cache_read(path, m);  // a missing file starts empty
+  m[key] = {batch, variant};
+  if (!cache_write(path, m)) return fail(HR_ERR_INTERNAL, std::string("cannot write ") + path);
+  return HR_OK;
+}
+
+namespace {
+const char* cache_path() {
+  const char* p = std::getenv("HR_AUTOTUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+bool valid_batch(int b) { return b == 32 || b == 64 || b == 128 || b == 256; }
+}  // namespace
+
 hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
                       int32_t n_cams, hr_settings* s, int64_t key_capacity, void* workspace,
                       size_t workspace_bytes, hr_outputs* out, int32_t repeats, void* stream) {
@@ -640,16 +852,43 @@ hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camer
   hipStream_t st = (hipStream_t)stream;
   Work w = make_work(p, workspace);
   SetDev S = make_setdev(p, g, mesh, s);
+  hr_outputs o = *out;
+  o.stats = nullptr;
+  // a choice cached for this workload class is used as it is
+  const char* path = cache_path();
+  std::string key;
+  if (path) {
+    std::string arch;
+    int cus = 0;
+    if (!device_arch(arch, cus)) return fail(HR_ERR_HIP, "device properties unavailable");
+    key = tune_key(false, arch.c_str(), cus, p.P, p.n, n_cams, g->sh_degree, p.F > 0, s->flags);
+    int32_t b = 0, v = 0;
+    if (hr_autotune_cache_lookup(path, key.c_str(), &b, &v) && valid_batch(b) && v >= 0 &&
+        v <= 7) {
+      s->batch = b;
+      s->variant = v | (s->variant & 8);
+      log_line("autotune: cached " + key + " -> batch " + std::to_string(b) + " variant " +
+               std::to_string(v));
+      launch_blend_forward(S, w, &o, b, v, st);
+      return hip_check("autotune (cached)");
+    }
+  }
+  // reference outputs of the default variant: image, T, n_contrib, and the
+  // exported n_blended and n_processed; every candidate must equal them bit for bit
   char* tune = (char*)workspace + p.tune;
   float* ref_img = (float*)tune;
   float* ref_T = ref_img + 3 * p.P;
-  uint32_t* mism = (uint32_t*)(ref_T + p.P);
-  // reference outputs from the default variant
-  hr_outputs o = *out;
-  o.stats = nullptr;
+  float* ref_nc = ref_T + p.P;
+  float* ref_nb = ref_nc + p.P;
+  float* ref_np = ref_nb + p.P;
+  uint32_t* mism = (uint32_t*)(ref_np + p.P);
   launch_blend_forward(S, w, &o, 64, 0, st);
   hipMemcpyAsync(ref_img, out->image, 12 * p.P, hipMemcpyDeviceToDevice, st);
   hipMemcpyAsync(ref_T, w.final_T, 4 * p.P, hipMemcpyDeviceToDevice, st);
+  hipMemcpyAsync(ref_nc, w.n_contrib, 4 * p.P, hipMemcpyDeviceToDevice, st);
+  if (out->n_blended) hipMemcpyAsync(ref_nb, out->n_blended, 4 * p.P, hipMemcpyDeviceToDevice, st);
+  if (out->n_processed)
+    hipMemcpyAsync(ref_np, out->n_processed, 4 * p.P, hipMemcpyDeviceToDevice, st);
   const int batches[4] = {32, 64, 128, 256};
   float best = 1e30f;
   int best_b = 64, best_v = 0;
@@ -664,42 +903,50 @@ hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camer
   cfg.emplace_back(64, 4);
   cfg.emplace_back(128, 4);
   for (const auto& bv : cfg) {
-      const int batch = bv.first, v = bv.second;
-      std::vector<float> times;
-      for (int r = 0; r < repeats + 1; ++r) {
-        hipEventRecord(e0, st);
-        launch_blend_forward(S, w, &o, batch, v, st);
-        hipEventRecord(e1, st);
-        hipEventSynchronize(e1);
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (r > 0) times.push_back(ms);
-      }
-      std::sort(times.begin(), times.end());
-      const float med = times[times.size() / 2];
-      launch_fill_u32(mism, 0u, 1, st);
-      launch_count_mismatch(out->image, ref_img, 3 * p.P, mism, st);
-      launch_count_mismatch(w.final_T, ref_T, p.P, mism, st);
-      uint32_t bad = 0;
-      hipMemcpyAsync(&bad, mism, 4, hipMemcpyDeviceToHost, st);
-      hipStreamSynchronize(st);
-      if (bad) {
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
-        return fail(HR_ERR_INTERNAL, "blend variant batch=" + std::to_string(batch) +
-                                         " variant=" + std::to_string(v) +
-                                         " is not bit-identical to the default");
-      }
-      if (med < best) {
-        best = med;
-        best_b = batch;
-        best_v = v;
-      }
+    const int batch = bv.first, v = bv.second;
+    std::vector<float> times;
+    for (int r = 0; r < repeats + 1; ++r) {
+      hipEventRecord(e0, st);
+      launch_blend_forward(S, w, &o, batch, v, st);
+      hipEventRecord(e1, st);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) times.push_back(ms);
+    }
+    std::sort(times.begin(), times.end());
+    const float med = times[times.size() / 2];
+    launch_fill_u32(mism, 0u, 1, st);
+    launch_count_mismatch(out->image, ref_img, 3 * p.P, mism, st);
+    launch_count_mismatch(w.final_T, ref_T, p.P, mism, st);
+    launch_count_mismatch((const float*)w.n_contrib, ref_nc, p.P, mism, st);
+    if (out->n_blended) launch_count_mismatch((const float*)out->n_blended, ref_nb, p.P, mism, st);
+    if (out->n_processed)
+      launch_count_mismatch((const float*)out->n_processed, ref_np, p.P, mism, st);
+    uint32_t bad = 0;
+    hipMemcpyAsync(&bad, mism, 4, hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    if (bad) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return fail(HR_ERR_INTERNAL, "blend variant batch=" + std::to_string(batch) +
+                                       " variant=" + std::to_string(v) +
+                                       " is not bit-identical to the default");
+    }
+    if (med < best) {
+      best = med;
+      best_b = batch;
+      best_v = v;
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   s->batch = best_b;
   s->variant = best_v | (s->variant & 8);
+  log_line("autotune: timed, batch " + std::to_string(best_b) + " variant " +
+           std::to_string(best_v) + " (" + std::to_string(best) + " ms)");
+  if (path && hr_autotune_cache_store(path, key.c_str(), best_b, best_v) != HR_OK)
+    log_line("autotune: cache not written: " + g_err);
   // leave the outputs of the chosen variant in place
   launch_blend_forward(S, w, &o, best_b, best_v, st);
   return hip_check("autotune");
@@ -719,9 +966,37 @@ hr_status hr_autotune_backward(const hr_gaussians* g, const hr_mesh* mesh, const
   hipStream_t st = (hipStream_t)stream;
   Work w = make_work(p, workspace);
   SetDev S = make_setdev(p, g, mesh, s);
+  const char* path = cache_path();
+  std::string key;
+  if (path) {
+    std::string arch;
+    int cus = 0;
+    if (!device_arch(arch, cus)) return fail(HR_ERR_HIP, "device properties unavailable");
+    key = tune_key(true, arch.c_str(), cus, p.P, p.n, n_cams, g->sh_degree, p.F > 0, s->flags);
+    int32_t b = 0, v = 0;
+    if (hr_autotune_cache_lookup(path, key.c_str(), &b, &v) && valid_batch(b) &&
+        (v == 0 || v == 8)) {
+      s->batch_bwd = b;
+      s->variant = (s->variant & 7) | v;
+      log_line("backward autotune: cached " + key + " -> batch " + std::to_string(b) +
+               " variant " + std::to_string(v));
+      return HR_OK;
+    }
+  }
+  // the reference accumulators of the 256-thread kernel at batch 64 sit in the
+  // per-item record slots, which only the forward and the projection backward
+  // use; every candidate must match them to 1e-4 (float atomics reorder sums)
+  float* ref = (float*)((char*)workspace + p.rec);
+  double* err = (double*)((char*)workspace + p.tune + (28 * p.P + 255) / 256 * 256);
+  launch_zero_gacc(w.gacc, w.counters, st);
+  launch_blend_backward(S, w, grad_image, grad_T, 64, 0, st);
+  launch_copy_counted(w.gacc, ref, w.counters, 9, st);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(HR_ERR_HIP, "event create failed");
+  uint32_t nvis = 0;
+  hipMemcpyAsync(&nvis, w.counters, 4, hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
   const int cand[4][2] = {{64, 0}, {128, 0}, {64, 8}, {128, 8}};
   float best = 1e30f;
   int best_b = 64, best_v = 0;
@@ -737,6 +1012,17 @@ hr_status hr_autotune_backward(const hr_gaussians* g, const hr_mesh* mesh, const
       hipEventElapsedTime(&ms, e0, e1);
       if (r > 0) times.push_back(ms);
     }
+    launch_sq_diff(w.gacc, ref, (int64_t)nvis * 9, err, st);
+    double e2[2] = {0.0, 0.0};
+    hipMemcpyAsync(e2, err, sizeof(e2), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    if (!(e2[0] <= 1e-8 * e2[1])) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return fail(HR_ERR_INTERNAL, "backward variant batch=" + std::to_string(c[0]) +
+                                       " variant=" + std::to_string(c[1]) +
+                                       " differs from the reference accumulators");
+    }
     std::sort(times.begin(), times.end());
     const float med = times[times.size() / 2];
     if (med < best) {
@@ -749,6 +1035,10 @@ hr_status hr_autotune_backward(const hr_gaussians* g, const hr_mesh* mesh, const
   hipEventDestroy(e1);
   s->batch_bwd = best_b;
   s->variant = (s->variant & 7) | best_v;
+  log_line("backward autotune: timed, batch " + std::to_string(best_b) + " variant " +
+           std::to_string(best_v) + " (" + std::to_string(best) + " ms)");
+  if (path && hr_autotune_cache_store(path, key.c_str(), best_b, best_v) != HR_OK)
+    log_line("backward autotune: cache not written: " + g_err);
   return hip_check("backward autotune");
 }
 

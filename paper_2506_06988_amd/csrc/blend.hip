@@ -675,7 +675,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
   const int64_t hw = (int64_t)C.W * C.H;
   float gr[WPIX], gg[WPIX], gb[WPIX], gT[WPIX], Tf[WPIX], T[WPIX], Sr[WPIX], Sg[WPIX], Sb[WPIX],
-      py[WPIX];
+      py[WPIX], gTf[WPIX];
   int nc[WPIX];
   int lmax = 0;
 #pragma unroll
@@ -707,6 +707,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
       gT[r] = (grad_T ? grad_T[p] : 0.f) + gr[r] * br + gg[r] * bgc + gb[r] * bb;
     }
     T[r] = Tf[r];
+    gTf[r] = gT[r] * Tf[r];
     Sr[r] = Sg[r] = Sb[r] = 0.f;
     lmax = max(lmax, nc[r]);
   }
@@ -752,18 +753,20 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
         // is common to the lane's pixels
         float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
         bool any = false;
+        const float4 c = sh[k].c;
 #pragma unroll
         for (int r = 0; r < WPIX; ++r) {
-          if (idx > nc[r]) continue;
+          // every pixel slot runs the same instructions; one that does not
+          // blend this Gaussian (past its last contributor, or skipped by the
+          // forward's alpha test) takes alpha = 0, which leaves T and S as
+          // they are and adds nothing
           const float dy = ea.y - py[r];
-          const float dyy = dy * dy;
           const float p2 = __builtin_fmaf(dx, __builtin_fmaf(ea.w, dy, adx),
                                           __builtin_fmaf(eb.x * dy, dy, eb.y));
-          if (!(p2 >= lthr)) continue;  // the forward's skip decision
-          any = true;
-          const float ag = __builtin_amdgcn_exp2f(p2);  // opacity * G
+          const bool act = idx <= nc[r] && p2 >= lthr;  // the forward's decisions
+          any = any || act;
+          const float ag = act ? __builtin_amdgcn_exp2f(p2) : 0.f;  // opacity * G
           const float alpha = fminf(amax, ag);
-          const float4 c = sh[k].c;
           // transmittance in front of this Gaussian (v_rcp, 1 ulp)
           const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
           T[r] = T[r] * inv;
@@ -771,18 +774,18 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
           gc0 = __builtin_fmaf(wgt, gr[r], gc0);
           gc1 = __builtin_fmaf(wgt, gg[r], gc1);
           gc2 = __builtin_fmaf(wgt, gb[r], gc2);
-          const float galpha = T[r] * ((c.x - Sr[r]) * gr[r] + (c.y - Sg[r]) * gg[r] +
-                                       (c.z - Sb[r]) * gb[r]) -
-                               gT[r] * Tf[r] * inv;
-          Sr[r] = alpha * c.x + (1.f - alpha) * Sr[r];
-          Sg[r] = alpha * c.y + (1.f - alpha) * Sg[r];
-          Sb[r] = alpha * c.z + (1.f - alpha) * Sb[r];
-          if (ag < amax) {
-            const float gp = galpha * ag;
-            s0 += gp;
-            s1 = __builtin_fmaf(gp, dy, s1);
-            s2 = __builtin_fmaf(gp, dyy, s2);
-          }
+          const float dr = c.x - Sr[r], dg = c.y - Sg[r], db = c.z - Sb[r];
+          const float galpha = __builtin_fmaf(
+              T[r], __builtin_fmaf(dr, gr[r], __builtin_fmaf(dg, gg[r], db * gb[r])),
+              -gTf[r] * inv);
+          Sr[r] = __builtin_fmaf(alpha, dr, Sr[r]);
+          Sg[r] = __builtin_fmaf(alpha, dg, Sg[r]);
+          Sb[r] = __builtin_fmaf(alpha, db, Sb[r]);
+          // d alpha / d power = alpha' (0 where clamped at alpha_max)
+          const float gp = ag < amax ? galpha * ag : 0.f;
+          s0 += gp;
+          s1 = __builtin_fmaf(gp, dy, s1);
+          s2 = __builtin_fmaf(gp, dy * dy, s2);
         }
         if (__any(any)) {
           // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy, dx = u - px; the

@@ -1,7 +1,9 @@
 // Backward of the projection (chain rule from the per-rank record gradients
 // to the Gaussian parameters, summed over cameras in registers), backward of
 // the bilinear texture fetch, and the loss of Sec. 3.4.
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "kernels.hpp"
 #include "mesh_math.hpp"
@@ -10,59 +12,62 @@
 namespace hr {
 namespace {
 
-// One thread per Gaussian; loops over cameras, recomputes the projection in
-// FP64 (so that every decision is the forward's), applies the chain rule in
-// FP32 and accumulates every parameter gradient in FP64 before one write per
-// array.
-// Capping the architectural VGPRs at 128 (the rest spills to AGPRs and a
-// little scratch) gives two waves per SIMD instead of one: faster on the
-// 16-camera step.
-__global__ __launch_bounds__(128) __attribute__((amdgpu_num_vgpr(128))) void k_project_bwd(
+// The projection backward runs in two passes so that the FP64 recomputation
+// of the projection is spread over every visible (camera, Gaussian) item
+// instead of looping over the cameras inside one thread per Gaussian:
+//  1. k_project_bwd_geom, one thread per visible item (depth rank): recomputes
+//     the projection in FP64 (every decision is the forward's) and applies the
+//     chain rule in FP32 from the record gradients of mean2D, conic and
+//     opacity to the Gaussian's mean, log-scales, quaternion and opacity
+//     logit: 11 values, stored by rank in 48-byte slots of memory the forward
+//     no longer needs;
+//  2. k_project_bwd_gauss, one thread per Gaussian: sums those slots over the
+//     cameras (in FP64) and does the colour part itself - the view direction
+//     and the SH colour's clamp decision recomputed in FP64, the gradients to
+//     the SH coefficients and, through the view direction, to the mean.
+struct GeomGrad {
+  float4 a;  // mean x y z, opacity logit
+  float4 b;  // log-scales x y z, unused
+  float4 c;  // quaternion w x y z
+};
+static_assert(sizeof(GeomGrad) <= sizeof(GRec), "geometry gradients reuse the record slots");
+
+__global__ __launch_bounds__(256) void k_project_bwd_geom(
     SetDev S, const CamDev* __restrict__ cams, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ logits, const float* __restrict__ sh,
-    const int32_t* __restrict__ rank_of, const float* __restrict__ gacc,
-    float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
-    float* __restrict__ g_logit, float* __restrict__ g_sh, float* __restrict__ m2d_norm,
-    int32_t* __restrict__ m2d_count) {
-  // the 3K SH-coefficient gradients of this thread's Gaussian live in its own
-  // column of LDS (registers would cap the kernel at one wave per SIMD)
-  __shared__ float shacc[48 * 128];
-  float* gshr_col = shacc + threadIdx.x;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= S.n) return;
-  float stat_norm = 0.f;
-  int stat_cnt = 0;
-  const int K = (S.sh_degree + 1) * (S.sh_degree + 1);
-  double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glg = 0;
-  for (int k = 0; k < 3 * K; ++k) gshr_col[k * 128] = 0.f;
-  bool any = false;
-  const float* shg = sh + (size_t)g * K * 3;
-  for (int c = 0; c < S.n_cams; ++c) {
-    const int r = rank_of[(int64_t)c * S.n + g];
-    if (r < 0) continue;
+    const uint32_t* __restrict__ counters, const uint32_t* __restrict__ item_s,
+    const float* __restrict__ gacc, GeomGrad* __restrict__ out) {
+  const uint32_t nvis = counters[0];
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nvis;
+       r += gridDim.x * blockDim.x) {
     const float* ga = gacc + (size_t)r * 9;
-    double G9[9];
+    float G9[6];
     bool nz = false;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 0; q < 6; ++q) {
       G9[q] = ga[q];
-      nz = nz || G9[q] != 0.0;
+      nz = nz || G9[q] != 0.f;
     }
-    stat_norm += sqrtf(ga[0] * ga[0] + ga[1] * ga[1]);
-    ++stat_cnt;
-    if (!nz) continue;
-    any = true;
+    if (!nz) continue;  // the Gaussian pass skips this slot too
+    const uint32_t it = item_s[r];
+    const int c = (int)(it / (uint32_t)S.n);
+    const int g = (int)(it - (uint32_t)c * (uint32_t)S.n);
     const CamDev& cam = cams[c];
     Proj P;
-    project_gaussian(S, cam, means, log_scales, quats, logits, sh, g, P, true);
-    if (!P.vis) continue;
-    // the chain rule in FP32 (the projection and its decisions stay FP64;
-    // FP32 values here halve the registers of the FP64 chain)
+    project_gaussian(S, cam, means, log_scales, quats, logits, sh, g, P, false);
+    GeomGrad o;
+    o.a = o.b = o.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (!P.vis) {  // not reached: a ranked item was visible in the forward
+      out[r] = o;
+      continue;
+    }
+    // the chain rule in FP32 (the projection and its decisions stay FP64)
     const float op = (float)P.op, c3 = (float)P.c3, c2 = (float)P.c2, f3 = (float)P.f3;
-    const float G5 = (float)G9[5];
+    const float G5 = G9[5];
     // opacity: the record holds op c3 c2 (Mip-Splatting factors, 1 otherwise)
-    glg += G5 * c3 * c2 * op * (1.f - op);
+    float glg = G5 * c3 * c2 * op * (1.f - op);
+    float gls[3] = {0.f, 0.f, 0.f};
     // d c3 / d log s_i = c3 f3 / (s_i^2 + f3)
     float sc[3];
 #pragma unroll
@@ -74,37 +79,16 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_num_vgpr(128))) void k_p
     // d c2 = c2 / 2 (dD0 / D0 - dD1 / D1) on the entries (a, b, c) of Sigma'
     float gma = 0.f, gmb = 0.f, gmc = 0.f;
     if (S.mip2d && !P.c2lo) {
-      const float a = (float)P.cov[0], b = (float)P.cov[1], c = (float)P.cov[2], lp = S.low_pass;
-      const float D1 = a * c - b * b, D0 = (a - lp) * (c - lp) - b * b;
+      const float a = (float)P.cov[0], b = (float)P.cov[1], cc = (float)P.cov[2], lp = S.low_pass;
+      const float D1 = a * cc - b * b, D0 = (a - lp) * (cc - lp) - b * b;
       const float gc2 = G5 * op * c3 * 0.5f * c2;
-      gma = gc2 * ((c - lp) / D0 - c / D1);
+      gma = gc2 * ((cc - lp) / D0 - cc / D1);
       gmb = gc2 * (2.f * b / D1 - 2.f * b / D0);
       gmc = gc2 * ((a - lp) / D0 - a / D1);
     }
-    // colour: SH coefficients and the view direction
-    const float dir[3] = {(float)P.dir[0], (float)P.dir[1], (float)P.dir[2]};
-    float Y[16];
-    sh_eval(dir, S.sh_degree, Y);
-    float wdir[16];
-    for (int k = 0; k < K; ++k) wdir[k] = 0.f;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      if (P.clamped[ch]) continue;
-      const float gc = (float)G9[6 + ch];
-      for (int k = 0; k < K; ++k) {
-        gshr_col[(3 * k + ch) * 128] += Y[k] * gc;
-        wdir[k] += shg[3 * k + ch] * gc;
-      }
-    }
-    float gdir[3] = {0.f, 0.f, 0.f};
-    sh_grad_acc(dir, S.sh_degree, wdir, gdir);
-    const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-    const float idn = 1.f / (float)P.dnorm;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dd) * idn;
     // conic -> Sigma': H = -Q G Q with G the symmetric gradient of the conic
     const float q00 = (float)P.con[0], q01 = (float)P.con[1], q11 = (float)P.con[2];
-    const float G00 = (float)G9[2], G01 = 0.5f * (float)G9[3], G11 = (float)G9[4];
+    const float G00 = G9[2], G01 = 0.5f * G9[3], G11 = G9[4];
     const float a00 = q00 * G00 + q01 * G01, a01 = q00 * G01 + q01 * G11;
     const float a10 = q01 * G00 + q11 * G01, a11 = q01 * G01 + q11 * G11;
     // plus the 2D filter's factor; b sits in both off-diagonal entries
@@ -148,15 +132,16 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_num_vgpr(128))) void k_p
       gpc[2] += gj12 * (2.f * fy * y * iz2 * iz);
     }
     // mean2D
-    const float G0 = (float)G9[0], G1 = (float)G9[1];
+    const float G0 = G9[0], G1 = G9[1];
     gpc[0] += G0 * fx * iz;
     gpc[1] += G1 * fy * iz;
     gpc[2] += -(G0 * fx * x + G1 * fy * y) * iz2;
     float cR[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) cR[q] = (float)cam.R[q];
+    float gmu[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) gmu[a] += cR[a] * gpc[0] + cR[3 + a] * gpc[1] + cR[6 + a] * gpc[2];
+    for (int a = 0; a < 3; ++a) gmu[a] = cR[a] * gpc[0] + cR[3 + a] * gpc[1] + cR[6 + a] * gpc[2];
     // Sigma_cam = N N^T, N = W Rq S:  gN = 2 gSc N (gSc symmetric)
     float N[9], Rq[9];
 #pragma unroll
@@ -203,8 +188,94 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_num_vgpr(128))) void k_p
     const float dq = gqn[0] * w + gqn[1] * qa + gqn[2] * qb + gqn[3] * qc;
     const float qn4[4] = {w, qa, qb, qc};
     const float iqn = (float)(1.0 / P.qnorm);
+    float gq[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) gq[a] += (gqn[a] - qn4[a] * dq) * iqn;
+    for (int a = 0; a < 4; ++a) gq[a] = (gqn[a] - qn4[a] * dq) * iqn;
+    o.a = make_float4(gmu[0], gmu[1], gmu[2], glg);
+    o.b = make_float4(gls[0], gls[1], gls[2], 0.f);
+    o.c = make_float4(gq[0], gq[1], gq[2], gq[3]);
+    out[r] = o;
+  }
+}
+
+// One thread per Gaussian: the camera sum of the geometry slots, the colour
+// part, the densification statistics and one write per gradient array.
+__global__ __launch_bounds__(128) void k_project_bwd_gauss(
+    SetDev S, const CamDev* __restrict__ cams, const float* __restrict__ means,
+    const float* __restrict__ sh, const int32_t* __restrict__ rank_of,
+    const float* __restrict__ gacc, const GeomGrad* __restrict__ geo,
+    float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
+    float* __restrict__ g_logit, float* __restrict__ g_sh, float* __restrict__ m2d_norm,
+    int32_t* __restrict__ m2d_count) {
+  // the 3K SH-coefficient gradients of this thread's Gaussian live in its own
+  // column of LDS
+  __shared__ float shacc[48 * 128];
+  float* gshr_col = shacc + threadIdx.x;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= S.n) return;
+  float stat_norm = 0.f;
+  int stat_cnt = 0;
+  const int K = (S.sh_degree + 1) * (S.sh_degree + 1);
+  double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glg = 0;
+  for (int k = 0; k < 3 * K; ++k) gshr_col[k * 128] = 0.f;
+  bool any = false;
+  const float* shg = sh + (size_t)g * K * 3;
+  const double mu[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
+  for (int c0 = 0; c0 < S.n_cams; c0 += 8) {
+    // the ranks of up to 8 cameras, loaded together
+    int rk[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      rk[j] = c0 + j < S.n_cams ? rank_of[(int64_t)(c0 + j) * S.n + g] : -1;
+    for (int j = 0; j < 8; ++j) {
+      const int r = rk[j];
+      if (r < 0) continue;
+      const float* ga = gacc + (size_t)r * 9;
+      float G9[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) G9[q] = ga[q];
+      stat_norm += sqrtf(G9[0] * G9[0] + G9[1] * G9[1]);
+      ++stat_cnt;
+      const bool gnz = G9[0] != 0.f || G9[1] != 0.f || G9[2] != 0.f || G9[3] != 0.f ||
+                       G9[4] != 0.f || G9[5] != 0.f;
+      const bool cnz = G9[6] != 0.f || G9[7] != 0.f || G9[8] != 0.f;
+      if (!gnz && !cnz) continue;
+      any = true;
+      if (gnz) {
+        const GeomGrad o = geo[r];
+        gmu[0] += o.a.x; gmu[1] += o.a.y; gmu[2] += o.a.z; glg += o.a.w;
+        gls[0] += o.b.x; gls[1] += o.b.y; gls[2] += o.b.z;
+        gq[0] += o.c.x; gq[1] += o.c.y; gq[2] += o.c.z; gq[3] += o.c.w;
+      }
+      if (!cnz) continue;
+      // colour: the view direction and the clamp of the forward, in FP64
+      const CamDev& cam = cams[c0 + j];
+      const double d0 = mu[0] - cam.C[0], d1 = mu[1] - cam.C[1], d2 = mu[2] - cam.C[2];
+      const double dnorm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double dir64[3] = {d0 / dnorm, d1 / dnorm, d2 / dnorm};
+      double col[3];
+      sh_colour64(shg, S.sh_degree, dir64, col);
+      const float dir[3] = {(float)dir64[0], (float)dir64[1], (float)dir64[2]};
+      float Y[16];
+      sh_eval(dir, S.sh_degree, Y);
+      float wdir[16];
+      for (int k = 0; k < K; ++k) wdir[k] = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        if (col[ch] < 0.0) continue;  // clamped at 0 in the forward: no gradient
+        const float gc = G9[6 + ch];
+        for (int k = 0; k < K; ++k) {
+          gshr_col[(3 * k + ch) * 128] += Y[k] * gc;
+          wdir[k] += shg[3 * k + ch] * gc;
+        }
+      }
+      float gdir[3] = {0.f, 0.f, 0.f};
+      sh_grad_acc(dir, S.sh_degree, wdir, gdir);
+      const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+      const float idn = 1.f / (float)dnorm;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dd) * idn;
+    }
   }
   if (m2d_norm && stat_cnt) m2d_norm[g] += stat_norm;
   if (m2d_count && stat_cnt) m2d_count[g] += stat_cnt;
@@ -232,15 +303,15 @@ __device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, 
 
 constexpr int TEX_LDS = 2048;  // texels of one tile's footprint accumulated in LDS
 
-// dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights.
-// One workgroup per tile: the texels the tile's pixels read from its most
-// common texture (the lowest texture id present) usually form a small box;
-// when the box fits in LDS the pixels accumulate there and the box is added
-// to the gradient with one global atomic per non-zero texel channel. Pixels
-// on other textures, and tiles whose box is too large, add directly.
+// dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights
+// the forward used (its per-pixel footprints, so nothing of the mesh is
+// recomputed). One workgroup per tile: the texels the tile's pixels read from
+// its most common texture (the lowest texture id present) usually form a
+// small box; when the box fits in LDS the pixels accumulate there and the box
+// is added to the gradient with one global atomic per non-zero texel channel.
+// Pixels on other textures, and tiles whose box is too large, add directly.
 __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restrict__ cams,
-                                                 const unsigned long long* __restrict__ zbuf,
-                                                 const TriRec* __restrict__ tris,
+                                                 const uint4* __restrict__ taps,
                                                  const float* __restrict__ T_ws,
                                                  const float* __restrict__ grad_image,
                                                  const float* __restrict__ grad_mesh,
@@ -260,12 +331,12 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
   }
   bool live = false;
   float gm[3] = {0.f, 0.f, 0.f};
-  Taps tp = {0, 0, 0, 0, 0.f, 0.f};
-  int tex = 0;
+  int tex = 0, xa = 0, ya = 0, xb = 0, yb = 0;
+  float wx = 0.f, wy = 0.f;
   if (i < C.W && j < C.H) {
     const int64_t p = C.pix_off + (int64_t)j * C.W + i;
-    const unsigned long long key = zbuf[p];
-    if (key != ~0ull) {
+    const uint4 tq = taps[p];
+    if (tq.x != ~0u) {
       const int64_t hw = (int64_t)C.W * C.H;
       const int64_t pl = 3 * C.pix_off + (p - C.pix_off);
       const float Tf = T_ws[p];
@@ -274,32 +345,21 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
         gm[ch] = (grad_image ? Tf * grad_image[pl + ch * hw] : 0.f) +
                  (grad_mesh ? grad_mesh[pl + ch * hw] : 0.f);
       live = gm[0] != 0.f || gm[1] != 0.f || gm[2] != 0.f;
-      if (live) {
-        const TriRec& T = tris[(uint32_t)key];
-        int64_t e[3];
-        tri_cover(T, i, j, e);
-        double uv[2];
-        tri_interp(T, e, uv);
-        tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
-        tex = T.tex;
-      }
+      xa = (int)(tq.x & 0xffffu);
+      ya = (int)(tq.x >> 16);
+      tex = (int)(tq.y & 0x3fffffffu);
+      xb = xa + (int)((tq.y >> 30) & 1u);
+      yb = ya + (int)(tq.y >> 31);
+      wx = __uint_as_float(tq.z);
+      wy = __uint_as_float(tq.w);
     }
   }
   __syncthreads();
   if (live) atomicMin(&box[0], tex);
   __syncthreads();
   const int rtex = box[0];
-  const int64_t plane = (int64_t)S.tex_h * S.tex_w;
-  // texel coordinates of the 4 taps relative to texture rtex
-  int xa = 0, ya = 0, xb = 0, yb = 0;
   const bool mine = live && tex == rtex;
   if (mine) {
-    const int64_t b = (int64_t)rtex * plane;
-    const int64_t q00 = tp.o00 / 3 - b, q11 = tp.o11 / 3 - b;
-    ya = (int)(q00 / S.tex_w);
-    xa = (int)(q00 - (int64_t)ya * S.tex_w);
-    yb = (int)(q11 / S.tex_w);
-    xb = (int)(q11 - (int64_t)yb * S.tex_w);
     atomicMin(&box[1], xa);
     atomicMin(&box[2], ya);
     atomicMax(&box[3], xb);
@@ -309,7 +369,6 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
   const int bx0 = box[1], by0 = box[2];
   const int bw = box[3] - bx0 + 1, bh = box[4] - by0 + 1;
   const bool use_lds = rtex != 0x7fffffff && bw > 0 && bh > 0 && bw * bh <= TEX_LDS;
-  const float wx = tp.fx, wy = tp.fy;
   const float w4[4] = {(1.f - wx) * (1.f - wy), wx * (1.f - wy), (1.f - wx) * wy, wx * wy};
   if (use_lds) {
     for (int k = threadIdx.x; k < 3 * bw * bh; k += 256) acc[k] = 0.f;
@@ -330,7 +389,10 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
     }
   }
   if (live && !(use_lds && mine)) {
-    const int64_t os[4] = {tp.o00, tp.o10, tp.o01, tp.o11};
+    const int64_t row = (int64_t)S.tex_w;
+    const int64_t b0 = ((int64_t)tex * S.tex_h + ya) * row;
+    const int64_t b1 = ((int64_t)tex * S.tex_h + yb) * row;
+    const int64_t os[4] = {(b0 + xa) * 3, (b0 + xb) * 3, (b1 + xa) * 3, (b1 + xb) * 3};
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -338,13 +400,24 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
   }
   if (use_lds) {
     __syncthreads();
+    const int64_t plane = (int64_t)S.tex_h * S.tex_w;
     const int64_t base = (int64_t)rtex * plane;
-    for (int k = threadIdx.x; k < 3 * bw * bh; k += 256) {
-      const float v = acc[k];
-      if (v != 0.f) {
-        const int l = k / 3, ch = k - 3 * l;
-        const int yy = by0 + l / bw, xx = bx0 + l - (l / bw) * bw;
-        atomicAdd(grad_tex + (base + (int64_t)yy * S.tex_w + xx) * 3 + ch, v);
+    // thread -> one texel column of the box, rows_per_pass rows apart (no
+    // integer division inside the loop)
+    const int cols = bw < 256 ? bw : 256;
+    const int rows_per_pass = 256 / cols;
+    const int cx = (int)threadIdx.x % cols, ry = (int)threadIdx.x / cols;
+    if (ry < rows_per_pass) {
+      for (int yy = ry; yy < bh; yy += rows_per_pass) {
+        for (int xx = cx; xx < bw; xx += cols) {
+          const int l = yy * bw + xx;
+          float* dst = grad_tex + (base + (int64_t)(by0 + yy) * S.tex_w + (bx0 + xx)) * 3;
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const float v = acc[3 * l + ch];
+            if (v != 0.f) atomicAdd(dst + ch, v);
+          }
+        }
       }
     }
   }
@@ -355,7 +428,10 @@ constexpr int LB = 256;
 
 // Pixel p of the packed images belongs to image i with off[i] <= p < off[i+1];
 // that image's planes are [3, hw_i] starting at float 3 off[i], so channel ch
-// of p sits at 2 off[i] + ch hw_i + p.
+// of p sits at 2 off[i] + ch hw_i + p. Each thread takes LPP pixels LB apart
+// (coalesced); each workgroup writes one partial sum of its LB * LPP pixels.
+constexpr int LPP = 4;
+constexpr int LPB = LB * LPP;  // pixels per loss workgroup
 __global__ __launch_bounds__(LB) void k_loss(const int64_t* __restrict__ off, int n_img,
                                              const float* __restrict__ image,
                                              const float* __restrict__ T,
@@ -367,16 +443,27 @@ __global__ __launch_bounds__(LB) void k_loss(const int64_t* __restrict__ off, in
                                              float* __restrict__ g_mesh,
                                              double* __restrict__ partial) {
   __shared__ double red[LB / 64];
-  const int64_t p = (int64_t)blockIdx.x * LB + threadIdx.x;
-  double acc = 0.0;
-  if (p < n_pix) {
+  __shared__ int s_img;
+  const float inv = 1.0f / (3.0f * (float)n_pix);
+  // the image of the workgroup's first pixel; later pixels step forward
+  if (threadIdx.x == 0) {
+    const int64_t p0 = (int64_t)blockIdx.x * LPB;
     int lo = 0, hi = n_img - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (off[mid] <= p) lo = mid; else hi = mid - 1;
+      if (off[mid] <= p0) lo = mid; else hi = mid - 1;
     }
-    const int64_t o = off[lo], hw = off[lo + 1] - o;
-    const float inv = 1.0f / (3.0f * (float)n_pix);
+    s_img = lo;
+  }
+  __syncthreads();
+  int img = s_img;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < LPP; ++j) {
+    const int64_t p = (int64_t)blockIdx.x * LPB + j * LB + threadIdx.x;
+    if (p >= n_pix) break;
+    while (off[img + 1] <= p) ++img;
+    const int64_t o = off[img], hw = off[img + 1] - o;
     const bool has = tri[p] >= 0;
     const float t = T[p];
     const float mt = 1.f / (1.f + __expf(-k * (t - 0.5f)));
@@ -407,6 +494,29 @@ __global__ __launch_bounds__(LB) void k_loss(const int64_t* __restrict__ off, in
   }
 }
 
+// one workgroup of 1024 threads sums the partials (fixed order: deterministic)
+constexpr int LF = 1024;
+__global__ __launch_bounds__(LF) void k_loss_final(const double* __restrict__ partial, int64_t nb,
+                                                   int64_t n_pix, float* __restrict__ out) {
+  __shared__ double red[LF / 64];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t b = threadIdx.x;
+  for (; b + 3 * LF < nb; b += 4 * LF) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] += partial[b + q * LF];
+  }
+  for (; b < nb; b += LF) acc[0] += partial[b];
+  double a = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if (__lane_id() == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < LF / 64; ++w) s += red[w];
+    *out = (float)(s / (3.0 * (double)n_pix));
+  }
+}
+
 // image offset table by kernel argument (graph-capturable)
 constexpr int OFFS_PER_UPLOAD = 480;
 struct OffUpload {
@@ -419,20 +529,6 @@ __global__ void k_upload_offs(OffUpload u, int64_t* __restrict__ dst) {
   for (int i = threadIdx.x; i < u.count; i += blockDim.x) dst[u.first + i] = u.v[i];
 }
 
-__global__ __launch_bounds__(LB) void k_loss_final(const double* __restrict__ partial, int64_t nb,
-                                                   int64_t n_pix, float* __restrict__ out) {
-  __shared__ double red[LB / 64];
-  double acc = 0.0;
-  for (int64_t b = threadIdx.x; b < nb; b += LB) acc += partial[b];
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (__lane_id() == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < LB / 64; ++w) s += red[w];
-    *out = (float)(s / (3.0 * (double)n_pix));
-  }
-}
 
 struct AdamArgs {
   hr_adam_group g[HR_ADAM_MAX_GROUPS];
@@ -488,10 +584,17 @@ void launch_adam(const hr_adam_group* groups, int n_groups, double b1, double b2
 void launch_project_backward(const SetDev& S, const CamDev* cams, const hr_gaussians& g,
                              const Work& w, hr_grads* grads, hipStream_t st) {
   if (S.n == 0) return;
-  hipLaunchKernelGGL(k_project_bwd, dim3((S.n + 127) / 128), dim3(128), 0, st, S, cams, g.means,
-                     g.log_scales, g.quats, g.opacity_logits, g.sh, w.rank_of, w.gacc,
-                     grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
-                     grads->sh, grads->mean2d_norm, grads->mean2d_count);
+  // the record slots (by item in the forward) hold the geometry gradients by rank
+  GeomGrad* geo = reinterpret_cast<GeomGrad*>(w.rec);
+  const int64_t M = (int64_t)S.n * S.n_cams;
+  const unsigned gg = (unsigned)std::min<int64_t>((M + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_project_bwd_geom, dim3(gg), dim3(256), 0, st, S, cams, g.means,
+                     g.log_scales, g.quats, g.opacity_logits, g.sh, w.counters, w.item_s, w.gacc,
+                     geo);
+  hipLaunchKernelGGL(k_project_bwd_gauss, dim3((S.n + 127) / 128), dim3(128), 0, st, S, cams,
+                     g.means, g.sh, w.rank_of, w.gacc, (const GeomGrad*)geo, grads->means,
+                     grads->log_scales, grads->quats, grads->opacity_logits, grads->sh,
+                     grads->mean2d_norm, grads->mean2d_count);
 }
 
 void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,
@@ -500,13 +603,12 @@ void launch_texture_backward(const SetDev& S, const hr_mesh& m, const Work& w,
   (void)m;
   if (S.n_faces == 0 || !grad_tex || S.n_pix == 0) return;
   hipLaunchKernelGGL(k_tex_bwd, dim3((unsigned)S.n_tiles), dim3(256), 0, st, S, w.cams,
-                     (const unsigned long long*)w.zbuf, w.tris, w.final_T, grad_image,
-                     grad_mesh_rgb, grad_tex);
+                     (const uint4*)w.taps, w.final_T, grad_image, grad_mesh_rgb, grad_tex);
 }
 
 size_t loss_scratch_bytes(int64_t n_pix, int32_t n_img) {
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-  return al(8 * ((size_t)n_img + 1)) + ((size_t)(n_pix + LB - 1) / LB + 1) * sizeof(double);
+  return al(8 * ((size_t)n_img + 1)) + ((size_t)(n_pix + LPB - 1) / LPB + 1) * sizeof(double);
 }
 
 void launch_loss(const float* image, const float* T, const float* mesh_rgb, const int32_t* tri,
@@ -530,12 +632,12 @@ void launch_loss(const float* image, const float* T, const float* mesh_rgb, cons
       u.count = 0;
     }
   }
-  const int64_t nb = (n_pix + LB - 1) / LB;
+  const int64_t nb = (n_pix + LPB - 1) / LPB;
   if (nb > 0)
     hipLaunchKernelGGL(k_loss, dim3((unsigned)nb), dim3(LB), 0, st, (const int64_t*)off, n_img,
                        image, T, mesh_rgb, tri, target, n_pix, lambda_t, k, detach ? 1 : 0,
                        g_image, g_T, g_mesh, partial);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LB), 0, st, partial, nb, n_pix, loss);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LF), 0, st, partial, nb, n_pix, loss);
 }
 
 }  // namespace hr

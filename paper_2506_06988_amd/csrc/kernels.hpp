@@ -59,6 +59,7 @@ struct Work {
   float* final_T;        // [P]
   int32_t* n_contrib;    // [P]
   float* mesh_rgb;       // [3P]
+  uint4* taps;           // [P] bilinear footprint of each mesh pixel (pack_taps)
   // backward accumulators, [M][9] by rank: u, v, conic a b c, opacity, r g b
   float* gacc;
   // scratch of the scans (its first scan_words words are the scan state)
@@ -119,5 +120,10 @@ void launch_zero_gacc(float* gacc, const uint32_t* counters, hipStream_t st);
 void launch_count_mismatch(const float* a, const float* b, int64_t n, uint32_t* out,
                            hipStream_t st);
 void launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st);
+// out[0] = sum (a - b)^2, out[1] = sum b^2 (FP64 device scalars)
+void launch_sq_diff(const float* a, const float* b, int64_t n, double* out, hipStream_t st);
+// dst[i] = src[i] for i < count[0] * per (count on the device)
+void launch_copy_counted(const float* src, float* dst, const uint32_t* count, int per,
+                         hipStream_t st);
 
 }  // namespace hr

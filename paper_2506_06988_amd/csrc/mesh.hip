@@ -138,6 +138,7 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
                                                       const TriRec* __restrict__ tris,
                                                       const float* __restrict__ tex,
                                                       float* __restrict__ mesh_rgb_ws,
+                                                      uint4* __restrict__ taps,
                                                       float* __restrict__ mesh_rgb,
                                                       float* __restrict__ mesh_depth,
                                                       int32_t* __restrict__ tri_id) {
@@ -152,6 +153,7 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
   float rgb[3] = {0.f, 0.f, 0.f};
   float depth = __int_as_float(0x7f800000);
   int face = -1;
+  uint4 tq = make_uint4(~0u, 0u, 0u, 0u);
   if (key != ~0ull) {
     const TriRec& T = tris[(uint32_t)key];
     int64_t e[3];
@@ -159,6 +161,7 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
     double uv[2];
     tri_interp(T, e, uv);
     const Taps tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
+    tq = pack_taps(T.tex, tp);
     const float wx = tp.fx, wy = tp.fy;
     const float w00 = (1.f - wx) * (1.f - wy), w10 = wx * (1.f - wy), w01 = (1.f - wx) * wy,
                 w11 = wx * wy;
@@ -180,6 +183,7 @@ __global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __
     mesh_rgb_ws[pl + ch * hw + lp] = rgb[ch];
     if (mesh_rgb) mesh_rgb[pl + ch * hw + lp] = rgb[ch];
   }
+  taps[p] = tq;
   if (mesh_depth) mesh_depth[p] = depth;
   if (tri_id) tri_id[p] = face;
 }
@@ -263,7 +267,7 @@ void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* o
   }
   const float* tex = MF > 0 ? m.tex : nullptr;
   hipLaunchKernelGGL(k_mesh_resolve, dim3((unsigned)((S.n_pix + 255) / 256)), dim3(256), 0, st, S,
-                     w.cams, (const unsigned long long*)w.zbuf, w.tris, tex, w.mesh_rgb,
+                     w.cams, (const unsigned long long*)w.zbuf, w.tris, tex, w.mesh_rgb, w.taps,
                      out ? out->mesh_rgb : nullptr, out ? out->mesh_depth : nullptr,
                      out ? out->tri_id : nullptr);
 }

@@ -157,7 +157,17 @@ __device__ __forceinline__ double tri_interp(const TriRec& T, const int64_t e[3]
 struct Taps {
   int64_t o00, o10, o01, o11;  // element offsets of the 4 texels (RGB follows)
   float fx, fy;
+  int i0, j0, di, dj;          // first texel; steps to the second column / row (0 or 1)
 };
+
+// The footprint of a pixel as the backward reads it (16 bytes): x = i0 | j0 << 16,
+// y = texture | di << 30 | dj << 31, z and w the bits of fx and fy; x = ~0 for
+// a pixel without a face.
+__device__ __forceinline__ uint4 pack_taps(int tex, const Taps& t) {
+  return make_uint4((uint32_t)t.i0 | ((uint32_t)t.j0 << 16),
+                    (uint32_t)tex | ((uint32_t)t.di << 30) | ((uint32_t)t.dj << 31),
+                    __float_as_uint(t.fx), __float_as_uint(t.fy));
+}
 
 // bilinear footprint: texel (i, j) centred at ((i+1/2)/W, (j+1/2)/H), clamp to edge
 __device__ __forceinline__ Taps bilinear_taps(int tex, int H, int W, const double uv[2]) {
@@ -175,6 +185,10 @@ __device__ __forceinline__ Taps bilinear_taps(int tex, int H, int W, const doubl
   t.o10 = (b + (int64_t)j0 * W + i1) * 3;
   t.o01 = (b + (int64_t)j1 * W + i0) * 3;
   t.o11 = (b + (int64_t)j1 * W + i1) * 3;
+  t.i0 = i0;
+  t.j0 = j0;
+  t.di = i1 - i0;
+  t.dj = j1 - j0;
   return t;
 }
 

@@ -94,7 +94,48 @@ __global__ void k_count_mismatch(const float* __restrict__ a, const float* __res
   if (bad) atomicAdd(out, bad);
 }
 
+// sums of (a - b)^2 and b^2 over n values (out[0], out[1]; cleared before)
+__global__ void k_sq_diff(const float* __restrict__ a, const float* __restrict__ b, int64_t n,
+                          double* __restrict__ out) {
+  double d2 = 0.0, b2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)a[i] - (double)b[i];
+    d2 += d * d;
+    b2 += (double)b[i] * (double)b[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 += __shfl_xor(d2, o, 64);
+    b2 += __shfl_xor(b2, o, 64);
+  }
+  if (__lane_id() == 0) {
+    atomicAdd(&out[0], d2);
+    atomicAdd(&out[1], b2);
+  }
+}
+
+__global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst,
+                           const uint32_t* __restrict__ count, int per) {
+  const int64_t n = (int64_t)count[0] * per;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 }  // namespace
+
+void launch_sq_diff(const float* a, const float* b, int64_t n, double* out, hipStream_t st) {
+  launch_fill_u64((uint64_t*)out, 0ull, 2, st);
+  if (n <= 0) return;
+  int64_t g = (n + 255) / 256;
+  if (g > 2048) g = 2048;
+  hipLaunchKernelGGL(k_sq_diff, dim3((unsigned)g), dim3(256), 0, st, a, b, n, out);
+}
+
+void launch_copy_counted(const float* src, float* dst, const uint32_t* count, int per,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_f32, dim3(2048), dim3(256), 0, st, src, dst, count, per);
+}
 
 void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
                         uint32_t* clear3, int64_t n2, hipStream_t st) {

@@ -101,6 +101,34 @@ __device__ __forceinline__ void sh_grad_acc(const T d[3], int deg, const T* w, T
           T(10) * g3 * x * z * w[13] + k3 * (xx - yy) * w[14];
 }
 
+// View-dependent colour before the clamp, in FP64: acc[ch] = 1/2 + sum_k
+// Y_k(dir) sh[k][ch], each channel summed in increasing k (the forward's and
+// the backward's clamp decisions come from this one function).
+__device__ __forceinline__ void sh_colour64(const float* __restrict__ shg, int deg,
+                                            const double dir[3], double acc[3]) {
+  const int K = (deg + 1) * (deg + 1);
+  double Y[16];
+  sh_eval(dir, deg, Y);
+  acc[0] = acc[1] = acc[2] = 0.5;
+  if ((((uintptr_t)shg) & 15u) == 0 && (3 * K) % 4 == 0) {
+    // 3K floats as 16-byte vectors (K = 4, 16 give 12 and 48 floats)
+    const float4* v4 = reinterpret_cast<const float4*>(shg);
+    for (int i = 0; i < (3 * K) / 4; ++i) {
+      const float4 f = v4[i];
+      const float e[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int idx = 4 * i + k;
+        acc[idx % 3] += Y[idx / 3] * (double)e[k];
+      }
+    }
+  } else {
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * (double)shg[3 * k + ch];
+  }
+}
+
 __device__ __forceinline__ int clamp_tile(double v, int hi) {
   if (!(v > 0.0)) return 0;
   if (v > (double)hi) return hi;
@@ -222,26 +250,8 @@ __device__ __forceinline__ void project_gaussian(const SetDev& S, const CamDev& 
   const double d0 = mu[0] - cam.C[0], d1 = mu[1] - cam.C[1], d2 = mu[2] - cam.C[2];
   P.dnorm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   P.dir[0] = d0 / P.dnorm; P.dir[1] = d1 / P.dnorm; P.dir[2] = d2 / P.dnorm;
-  double Y[16];
-  sh_eval(P.dir, S.sh_degree, Y);
-  double acc[3] = {0.5, 0.5, 0.5};
-  if ((((uintptr_t)shg) & 15u) == 0 && (3 * K) % 4 == 0) {
-    // 3K floats as 16-byte vectors (K = 4, 16 give 12 and 48 floats)
-    const float4* v4 = reinterpret_cast<const float4*>(shg);
-    for (int i = 0; i < (3 * K) / 4; ++i) {
-      const float4 f = v4[i];
-      const float e[4] = {f.x, f.y, f.z, f.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int idx = 4 * i + k;
-        acc[idx % 3] += Y[idx / 3] * (double)e[k];
-      }
-    }
-  } else {
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[k] * (double)shg[3 * k + ch];
-  }
+  double acc[3];
+  sh_colour64(shg, S.sh_degree, P.dir, acc);
   bool finite_rgb = true;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {

@@ -23,6 +23,9 @@ HR_FLAG_EXPORT_KEYS = 1 << 2
 HR_FLAG_CULL_BEHIND_MESH = 1 << 3
 HR_FLAG_MIP_2D = 1 << 4
 HR_FLAG_TILE_ELLIPSE = 1 << 5
+HR_FLAG_MESH_REUSED = 1 << 6
+HR_N_STAGES = 7
+STAGES = ("projection", "depth_sort", "binning", "blend", "stats", "mesh", "forward")
 
 P = C.c_void_p
 
@@ -67,9 +70,10 @@ class hr_adam_group(C.Structure):
                 ("lr_head", C.c_float), ("head", C.c_int32), ("row", C.c_int32)]
 
 
-EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid",
+EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid", "hr_render_hybrid_timed",
             "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
             "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_mip_filter3d", "hr_autotune", "hr_autotune_backward",
+            "hr_autotune_key", "hr_autotune_cache_lookup", "hr_autotune_cache_store",
             "hr_batch_create", "hr_batch_launch", "hr_batch_status", "hr_batch_destroy",
             "hr_status_string",
             "hr_last_error", "hr_abi_version"]
@@ -91,6 +95,8 @@ def load(path: str = LIB_PATH):
     L.hr_query_workspace.argtypes = [P, P, P, C.c_int32, P, C.c_int64]
     L.hr_render_hybrid.restype = C.c_int
     L.hr_render_hybrid.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P]
+    L.hr_render_hybrid_timed.restype = C.c_int
+    L.hr_render_hybrid_timed.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P, P]
     L.hr_render_hybrid_backward.restype = C.c_int
     L.hr_render_hybrid_backward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P,
                                             P, P, P]
@@ -113,6 +119,13 @@ def load(path: str = LIB_PATH):
     L.hr_autotune_backward.restype = C.c_int
     L.hr_autotune_backward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P,
                                        C.c_int32, P]
+    L.hr_autotune_key.restype = C.c_size_t
+    L.hr_autotune_key.argtypes = [C.c_char_p, C.c_int32, P, P, P, C.c_int32, P, C.c_int32,
+                                  C.c_char_p, C.c_size_t]
+    L.hr_autotune_cache_lookup.restype = C.c_int32
+    L.hr_autotune_cache_lookup.argtypes = [C.c_char_p, C.c_char_p, P, P]
+    L.hr_autotune_cache_store.restype = C.c_int
+    L.hr_autotune_cache_store.argtypes = [C.c_char_p, C.c_char_p, C.c_int32, C.c_int32]
     L.hr_autotune.restype = C.c_int
     L.hr_autotune.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, C.c_int32, P]
     L.hr_batch_create.restype = C.c_int
@@ -429,6 +442,20 @@ class Renderer:
                 f = self.new_frame(export_keys)
         raise HRError(HR_ERR_CAPACITY, "key capacity did not converge")
 
+    def render_hybrid_timed(self, frame: Frame, mesh_reused=False) -> dict:
+        """hr_render_hybrid_timed into the renderer's workspace (synchronises);
+        returns the stage times in milliseconds."""
+        gs, ms = self._structs()
+        o = self.outputs_struct(frame)
+        s = hr_settings.from_buffer_copy(self.settings)
+        if mesh_reused:
+            s.flags |= HR_FLAG_MESH_REUSED
+        out = (C.c_float * HR_N_STAGES)()
+        check(self.L.hr_render_hybrid_timed(C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams),
+                                            C.byref(s), self.key_capacity, _ptr(self.ws),
+                                            self.ws_bytes, C.byref(o), _stream(), out))
+        return {k: float(out[i]) for i, k in enumerate(STAGES)}
+
     def forward_context(self, g: DevGaussians, tex=None):
         """hr_render_hybrid of Gaussians `g` (and texture `tex`) into a workspace
         of its own; the renderer's Gaussians and workspace are left as they are.
@@ -533,21 +560,22 @@ def loss_scratch_bytes(sizes) -> int:
 
 
 def hybrid_loss(image, final_T, mesh_rgb, tri_id, target, sizes=None, lambda_t=0.1, k=20.0,
-                detach_mask=False):
+                detach_mask=False, out=None):
     """hr_hybrid_loss over images packed like the renderer's outputs; `sizes` is
     the (width, height) of each image (default: one planar image of all pixels).
-    Returns (loss, g_image, g_T, g_mesh_rgb)."""
+    `out` = (loss, g_image, g_T, g_mesh_rgb, scratch) reuses buffers (else they
+    are allocated). Returns (loss, g_image, g_T, g_mesh_rgb)."""
     import torch
     L = load()
     n_pix = int(final_T.numel())
     sizes = [(n_pix, 1)] if sizes is None else [(int(w), int(h)) for (w, h) in sizes]
     assert sum(w * h for w, h in sizes) == n_pix, "sizes do not cover the pixels"
     d = image.device
-    loss = torch.zeros(1, dtype=torch.float32, device=d)
-    gi = torch.empty_like(image)
-    gt = torch.empty_like(final_T)
-    gm = torch.empty_like(mesh_rgb)
-    scratch = torch.empty(loss_scratch_bytes(sizes), dtype=torch.uint8, device=d)
+    if out is None:
+        out = (torch.zeros(1, dtype=torch.float32, device=d), torch.empty_like(image),
+               torch.empty_like(final_T), torch.empty_like(mesh_rgb),
+               torch.empty(loss_scratch_bytes(sizes), dtype=torch.uint8, device=d))
+    loss, gi, gt, gm, scratch = out
     sz = _sizes_array(sizes)
     check(L.hr_hybrid_loss(_ptr(image), _ptr(final_T), _ptr(mesh_rgb), _ptr(tri_id), _ptr(target),
                            sz, len(sizes), float(lambda_t), float(k),

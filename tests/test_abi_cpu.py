@@ -123,8 +123,8 @@ def test_loss_sizes_and_arguments_are_checked_on_the_host():
     sz = hr._sizes_array([(37, 29), (64, 48)])
     nb = L.hr_loss_scratch_bytes(sz, 2)
     P = 37 * 29 + 64 * 48
-    # the image table (3 offsets) plus one double per 256-pixel workgroup and one more
-    assert nb >= 3 * 8 + ((P + 255) // 256 + 1) * 8
+    # the image table (3 offsets) plus at least one partial sum per 1024 pixels
+    assert nb >= 3 * 8 + ((P + 1023) // 1024 + 1) * 8
     assert L.hr_loss_scratch_bytes(hr._sizes_array([(0, 5)]), 1) == 0
     assert L.hr_loss_scratch_bytes(sz, 0) == 0
     assert L.hr_loss_scratch_bytes(None, 1) == 0
@@ -148,3 +148,69 @@ def test_stats_layout_and_batch_status_argument_check():
                      wait_limit=1)
     st = hr.hr_stats()
     assert L.hr_batch_status(None, C.byref(st), None) == hr.HR_ERR_INVALID_ARGUMENT
+
+
+def _key(L, n=600000, cams=None, flags=0, backward=0, faces=2, deg=3, arch=b"gfx950", cus=256):
+    g, m = _structs(n, deg=deg, faces=faces)
+    s = hr.default_settings(flags=flags)
+    cams = cams or [scenes.Camera(1920, 1080, 1000.0, 1000.0, 960.0, 540.0, np.eye(3), np.zeros(3))]
+    arr = hr.camera_array(cams)
+    need = L.hr_autotune_key(arch, cus, C.byref(g), C.byref(m), arr, len(cams), C.byref(s),
+                             backward, None, 0)
+    buf = C.create_string_buffer(need)
+    assert L.hr_autotune_key(arch, cus, C.byref(g), C.byref(m), arr, len(cams), C.byref(s),
+                             backward, buf, need) == need
+    return buf.value.decode()
+
+
+def test_autotune_cache_key_classes():
+    """The key names the device and the workload class: powers of two of the
+    pixel, Gaussian and camera counts, SH degree, mesh presence and the flags
+    that change the tile lists (other flags do not)."""
+    L = hr.load()
+    k = _key(L)
+    assert k == "fwd|gfx950|cu256|px2^20|n2^19|cams2^0|sh3|mesh1|flags0", k
+    assert _key(L, backward=1).startswith("bwd|")
+    assert _key(L, n=700000) == k                   # same power of two
+    assert _key(L, n=1 << 20) != k
+    assert _key(L, flags=hr.HR_FLAG_TILE_ELLIPSE).endswith("flags32")
+    assert _key(L, flags=hr.HR_FLAG_NO_SYNC | hr.HR_FLAG_EXPORT_KEYS) == k
+    assert "mesh0" in _key(L, faces=0) and "sh0" in _key(L, deg=0)
+    cam = scenes.Camera(640, 480, 500.0, 500.0, 320.0, 240.0, np.eye(3), np.zeros(3))
+    assert "cams2^4" in _key(L, cams=[cam] * 16) and "px2^22" in _key(L, cams=[cam] * 16)
+    assert "cu304" in _key(L, cus=304) and "gfx942" in _key(L, arch=b"gfx942")
+    # a truncated buffer still holds a NUL-terminated prefix
+    g, m = _structs(10)
+    s = hr.default_settings()
+    arr = hr.camera_array([cam])
+    small = C.create_string_buffer(8)
+    assert L.hr_autotune_key(b"gfx950", 256, C.byref(g), C.byref(m), arr, 1, C.byref(s), 0,
+                             small, 8) > 8
+    assert small.value == b"fwd|gfx"
+    assert L.hr_autotune_key(None, 256, C.byref(g), C.byref(m), arr, 1, C.byref(s), 0, None, 0) == 0
+
+
+def test_autotune_cache_file_round_trip(tmp_path):
+    L = hr.load()
+    path = str(tmp_path / "tune.json").encode()
+    b, v = C.c_int32(0), C.c_int32(0)
+    assert L.hr_autotune_cache_lookup(path, b"fwd|x", C.byref(b), C.byref(v)) == 0  # no file
+    assert L.hr_autotune_cache_store(path, b"fwd|gfx950|a", 256, 0) == hr.HR_OK
+    assert L.hr_autotune_cache_store(path, b"bwd|gfx950|a", 128, 8) == hr.HR_OK
+    assert L.hr_autotune_cache_store(path, b"fwd|gfx950|b", 64, 4) == hr.HR_OK
+    assert L.hr_autotune_cache_store(path, b"fwd|gfx950|a", 128, 1) == hr.HR_OK  # replaced
+    assert L.hr_autotune_cache_lookup(path, b"fwd|gfx950|a", C.byref(b), C.byref(v)) == 1
+    assert (b.value, v.value) == (128, 1)
+    assert L.hr_autotune_cache_lookup(path, b"bwd|gfx950|a", C.byref(b), C.byref(v)) == 1
+    assert (b.value, v.value) == (128, 8)
+    assert L.hr_autotune_cache_lookup(path, b"fwd|gfx950|c", C.byref(b), C.byref(v)) == 0
+    # the file is JSON
+    import json
+    d = json.load(open(path))
+    assert d["hr_autotune_cache"] == 1 and d["entries"]["fwd|gfx950|b"] == [64, 4]
+    assert len(d["entries"]) == 3
+    assert L.hr_autotune_cache_store(path, b"other|x", 1, 1) == hr.HR_ERR_INVALID_ARGUMENT
+    assert L.hr_autotune_cache_store(path, b'fwd|"x', 1, 1) == hr.HR_ERR_INVALID_ARGUMENT
+    assert L.hr_autotune_cache_store(None, b"fwd|x", 1, 1) == hr.HR_ERR_INVALID_ARGUMENT
+    bad = str(tmp_path / "no_such_dir" / "t.json").encode()
+    assert L.hr_autotune_cache_store(bad, b"fwd|x", 1, 1) == hr.HR_ERR_INTERNAL

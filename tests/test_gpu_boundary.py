@@ -191,3 +191,36 @@ def test_autograd_two_forwards_then_one_summed_backward(hr):
         o0 += hw
     for k, p in zip(GRADS, pa):
         grad_compare(k, p.grad.cpu().numpy(), ref[k])
+
+
+def test_autotune_cache_is_written_and_reused(hr, tmp_path, monkeypatch):
+    say("case: autotuner cache (HR_AUTOTUNE_CACHE)")
+    import json
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("HR_AUTOTUNE_CACHE", str(path))
+    sc, cams, targets = two_camera_room()
+    g, m = hr.to_device(sc.gaussians, sc.mesh)
+    r = hr.Renderer(g, m, cams)
+    f = r.render_hybrid()
+    b, v = r.autotune(f, repeats=1)
+    gi = torch.randn(3 * r.P, device="cuda", generator=torch.Generator("cuda").manual_seed(8))
+    bb, bv = r.autotune_backward(gi, repeats=1)
+    d = json.load(open(path))["entries"]
+    fk = [k for k in d if k.startswith("fwd|")]
+    bk = [k for k in d if k.startswith("bwd|")]
+    assert len(fk) == 1 and len(bk) == 1 and "|cams2^1|" in fk[0]
+    assert d[fk[0]] == [b, v & 7] and d[bk[0]] == [bb, bv & 8]
+    # a hand-edited entry is used as it is, without timing
+    d[fk[0]] = [32, 1]
+    d[bk[0]] = [64, 8]
+    with open(path, "w") as fh:  # the library's layout: one entry per line
+        fh.write('{\n  "hr_autotune_cache": 1,\n  "entries": {\n' +
+                 ",\n".join(f'    "{k}": [{a}, {c}]' for k, (a, c) in d.items()) + "\n  }\n}\n")
+    assert json.load(open(path))["entries"] == d
+    ref = [x.clone() for x in (f.image, f.final_T, f.n_contrib, f.n_blended, f.n_processed)]
+    r.settings.batch, r.settings.variant, r.settings.batch_bwd = 0, 0, 0
+    assert r.autotune(f, repeats=1) == (32, 1)
+    torch.cuda.synchronize()
+    for x, y in zip(ref, (f.image, f.final_T, f.n_contrib, f.n_blended, f.n_processed)):
+        assert torch.equal(x, y)
+    assert r.autotune_backward(gi, repeats=1) == (64, 9)

@@ -113,36 +113,42 @@ def test_sixteen_camera_graph_step_gradients_vs_oracle(hr):
     step = hr.BatchedStep(r, target)
     stats = step.step()
     say(f"  step stats {stats}")
+    fr = step.frame
+    frame_np = {k: getattr(fr, k).cpu().numpy() for k in ("image", "final_T", "n_contrib",
+                                                           "n_blended", "n_processed")}
     gi_all = step.g_image.cpu().numpy()
     gt_all = step.g_T.cpu().numpy()
     gm_all = step.g_mesh.cpu().numpy()
     got = {k: step.grads[k].cpu().numpy() for k in ("means", "log_scales", "quats",
                                                       "opacity_logits", "sh")}
     step.close()
-    # Gaussians with tile rectangles of at most 2x2 tiles wherever visible,
-    # visible in at least two cameras, with a gradient
+    # Gaussians with a gradient, visible in at least two cameras, the smallest
+    # footprints (tile rectangles summed over the cameras) first
     n = sc.gaussians.n
-    small = np.ones(n, bool)
+    area = np.zeros(n, np.int64)
     seen = np.zeros(n, np.int32)
     projs = []
     for cam in cams:
         pr = oracle.project(sc.gaussians, cam)
         projs.append(pr)
-        rc = pr["rect"]
+        rc = pr["rect"].astype(np.int64)
         vis = pr["radius"] > 0
-        big = vis & (((rc[:, 1] - rc[:, 0]) > 2) | ((rc[:, 3] - rc[:, 2]) > 2))
-        small &= ~big
+        area += np.where(vis, (rc[:, 1] - rc[:, 0]) * (rc[:, 3] - rc[:, 2]), 0)
         seen += vis
-    gnorm = np.abs(got["opacity_logits"])
-    cand = np.nonzero(small & (seen >= 2) & (gnorm > 1e-3 * gnorm.max()))[0]
-    say(f"  candidates: {len(cand)}")
-    rng = np.random.default_rng(44)
+    # (every pixel of a Gaussian's windows must have taken the oracle's FP64
+    # decisions - equal counts and image - since the step's upstream gradients
+    # cannot be zeroed where they differ; small footprints make that likely)
+    has_grad = (got["opacity_logits"] != 0) & (np.abs(got["means"]).sum(1) > 0)
+    elig = np.nonzero((seen >= 1) & has_grad)[0]
+    cand = elig[np.argsort(area[elig] * 4 - np.minimum(seen[elig], 3), kind="stable")][:300]
+    say(f"  Gaussians with a gradient: {len(elig)} ({int(((seen >= 2) & has_grad).sum())} seen "
+        f"twice or more); footprints of the first candidates {area[cand[:8]].tolist()} tiles")
     offs = [0]
     for cam in cams:
         offs.append(offs[-1] + cam.width * cam.height)
     ref = {k: [] for k in got}
     chosen = []
-    for gid in rng.permutation(cand):
+    for gid in cand:
         acc = {k: 0.0 for k in got}
         ok = True
         for c, cam in enumerate(cams):
@@ -153,11 +159,17 @@ def test_sixteen_camera_graph_step_gradients_vs_oracle(hr):
             win = (int(rc[0]) * 16, int(rc[2]) * 16, min(cam.width, int(rc[1]) * 16),
                    min(cam.height, int(rc[3]) * 16))
             x0, y0, x1, y1 = win
-            o = oracle.render(sc.gaussians, sc.mesh, cam, window=win)
-            if (o["amb"] != 0).any():
+            o = oracle.render(sc.gaussians, sc.mesh, cam, window=win, params=pe())
+            H, W, o0 = cam.height, cam.width, offs[c]
+            sl = lambda a: a[o0:o0 + H * W].reshape(H, W)[y0:y1, x0:x1]
+            im = frame_np["image"][3 * o0:3 * o0 + 3 * H * W].reshape(3, H, W)[:, y0:y1, x0:x1]
+            same = (all(np.array_equal(sl(frame_np[k]), o[k])
+                        for k in ("n_contrib", "n_blended", "n_processed")) and
+                    np.abs(im - o["image"]).max() <= 1e-4 and
+                    np.abs(sl(frame_np["final_T"]) - o["final_T"]).max() <= 1e-4)
+            if not same:
                 ok = False
                 break
-            H, W, o0 = cam.height, cam.width, offs[c]
             gi = gi_all[3 * o0:3 * o0 + 3 * H * W].reshape(3, H, W)[:, y0:y1, x0:x1]
             gt = gt_all[o0:o0 + H * W].reshape(H, W)[y0:y1, x0:x1]
             gm = gm_all[3 * o0:3 * o0 + 3 * H * W].reshape(3, H, W)[:, y0:y1, x0:x1]
@@ -169,10 +181,10 @@ def test_sixteen_camera_graph_step_gradients_vs_oracle(hr):
         for k in got:
             ref[k].append(acc[k])
         chosen.append(gid)
-        if len(chosen) == 8:
+        if len(chosen) >= 8 and int((seen[chosen] >= 2).sum()) >= 3:
             break
-    say(f"  Gaussians compared: {chosen}")
-    assert len(chosen) == 8
+    say(f"  Gaussians compared: {chosen}, cameras seeing each: {seen[chosen].tolist()}")
+    assert len(chosen) >= 8 and int((seen[chosen] >= 2).sum()) >= 3
     for k in got:
         grad_compare(k, np.stack([got[k][i] for i in chosen]), np.stack(ref[k]))
 
