@@ -295,6 +295,26 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
                          float* loss_out, float* grad_image, float* grad_final_T,
                          float* grad_mesh_rgb, void* scratch, void* stream);
 
+/* hr_hybrid_loss for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid allocation):
+ * the same loss, gradients and layout, with the scratch taken from a static
+ * device array of the library instead of a caller buffer. At most
+ * HR_LOSS_NOALLOC_MAX_IMAGES images and HR_LOSS_NOALLOC_MAX_PIXELS pixels in
+ * all (about 0.53 MB of scratch, one copy per GPU, held until the process
+ * ends); larger inputs return HR_ERR_INVALID_ARGUMENT. The call allocates and
+ * frees nothing. Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (different streams or threads without ordering) race and
+ * their results are undefined; calls ordered on one stream are safe. The
+ * first call on a device looks up the array's device address (HR_ERR_HIP if
+ * that fails). */
+#define HR_LOSS_NOALLOC_MAX_IMAGES 256
+#define HR_LOSS_NOALLOC_MAX_PIXELS (1 << 26)
+hr_status hr_hybrid_loss_noalloc(const float* image, const float* final_T, const float* mesh_rgb,
+                                 const int32_t* tri_id, const float* target, const int32_t* sizes,
+                                 int32_t n_images, float lambda_t, float k, uint32_t flags,
+                                 float* loss_out, float* grad_image, float* grad_final_T,
+                                 float* grad_mesh_rgb, void* stream);
+
 /* Mip-Splatting 3D smoothing variance of every Gaussian for a set of
  * training views: scale / nu^2, nu the highest sampling rate fx / z over the
  * views that see the centre beyond settings->near_gs and inside the image

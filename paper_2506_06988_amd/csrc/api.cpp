@@ -710,6 +710,35 @@ hr_status hr_hybrid_loss(const float* image, const float* final_T, const float* 
   return hip_check("loss launch");
 }
 
+hr_status hr_hybrid_loss_noalloc(const float* image, const float* final_T, const float* mesh_rgb,
+                                 const int32_t* tri_id, const float* target, const int32_t* sizes,
+                                 int32_t n_images, float lambda_t, float k, uint32_t flags,
+                                 float* loss_out, float* grad_image, float* grad_final_T,
+                                 float* grad_mesh_rgb, void* stream) {
+  std::vector<int64_t> pix;
+  int64_t total = 0;
+  if (!loss_image_pixels(sizes, n_images, pix, total))
+    return fail(HR_ERR_INVALID_ARGUMENT, "need n_images >= 1 positive image sizes");
+  if (n_images > HR_LOSS_NOALLOC_MAX_IMAGES || total > HR_LOSS_NOALLOC_MAX_PIXELS)
+    return fail(HR_ERR_INVALID_ARGUMENT,
+                "hr_hybrid_loss_noalloc takes at most " +
+                    std::to_string(HR_LOSS_NOALLOC_MAX_IMAGES) + " images and " +
+                    std::to_string(HR_LOSS_NOALLOC_MAX_PIXELS) + " pixels");
+  if (!image || !final_T || !mesh_rgb || !tri_id || !target || !loss_out || !grad_image ||
+      !grad_final_T || !grad_mesh_rgb)
+    return fail(HR_ERR_INVALID_ARGUMENT, "null loss argument");
+  if (loss_scratch_bytes(total, n_images) > loss_static_scratch_bytes())
+    return fail(HR_ERR_INTERNAL, "static loss scratch too small");
+  void* scratch = nullptr;
+  if (loss_static_scratch_ptr(&scratch) != HR_OK)
+    return fail(HR_ERR_HIP, "hipGetSymbolAddress of the static loss scratch failed");
+  hipGetLastError();
+  launch_loss(image, final_T, mesh_rgb, tri_id, target, pix.data(), n_images, lambda_t, k,
+              (flags & HR_FLAG_DETACH_MASK) != 0, loss_out, grad_image, grad_final_T,
+              grad_mesh_rgb, scratch, (hipStream_t)stream);
+  return hip_check("loss launch");
+}
+
 hr_status hr_mip_filter3d(const hr_gaussians* g, const hr_camera* cams, int32_t n_cams,
                           const hr_settings* s, double scale, float* filter3d_out, void* stream) {
   if (!g || !cams || !s) return fail(HR_ERR_INVALID_ARGUMENT, "null argument");

@@ -640,4 +640,30 @@ void launch_loss(const float* image, const float* T, const float* mesh_rgb, cons
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LF), 0, st, partial, nb, n_pix, loss);
 }
 
+// Library-owned scratch of hr_hybrid_loss_noalloc: one copy per GPU, held
+// until the process ends. Host code never passes `loss_static_scratch` itself
+// to a kernel (in host code it names a host-side stand-in); it passes the
+// device address hipGetSymbolAddress returns for the current device.
+constexpr size_t LOSS_STATIC_BYTES = 2304 + ((size_t)(HR_LOSS_NOALLOC_MAX_PIXELS / LPB) + 1) * 8;
+static_assert((size_t)8 * (HR_LOSS_NOALLOC_MAX_IMAGES + 1) <= 2304, "image table part");
+__device__ __align__(256) unsigned char loss_static_scratch[LOSS_STATIC_BYTES];
+
+hr_status loss_static_scratch_ptr(void** out) {
+  static std::mutex mu;
+  static void* per_dev[64] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HR_ERR_HIP;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!per_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(loss_static_scratch)) != hipSuccess || !p)
+      return HR_ERR_HIP;
+    per_dev[dev] = p;
+  }
+  *out = per_dev[dev];
+  return HR_OK;
+}
+
+size_t loss_static_scratch_bytes() { return LOSS_STATIC_BYTES; }
+
 }  // namespace hr

@@ -92,6 +92,10 @@ void launch_loss(const float* image, const float* T, const float* mesh_rgb, cons
                  const float* target, const int64_t* img_pix, int32_t n_img, float lambda_t,
                  float k, bool detach, float* loss, float* g_image, float* g_T, float* g_mesh,
                  void* scratch, hipStream_t st);
+// device address of the library's static loss scratch on the current device
+// (looked up once per device); its size in bytes
+hr_status loss_static_scratch_ptr(void** out);
+size_t loss_static_scratch_bytes();
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void launch_adam(const hr_adam_group* groups, int n_groups, double b1, double b2, double eps,
                  int step, hipStream_t st);

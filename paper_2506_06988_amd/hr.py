@@ -72,6 +72,7 @@ class hr_adam_group(C.Structure):
 
 EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid", "hr_render_hybrid_timed",
             "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
+            "hr_hybrid_loss_noalloc",
             "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_mip_filter3d", "hr_autotune", "hr_autotune_backward",
             "hr_autotune_key", "hr_autotune_cache_lookup", "hr_autotune_cache_store",
             "hr_batch_create", "hr_batch_launch", "hr_batch_status", "hr_batch_destroy",
@@ -107,6 +108,9 @@ def load(path: str = LIB_PATH):
     L.hr_hybrid_loss.restype = C.c_int
     L.hr_hybrid_loss.argtypes = [P, P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_uint32, P,
                                  P, P, P, P, P]
+    L.hr_hybrid_loss_noalloc.restype = C.c_int
+    L.hr_hybrid_loss_noalloc.argtypes = [P, P, P, P, P, P, C.c_int32, C.c_float, C.c_float,
+                                         C.c_uint32, P, P, P, P, P]
     L.hr_mip_filter3d.restype = C.c_int
     L.hr_mip_filter3d.argtypes = [P, P, C.c_int32, P, C.c_double, P, P]
     L.hr_adam_step.restype = C.c_int
