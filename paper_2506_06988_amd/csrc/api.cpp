@@ -4,6 +4,8 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <cerrno>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -86,10 +88,22 @@ bool cache_read(const char* path, TuneMap& m) {
     const std::string key = line.substr(q0 + 1, q1 - q0 - 1);
     if (key.rfind("fwd|", 0) != 0 && key.rfind("bwd|", 0) != 0) continue;
     const size_t br = line.find('[', q1);
-    int b = 0, v = 0;
-    if (br == std::string::npos || std::sscanf(line.c_str() + br, "[%d , %d]", &b, &v) != 2)
-      continue;
-    m[key] = {b, v};
+    if (br == std::string::npos) continue;
+    // "[batch, variant]" with both values in int range; anything else is skipped
+    const char* c = line.c_str() + br + 1;
+    char* end = nullptr;
+    errno = 0;
+    const long long b = std::strtoll(c, &end, 10);
+    if (end == c || errno != 0 || b < INT32_MIN || b > INT32_MAX) continue;
+    c = end;
+    while (*c == ' ') ++c;
+    if (*c++ != ',') continue;
+    const long long v = std::strtoll(c, &end, 10);
+    if (end == c || errno != 0 || v < INT32_MIN || v > INT32_MAX) continue;
+    c = end;
+    while (*c == ' ') ++c;
+    if (*c != ']') continue;
+    m[key] = {(int)b, (int)v};
   }
   return true;
 }
