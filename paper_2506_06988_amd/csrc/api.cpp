@@ -61,7 +61,7 @@ struct Plan {
   int64_t n, n_cams, M, F, MF, P, n_tiles, key_cap, rs_blocks, chunk_rows, mat_entries,
       bin_items;
   size_t cams, counters, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
-      sval1, rs_hist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
+      sval1, rs1, rs_ghist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
       tile_start, tile_order, sched_cnt, sched_sum, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, taps, gacc, tune, scan_scratch, scan_scratch2, total;
   int64_t scan_words;
@@ -267,7 +267,8 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.skey1 = L.take(4 * M);
   p.sval0 = L.take(4 * M);
   p.sval1 = L.take(4 * M);
-  p.rs_hist = L.take(4 * 256 * p.rs_blocks);
+  p.rs1 = L.take(4 * rs1_words_for(p.rs_blocks));
+  p.rs_ghist = L.take(4 * 256 * RS_MAX_PASSES * RS_GHIST_COPIES);
   p.vis_off = L.take(4 * (n_cams + 1));
   p.rec_s = L.take(sizeof(GRec) * M);
   p.rect_s = L.take(8 * M);
@@ -295,7 +296,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.gacc = L.take(36 * M);
   p.tune = L.take((28 * P + 255) / 256 * 256 + 256);
   int64_t longest =
-      std::max<int64_t>({M + 1, 256 * p.rs_blocks, p.n_tiles, p.MF + 1, p.chunk_rows + 1, 1});
+      std::max<int64_t>({M + 1, p.n_tiles, p.MF + 1, p.chunk_rows + 1, 1});
   p.scan_scratch = L.take(scan_scratch_bytes(longest) + 4096);
   p.scan_scratch2 = L.take(scan_scratch_bytes(longest) + 4096);  // the mesh stream's scans
   p.scan_words = (int64_t)scan_state_words(longest);
@@ -318,8 +319,11 @@ Work make_work(const Plan& p, void* ws) {
   w.skey[1] = (uint32_t*)(b + p.skey1);
   w.sval[0] = (uint32_t*)(b + p.sval0);
   w.sval[1] = (uint32_t*)(b + p.sval1);
-  w.rs_hist = (uint32_t*)(b + p.rs_hist);
   w.rs_blocks = p.rs_blocks;
+  w.rs1 = (uint32_t*)(b + p.rs1);
+  w.rs1_words = rs1_words_for(p.rs_blocks);
+  w.rs_ghist = (uint32_t*)(b + p.rs_ghist);
+  w.rs_groups = (p.rs_blocks + RS_GROUP - 1) / RS_GROUP;
   w.vis_off = (uint32_t*)(b + p.vis_off);
   w.rec_s = (GRec*)(b + p.rec_s);
   w.rect_s = (uint2*)(b + p.rect_s);
@@ -429,7 +433,7 @@ void upload_cams(const Plan& p, const Work& w, bool clear_counters, hipStream_t 
     for (int k = 0; k < u.count; ++k) u.c[k] = p.camdev[c0 + k];
     const bool clr = clear_counters && c0 == 0;
     launch_upload_cams(u, w.cams, clr ? w.counters : nullptr, (uint32_t*)w.scan_scratch,
-                       (uint32_t*)w.scan_scratch2, w.scan_words, st);
+                       (uint32_t*)w.scan_scratch2, w.scan_words, clr ? w.rs_ghist : nullptr, st);
   }
 }
 
@@ -959,6 +963,8 @@ hr_status hr_autotune(const hr_gaussians* g, const hr_mesh* mesh, const hr_camer
     }
     std::sort(times.begin(), times.end());
     const float med = times[times.size() / 2];
+    log_line("autotune: batch " + std::to_string(batch) + " variant " + std::to_string(v) +
+             " median " + std::to_string(med) + " ms");
     launch_fill_u32(mism, 0u, 1, st);
     launch_count_mismatch(out->image, ref_img, 3 * p.P, mism, st);
     launch_count_mismatch(w.final_T, ref_T, p.P, mism, st);
@@ -1068,6 +1074,8 @@ hr_status hr_autotune_backward(const hr_gaussians* g, const hr_mesh* mesh, const
     }
     std::sort(times.begin(), times.end());
     const float med = times[times.size() / 2];
+    log_line("backward autotune: batch " + std::to_string(c[0]) + " variant " +
+             std::to_string(c[1]) + " median " + std::to_string(med) + " ms");
     if (med < best) {
       best = med;
       best_b = c[0];

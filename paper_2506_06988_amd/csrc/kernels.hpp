@@ -22,11 +22,19 @@ struct Work {
   GRec* rec;             // [M]
   uint2* rect;           // [M] packed tile rectangle
   int32_t* rank_of;      // [M] depth rank, -1 = culled
-  // depth sort (radix, ping-pong) and per-rank arrays
+  // depth sort (radix, ping-pong; rs_blocks blocks of keys) and per-rank arrays
   uint32_t* skey[2];     // [M]
   uint32_t* sval[2];     // [M]
-  uint32_t* rs_hist;     // [256 * rs_blocks]
   int64_t rs_blocks;
+  // one-dispatch radix passes: per pass a ticket, the global digit counts
+  // (digit 0 from the compaction, digit p + 1 from pass p), and the published
+  // digit counts of every block and of every group of RS_GROUP blocks; the
+  // compaction clears the part of rs1 the passes use, the camera upload
+  // clears rs_ghist
+  uint32_t* rs1;         // [rs1_words]: tickets | group counters | group counts | block counts
+  int64_t rs1_words;
+  uint32_t* rs_ghist;    // [RS_MAX_PASSES][RS_GHIST_COPIES][256]
+  int64_t rs_groups;     // ceil(rs_blocks / RS_GROUP)
   uint32_t* vis_off;     // [n_cams + 1] first rank of each camera
   GRec* rec_s;           // [M] by rank
   uint2* rect_s;         // [M] by rank
@@ -67,6 +75,18 @@ struct Work {
   void* scan_scratch2;  // the same for the mesh pass on the second stream
   int64_t scan_words;
 };
+
+constexpr int RS_MAX_PASSES = 6;  // 4 depth bytes, up to 2 camera bytes
+constexpr int RS_GROUP = 32;      // blocks per published group total
+// copies of the global digit counts: workgroup w adds into copy w % 16, so
+// that the few digits every workgroup holds (the exponent byte of the depths)
+// do not serialise all of their atomics on one address
+constexpr int RS_GHIST_COPIES = 16;
+// words of the one-dispatch radix state for rs_blocks blocks of keys
+inline int64_t rs1_words_for(int64_t rs_blocks) {
+  const int64_t groups = (rs_blocks + RS_GROUP - 1) / RS_GROUP;
+  return 8 + RS_MAX_PASSES * groups + (int64_t)RS_MAX_PASSES * 256 * (groups + rs_blocks);
+}
 
 // host launch wrappers (all asynchronous on `st`)
 void launch_project(const SetDev& S, const CamDev* cams, const hr_gaussians& g, const Work& w,
@@ -113,7 +133,7 @@ struct CamUpload {
 };
 static_assert(sizeof(CamUpload) + 8 <= 4096, "camera upload must fit in kernel arguments");
 void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
-                        uint32_t* clear3, int64_t n2, hipStream_t st);
+                        uint32_t* clear3, int64_t n2, uint32_t* ghist, hipStream_t st);
 void launch_mip_filter3d(const float* means, int n, const CamDev* cams, int n_cams, float near,
                          double scale, float* f3, hipStream_t st);
 // scan1, scan2: the two scan scratch states (word 2 = bounded wait gave up)

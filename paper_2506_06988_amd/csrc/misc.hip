@@ -6,10 +6,10 @@ namespace hr {
 
 namespace {
 
-// also clears the 64 forward counters and `n2` words of each of the two scan
-// states when `clear` is given
+// also clears the 64 forward counters, `n2` words of each of the two scan
+// states and the radix sort's global digit counts when `clear` is given
 __global__ void k_upload_cams(CamUpload u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
-                              uint32_t* clear3, int64_t n2) {
+                              uint32_t* clear3, int64_t n2, uint32_t* ghist) {
   const int k = threadIdx.x;
   if (k < u.count) dst[u.first + k] = u.c[k];
   if (!clear) return;
@@ -18,6 +18,8 @@ __global__ void k_upload_cams(CamUpload u, CamDev* dst, uint32_t* clear, uint32_
     clear2[i] = 0u;
     clear3[i] = 0u;
   }
+  if (ghist)
+    for (int i = k; i < 256 * RS_MAX_PASSES * RS_GHIST_COPIES; i += blockDim.x) ghist[i] = 0u;
 }
 
 // one group of 1024 threads: the counters, and the examined / blended pairs
@@ -138,8 +140,9 @@ void launch_copy_counted(const float* src, float* dst, const uint32_t* count, in
 }
 
 void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
-                        uint32_t* clear3, int64_t n2, hipStream_t st) {
-  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(256), 0, st, u, dst, clear, clear2, clear3, n2);
+                        uint32_t* clear3, int64_t n2, uint32_t* ghist, hipStream_t st) {
+  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(256), 0, st, u, dst, clear, clear2, clear3, n2,
+                     ghist);
 }
 
 void launch_counters_to_stats(const uint32_t* counters, const uint64_t* tile_np, int n_tiles,

@@ -55,10 +55,24 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return valid ? m : 0ull;
 }
 
-// Compaction of the visible items into the first radix-sort buffers; the
-// first n_cams + 1 threads also write each camera's first rank and the total,
-// and thread n_cams the binning items of every camera: (used chunk row, tile
-// row) pairs, item_off[c] the first of camera c, item_off[n_cams] the total.
+// digit `pass` of an item's sort key: bytes 0-3 of the fp32 depth bits, then
+// bytes of the camera index (several cameras)
+__device__ __forceinline__ uint32_t rs_digit(uint32_t key, uint32_t val, int pass, int n) {
+  if (pass < 4) return (key >> (8 * pass)) & 255u;
+  const uint32_t cam = val / (uint32_t)n;
+  return (cam >> (8 * (pass - 4))) & 255u;
+}
+
+// Compaction of the visible items into the first radix-sort buffers, CB_ITEMS
+// items per workgroup; the first n_cams + 1 threads also write each camera's
+// first rank and the total, and thread n_cams the binning items of every
+// camera: (used chunk row, tile row) pairs, item_off[c] the first of camera c,
+// item_off[n_cams] the total. It counts digit 0 of the visible keys into the
+// global digit counts (the counts do not depend on the order; pass p counts
+// digit p + 1) and clears the state the radix passes will use for this number
+// of visible items.
+constexpr int CB_ITEMS = 1024;
+
 __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ vis,
                                                  const uint32_t* __restrict__ vis_scan,
                                                  const uint32_t* __restrict__ dkey, int n,
@@ -67,73 +81,172 @@ __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ vi
                                                  uint32_t* __restrict__ sval,
                                                  uint32_t* __restrict__ vis_off,
                                                  uint32_t* __restrict__ item_off,
-                                                 uint32_t* __restrict__ counters) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                 uint32_t* __restrict__ counters, int passes,
+                                                 uint32_t kpb, uint32_t* __restrict__ ghist,
+                                                 uint32_t* __restrict__ rs1, int64_t groups,
+                                                 int64_t nb_max) {
+  __shared__ uint32_t lh[256];
+  lh[threadIdx.x] = 0u;
   const int64_t M = (int64_t)n * n_cams;
-  if (i < n_cams) {
-    vis_off[i] = vis_scan[i * n];
-  } else if (i == n_cams) {
-    const uint32_t v = vis_scan[M - 1] + vis[M - 1];
-    vis_off[i] = v;
-    counters[0] = v;
+  const uint32_t nv = vis_scan[M - 1] + vis[M - 1];
+  // the radix state of the passes: tickets and group counters whole, then per
+  // pass the group and block counts of the blocks this many keys fill
+  {
+    const int64_t nbk = ((int64_t)nv + kpb - 1) / kpb;
+    const int64_t gk = (nbk + RS_GROUP - 1) / RS_GROUP;
+    const int64_t head = 8 + RS_MAX_PASSES * groups;
+    const int64_t per = 256 * (gk + nbk);
+    const int64_t total = head + passes * per;
+    uint32_t* gpub = rs1 + head;
+    uint32_t* pub = gpub + (int64_t)RS_MAX_PASSES * groups * 256;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+      if (q < head) {
+        rs1[q] = 0u;
+        continue;
+      }
+      const int64_t r = q - head, p = r / per, e = r - p * per;
+      if (e < 256 * gk)
+        gpub[p * groups * 256 + e] = 0u;
+      else
+        pub[p * nb_max * 256 + (e - 256 * gk)] = 0u;
+    }
+  }
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= n_cams;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    if (q < n_cams) {
+      vis_off[q] = vis_scan[q * n];
+      continue;
+    }
+    vis_off[q] = nv;
+    counters[0] = nv;
     uint32_t acc = 0;
     for (int c = 0; c < n_cams; ++c) {
       item_off[c] = acc;
-      const uint32_t end = c + 1 < n_cams ? vis_scan[(int64_t)(c + 1) * n] : v;
+      const uint32_t end = c + 1 < n_cams ? vis_scan[(int64_t)(c + 1) * n] : nv;
       const uint32_t rows = (end - vis_scan[(int64_t)c * n] + CHUNK - 1) / CHUNK;
       acc += rows * (uint32_t)cams[c].TY;
     }
     item_off[n_cams] = acc;
   }
-  if (i >= M || !vis[i]) return;
-  const uint32_t p = vis_scan[i];
-  skey[p] = dkey[i];
-  sval[p] = (uint32_t)i;
-}
-
-__device__ __forceinline__ uint32_t rs_digit(uint32_t key, uint32_t val, int pass, int n) {
-  if (pass < 4) return (key >> (8 * pass)) & 255u;
-  const uint32_t cam = val / (uint32_t)n;
-  return (cam >> (8 * (pass - 4))) & 255u;
-}
-
-// RS_ROUNDS striped rounds of RS_B keys per workgroup (4 or 16, rs_keys_for)
-template <int RS_ROUNDS>
-__global__ __launch_bounds__(RS_B) void k_rs_hist(const uint32_t* __restrict__ key,
-                                                  const uint32_t* __restrict__ val,
-                                                  const uint32_t* __restrict__ counters, int pass,
-                                                  int n, int64_t nb, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  const int64_t i0 = (int64_t)blockIdx.x * CB_ITEMS + threadIdx.x;
   __syncthreads();
-  const uint32_t nv = counters[0];
-  const int64_t base = (int64_t)blockIdx.x * (RS_ROUNDS * RS_B);
-  for (int k = 0; k < RS_ROUNDS; ++k) {
-    const int64_t i = base + k * RS_B + threadIdx.x;
-    if (i < nv) atomicAdd(&h[rs_digit(key[i], val[i], pass, n)], 1u);
+  uint32_t fl[CB_ITEMS / 256], sc[CB_ITEMS / 256], dk[CB_ITEMS / 256];
+#pragma unroll
+  for (int r = 0; r < CB_ITEMS / 256; ++r) {
+    const int64_t i = i0 + 256 * r;
+    fl[r] = i < M ? vis[i] : 0u;
+    sc[r] = i < M ? vis_scan[i] : 0u;
+    dk[r] = i < M ? dkey[i] : 0u;
   }
+#pragma unroll
+  for (int r = 0; r < CB_ITEMS / 256; ++r)
+    if (fl[r]) {
+      skey[sc[r]] = dk[r];
+      sval[sc[r]] = (uint32_t)(i0 + 256 * r);
+      atomicAdd(&lh[rs_digit(dk[r], (uint32_t)(i0 + 256 * r), 0, n)], 1u);
+    }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  const uint32_t c = lh[threadIdx.x];
+  if (c) atomicAdd(&ghist[(blockIdx.x % RS_GHIST_COPIES) * 256 + threadIdx.x], c);
 }
 
-// stable scatter: keys keep their input order within a digit
+// One radix pass in one dispatch. Workgroups take block numbers from a ticket,
+// so a workgroup only ever waits for blocks whose workgroups already run. Each
+// counts the digits of its block of keys and publishes the counts at once
+// (device-coherent words, flagged); the last block of each group of RS_GROUP
+// to publish also publishes the group's sum. A block's offset for digit d is
+// the global offset of d (the digit counts made before the pass) plus the
+// counts of d in the groups and the blocks of its group before it; those
+// published words are read 16 at a time, since each read crosses to another
+// XCD's writes and costs a round trip to memory. The scatter is stable inside
+// the block (lanes ranked by equal digits per wave, waves in order). Each
+// block also counts the next pass's digit of its keys into that pass's global
+// counts.
+constexpr uint32_t RS_PUB = 0x80000000u;
+constexpr uint32_t RS_SPIN_LIMIT = 1u << 16;
+constexpr int RS_BATCH = 16;
+
+__device__ __forceinline__ void rs_publish(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v | RS_PUB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t rs_peek(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// sum of the published words p[q * 256] for q in [q0, q1), waiting for each
+// (bounded: a give-up sets gave_up and counts the word as 0)
+__device__ __forceinline__ uint32_t rs_sum_published(const uint32_t* p, uint32_t q0, uint32_t q1,
+                                                     bool& gave_up) {
+  uint32_t s = 0;
+  for (uint32_t qb = q0; qb < q1; qb += RS_BATCH) {
+    uint32_t v[RS_BATCH];
+#pragma unroll
+    for (int j = 0; j < RS_BATCH; ++j) {
+      const uint32_t q = qb + j < q1 ? qb + j : q1 - 1;
+      v[j] = rs_peek(p + (int64_t)q * 256);
+    }
+#pragma unroll
+    for (int j = 0; j < RS_BATCH; ++j) {
+      if (qb + j >= q1) continue;
+      uint32_t x = v[j];
+      for (uint32_t spins = 0; !(x & RS_PUB); ++spins) {
+        if (spins >= RS_SPIN_LIMIT) {
+          gave_up = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        x = rs_peek(p + (int64_t)(qb + j) * 256);
+      }
+      s += x & ~RS_PUB;
+    }
+  }
+  return s;
+}
+
 template <int RS_ROUNDS>
-__global__ __launch_bounds__(RS_B) void k_rs_scatter(const uint32_t* __restrict__ key,
+__global__ __launch_bounds__(RS_B) void k_rs_onepass(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ val,
                                                      uint32_t* __restrict__ key_out,
                                                      uint32_t* __restrict__ val_out,
                                                      const uint32_t* __restrict__ counters,
-                                                     int pass, int n, int64_t nb,
-                                                     const uint32_t* __restrict__ hist) {
+                                                     int pass, int passes, int n,
+                                                     uint32_t* __restrict__ ghist_all,
+                                                     uint32_t* __restrict__ rs1, int64_t groups,
+                                                     int64_t nb_max,
+                                                     uint32_t* __restrict__ wait_flag) {
   __shared__ uint32_t off[256];
+  __shared__ uint32_t lh[256];
+  __shared__ uint32_t nh[256];
   __shared__ uint32_t wcnt[RS_B / 64][256];
+  __shared__ uint32_t red4[4];
+  __shared__ uint32_t s_b, s_last;
   const int tid = threadIdx.x, w = tid >> 6;
-  off[tid] = hist[(int64_t)tid * nb + blockIdx.x];
-  for (int k = 0; k < RS_B / 64; ++k) wcnt[k][tid] = 0;
-  __syncthreads();
   const uint32_t nv = counters[0];
-  const int64_t base = (int64_t)blockIdx.x * (RS_ROUNDS * RS_B);
-  if (base >= nv) return;
+  constexpr uint32_t KPB = RS_ROUNDS * RS_B;
+  const uint32_t nbk = (nv + KPB - 1) / KPB;
+  // the grid is sized for every item being visible: the surplus leaves at once
+  if (blockIdx.x >= nbk) return;
+  uint32_t* ticket = rs1 + pass;
+  uint32_t* gcnt = rs1 + 8 + (int64_t)pass * groups;
+  uint32_t* gpub = rs1 + 8 + RS_MAX_PASSES * groups + (int64_t)pass * groups * 256;
+  uint32_t* pub = rs1 + 8 + RS_MAX_PASSES * groups + (int64_t)RS_MAX_PASSES * groups * 256 +
+                  (int64_t)pass * nb_max * 256;
+  const uint32_t* ghist = ghist_all + (int64_t)pass * RS_GHIST_COPIES * 256;
+  const bool count_next = pass + 1 < passes;
+  if (tid == 0) s_b = atomicAdd(ticket, 1u);
+  lh[tid] = 0u;
+  nh[tid] = 0u;
+#pragma unroll
+  for (int k = 0; k < RS_B / 64; ++k) wcnt[k][tid] = 0u;
+  // global counts of this thread's digit (the copies summed)
+  uint32_t gd[RS_GHIST_COPIES];
+#pragma unroll
+  for (int c = 0; c < RS_GHIST_COPIES; ++c) gd[c] = ghist[c * 256 + tid];
+  __syncthreads();
+  const uint32_t b = s_b;
+  const int64_t base = (int64_t)b * KPB;
   // every round's keys are loaded up front, so the loads overlap
   uint32_t kr[RS_ROUNDS], vr[RS_ROUNDS];
 #pragma unroll
@@ -142,6 +255,39 @@ __global__ __launch_bounds__(RS_B) void k_rs_scatter(const uint32_t* __restrict_
     kr[r] = i < nv ? key[i] : 0u;
     vr[r] = i < nv ? val[i] : 0u;
   }
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r)
+    if (base + r * RS_B + tid < nv) atomicAdd(&lh[rs_digit(kr[r], vr[r], pass, n)], 1u);
+  __syncthreads();
+  rs_publish(&pub[(int64_t)b * 256 + tid], lh[tid]);
+  if (count_next) {
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r)
+      if (base + r * RS_B + tid < nv) atomicAdd(&nh[rs_digit(kr[r], vr[r], pass + 1, n)], 1u);
+  }
+  uint32_t gsum = 0;
+#pragma unroll
+  for (int c = 0; c < RS_GHIST_COPIES; ++c) gsum += gd[c];
+  uint32_t total;
+  const uint32_t gex = group_excl_scan(gsum, red4, total);  // has barriers
+  if (count_next && nh[tid])
+    atomicAdd(&ghist_all[((int64_t)(pass + 1) * RS_GHIST_COPIES + b % RS_GHIST_COPIES) * 256 + tid],
+              nh[tid]);
+  const uint32_t g = b / RS_GROUP, g0 = g * RS_GROUP;
+  const uint32_t gsize = nbk - g0 < (uint32_t)RS_GROUP ? nbk - g0 : (uint32_t)RS_GROUP;
+  if (tid == 0) s_last = atomicAdd(&gcnt[g], 1u) == gsize - 1 ? 1u : 0u;
+  __syncthreads();
+  bool gave_up = false;
+  // the last of the group to arrive publishes the group's sum
+  if (s_last)
+    rs_publish(&gpub[(int64_t)g * 256 + tid],
+               rs_sum_published(pub + tid, g0, g0 + gsize, gave_up));
+  // the counts of this digit before the block: whole groups, then blocks
+  const uint32_t pre = rs_sum_published(gpub + tid, 0, g, gave_up) +
+                       rs_sum_published(pub + tid, g0, b, gave_up);
+  if (gave_up) atomicOr(wait_flag, 1u);
+  off[tid] = gex + pre;
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t i = base + r * RS_B + tid;
@@ -159,12 +305,12 @@ __global__ __launch_bounds__(RS_B) void k_rs_scatter(const uint32_t* __restrict_
       val_out[pos] = vv;
     }
     __syncthreads();
-    uint32_t s = 0;
+    uint32_t sum = 0;
     for (int k = 0; k < RS_B / 64; ++k) {
-      s += wcnt[k][tid];
+      sum += wcnt[k][tid];
       wcnt[k][tid] = 0;
     }
-    off[tid] += s;
+    off[tid] += sum;
     __syncthreads();
   }
 }
@@ -704,23 +850,21 @@ void launch_depth_sort(const SetDev& S, const Work& w, bool ell, hipStream_t st)
     return;
   }
   scan_u32(w.vis, w.vis_scan, M, nullptr, w.scan_scratch, st);
-  const unsigned gb = (unsigned)((std::max<int64_t>(M, S.n_cams + 1) + 255) / 256);
-  hipLaunchKernelGGL(k_compact, dim3(gb), dim3(256), 0, st, w.vis, w.vis_scan, w.dkey, S.n,
-                     S.n_cams, w.cams, w.skey[0], w.sval[0], w.vis_off, w.item_off, w.counters);
   int passes = 4;
   if (S.n_cams > 1) passes = S.n_cams > 256 ? 6 : 5;
   const int64_t nb = w.rs_blocks;
-  const bool long_sort = rs_keys_for(M) > 1024;
-  auto hist = long_sort ? k_rs_hist<16> : k_rs_hist<4>;
-  auto scat = long_sort ? k_rs_scatter<16> : k_rs_scatter<4>;
+  const int kpb = rs_keys_for(M);
+  const unsigned gb = (unsigned)((std::max<int64_t>(M, S.n_cams + 1) + CB_ITEMS - 1) / CB_ITEMS);
+  hipLaunchKernelGGL(k_compact, dim3(gb), dim3(256), 0, st, w.vis, w.vis_scan, w.dkey, S.n,
+                     S.n_cams, w.cams, w.skey[0], w.sval[0], w.vis_off, w.item_off, w.counters,
+                     passes, (uint32_t)kpb, w.rs_ghist, w.rs1, w.rs_groups, nb);
+  auto pass_k = kpb > 1024 ? k_rs_onepass<16> : k_rs_onepass<4>;
+  uint32_t* wait_flag = (uint32_t*)w.scan_scratch + 2;  // reported with the scans' flag
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(hist, dim3((unsigned)nb), dim3(RS_B), 0, st, w.skey[cur], w.sval[cur],
-                       w.counters, p, S.n, nb, w.rs_hist);
-    scan_u32(w.rs_hist, w.rs_hist, 256 * nb, nullptr, w.scan_scratch, st);
-    hipLaunchKernelGGL(scat, dim3((unsigned)nb), dim3(RS_B), 0, st, w.skey[cur],
-                       w.sval[cur], w.skey[cur ^ 1], w.sval[cur ^ 1], w.counters, p, S.n, nb,
-                       w.rs_hist);
+    hipLaunchKernelGGL(pass_k, dim3((unsigned)nb), dim3(RS_B), 0, st, w.skey[cur], w.sval[cur],
+                       w.skey[cur ^ 1], w.sval[cur ^ 1], w.counters, p, passes, S.n,
+                       w.rs_ghist, w.rs1, w.rs_groups, nb, wait_flag);
     cur ^= 1;
   }
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
