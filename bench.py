@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gaussian-only", action="store_true")
     ap.add_argument("--no-720p", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="for traces: only the 16-camera batched step and the single-view "
+                         "comparison (prints their figures, not the headline line)")
     ap.add_argument("--rect-pairs", action="store_true",
                     help="bin every tile of the 3-sigma rectangle (no tile-ellipse culling)")
     ap.add_argument("--pmc-probe-step", action="store_true",
@@ -156,8 +159,10 @@ def frame_roofline(stage_ms, counts, blend_stats, n_gauss, sh_degree, faces, ble
     nv, nk = counts["n_visible"], counts["n_keys"]
     ex, bl = blend_stats["pairs_examined_per_view"], blend_stats["pairs_blended_per_view"]
     work = {
-        # read every Gaussian's parameters; write a 48-byte record per visible one
-        "projection": ("hbm", n_gauss * 4 * (11 + 3 * K) + nv * 48),
+        # per Gaussian its 11 geometry and opacity floats in, its visibility and rank
+        # out; per visible one its SH coefficients in, depth key, record and
+        # rectangle out (culled Gaussians never need their SH)
+        "projection": ("hbm", n_gauss * (4 * 11 + 8) + nv * (4 * 3 * K + 4 + 48 + 8)),
         # 4 LSD passes over the visible (depth key, index) pairs, each read and written
         "depth_sort": ("hbm", nv * 8 * 2 * 4),
         # one 4-byte rank per kept (tile, Gaussian) pair
@@ -301,6 +306,54 @@ def cpu_baseline(scenes):
     return out
 
 
+def batched_step(torch, hr, scenes, dev, args, result):
+    """The 16-camera hipGraph training step (forward, loss, backward), then the
+    same cameras through the plain single-view path; fills `result`."""
+    s4 = scenes.config4()
+    g, m = hr.to_device(s4.gaussians, s4.mesh, device=dev)
+    r = hr.Renderer(g, m, s4.cameras, settings=hr.default_settings(flags=PAIR_CULL))
+    f = r.render_hybrid(sync_check=True)
+    torch.cuda.synchronize()
+    target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
+    r.autotune(f, repeats=2)
+    L0, gi0, gt0, _ = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target,
+                                      r.sizes)
+    r.autotune_backward(gi0, gt0, repeats=2)
+    log(f"batched tuning: forward batch {r.settings.batch}, backward batch "
+        f"{r.settings.batch_bwd}, variant {r.settings.variant}")
+    del L0, gi0, gt0
+    step = hr.BatchedStep(r, target)
+    for _ in range(2):
+        step.launch()
+    step.stream.synchronize()
+    nst = max(4, args.steps // 8)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(step.stream)
+    for _ in range(nst):
+        step.launch()
+    e1.record(step.stream)
+    step.stream.synchronize()
+    bsec = e0.elapsed_time(e1) / 1e3 / nst
+    views_s = len(s4.cameras) / bsec
+    log(f"batched fwd+bwd (16 cams, graph): {bsec * 1e3:.2f} ms/step, {views_s:.1f} views/s, "
+        f"loss {step.loss.item():.5f}")
+    result["batched_fwd_bwd_views_per_s"] = round(views_s, 2)
+    result["batched_tuning"] = {"batch": int(r.settings.batch),
+                                "batch_bwd": int(r.settings.batch_bwd),
+                                "variant": int(r.settings.variant)}
+    result["batched_ms_per_step"] = round(bsec * 1e3, 3)
+    step.close()
+    # the plain single-view path on the same GPU: the 16 cameras one by one
+    parts = [torch.as_tensor(t.reshape(-1)).to(dev) for t in s4.target]
+    sv_ms = single_view_steps(torch, hr, s4, g, m, r.settings, parts, dev)
+    log(f"single-view fwd+bwd of the 16 cameras one by one: {sv_ms:.2f} ms "
+        f"({len(s4.cameras) / sv_ms * 1e3:.1f} views/s)")
+    result["single_view_fwd_bwd_views_per_s"] = round(len(s4.cameras) / sv_ms * 1e3, 2)
+    result["batched_vs_single_view"] = round(sv_ms / (bsec * 1e3), 3)
+    del step, r, f, g, m, s4, parts
+    torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -324,6 +377,11 @@ def main():
         return
     if args.pmc_probe_step:
         pmc_probe_step(torch, hr, scenes, dev)
+        return
+    if args.batched_only:
+        part = {}
+        batched_step(torch, hr, scenes, dev, args, part)
+        print(json.dumps(part), flush=True)
         return
 
     # ----------------------------------------------------- headline: 1080p
@@ -487,49 +545,7 @@ def main():
 
     # --------------------------------------------------- batched fwd + bwd
     if not args.no_batched:
-        s4 = scenes.config4()
-        g, m = hr.to_device(s4.gaussians, s4.mesh, device=dev)
-        r = hr.Renderer(g, m, s4.cameras, settings=hr.default_settings(flags=PAIR_CULL))
-        f = r.render_hybrid(sync_check=True)
-        torch.cuda.synchronize()
-        target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
-        r.autotune(f, repeats=2)
-        L0, gi0, gt0, _ = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target,
-                                          r.sizes)
-        r.autotune_backward(gi0, gt0, repeats=2)
-        log(f"batched tuning: forward batch {r.settings.batch}, backward batch "
-            f"{r.settings.batch_bwd}, variant {r.settings.variant}")
-        del L0, gi0, gt0
-        step = hr.BatchedStep(r, target)
-        for _ in range(2):
-            step.launch()
-        step.stream.synchronize()
-        nst = max(4, args.steps // 8)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(step.stream)
-        for _ in range(nst):
-            step.launch()
-        e1.record(step.stream)
-        step.stream.synchronize()
-        bsec = e0.elapsed_time(e1) / 1e3 / nst
-        views_s = len(s4.cameras) / bsec
-        log(f"batched fwd+bwd (16 cams, graph): {bsec * 1e3:.2f} ms/step, {views_s:.1f} views/s, "
-            f"loss {step.loss.item():.5f}")
-        result["batched_fwd_bwd_views_per_s"] = round(views_s, 2)
-        result["batched_tuning"] = {"batch": int(r.settings.batch),
-                                    "batch_bwd": int(r.settings.batch_bwd),
-                                    "variant": int(r.settings.variant)}
-        result["batched_ms_per_step"] = round(bsec * 1e3, 3)
-        step.close()
-        # the plain single-view path on the same GPU: the 16 cameras one by one
-        parts = [torch.as_tensor(t.reshape(-1)).to(dev) for t in s4.target]
-        sv_ms = single_view_steps(torch, hr, s4, g, m, r.settings, parts, dev)
-        log(f"single-view fwd+bwd of the 16 cameras one by one: {sv_ms:.2f} ms "
-            f"({len(s4.cameras) / sv_ms * 1e3:.1f} views/s)")
-        result["single_view_fwd_bwd_views_per_s"] = round(len(s4.cameras) / sv_ms * 1e3, 2)
-        result["batched_vs_single_view"] = round(sv_ms / (bsec * 1e3), 3)
-        del step, r, f, g, m, s4, parts
-        torch.cuda.empty_cache()
+        batched_step(torch, hr, scenes, dev, args, result)
 
     # ------------------------------------------------------- CPU baseline
     if not args.no_cpu_baseline:
