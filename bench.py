@@ -37,15 +37,20 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # addressing and loop control are not counted.
 BLEND_OPS_EXAMINED = 11
 BLEND_OPS_BLENDED = 7
+# FP32 atomic adds (no return) per second to scattered addresses of a 64 MiB
+# buffer, measured on this GPU (2.4e11/s when the lanes of a wave hit consecutive
+# words): the ceiling of the texture backward, whose atomics land on the texels
+# of minified textures, far apart from one pixel to the next
+ATOMICS_PER_S = 2.1e10
 # HBM bytes per blend launch over the 32 headline views, by (batch, variant),
 # from the FETCH_SIZE and WRITE_SIZE counter passes of `bench.py --pmc-probe`
 # (scaled by a 256 MiB copy: FETCH x2, WRITE x1), tile-ellipse binning; valid
 # for the blend kernels they were taken with
-BLEND_TRAFFIC = {(32, 0): 165.9e6, (32, 1): 166.2e6, (32, 2): 161.0e6, (32, 3): 161.4e6,
-                 (64, 0): 166.1e6, (64, 1): 166.8e6, (64, 2): 161.3e6, (64, 3): 162.0e6,
-                 (64, 4): 166.4e6, (128, 0): 166.5e6, (128, 1): 167.5e6, (128, 2): 161.7e6,
+BLEND_TRAFFIC = {(32, 0): 165.9e6, (32, 1): 166.2e6, (32, 2): 161.2e6, (32, 3): 161.8e6,
+                 (64, 0): 166.1e6, (64, 1): 166.8e6, (64, 2): 161.6e6, (64, 3): 162.3e6,
+                 (64, 4): 166.4e6, (128, 0): 166.5e6, (128, 1): 167.6e6, (128, 2): 161.8e6,
                  (128, 3): 162.7e6, (128, 4): 166.9e6, (256, 0): 167.3e6, (256, 1): 168.8e6,
-                 (256, 2): 162.2e6, (256, 3): 163.8e6}
+                 (256, 2): 162.5e6, (256, 3): 163.6e6}
 # every configuration the forward autotuner may choose
 BLEND_CONFIGS = [(b, v) for v in range(4) for b in (32, 64, 128, 256)] + [(64, 4), (128, 4)]
 # pairs outside the alpha >= alpha_min ellipse are skipped by every pixel:
@@ -184,6 +189,38 @@ def frame_roofline(stage_ms, counts, blend_stats, n_gauss, sh_degree, faces, ble
             out[k]["GB_per_s"] = round(amount / (meas * 1e-3) / 1e9, 1)
     out["frame"] = {"roof_ms": round(total_roof, 5), "measured_ms": round(stage_ms["forward"], 5),
                     "frac": round(total_roof / stage_ms["forward"], 4)}
+    return out
+
+
+# lane-operations of the backward per blended (pixel, Gaussian) pair: the pair's
+# exponent, alpha and T recovery (12), colour and alpha gradients (10), the
+# running colour behind it (3), the power gradient and its three sums (5)
+BWD_OPS_BLENDED = 30
+# HBM bytes of the projection backward: per Gaussian its parameters in and
+# their gradients out plus the per-Gaussian sums (560 B at SH degree 3), per
+# visible (Gaussian, camera) item its 9 accumulated gradients (36 B)
+PROJ_BWD_BYTES_PER_G, PROJ_BWD_BYTES_PER_ITEM = 560, 36
+# FP32 atomics of the texture backward per mesh pixel: 4 texels x 3 channels
+TEX_BWD_ATOMICS_PER_PIXEL = 12
+
+
+def backward_roofline(stage_ms, n_blended, n_gauss, n_visible, mesh_pixels):
+    """Per stage of the backward (timed alone): its algorithmic work, the time
+    that takes at the unit's peak, and that time over the measured time."""
+    work = {
+        "blend_backward": ("alu", n_blended * BWD_OPS_BLENDED, VALU_PEAK_TOPS * 1e12, "lane-ops"),
+        "projection_backward": ("hbm", n_gauss * PROJ_BWD_BYTES_PER_G +
+                                n_visible * PROJ_BWD_BYTES_PER_ITEM, HBM_BYTES_PER_S, "bytes"),
+        "texture_backward": ("atomics", mesh_pixels * TEX_BWD_ATOMICS_PER_PIXEL,
+                             ATOMICS_PER_S, "atomics"),
+    }
+    out = {}
+    for k, (bound, amount, peak, unit) in work.items():
+        meas = stage_ms[k]
+        roof = amount / peak * 1e3
+        out[k] = {"bound": bound, "work": int(amount), "unit": unit, "peak_per_s": peak,
+                  "roof_ms": round(roof, 5), "measured_ms": round(meas, 5),
+                  "frac": round(roof / meas, 4) if meas > 0 else None}
     return out
 
 
@@ -343,6 +380,20 @@ def batched_step(torch, hr, scenes, dev, args, result):
                                 "variant": int(r.settings.variant)}
     result["batched_ms_per_step"] = round(bsec * 1e3, 3)
     step.close()
+    # the backward's stages timed one after another (hr_render_hybrid_backward_timed,
+    # serial), median of 3, with their roofline fractions
+    f = r.render_hybrid(sync_check=True)
+    _, gi1, gt1, gm1 = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target, r.sizes)
+    sb = f.stats_dict()
+    mesh_px = float((f.tri_id >= 0).sum().item())
+    reps = [r.render_hybrid_backward_timed(gi1, gt1, gm1, serial=True)[0] for _ in range(3)]
+    bt = {k: sorted(x[k] for x in reps)[1] for k in hr.BWD_STAGES}
+    log("step backward stages (alone): " + ", ".join(f"{k} {v:.3f} ms" for k, v in bt.items()))
+    result["step_backward_stage_ms"] = {k: round(v, 4) for k, v in bt.items()}
+    result["step_backward_roofline"] = backward_roofline(bt, sb["n_blended"], s4.gaussians.n,
+                                                         sb["n_visible"], mesh_px)
+    log("step backward roofline: " + json.dumps(result["step_backward_roofline"]))
+    del gi1, gt1, gm1
     # the plain single-view path on the same GPU: the 16 cameras one by one
     parts = [torch.as_tensor(t.reshape(-1)).to(dev) for t in s4.target]
     sv_ms = single_view_steps(torch, hr, s4, g, m, r.settings, parts, dev)

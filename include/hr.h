@@ -265,6 +265,25 @@ hr_status hr_render_hybrid_backward(const hr_gaussians* g, const hr_mesh* mesh,
                                     const float* grad_image, const float* grad_final_T,
                                     const float* grad_mesh_rgb, hr_grads* grads, void* stream);
 
+/* hr_render_hybrid_backward that also times its stages with events,
+ * synchronising the stream before it returns (not for graph capture).
+ * stage_ms (host, HR_N_BWD_STAGES floats) receives milliseconds: 0 the blend
+ * backward (clearing the accumulators included), 1 the projection backward,
+ * 2 the texture backward, 3 the whole backward on the given stream. With
+ * serial = 0 the texture backward runs beside the blend backward on the
+ * library's second stream, as in hr_render_hybrid_backward; with serial != 0 it
+ * runs on the given stream after the projection backward, so that each stage is
+ * timed alone. Errors as hr_render_hybrid_backward, plus HR_ERR_INVALID_ARGUMENT
+ * for a null stage_ms. */
+#define HR_N_BWD_STAGES 4
+hr_status hr_render_hybrid_backward_timed(const hr_gaussians* g, const hr_mesh* mesh,
+                                          const hr_camera* cams, int32_t n_cams,
+                                          const hr_settings* s, int64_t key_capacity,
+                                          void* workspace, size_t workspace_bytes,
+                                          const float* grad_image, const float* grad_final_T,
+                                          const float* grad_mesh_rgb, hr_grads* grads,
+                                          void* stream, int32_t serial, float* stage_ms);
+
 /* Re-runs only the per-tile blend and composite of the forward that last
  * filled this workspace (all arguments equal to that forward's), rewriting
  * the same outputs. Used to time the blend kernel on its own and by the

@@ -529,20 +529,38 @@ hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const h
 // The texture backward reads only forward outputs and writes only the texture
 // gradient: it runs on the second stream beside the blend and projection
 // backward.
+// ev (optional, 6 events): 0 start, 1 after the blend backward, 2 after the
+// projection backward, 3-4 around the texture backward, 5 end. `serial` runs
+// the texture backward on `st` after the projection backward instead of beside
+// the blend backward on the second stream.
 hr_status enqueue_backward(const Plan& p, const Work& w, const SetDev& S, const hr_gaussians* g,
                            const hr_mesh* m, const hr_settings* s, const float* grad_image,
                            const float* grad_T, const float* grad_mesh, hr_grads* grads,
-                           hipStream_t st) {
+                           hipStream_t st, hipEvent_t* ev = nullptr, bool serial = false) {
   (void)p;
   SideStream* ss = nullptr;
   hr_status rc = side_stream(ss);
   if (rc != HR_OK) return rc;
-  if (!ss->fork_from(st)) return fail(HR_ERR_HIP, "stream fork failed");
-  launch_texture_backward(S, *m, w, grad_image, grad_mesh, grads->tex, ss->st);
+  if (ev) hipEventRecord(ev[0], st);
+  if (!serial) {
+    if (!ss->fork_from(st)) return fail(HR_ERR_HIP, "stream fork failed");
+    if (ev) hipEventRecord(ev[3], ss->st);
+    launch_texture_backward(S, *m, w, grad_image, grad_mesh, grads->tex, ss->st);
+    if (ev) hipEventRecord(ev[4], ss->st);
+  }
   launch_zero_gacc(w.gacc, w.counters, st);
   launch_blend_backward(S, w, grad_image, grad_T, pick_batch_bwd(s), s->variant, st);
+  if (ev) hipEventRecord(ev[1], st);
   launch_project_backward(S, w.cams, *g, w, grads, st);
-  if (!ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
+  if (ev) hipEventRecord(ev[2], st);
+  if (serial) {
+    if (ev) hipEventRecord(ev[3], st);
+    launch_texture_backward(S, *m, w, grad_image, grad_mesh, grads->tex, st);
+    if (ev) hipEventRecord(ev[4], st);
+  } else if (!ss->join_into(st)) {
+    return fail(HR_ERR_HIP, "stream join failed");
+  }
+  if (ev) hipEventRecord(ev[5], st);
   return HR_OK;
 }
 
@@ -666,6 +684,51 @@ hr_status hr_render_hybrid_backward(const hr_gaussians* g, const hr_mesh* mesh,
                              st)) != HR_OK)
     return rc;
   return hip_check("backward launch");
+}
+
+hr_status hr_render_hybrid_backward_timed(const hr_gaussians* g, const hr_mesh* mesh,
+                                          const hr_camera* cams, int32_t n_cams,
+                                          const hr_settings* s, int64_t key_capacity,
+                                          void* workspace, size_t workspace_bytes,
+                                          const float* grad_image, const float* grad_final_T,
+                                          const float* grad_mesh_rgb, hr_grads* grads,
+                                          void* stream, int32_t serial, float* stage_ms) {
+  if (!stage_ms) return fail(HR_ERR_INVALID_ARGUMENT, "stage_ms is required");
+  Plan p;
+  hr_status rc = make_plan(g, mesh, cams, n_cams, s, key_capacity, p);
+  if (rc != HR_OK) return rc;
+  if (!workspace || workspace_bytes < p.total)
+    return fail(HR_ERR_INVALID_ARGUMENT, "workspace smaller than hr_query_workspace()");
+  if (!grad_image) return fail(HR_ERR_INVALID_ARGUMENT, "grad_image is required");
+  if (!grads) return fail(HR_ERR_INVALID_ARGUMENT, "grads is required");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[6];
+  int made = 0;
+  for (; made < 6; ++made)
+    if (hipEventCreate(&ev[made]) != hipSuccess) break;
+  if (made < 6) {
+    for (int k = 0; k < made; ++k) hipEventDestroy(ev[k]);
+    return fail(HR_ERR_HIP, "event create failed");
+  }
+  Work w = make_work(p, workspace);
+  SetDev S = make_setdev(p, g, mesh, s);
+  hipGetLastError();
+  rc = enqueue_backward(p, w, S, g, mesh, s, grad_image, grad_final_T, grad_mesh_rgb, grads, st,
+                        ev, serial != 0);
+  if (rc == HR_OK) rc = hip_check("backward launch");
+  if (rc == HR_OK && hipStreamSynchronize(st) != hipSuccess)
+    rc = fail(HR_ERR_HIP, "synchronize failed");
+  if (rc == HR_OK) {
+    const int a[HR_N_BWD_STAGES] = {0, 1, 3, 0};
+    const int b[HR_N_BWD_STAGES] = {1, 2, 4, 5};
+    for (int k = 0; k < HR_N_BWD_STAGES; ++k) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[a[k]], ev[b[k]]);
+      stage_ms[k] = ms;
+    }
+  }
+  for (int k = 0; k < 6; ++k) hipEventDestroy(ev[k]);
+  return rc;
 }
 
 hr_status hr_blend_forward(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,

@@ -26,6 +26,8 @@ HR_FLAG_TILE_ELLIPSE = 1 << 5
 HR_FLAG_MESH_REUSED = 1 << 6
 HR_N_STAGES = 7
 STAGES = ("projection", "depth_sort", "binning", "blend", "stats", "mesh", "forward")
+HR_N_BWD_STAGES = 4
+BWD_STAGES = ("blend_backward", "projection_backward", "texture_backward", "backward")
 
 P = C.c_void_p
 
@@ -71,7 +73,7 @@ class hr_adam_group(C.Structure):
 
 
 EXPORTED = ["hr_default_settings", "hr_query_workspace", "hr_render_hybrid", "hr_render_hybrid_timed",
-            "hr_render_hybrid_backward", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
+            "hr_render_hybrid_backward", "hr_render_hybrid_backward_timed", "hr_blend_forward", "hr_loss_scratch_bytes", "hr_hybrid_loss",
             "hr_hybrid_loss_noalloc",
             "hr_full_loss_scratch_bytes", "hr_full_loss", "hr_adam_step", "hr_mip_filter3d", "hr_autotune", "hr_autotune_backward",
             "hr_autotune_key", "hr_autotune_cache_lookup", "hr_autotune_cache_store",
@@ -101,6 +103,9 @@ def load(path: str = LIB_PATH):
     L.hr_render_hybrid_backward.restype = C.c_int
     L.hr_render_hybrid_backward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P,
                                             P, P, P]
+    L.hr_render_hybrid_backward_timed.restype = C.c_int
+    L.hr_render_hybrid_backward_timed.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t,
+                                                  P, P, P, P, P, C.c_int32, P]
     L.hr_blend_forward.restype = C.c_int
     L.hr_blend_forward.argtypes = [P, P, P, C.c_int32, P, C.c_int64, P, C.c_size_t, P, P]
     L.hr_loss_scratch_bytes.restype = C.c_size_t
@@ -502,6 +507,26 @@ class Renderer:
             _ptr(None if grad_mesh_rgb is None else grad_mesh_rgb.contiguous()), C.byref(gr),
             _stream()))
         return grads
+
+    def render_hybrid_backward_timed(self, grad_image, grad_final_T=None, grad_mesh_rgb=None,
+                                     serial=True):
+        """hr_render_hybrid_backward_timed of the last render_hybrid; returns the
+        stage times in ms keyed by BWD_STAGES, and the gradients (fresh tensors)."""
+        grads = self._zero_grads(self.g)
+        gr = hr_grads()
+        for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "tex", "mean2d_norm",
+                  "mean2d_count"):
+            setattr(gr, k, _ptr(grads.get(k)))
+        gs, ms = self._structs()
+        t = (C.c_float * HR_N_BWD_STAGES)()
+        check(self.L.hr_render_hybrid_backward_timed(
+            C.byref(gs), C.byref(ms), self.cam_arr, len(self.cams), C.byref(self.settings),
+            int(self.key_capacity), _ptr(self.ws), int(self.ws.numel()),
+            _ptr(grad_image.contiguous()),
+            _ptr(None if grad_final_T is None else grad_final_T.contiguous()),
+            _ptr(None if grad_mesh_rgb is None else grad_mesh_rgb.contiguous()), C.byref(gr),
+            _stream(), 1 if serial else 0, t))
+        return dict(zip(BWD_STAGES, list(t))), grads
 
     def render_hybrid_backward(self, grad_image, grad_final_T=None, grad_mesh_rgb=None, grads=None,
                                tex=None):

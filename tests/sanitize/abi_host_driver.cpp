@@ -190,6 +190,21 @@ void loss_sizes() {
   EXPECT(hr_hybrid_loss_noalloc(d, d, d, fake<int32_t>(), d, many.data(), 300, 0.1f, 20.f, 0, d,
                                 d, d, d, nullptr) == HR_ERR_INVALID_ARGUMENT);
   EXPECT(hr_batch_status(nullptr, nullptr, nullptr) == HR_ERR_INVALID_ARGUMENT);
+  {  // the timed backward checks its arguments before any launch
+    hr_settings s = hr_default_settings();
+    hr_camera c = camera(64, 48, 50.0);
+    hr_gaussians g = gaussians(10);
+    hr_mesh m = mesh(0);
+    hr_grads gr;
+    std::memset(&gr, 0, sizeof gr);
+    float st[HR_N_BWD_STAGES];
+    EXPECT(hr_render_hybrid_backward_timed(&g, &m, &c, 1, &s, 100, fake_mut<void>(), 1 << 20, d,
+                                           nullptr, nullptr, &gr, nullptr, 1,
+                                           nullptr) == HR_ERR_INVALID_ARGUMENT);
+    EXPECT(hr_render_hybrid_backward_timed(&g, &m, &c, 1, &s, 100, fake_mut<void>(), 16, d,
+                                           nullptr, nullptr, &gr, nullptr, 1,
+                                           st) == HR_ERR_INVALID_ARGUMENT);
+  }
 }
 
 void autotune_keys() {

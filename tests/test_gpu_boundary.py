@@ -86,6 +86,34 @@ def test_graph_step_matches_oracle_per_camera(hr, variant, batch_bwd):
     step.close()
 
 
+def test_timed_backward_matches_the_backward_and_the_oracle(hr):
+    say("case: hr_render_hybrid_backward_timed (serial and beside) on 2 cameras vs oracle")
+    sc, cams, targets = two_camera_room()
+    renders = [oracle.render(sc.gaussians, sc.mesh, c) for c in cams]
+    Lr, ups = packed_loss_oracle(oracle, renders, targets)
+    ref = None
+    for c, o, (gi, gt, gm) in zip(cams, renders, ups):
+        b = oracle.backward(sc.gaussians, sc.mesh, c, gi, gt, gm)
+        ref = b if ref is None else {k: ref[k] + b[k] for k in GRADS}
+    g, m = hr.to_device(sc.gaussians, sc.mesh)
+    r = hr.Renderer(g, m, cams)
+    f = r.render_hybrid(sync_check=True)
+    target = torch.as_tensor(np.concatenate([t.reshape(-1) for t in targets])).cuda()
+    _, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target, r.sizes)
+    plain = r.render_hybrid_backward(gi, gt, gm)
+    for serial in (True, False):
+        t, grads = r.render_hybrid_backward_timed(gi, gt, gm, serial=serial)
+        torch.cuda.synchronize()
+        say(f"  serial={serial}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in t.items()))
+        assert all(v > 0 for v in t.values())
+        assert t["backward"] >= t["blend_backward"] and t["backward"] >= t["projection_backward"]
+        for k in GRADS:
+            a, b = grads[k].cpu().numpy(), plain[k].cpu().numpy()
+            # the same kernels; only the order of float atomics may differ
+            assert np.abs(a - b).max() <= 1e-5 * max(np.abs(b).max(), 1e-30), k
+            grad_compare(f"{k} (timed, serial={serial})", a, ref[k])
+
+
 def test_graph_step_overflow_is_reported_and_recaptured(hr):
     say("case: hipGraph step captured with a key capacity far too small")
     sc, cams, targets = two_camera_room()
