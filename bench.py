@@ -37,11 +37,6 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # addressing and loop control are not counted.
 BLEND_OPS_EXAMINED = 11
 BLEND_OPS_BLENDED = 7
-# FP32 atomic adds (no return) per second to scattered addresses of a 64 MiB
-# buffer, measured on this GPU (2.4e11/s when the lanes of a wave hit consecutive
-# words): the ceiling of the texture backward, whose atomics land on the texels
-# of minified textures, far apart from one pixel to the next
-ATOMICS_PER_S = 2.1e10
 # HBM bytes per blend launch over the 32 headline views, by (batch, variant),
 # from the FETCH_SIZE and WRITE_SIZE counter passes of `bench.py --pmc-probe`
 # (scaled by a 256 MiB copy: FETCH x2, WRITE x1), tile-ellipse binning; valid
@@ -200,19 +195,22 @@ BWD_OPS_BLENDED = 30
 # their gradients out plus the per-Gaussian sums (560 B at SH degree 3), per
 # visible (Gaussian, camera) item its 9 accumulated gradients (36 B)
 PROJ_BWD_BYTES_PER_G, PROJ_BWD_BYTES_PER_ITEM = 560, 36
-# FP32 atomics of the texture backward per mesh pixel: 4 texels x 3 channels
-TEX_BWD_ATOMICS_PER_PIXEL = 12
+# HBM bytes of the texture backward: per mesh pixel its stored footprint (16 B)
+# and dL/dI_m (12 B) in; per texel its gradient read and written once (24 B).
+# The kernel itself is bound by its atomics (the texels of a workgroup's box
+# are summed in LDS first, then added to the gradient with one atomic each)
+TEX_BWD_BYTES_PER_PIXEL, TEX_BWD_BYTES_PER_TEXEL = 28, 24
 
 
-def backward_roofline(stage_ms, n_blended, n_gauss, n_visible, mesh_pixels):
+def backward_roofline(stage_ms, n_blended, n_gauss, n_visible, mesh_pixels, texels):
     """Per stage of the backward (timed alone): its algorithmic work, the time
     that takes at the unit's peak, and that time over the measured time."""
     work = {
         "blend_backward": ("alu", n_blended * BWD_OPS_BLENDED, VALU_PEAK_TOPS * 1e12, "lane-ops"),
         "projection_backward": ("hbm", n_gauss * PROJ_BWD_BYTES_PER_G +
                                 n_visible * PROJ_BWD_BYTES_PER_ITEM, HBM_BYTES_PER_S, "bytes"),
-        "texture_backward": ("atomics", mesh_pixels * TEX_BWD_ATOMICS_PER_PIXEL,
-                             ATOMICS_PER_S, "atomics"),
+        "texture_backward": ("hbm", mesh_pixels * TEX_BWD_BYTES_PER_PIXEL +
+                             texels * TEX_BWD_BYTES_PER_TEXEL, HBM_BYTES_PER_S, "bytes"),
     }
     out = {}
     for k, (bound, amount, peak, unit) in work.items():
@@ -390,8 +388,9 @@ def batched_step(torch, hr, scenes, dev, args, result):
     bt = {k: sorted(x[k] for x in reps)[1] for k in hr.BWD_STAGES}
     log("step backward stages (alone): " + ", ".join(f"{k} {v:.3f} ms" for k, v in bt.items()))
     result["step_backward_stage_ms"] = {k: round(v, 4) for k, v in bt.items()}
+    texels = int(s4.mesh.tex.shape[0] * s4.mesh.tex.shape[1] * s4.mesh.tex.shape[2])
     result["step_backward_roofline"] = backward_roofline(bt, sb["n_blended"], s4.gaussians.n,
-                                                         sb["n_visible"], mesh_px)
+                                                         sb["n_visible"], mesh_px, texels)
     log("step backward roofline: " + json.dumps(result["step_backward_roofline"]))
     del gi1, gt1, gm1
     # the plain single-view path on the same GPU: the 16 cameras one by one
@@ -517,7 +516,29 @@ def main():
                           sh_degree=sc.gaussians.sh_degree, faces=sc.mesh.n_faces,
                           blend_ms=blend_s / launches * 1e3)
     log("frame roofline: " + json.dumps(roof))
-    del r, frame, g, m
+    del r, frame
+    torch.cuda.empty_cache()
+    # throughput with 4 of the views per call (one forward over 4 cameras: the
+    # latency-bound sort and binning run once for the 4)
+    groups = [sc.cameras[4 * k:4 * k + 4] for k in range(len(sc.cameras) // 4)]
+    r4 = hr.Renderer(g, m, groups[0], settings=hr.default_settings(flags=PAIR_CULL))
+    r4.settings.batch, r4.settings.variant = tuning["batch"], tuning["variant"]
+    f4 = r4.new_frame()
+    for grp in groups:
+        r4.set_cameras(grp)
+        r4.render_hybrid(f4, sync_check=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n4 = max(8, args.steps // 4)
+    e0.record(st)
+    for k in range(n4):
+        r4.set_cameras(groups[k % len(groups)])
+        r4.render_hybrid(f4, sync_check=False)
+    e1.record(st)
+    torch.cuda.synchronize()
+    fps4 = 4 * n4 / (e0.elapsed_time(e1) / 1e3)
+    log(f"1080p hybrid, 4 views per call: {fps4:.1f} frames/s")
+    del r4, f4, g, m
     torch.cuda.empty_cache()
 
     result = {
@@ -553,6 +574,7 @@ def main():
         "n_visible_per_view": int(counts["n_visible"]),
         "stage_ms_per_view": {k: round(v, 4) for k, v in stage_sum.items()},
         "frames_per_s_without_mesh_pass": round(1e3 / no_mesh_ms, 2),
+        "frames_per_s_4_views_per_call": round(fps4, 2),
         "frame_roofline": roof,
     }
     del sc
