@@ -338,7 +338,50 @@ def cpu_baseline(scenes):
         out["single_thread"] = {"value": round(one["fps"], 6), "unit": "frames/s",
                                 "threads": one["threads"],
                                 "sample": "2 views, 16x16 and 192x192 windows, extrapolated"}
+    out["other_workloads"] = cpu_other_workloads(scenes, oracle)
     return out
+
+
+def cpu_other_workloads(scenes, oracle):
+    """The oracle on the other workloads, on all the host's threads: full frames
+    of the 64x64 quad scene and of the 720p room, 64 tiles (a 128x128 window at
+    the centre) of the 1600x1064 and of one 1920x1080 view of the 16-camera
+    room, and the gradient over the 32x32 crop of the 1600x1064 room."""
+    import numpy as np
+    res = {}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    s1 = scenes.config1()
+    c1 = s1.cameras[0]
+    res["config1_64x64_frames_per_s"] = round(1.0 / timed(lambda: oracle.render(s1.gaussians, s1.mesh, c1)), 3)
+    s2 = scenes.config2()
+    c2 = s2.cameras[0]
+    res["config2_720p_frames_per_s"] = round(1.0 / timed(lambda: oracle.render(s2.gaussians, s2.mesh, c2)), 4)
+    del s2
+    s3 = scenes.config3()
+    c3 = s3.cameras[0]
+    cx, cy = c3.width // 2, c3.height // 2
+    win = (cx - 64, cy - 64, cx + 64, cy + 64)
+    res["config3_64_tiles_s"] = round(timed(lambda: oracle.render(s3.gaussians, s3.mesh, c3, window=win)), 3)
+    rng = np.random.default_rng(7)
+    crop = (cx - 16, cy - 16, cx + 16, cy + 16)
+    gi = rng.normal(0, 1, (3, 32, 32))
+    gt = rng.normal(0, 1, (32, 32))
+    gm = rng.normal(0, 1, (3, 32, 32))
+    res["config3_crop_32x32_gradient_s"] = round(
+        timed(lambda: oracle.backward(s3.gaussians, s3.mesh, c3, gi, gt, gm, window=crop)), 3)
+    del s3
+    s4 = scenes.config4()
+    c4 = max(s4.cameras, key=lambda c: c.width * c.height)
+    cx, cy = c4.width // 2, c4.height // 2
+    win = (cx - 64, cy - 64, cx + 64, cy + 64)
+    res["config4_64_tiles_s"] = round(timed(lambda: oracle.render(s4.gaussians, s4.mesh, c4, window=win)), 3)
+    log(f"cpu oracle, other workloads: {res}")
+    return res
 
 
 def batched_step(torch, hr, scenes, dev, args, result):
