@@ -62,7 +62,8 @@ struct Plan {
       bin_items;
   size_t cams, counters, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
       sval1, rs1, rs_ghist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
-      tile_start, tile_order, sched_cnt, sched_sum, tile_dmax, tile_np, item_off, lists, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
+      tile_start, tile_order, sched_cnt, sched_sum, tile_dmax, tile_np, item_off, lists, runs,
+      unit_runs, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, taps, gacc, tune, scan_scratch, scan_scratch2, total;
   int64_t scan_words;
   std::vector<CamDev> camdev;
@@ -283,6 +284,8 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.tile_np = L.take(16 * p.n_tiles);
   p.item_off = L.take(4 * (p.n_cams + 1));
   p.lists = L.take(4 * key_cap);
+  p.runs = L.take(4 * key_cap);
+  p.unit_runs = L.take(8 * std::max<int64_t>(p.bin_items, 1));
   p.zbuf = L.take(8 * P);
   p.tri_cnt = L.take(4 * p.MF);
   p.blk_cnt = L.take(4 * (p.MF + 1));
@@ -340,6 +343,8 @@ Work make_work(const Plan& p, void* ws) {
   w.item_off = (uint32_t*)(b + p.item_off);
   w.bin_items_max = p.bin_items;
   w.lists = (uint32_t*)(b + p.lists);
+  w.runs = (uint32_t*)(b + p.runs);
+  w.unit_runs = (uint2*)(b + p.unit_runs);
   w.zbuf = (uint64_t*)(b + p.zbuf);
   w.tri_cnt = (uint32_t*)(b + p.tri_cnt);
   w.blk_cnt = (uint32_t*)(b + p.blk_cnt);

@@ -53,6 +53,8 @@ struct Work {
   uint32_t* tile_dmax;   // [n_tiles] largest mesh depth bits over the tile (culling)
   uint64_t* tile_np;     // [2 * n_tiles] examined and blended pairs of each tile (forward)
   uint32_t* lists;       // [key_cap] ranks grouped by tile, chunk sub-segments in chunk order
+  uint32_t* runs;        // [key_cap] the count pass's tile runs, packed, unit after unit
+  uint2* unit_runs;      // [bin_items_max] first run and run count of each binning unit
   // counters: [0] n_vis, [1] overflow, [2..3] K = pairs in the tile lists (u64),
   // [4] n_tris, [5] n_blocks, [14] tile queue
   uint32_t* counters;
@@ -76,6 +78,7 @@ struct Work {
   int64_t scan_words;
 };
 
+constexpr int RUN_ALLOC = 24;     // counters slot: runs handed out to the binning units
 constexpr int RS_MAX_PASSES = 6;  // 4 depth bytes, up to 2 camera bytes
 constexpr int RS_GROUP = 32;      // blocks per published group total
 // copies of the global digit counts: workgroup w adds into copy w % 16, so

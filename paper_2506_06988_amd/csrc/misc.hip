@@ -8,7 +8,7 @@ namespace {
 
 // also clears the 64 forward counters, `n2` words of each of the two scan
 // states and the radix sort's global digit counts when `clear` is given
-__global__ void k_upload_cams(CamUpload u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
+__global__ __launch_bounds__(1024) void k_upload_cams(CamUpload u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
                               uint32_t* clear3, int64_t n2, uint32_t* ghist) {
   const int k = threadIdx.x;
   if (k < u.count) dst[u.first + k] = u.c[k];
@@ -141,7 +141,7 @@ void launch_copy_counted(const float* src, float* dst, const uint32_t* count, in
 
 void launch_upload_cams(const CamUpload& u, CamDev* dst, uint32_t* clear, uint32_t* clear2,
                         uint32_t* clear3, int64_t n2, uint32_t* ghist, hipStream_t st) {
-  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(256), 0, st, u, dst, clear, clear2, clear3, n2,
+  hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(1024), 0, st, u, dst, clear, clear2, clear3, n2,
                      ghist);
 }
 

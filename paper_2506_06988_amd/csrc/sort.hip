@@ -501,14 +501,21 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
                                                    const GRec* __restrict__ rec_s,
                                                    const uint32_t* __restrict__ tile_dmax,
                                                    const EllP* __restrict__ ell,
-                                                   uint32_t* __restrict__ mat) {
+                                                   uint32_t* __restrict__ mat,
+                                                   uint32_t* __restrict__ counters,
+                                                   uint32_t* __restrict__ runs,
+                                                   uint2* __restrict__ unit_runs,
+                                                   int64_t key_cap) {
   __shared__ int32_t diff[MAX_TX + 1];
   __shared__ uint32_t red4[4];
+  __shared__ uint32_t lr[CHUNK];  // the unit's runs: x0 | x1 << 10 | rank offset << 21
+  __shared__ uint32_t nlr, lbase, lkeep;
   const uint32_t n_items = item_off[n_cams];
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const BinItem B = bin_item(cams, n_cams, vis_off, item_off, it);
     const CamDev& cam = cams[B.cam];
     for (int x = threadIdx.x; x <= B.TX; x += 256) diff[x] = 0;
+    if (threadIdx.x == 0) nlr = 0;
     __syncthreads();
     const uint32_t* tdm = tile_dmax ? tile_dmax + cam.tile_off + B.y * B.TX : nullptr;
     for (int64_t k0 = B.r0 + threadIdx.x; k0 < B.r1; k0 += 256 * RUNS) {
@@ -518,6 +525,8 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
       for (int j = 0; j < RUNS; ++j) {
         const int x0 = rx0[j], x1 = rx1[j];
         if (x1 <= x0) continue;
+        lr[atomicAdd(&nlr, 1u)] =
+            (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k0 + 256 * j - B.r0) << 21);
         if (!tdm) {
           atomicAdd(&diff[x0], 1);
           atomicSub(&diff[x1], 1);
@@ -548,6 +557,21 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
       run += v[q];
       if (x0 + q < B.TX) row[x0 + q] = (uint32_t)run;
     }
+    // the runs go to the scatter pass: one reservation per unit (there are no
+    // more runs than pairs, so key_cap entries hold them unless the pairs
+    // overflow, which the capacity check reports)
+    if (threadIdx.x == 0) {
+      const uint32_t nr = nlr;
+      const uint32_t base = nr ? atomicAdd(&counters[RUN_ALLOC], nr) : 0u;
+      const uint32_t keep = (int64_t)base >= key_cap ? 0u
+                            : (uint32_t)min((int64_t)nr, key_cap - (int64_t)base);
+      lbase = base;
+      lkeep = keep;
+      unit_runs[it] = make_uint2(base, keep);
+    }
+    __syncthreads();
+    const uint32_t nr = lkeep, base = lbase;
+    for (uint32_t q = threadIdx.x; q < nr; q += 256) runs[base + q] = lr[q];
     __syncthreads();
   }
 }
@@ -563,10 +587,10 @@ __global__ __launch_bounds__(256) void k_bin_count(const CamDev* __restrict__ ca
 __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ cams, int n_cams,
                                                      const uint32_t* __restrict__ vis_off,
                                                      const uint32_t* __restrict__ item_off,
-                                                     const uint2* __restrict__ rect_s,
+                                                     const uint32_t* __restrict__ runs,
+                                                     const uint2* __restrict__ unit_runs,
                                                      const GRec* __restrict__ rec_s,
                                                      const uint32_t* __restrict__ tile_dmax,
-                                                     const EllP* __restrict__ ell,
                                                      uint32_t* __restrict__ mat,
                                                      const uint32_t* __restrict__ tile_start,
                                                      int64_t key_cap, uint32_t* __restrict__ lists) {
@@ -591,29 +615,24 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const CamDev* __restrict__ 
       if ((int64_t)pos < key_cap) lists[pos] = k;
     };
     const int half = B.TX / 2;
-    // short runs by one lane; the others are sorted into the two lists
-    for (int64_t k0 = B.r0 + threadIdx.x; k0 < B.r1; k0 += 256 * RUNS) {
-      int rx0[RUNS], rx1[RUNS];
-      item_runs(B, k0, rect_s, rec_s, ell, rx0, rx1);
-#pragma unroll
-      for (int j = 0; j < RUNS; ++j) {
-        const int x0 = rx0[j], x1 = rx1[j];
-        if (x1 <= x0) continue;
-        const int64_t k = k0 + 256 * j;
-        const uint32_t packed =
-            (uint32_t)x0 | ((uint32_t)x1 << 10) | ((uint32_t)(k - B.r0) << 21);
-        const int w = x1 - x0;
-        if (w > NARROW_RUN && w > half) {
-          const uint32_t q = atomicAdd(&nwide, 1u);
-          wide[q] = packed;
-          if (tdm) wide_dep[q] = __float_as_uint(rec_s[k].depth);
-        } else if (w > NARROW_RUN) {
-          mid[atomicAdd(&nmid, 1u)] = packed;
-        } else {
-          const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
-          for (int x = x0; x < x1; ++x)
-            if (!tdm || dep < tdm[x]) put((uint32_t)k, x);
-        }
+    // the unit's runs from the count pass: short ones by one lane; the others
+    // are sorted into the two lists
+    const uint2 ur = unit_runs[it];
+    for (uint32_t q = threadIdx.x; q < ur.y; q += 256) {
+      const uint32_t packed = runs[ur.x + q];
+      const int x0 = (int)(packed & 1023u), x1 = (int)((packed >> 10) & 2047u);
+      const int64_t k = B.r0 + (packed >> 21);
+      const int w = x1 - x0;
+      if (w > NARROW_RUN && w > half) {
+        const uint32_t qw = atomicAdd(&nwide, 1u);
+        wide[qw] = packed;
+        if (tdm) wide_dep[qw] = __float_as_uint(rec_s[k].depth);
+      } else if (w > NARROW_RUN) {
+        mid[atomicAdd(&nmid, 1u)] = packed;
+      } else {
+        const uint32_t dep = tdm ? __float_as_uint(rec_s[k].depth) : 0u;
+        for (int x = x0; x < x1; ++x)
+          if (!tdm || dep < tdm[x]) put((uint32_t)k, x);
       }
     }
     __syncthreads();
@@ -882,7 +901,8 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
   const unsigned grid = (unsigned)std::max<int64_t>(1, w.bin_items_max);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
-                       w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat);
+                       w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat, w.counters, w.runs,
+                       w.unit_runs, S.key_cap);
   const unsigned tb = (unsigned)((S.n_tiles + 255) / 256);
   hipLaunchKernelGGL(k_colscan, dim3(tb), dim3(256), 0, st, w.cams, n_cams, S.n_tiles, w.vis_off,
                      w.mat, w.tile_total, w.tile_start, w.sched_cnt, w.sched_sum);
@@ -891,7 +911,7 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
                      w.counters);
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
-                       w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat, w.tile_start,
+                       w.item_off, w.runs, w.unit_runs, w.rec_s, tdm, w.mat, w.tile_start,
                        S.key_cap, w.lists);
   if (out && out->ranges)
     hipLaunchKernelGGL(k_ranges, dim3((S.n_tiles + 255) / 256), dim3(256), 0, st, S.n_tiles,
