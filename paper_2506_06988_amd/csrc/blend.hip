@@ -647,6 +647,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
   }
 }
 
+constexpr int RB = 4;  // Gaussians whose gradients the one-wave backward sums together
+
 template <int BG>
 __global__ __launch_bounds__(64) void k_blend_bwd_w(
     SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
@@ -660,7 +662,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
   __shared__ Staged sh[BG];
   __shared__ uint32_t rk[BG];
   __shared__ uint32_t bitmap[WIN_WORDS];
-  __shared__ float rowsum[4][12];  // per row of 16 lanes: the 9 record gradients
+  // the 9 record gradients of up to RB Gaussians, one row of 64 lane partials
+  // each (padded: the summing lanes read across the banks)
+  __shared__ float part[RB][9][65];
+  __shared__ uint32_t prk[RB];
   const int t = (int)tile_order[blockIdx.x];
   const int cam = find_cam_by_tile(cams, S.n_cams, t);
   const CamDev& C = cams[cam];
@@ -715,6 +720,27 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
   for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o, 64));
   const int64_t last = lmax;
   if (last == 0) return;
+  // RB Gaussians' partials are summed together: lane L < 9 nb sums row L over
+  // the 64 lanes and adds it to the Gaussian's accumulators (one atomic
+  // instruction for all of them)
+  int nb = 0;
+  auto flush = [&]() {
+    __syncthreads();
+    if (lane < 9 * nb) {
+      const int gs = lane / 9, q = lane - 9 * gs;
+      const float* row = &part[gs][q][0];
+      float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+#pragma unroll 4
+      for (int l = 0; l < 64; l += 4) {
+        v0 += row[l];
+        v1 += row[l + 1];
+        v2 += row[l + 2];
+        v3 += row[l + 3];
+      }
+      atomicAdd(gacc + (size_t)prk[gs] * 9 + q, (v0 + v1) + (v2 + v3));
+    }
+    __syncthreads();
+  };
   for (int w = W.nwin - 1; w >= 0; --w) {
     int64_t a, b;
     win_range(W, w, a, b);
@@ -801,24 +827,18 @@ __global__ __launch_bounds__(64) void k_blend_bwd_w(
           g[6] = gc0;
           g[7] = gc1;
           g[8] = gc2;
-          // rows of 16 lanes by DPP, then the 4 row sums through LDS; lanes
-          // 0-8 add one gradient each
 #pragma unroll
-          for (int q = 0; q < 9; ++q) g[q] = row_sum_to_last(g[q]);
-          if ((lane & 15) == 15) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) rowsum[lane >> 4][q] = g[q];
+          for (int q = 0; q < 9; ++q) part[nb][q][lane] = g[q];
+          if (lane == 0) prk[nb] = rk[k];
+          if (++nb == RB) {
+            flush();
+            nb = 0;
           }
-          __syncthreads();
-          if (lane < 9) {
-            const float v = rowsum[0][lane] + rowsum[1][lane] + rowsum[2][lane] + rowsum[3][lane];
-            atomicAdd(gacc + (size_t)rk[k] * 9 + lane, v);
-          }
-          __syncthreads();
         }
       }
     }
   }
+  if (nb) flush();
 }
 
 }  // namespace
