@@ -647,10 +647,10 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
   }
 }
 
-constexpr int RB = 4;  // Gaussians whose gradients the one-wave backward sums together
+constexpr int RB = 2;  // Gaussians whose gradients the one-wave backward sums together
 
 template <int BG>
-__global__ __launch_bounds__(64) void k_blend_bwd_w(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_num_vgpr(128))) void k_blend_bwd_w(
     SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
     const uint32_t* __restrict__ mat, const uint32_t* __restrict__ tile_start,
     const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ tile_order,
