@@ -301,7 +301,7 @@ __device__ __forceinline__ int find_cam_by_tile(const CamDev* cams, int n_cams, 
   return lo;
 }
 
-constexpr int TEX_LDS = 2048;  // texels of one tile's footprint accumulated in LDS
+constexpr int TEX_LDS = 4096;  // texels of one tile's footprint accumulated in LDS
 
 // dL/dI_m = T dL/dI_h + (direct term), scattered through the bilinear weights
 // the forward used (its per-pixel footprints, so nothing of the mesh is
@@ -402,22 +402,22 @@ __global__ __launch_bounds__(256) void k_tex_bwd(SetDev S, const CamDev* __restr
     __syncthreads();
     const int64_t plane = (int64_t)S.tex_h * S.tex_w;
     const int64_t base = (int64_t)rtex * plane;
-    // thread -> one texel column of the box, rows_per_pass rows apart (no
-    // integer division inside the loop)
-    const int cols = bw < 256 ? bw : 256;
-    const int rows_per_pass = 256 / cols;
-    const int cx = (int)threadIdx.x % cols, ry = (int)threadIdx.x / cols;
-    if (ry < rows_per_pass) {
-      for (int yy = ry; yy < bh; yy += rows_per_pass) {
-        for (int xx = cx; xx < bw; xx += cols) {
-          const int l = yy * bw + xx;
-          float* dst = grad_tex + (base + (int64_t)(by0 + yy) * S.tex_w + (bx0 + xx)) * 3;
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) {
-            const float v = acc[3 * l + ch];
-            if (v != 0.f) atomicAdd(dst + ch, v);
-          }
-        }
+    // consecutive threads take consecutive floats of the box's rows (the
+    // three channels interleaved as in the texture), so one atomic
+    // instruction covers whole cache lines; e advances by 256 = q rows + r
+    const int row3 = 3 * bw, n3 = row3 * bh;
+    const int q = 256 / row3, r = 256 - q * row3;
+    int yy = (int)threadIdx.x / row3, rem = (int)threadIdx.x - yy * row3;
+    const int64_t pitch = (int64_t)S.tex_w * 3;
+    float* const dst0 = grad_tex + (base + (int64_t)by0 * S.tex_w + bx0) * 3;
+    for (int e = threadIdx.x; e < n3; e += 256) {
+      const float v = acc[e];
+      if (v != 0.f) atomicAdd(dst0 + yy * pitch + rem, v);
+      yy += q;
+      rem += r;
+      if (rem >= row3) {
+        rem -= row3;
+        ++yy;
       }
     }
   }
