@@ -852,9 +852,13 @@ void launch_fwd(const FwdArgs& A, bool persistent, uint32_t* queue, hipStream_t 
   static int grid = 0;
   if (grid == 0) {
     int dev = 0, cus = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_blend_fwd_persistent<BG, D>, 256, 0);
+    // a failed query leaves the fallback of one group per CU of a 256-CU chip
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_blend_fwd_persistent<BG, D>, 256,
+                                                     0) != hipSuccess)
+      per = 0;
     grid = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
   }
   launch_fill_u32(queue, 0u, 1, st);
