@@ -61,7 +61,7 @@ struct Plan {
   int64_t n, n_cams, M, F, MF, P, n_tiles, key_cap, rs_blocks, chunk_rows, mat_entries,
       bin_items;
   size_t cams, counters, vis, vis_scan, dkey, rec, rect, rank_of, skey0, skey1, sval0,
-      sval1, rs1, rs_ghist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
+      sval1, rs1, rs_ghist, rs_hist, vis_off, rec_s, rect_s, item_s, mat, tile_total,
       tile_start, tile_order, sched_cnt, sched_sum, tile_dmax, tile_np, item_off, lists, runs,
       unit_runs, zbuf, tri_cnt, blk_cnt, tri_off, blk_off, tris, final_T, n_contrib,
       mesh_rgb, taps, gacc, tune, scan_scratch, scan_scratch2, total;
@@ -270,6 +270,7 @@ hr_status make_plan(const hr_gaussians* g, const hr_mesh* m, const hr_camera* ca
   p.sval1 = L.take(4 * M);
   p.rs1 = L.take(4 * rs1_words_for(p.rs_blocks));
   p.rs_ghist = L.take(4 * 256 * RS_MAX_PASSES * RS_GHIST_COPIES);
+  p.rs_hist = L.take(4 * 256 * RS_MAX_PASSES * RSC_MAX_BLOCKS);
   p.vis_off = L.take(4 * (n_cams + 1));
   p.rec_s = L.take(sizeof(GRec) * M);
   p.rect_s = L.take(8 * M);
@@ -326,6 +327,7 @@ Work make_work(const Plan& p, void* ws) {
   w.rs1 = (uint32_t*)(b + p.rs1);
   w.rs1_words = rs1_words_for(p.rs_blocks);
   w.rs_ghist = (uint32_t*)(b + p.rs_ghist);
+  w.rs_hist = (uint32_t*)(b + p.rs_hist);
   w.rs_groups = (p.rs_blocks + RS_GROUP - 1) / RS_GROUP;
   w.vis_off = (uint32_t*)(b + p.vis_off);
   w.rec_s = (GRec*)(b + p.rec_s);

@@ -34,6 +34,7 @@ struct Work {
   uint32_t* rs1;         // [rs1_words]: tickets | group counters | group counts | block counts
   int64_t rs1_words;
   uint32_t* rs_ghist;    // [RS_MAX_PASSES][RS_GHIST_COPIES][256]
+  uint32_t* rs_hist;     // [RS_MAX_PASSES][RSC_MAX_BLOCKS][256] slice counts of the grid-barrier sort
   int64_t rs_groups;     // ceil(rs_blocks / RS_GROUP)
   uint32_t* vis_off;     // [n_cams + 1] first rank of each camera
   GRec* rec_s;           // [M] by rank
@@ -81,6 +82,7 @@ struct Work {
 constexpr int RUN_ALLOC = 24;     // counters slot: runs handed out to the binning units
 constexpr int RS_MAX_PASSES = 6;  // 4 depth bytes, up to 2 camera bytes
 constexpr int RS_GROUP = 32;      // blocks per published group total
+constexpr int RSC_MAX_BLOCKS = 64;  // workgroups of the grid-barrier sort (all resident)
 // copies of the global digit counts: workgroup w adds into copy w % 16, so
 // that the few digits every workgroup holds (the exponent byte of the depths)
 // do not serialise all of their atomics on one address

@@ -315,6 +315,161 @@ __global__ __launch_bounds__(RS_B) void k_rs_onepass(const uint32_t* __restrict_
   }
 }
 
+// All passes of the radix sort in one dispatch of a few 1024-thread
+// workgroups (at most RSC_MAX_BLOCKS, so that all of them are resident at
+// once) that meet at grid barriers. In pass p each workgroup owns a slice of
+// ceil(nv / grid) consecutive positions: it counts digit p over its slice and
+// stores the counts, the workgroups meet, each sums every workgroup's counts
+// (digit totals, and the counts of the workgroups before it) into its digit
+// offsets, scatters its slice stably, and the workgroups meet again before
+// the next pass reads the scattered keys. No workgroup waits on another's
+// prefix, so a pass costs two barrier round trips instead of a look-back
+// chain. The waits are bounded: a give-up sets wait_flag, every wave still
+// leaves.
+constexpr int RSC_T = 1024;             // threads per workgroup
+constexpr int RSC_W = RSC_T / 64;       // waves per workgroup
+
+// grid barrier number k (1, 2, ...) of a dispatch: arrive, then wait until
+// every workgroup has arrived k times; the fences make the workgroup's global
+// writes before the barrier visible to every workgroup after it
+__device__ __forceinline__ void rsc_barrier(uint32_t* ctr, uint32_t k, uint32_t* wait_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(ctr, 1u);
+    const uint32_t target = k * gridDim.x;
+    uint32_t spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins >= RS_SPIN_LIMIT) {
+        atomicOr(wait_flag, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// exclusive scan of one value per thread over the RSC_T-thread workgroup
+__device__ __forceinline__ uint32_t rsc_excl_scan(uint32_t v, uint32_t* lds) {
+  const int w = threadIdx.x >> 6, l = __lane_id();
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(inc, o, 64);
+    if (l >= o) inc += u;
+  }
+  if (l == 63) lds[w] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int k = 0; k < w; ++k) base += lds[k];
+  __syncthreads();
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(RSC_T) void k_rs_coop(uint32_t* __restrict__ key0,
+                                                   uint32_t* __restrict__ val0,
+                                                   uint32_t* __restrict__ key1,
+                                                   uint32_t* __restrict__ val1,
+                                                   const uint32_t* __restrict__ counters,
+                                                   int passes, int n, uint32_t* __restrict__ hist,
+                                                   uint32_t* __restrict__ bar,
+                                                   uint32_t* __restrict__ wait_flag) {
+  __shared__ uint32_t lh[256];             // this slice's digit counts, then digit totals
+  __shared__ uint32_t part[4][256];        // partial sums over workgroup ranges
+  __shared__ uint32_t off[256];            // next position of each digit
+  __shared__ uint32_t wc[2][RSC_W][256];   // a round's counts per wave, then positions
+  __shared__ uint32_t red16[RSC_W];
+  constexpr int QK = RSC_MAX_BLOCKS / 4;
+  const int tid = threadIdx.x, w = tid >> 6;
+  const uint32_t G = gridDim.x, b = blockIdx.x;
+  const uint32_t nv = counters[0];
+  const uint32_t S = (nv + G - 1) / G;
+  const uint32_t lo = min(b * S, nv), hi = min(lo + S, nv);
+  uint32_t nbar = 0;
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t* ks = (p & 1) ? key1 : key0;
+    const uint32_t* vs = (p & 1) ? val1 : val0;
+    uint32_t* kd = (p & 1) ? key0 : key1;
+    uint32_t* vd = (p & 1) ? val0 : val1;
+    uint32_t* H = hist + (int64_t)p * RSC_MAX_BLOCKS * 256;
+    if (tid < 256) lh[tid] = 0u;
+    for (int k = tid; k < 2 * RSC_W * 256; k += RSC_T) (&wc[0][0][0])[k] = 0u;
+    __syncthreads();
+    for (uint32_t i = lo + tid; i < hi; i += RSC_T) atomicAdd(&lh[rs_digit(ks[i], vs[i], p, n)], 1u);
+    __syncthreads();
+    if (tid < 256) H[(int64_t)b * 256 + tid] = lh[tid];
+    rsc_barrier(bar, ++nbar, wait_flag);
+    // digit d = tid & 255: quarter q sums the counts of workgroups q, q + 4,
+    // ... (all loads in flight at once)
+    {
+      const int d = tid & 255, q = tid >> 8;
+      uint32_t c[QK];
+#pragma unroll
+      for (int k = 0; k < QK; ++k) {
+        const uint32_t g = (uint32_t)(q + 4 * k);
+        c[k] = g < G ? H[(int64_t)g * 256 + d] : 0u;
+      }
+      uint32_t before = 0, all = 0;
+#pragma unroll
+      for (int k = 0; k < QK; ++k) {
+        all += c[k];
+        if ((uint32_t)(q + 4 * k) < b) before += c[k];
+      }
+      part[q][d] = all;
+      wc[0][q][d] = before;  // wc is free until the first round
+    }
+    __syncthreads();
+    if (tid < 256) {
+      lh[tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+      off[tid] = wc[0][0][tid] + wc[0][1][tid] + wc[0][2][tid] + wc[0][3][tid];
+    }
+    __syncthreads();
+    {
+      // exclusive scan of the digit totals (threads past 256 add zeros)
+      const uint32_t v = tid < 256 ? lh[tid] : 0u;
+      const uint32_t gex = rsc_excl_scan(v, red16);
+      if (tid < 256) off[tid] += gex;
+    }
+    for (int k = tid; k < RSC_W * 256; k += RSC_T) (&wc[0][0][0])[k] = 0u;
+    __syncthreads();
+    // stable scatter in rounds of RSC_T positions: wave w holds positions
+    // [64 w, 64 w + 64) of the round, so (round, wave, lane) is position
+    // order. The two count buffers alternate: a round clears the one the
+    // next round fills, two barriers per round.
+    int cb = 0;
+    for (uint32_t r0 = lo; r0 < hi; r0 += RSC_T, cb ^= 1) {
+      const uint32_t i = r0 + tid;
+      const bool valid = i < hi;
+      const uint32_t kk = valid ? ks[i] : 0u, vv = valid ? vs[i] : 0u;
+      const uint32_t d = valid ? rs_digit(kk, vv, p, n) : 0u;
+      const uint64_t m = match_digit(d, valid);
+      const uint32_t below = (uint32_t)__popcll(m & lanemask_lt());
+      if (valid && below == 0) wc[cb][w][d] = (uint32_t)__popcll(m);
+      __syncthreads();
+      if (tid < 256) {  // first position of each (wave, digit), in place
+        uint32_t s = off[tid];
+#pragma unroll
+        for (int k = 0; k < RSC_W; ++k) {
+          const uint32_t c = wc[cb][k][tid];
+          wc[cb][k][tid] = s;
+          s += c;
+        }
+        off[tid] = s;
+      }
+      for (int k = tid; k < RSC_W * 256; k += RSC_T) (&wc[cb ^ 1][0][0])[k] = 0u;
+      __syncthreads();
+      if (valid) {
+        const uint32_t pos = wc[cb][w][d] + below;
+        kd[pos] = kk;
+        vd[pos] = vv;
+      }
+    }
+    if (p + 1 < passes) rsc_barrier(bar, ++nbar, wait_flag);
+  }
+}
+
 // The per-rank part of the tile-ellipse test (see ellipse_cut), FP64.
 __device__ __forceinline__ EllP ell_params(const GRec& R, const uint2 rc, double ln_amin) {
   const double a = R.ca, b = R.cb, c = R.cc;
@@ -877,15 +1032,22 @@ void launch_depth_sort(const SetDev& S, const Work& w, bool ell, hipStream_t st)
   hipLaunchKernelGGL(k_compact, dim3(gb), dim3(256), 0, st, w.vis, w.vis_scan, w.dkey, S.n,
                      S.n_cams, w.cams, w.skey[0], w.sval[0], w.vis_off, w.item_off, w.counters,
                      passes, (uint32_t)kpb, w.rs_ghist, w.rs1, w.rs_groups, nb);
-  auto pass_k = kpb > 1024 ? k_rs_onepass<16> : k_rs_onepass<4>;
   uint32_t* wait_flag = (uint32_t*)w.scan_scratch + 2;  // reported with the scans' flag
-  int cur = 0;
-  for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(pass_k, dim3((unsigned)nb), dim3(RS_B), 0, st, w.skey[cur], w.sval[cur],
-                       w.skey[cur ^ 1], w.sval[cur ^ 1], w.counters, p, passes, S.n,
-                       w.rs_ghist, w.rs1, w.rs_groups, nb, wait_flag);
-    cur ^= 1;
+  if (kpb > 1024) {
+    // many items (several cameras): the look-back of the one-dispatch passes
+    // would chain over hundreds of blocks, the grid-barrier sort waits only
+    // for its RSC_MAX_BLOCKS workgroups
+    hipLaunchKernelGGL(k_rs_coop, dim3(RSC_MAX_BLOCKS), dim3(RSC_T), 0, st, w.skey[0],
+                       w.sval[0], w.skey[1], w.sval[1], w.counters, passes, S.n, w.rs_hist,
+                       w.rs1 + 7, wait_flag);
+  } else {
+    for (int p = 0; p < passes; ++p)
+      hipLaunchKernelGGL(k_rs_onepass<4>, dim3((unsigned)nb), dim3(RS_B), 0, st,
+                         w.skey[p & 1], w.sval[p & 1], w.skey[(p & 1) ^ 1], w.sval[(p & 1) ^ 1],
+                         w.counters, p, passes, S.n, w.rs_ghist, w.rs1, w.rs_groups, nb,
+                         wait_flag);
   }
+  const int cur = passes & 1;
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
                      w.sval[cur], w.counters, M, w.rec, w.rect, w.rec_s, w.rect_s,
                      w.item_s, w.rank_of, std::log((double)S.alpha_min),
