@@ -650,7 +650,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
 constexpr int RB = 2;  // Gaussians whose gradients the one-wave backward sums together
 
 template <int BG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_num_vgpr(128))) void k_blend_bwd_w(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_blend_bwd_w(
     SetDev S, const CamDev* __restrict__ cams, const uint32_t* __restrict__ vis_off,
     const uint32_t* __restrict__ mat, const uint32_t* __restrict__ tile_start,
     const uint32_t* __restrict__ tile_total, const uint32_t* __restrict__ tile_order,
@@ -720,24 +720,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_num_vgpr(128))) void k_bl
   for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o, 64));
   const int64_t last = lmax;
   if (last == 0) return;
-  // RB Gaussians' partials are summed together: lane L < 9 nb sums row L over
-  // the 64 lanes and adds it to the Gaussian's accumulators (one atomic
-  // instruction for all of them)
+  // RB Gaussians' partials are summed together: row r = 9 gs + q of part
+  // holds gradient q of Gaussian gs over the 64 lanes; lanes r and r + 32
+  // sum its entries [0, 32) and [32, 64), lane r adds the two and the result
+  // to the Gaussian's accumulators (one atomic instruction for all rows)
+  static_assert(9 * RB <= 32, "two lanes per row");
   int nb = 0;
   auto flush = [&]() {
     __syncthreads();
+    const int r = lane & 31;
+    float v = 0.f;
+    if (r < 9 * nb) {
+      const float* row = &part[0][0][0] + r * 65 + (lane & 32);
+#pragma unroll 4
+      for (int k = 0; k < 32; k += 2) v += row[k] + row[k + 1];
+    }
+    v += __shfl_down(v, 32, 64);
     if (lane < 9 * nb) {
       const int gs = lane / 9, q = lane - 9 * gs;
-      const float* row = &part[gs][q][0];
-      float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
-#pragma unroll 4
-      for (int l = 0; l < 64; l += 4) {
-        v0 += row[l];
-        v1 += row[l + 1];
-        v2 += row[l + 2];
-        v3 += row[l + 3];
-      }
-      atomicAdd(gacc + (size_t)prk[gs] * 9 + q, (v0 + v1) + (v2 + v3));
+      atomicAdd(gacc + (size_t)prk[gs] * 9 + q, v);
     }
     __syncthreads();
   };
