@@ -679,8 +679,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
   const float lthr = __log2f(S.alpha_min), amax = S.alpha_max;
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
   const int64_t hw = (int64_t)C.W * C.H;
-  float gr[WPIX], gg[WPIX], gb[WPIX], gT[WPIX], Tf[WPIX], T[WPIX], Sr[WPIX], Sg[WPIX], Sb[WPIX],
-      py[WPIX], gTf[WPIX];
+  // U: the colour of the Gaussians behind, dotted with the pixel's colour
+  // gradient (the one scalar of it the alpha gradient needs)
+  float gr[WPIX], gg[WPIX], gb[WPIX], gT[WPIX], Tf[WPIX], T[WPIX], U[WPIX], py[WPIX], gTf[WPIX];
   int nc[WPIX];
   int lmax = 0;
 #pragma unroll
@@ -713,7 +714,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
     T[r] = Tf[r];
     gTf[r] = gT[r] * Tf[r];
-    Sr[r] = Sg[r] = Sb[r] = 0.f;
+    U[r] = 0.f;
     lmax = max(lmax, nc[r]);
   }
 #pragma unroll
@@ -801,18 +802,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
           gc0 = __builtin_fmaf(wgt, gr[r], gc0);
           gc1 = __builtin_fmaf(wgt, gg[r], gc1);
           gc2 = __builtin_fmaf(wgt, gb[r], gc2);
-          const float dr = c.x - Sr[r], dg = c.y - Sg[r], db = c.z - Sb[r];
-          const float galpha = __builtin_fmaf(
-              T[r], __builtin_fmaf(dr, gr[r], __builtin_fmaf(dg, gg[r], db * gb[r])),
-              -gTf[r] * inv);
-          Sr[r] = __builtin_fmaf(alpha, dr, Sr[r]);
-          Sg[r] = __builtin_fmaf(alpha, dg, Sg[r]);
-          Sb[r] = __builtin_fmaf(alpha, db, Sb[r]);
+          // (c - S) . g with S the colour behind, S <- S + alpha (c - S)
+          const float du =
+              __builtin_fmaf(c.x, gr[r], __builtin_fmaf(c.y, gg[r], c.z * gb[r])) - U[r];
+          const float galpha = __builtin_fmaf(T[r], du, -gTf[r] * inv);
+          U[r] = __builtin_fmaf(alpha, du, U[r]);
           // d alpha / d power = alpha' (0 where clamped at alpha_max)
           const float gp = ag < amax ? galpha * ag : 0.f;
+          const float gpdy = gp * dy;
           s0 += gp;
-          s1 = __builtin_fmaf(gp, dy, s1);
-          s2 = __builtin_fmaf(gp, dy * dy, s2);
+          s1 += gpdy;
+          s2 = __builtin_fmaf(gpdy, dy, s2);
         }
         if (__any(any)) {
           // power = -1/2 (ca dx^2 + cc dy^2) - cb dx dy, dx = u - px; the
