@@ -22,9 +22,10 @@ namespace {
 //     logit: 11 values, stored by rank in 48-byte slots of memory the forward
 //     no longer needs;
 //  2. k_project_bwd_gauss, one thread per Gaussian: sums those slots over the
-//     cameras (in FP64) and does the colour part itself - the view direction
-//     and the SH colour's clamp decision recomputed in FP64, the gradients to
-//     the SH coefficients and, through the view direction, to the mean.
+//     cameras (in FP64); the colour part - the view direction and the SH
+//     colour's clamp decision recomputed in FP64, the gradients to the SH
+//     coefficients and, through the view direction, to the mean - runs one
+//     visible item per thread of the workgroup, into the owner's LDS sums.
 struct GeomGrad {
   float4 a;  // mean x y z, opacity logit
   float4 b;  // log-scales x y z, unused
@@ -198,8 +199,9 @@ __global__ __launch_bounds__(256) void k_project_bwd_geom(
   }
 }
 
-// One thread per Gaussian: the camera sum of the geometry slots, the colour
-// part, the densification statistics and one write per gradient array.
+// One thread per Gaussian: the camera sum of the geometry slots, the
+// densification statistics and one write per gradient array; the colour part
+// of every visible item spread over the workgroup's threads.
 __global__ __launch_bounds__(128) void k_project_bwd_gauss(
     SetDev S, const CamDev* __restrict__ cams, const float* __restrict__ means,
     const float* __restrict__ sh, const int32_t* __restrict__ rank_of,
@@ -207,50 +209,73 @@ __global__ __launch_bounds__(128) void k_project_bwd_gauss(
     float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q,
     float* __restrict__ g_logit, float* __restrict__ g_sh, float* __restrict__ m2d_norm,
     int32_t* __restrict__ m2d_count) {
-  // the 3K SH-coefficient gradients of this thread's Gaussian live in its own
-  // column of LDS
+  // the 3K SH-coefficient gradients of each thread's Gaussian live in its own
+  // column of LDS, the colour part of its mean gradient in gmc
   __shared__ float shacc[48 * 128];
-  float* gshr_col = shacc + threadIdx.x;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= S.n) return;
+  __shared__ float gmc[3 * 128];
+  // the (Gaussian, camera) items of a group of 8 cameras with a colour
+  // gradient: owner thread | camera offset << 8, rank
+  __shared__ uint2 q[8 * 128];
+  __shared__ uint32_t nq;
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x * blockDim.x + tid;
+  const bool own = g < S.n;
   float stat_norm = 0.f;
   int stat_cnt = 0;
   const int K = (S.sh_degree + 1) * (S.sh_degree + 1);
-  double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glg = 0;
-  for (int k = 0; k < 3 * K; ++k) gshr_col[k * 128] = 0.f;
+  double gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glg = 0, gmu[3] = {0, 0, 0};
+  for (int k = 0; k < 3 * K; ++k) shacc[k * 128 + tid] = 0.f;
+  gmc[3 * tid] = gmc[3 * tid + 1] = gmc[3 * tid + 2] = 0.f;
   bool any = false;
-  const float* shg = sh + (size_t)g * K * 3;
-  const double mu[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
   for (int c0 = 0; c0 < S.n_cams; c0 += 8) {
-    // the ranks of up to 8 cameras, loaded together
-    int rk[8];
+    if (tid == 0) nq = 0;
+    __syncthreads();
+    if (own) {
+      // the ranks of up to 8 cameras, loaded together
+      int rk[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      rk[j] = c0 + j < S.n_cams ? rank_of[(int64_t)(c0 + j) * S.n + g] : -1;
-    for (int j = 0; j < 8; ++j) {
-      const int r = rk[j];
-      if (r < 0) continue;
-      const float* ga = gacc + (size_t)r * 9;
-      float G9[9];
+      for (int j = 0; j < 8; ++j)
+        rk[j] = c0 + j < S.n_cams ? rank_of[(int64_t)(c0 + j) * S.n + g] : -1;
+      for (int j = 0; j < 8; ++j) {
+        const int r = rk[j];
+        if (r < 0) continue;
+        const float* ga = gacc + (size_t)r * 9;
+        float G9[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) G9[q] = ga[q];
-      stat_norm += sqrtf(G9[0] * G9[0] + G9[1] * G9[1]);
-      ++stat_cnt;
-      const bool gnz = G9[0] != 0.f || G9[1] != 0.f || G9[2] != 0.f || G9[3] != 0.f ||
-                       G9[4] != 0.f || G9[5] != 0.f;
-      const bool cnz = G9[6] != 0.f || G9[7] != 0.f || G9[8] != 0.f;
-      if (!gnz && !cnz) continue;
-      any = true;
-      if (gnz) {
-        const GeomGrad o = geo[r];
-        gmu[0] += o.a.x; gmu[1] += o.a.y; gmu[2] += o.a.z; glg += o.a.w;
-        gls[0] += o.b.x; gls[1] += o.b.y; gls[2] += o.b.z;
-        gq[0] += o.c.x; gq[1] += o.c.y; gq[2] += o.c.z; gq[3] += o.c.w;
+        for (int k = 0; k < 9; ++k) G9[k] = ga[k];
+        stat_norm += sqrtf(G9[0] * G9[0] + G9[1] * G9[1]);
+        ++stat_cnt;
+        const bool gnz = G9[0] != 0.f || G9[1] != 0.f || G9[2] != 0.f || G9[3] != 0.f ||
+                         G9[4] != 0.f || G9[5] != 0.f;
+        const bool cnz = G9[6] != 0.f || G9[7] != 0.f || G9[8] != 0.f;
+        if (!gnz && !cnz) continue;
+        any = true;
+        if (gnz) {
+          const GeomGrad o = geo[r];
+          gmu[0] += o.a.x; gmu[1] += o.a.y; gmu[2] += o.a.z; glg += o.a.w;
+          gls[0] += o.b.x; gls[1] += o.b.y; gls[2] += o.b.z;
+          gq[0] += o.c.x; gq[1] += o.c.y; gq[2] += o.c.z; gq[3] += o.c.w;
+        }
+        if (cnz) q[atomicAdd(&nq, 1u)] = make_uint2((uint32_t)tid | ((uint32_t)j << 8), (uint32_t)r);
       }
-      if (!cnz) continue;
-      // colour: the view direction and the clamp of the forward, in FP64
-      const CamDev& cam = cams[c0 + j];
-      const double d0 = mu[0] - cam.C[0], d1 = mu[1] - cam.C[1], d2 = mu[2] - cam.C[2];
+    }
+    __syncthreads();
+    // the colour part, one item per thread (the items of a Gaussian seen by
+    // few cameras would otherwise leave most lanes of its wave idle): the
+    // view direction and the clamp of the forward in FP64, the gradients to
+    // the SH coefficients and, through the view direction, to the mean, added
+    // to the owner's LDS accumulators
+    const uint32_t n_q = nq;
+    for (uint32_t e = (uint32_t)tid; e < n_q; e += 128) {
+      const uint2 it = q[e];
+      const int o = (int)(it.x & 255u), cam_i = c0 + (int)(it.x >> 8);
+      const int go = blockIdx.x * blockDim.x + o;
+      const float* ga = gacc + (size_t)it.y * 9;
+      const float gcol[3] = {ga[6], ga[7], ga[8]};
+      const float* shg = sh + (size_t)go * K * 3;
+      const CamDev& cam = cams[cam_i];
+      const double d0 = (double)means[3 * go] - cam.C[0], d1 = (double)means[3 * go + 1] - cam.C[1],
+                   d2 = (double)means[3 * go + 2] - cam.C[2];
       const double dnorm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
       const double dir64[3] = {d0 / dnorm, d1 / dnorm, d2 / dnorm};
       double col[3];
@@ -263,9 +288,9 @@ __global__ __launch_bounds__(128) void k_project_bwd_gauss(
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         if (col[ch] < 0.0) continue;  // clamped at 0 in the forward: no gradient
-        const float gc = G9[6 + ch];
+        const float gc = gcol[ch];
         for (int k = 0; k < K; ++k) {
-          gshr_col[(3 * k + ch) * 128] += Y[k] * gc;
+          atomicAdd(&shacc[(3 * k + ch) * 128 + o], Y[k] * gc);
           wdir[k] += shg[3 * k + ch] * gc;
         }
       }
@@ -274,21 +299,23 @@ __global__ __launch_bounds__(128) void k_project_bwd_gauss(
       const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
       const float idn = 1.f / (float)dnorm;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dd) * idn;
+      for (int a = 0; a < 3; ++a) atomicAdd(&gmc[3 * o + a], (gdir[a] - dir[a] * dd) * idn);
     }
+    __syncthreads();
   }
+  if (!own) return;
   if (m2d_norm && stat_cnt) m2d_norm[g] += stat_norm;
   if (m2d_count && stat_cnt) m2d_count[g] += stat_cnt;
   if (!any) return;
   if (g_means)
-    for (int a = 0; a < 3; ++a) g_means[3 * g + a] += (float)gmu[a];
+    for (int a = 0; a < 3; ++a) g_means[3 * g + a] += (float)(gmu[a] + (double)gmc[3 * tid + a]);
   if (g_ls)
     for (int a = 0; a < 3; ++a) g_ls[3 * g + a] += (float)gls[a];
   if (g_q)
     for (int a = 0; a < 4; ++a) g_q[4 * g + a] += (float)gq[a];
   if (g_logit) g_logit[g] += (float)glg;
   if (g_sh)
-    for (int k = 0; k < 3 * K; ++k) g_sh[(size_t)g * K * 3 + k] += gshr_col[k * 128];
+    for (int k = 0; k < 3 * K; ++k) g_sh[(size_t)g * K * 3 + k] += shacc[k * 128 + tid];
 }
 
 
