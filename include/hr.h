@@ -244,8 +244,10 @@ hr_status hr_render_hybrid(const hr_gaussians* g, const hr_mesh* mesh, const hr_
  * HR_N_STAGES floats) receives milliseconds: on the given stream 0 camera
  * upload and projection, 1 depth sort (visibility scan, compaction, radix
  * passes, gather), 2 tile binning (with the mesh-depth bound when culling,
- * which waits for the mesh), 3 blend, 4 statistics export; 5 the mesh pass on
- * the internal stream (concurrent with 1-2; 0 with HR_FLAG_MESH_REUSED); 6 the
+ * which waits for the mesh), 3 blend (with the shading of the mesh pixels
+ * unless the mesh is reused), 4 statistics export; 5 the mesh pass up to the
+ * z-buffer on the internal stream (concurrent with 1-2; 0 with
+ * HR_FLAG_MESH_REUSED); 6 the
  * whole forward on the given stream. Errors as hr_render_hybrid (the capacity
  * check is always made). */
 #define HR_N_STAGES 7
@@ -286,8 +288,9 @@ hr_status hr_render_hybrid_backward_timed(const hr_gaussians* g, const hr_mesh* 
 
 /* Re-runs only the per-tile blend and composite of the forward that last
  * filled this workspace (all arguments equal to that forward's), rewriting
- * the same outputs. Used to time the blend kernel on its own and by the
- * autotuner. */
+ * the same image, T and counts; the mesh colour is the one that forward's
+ * shading left in the workspace (mesh_rgb, mesh_depth and tri_id are not
+ * written). Used to time the blend kernel on its own and by the autotuner. */
 hr_status hr_blend_forward(const hr_gaussians* g, const hr_mesh* mesh, const hr_camera* cams,
                            int32_t n_cams, const hr_settings* s, int64_t key_capacity,
                            void* workspace, size_t workspace_bytes, hr_outputs* out,

@@ -524,7 +524,10 @@ hr_status enqueue_forward(const Plan& p, const Work& w, const SetDev& S, const h
   launch_binning(S, w, (int)p.n_cams, cull, (s->flags & HR_FLAG_TILE_ELLIPSE) != 0, out, st);
   if (ev) hipEventRecord(ev[3], st);
   if (!cull && !reuse && !ss->join_into(st)) return fail(HR_ERR_HIP, "stream join failed");
-  launch_blend_forward(S, w, out, pick_batch(s), s->variant, st);
+  // without the mesh reused, the blend also shades the mesh pixels (and writes
+  // the mesh outputs), beside compositing them
+  launch_blend_forward(S, w, out, pick_batch(s), s->variant, st, !reuse,
+                       S.n_faces > 0 ? m->tex : nullptr);
   if (ev) hipEventRecord(ev[4], st);
   if (out->stats)
     launch_counters_to_stats(w.counters, w.tile_np, (int)S.n_tiles, (const uint32_t*)w.scan_scratch,

@@ -7,6 +7,7 @@
 // stops at the first Gaussian whose depth reaches D_m, or before T would drop
 // under t_min; the workgroup leaves as soon as every pixel has stopped.
 #include "kernels.hpp"
+#include "mesh_math.hpp"
 #include "window.hpp"
 
 namespace hr {
@@ -146,6 +147,10 @@ struct FwdArgs {
   int32_t* nb_out;
   int32_t* np_out;
   unsigned long long* tile_np;  // [2 * n_tiles] examined, blended pairs of each tile
+  // shading of the mesh pixels (SHADE kernels): triangles, textures, outputs
+  const TriRec* tris;
+  const float* tex;
+  MeshOut mo;
 };
 
 template <int BG, int DEPTH>
@@ -157,14 +162,15 @@ struct FwdShared {
   unsigned long long red[2];
 };
 
-// blend and composite one tile t (all 256 threads of the group)
-template <int BG, int DEPTH>
+// blend and composite one tile t (all 256 threads of the group); SHADE: the
+// mesh colour of each pixel is computed here (mesh_shade) rather than read
+template <int BG, int DEPTH, bool SHADE>
 __device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH>& L, int t) {
   const SetDev& S = A.S;
   const CamDev* __restrict__ cams = A.cams;
   const uint32_t* __restrict__ lists = A.lists;
   const GRec* __restrict__ rec_s = A.rec_s;
-  const float* __restrict__ mesh_rgb = A.mesh_rgb;
+  const float* mesh_rgb = A.mesh_rgb;  // written by mesh_shade in SHADE mode: no restrict
   auto& sh = L.sh;
   auto& rk = L.rk;
   auto& bitmap = L.bitmap;
@@ -177,6 +183,12 @@ __device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH
   unsigned long long key = ~0ull;
   if (tc.inside) key = A.zbuf[tc.p];
   const float Dm = key == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(key >> 32));
+  // the pixel's mesh shading first: its loads overlap the tile's list work,
+  // and the composite reads the colour back (this thread's own store)
+  if (SHADE && tc.inside) {
+    float rgb[3];
+    mesh_shade(S, C, tc.i, tc.j, tc.p, key, A.tris, A.tex, A.mo, rgb);
+  }
   const float lthr = __log2f(S.alpha_min), amax = S.alpha_max, tmin = S.t_min;
   const uint32_t rmax = (uint32_t)((int64_t)S.n * S.n_cams - 1);
   PixState ps;
@@ -284,14 +296,14 @@ __device__ __forceinline__ void blend_tile(const FwdArgs& A, FwdShared<BG, DEPTH
 }
 
 // one workgroup per tile, in the longest-list-first order
-template <int BG, int DEPTH>
+template <int BG, int DEPTH, bool SHADE>
 __global__ __launch_bounds__(256) void k_blend_fwd(FwdArgs A) {
   __shared__ FwdShared<BG, DEPTH> L;
-  blend_tile<BG, DEPTH>(A, L, (int)A.tile_order[blockIdx.x]);
+  blend_tile<BG, DEPTH, SHADE>(A, L, (int)A.tile_order[blockIdx.x]);
 }
 
 // persistent workgroups pull tiles from an atomic queue over the same order
-template <int BG, int DEPTH>
+template <int BG, int DEPTH, bool SHADE>
 __global__ __launch_bounds__(256) void k_blend_fwd_persistent(FwdArgs A, uint32_t* queue) {
   __shared__ FwdShared<BG, DEPTH> L;
   __shared__ uint32_t next;
@@ -301,7 +313,7 @@ __global__ __launch_bounds__(256) void k_blend_fwd_persistent(FwdArgs A, uint32_
     const uint32_t q = next;
     __syncthreads();
     if (q >= (uint32_t)A.S.n_tiles) break;
-    blend_tile<BG, DEPTH>(A, L, (int)A.tile_order[q]);
+    blend_tile<BG, DEPTH, SHADE>(A, L, (int)A.tile_order[q]);
   }
 }
 
@@ -507,7 +519,7 @@ __device__ __forceinline__ void wave_extract(const WinWords& ww, uint32_t q, uin
   }
 }
 
-template <int BG>
+template <int BG, bool SHADE>
 __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
   __shared__ Staged sh[BG];
   __shared__ uint32_t rk[BG];
@@ -534,6 +546,10 @@ __global__ __launch_bounds__(64) void k_blend_fwd_w(FwdArgs A) {
     const int j = j0 + r;
     const bool inside = i < C.W && j < C.H;
     key[r] = inside ? A.zbuf[C.pix_off + (int64_t)j * C.W + i] : ~0ull;
+    if (SHADE && inside) {  // the mesh shading first, as in blend_tile
+      float rgb[3];
+      mesh_shade(S, C, i, j, C.pix_off + (int64_t)j * C.W + i, key[r], A.tris, A.tex, A.mo, rgb);
+    }
     Dm[r] = key[r] == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(key[r] >> 32));
     py[r] = (float)j + 0.5f;
     T[r] = 1.f;
@@ -844,10 +860,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 
 }  // namespace
 
-template <int BG, int D>
+template <int BG, int D, bool SH>
 void launch_fwd(const FwdArgs& A, bool persistent, uint32_t* queue, hipStream_t st) {
   if (!persistent) {
-    hipLaunchKernelGGL((k_blend_fwd<BG, D>), dim3(A.S.n_tiles), dim3(256), 0, st, A);
+    hipLaunchKernelGGL((k_blend_fwd<BG, D, SH>), dim3(A.S.n_tiles), dim3(256), 0, st, A);
     return;
   }
   static int grid = 0;
@@ -857,38 +873,58 @@ void launch_fwd(const FwdArgs& A, bool persistent, uint32_t* queue, hipStream_t 
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_blend_fwd_persistent<BG, D>, 256,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_blend_fwd_persistent<BG, D, SH>, 256,
                                                      0) != hipSuccess)
       per = 0;
     grid = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
   }
   launch_fill_u32(queue, 0u, 1, st);
-  hipLaunchKernelGGL((k_blend_fwd_persistent<BG, D>), dim3(grid), dim3(256), 0, st, A, queue);
+  hipLaunchKernelGGL((k_blend_fwd_persistent<BG, D, SH>), dim3(grid), dim3(256), 0, st, A, queue);
 }
 
-// variant bit 0: two-deep staging; bit 1: persistent workgroups on a tile queue
+template <bool SH>
+void launch_variant(const FwdArgs& A, int batch, int variant, uint32_t* queue, hipStream_t st) {
+  const bool d2 = (variant & 1) != 0, pers = (variant & 2) != 0;
+  if (variant & 4) {
+    if (batch >= 128)
+      hipLaunchKernelGGL((k_blend_fwd_w<128, SH>), dim3(A.S.n_tiles), dim3(64), 0, st, A);
+    else
+      hipLaunchKernelGGL((k_blend_fwd_w<64, SH>), dim3(A.S.n_tiles), dim3(64), 0, st, A);
+    return;
+  }
+  switch (batch) {
+    case 32:
+      d2 ? launch_fwd<32, 2, SH>(A, pers, queue, st) : launch_fwd<32, 1, SH>(A, pers, queue, st);
+      break;
+    case 64:
+      d2 ? launch_fwd<64, 2, SH>(A, pers, queue, st) : launch_fwd<64, 1, SH>(A, pers, queue, st);
+      break;
+    case 128:
+      d2 ? launch_fwd<128, 2, SH>(A, pers, queue, st) : launch_fwd<128, 1, SH>(A, pers, queue, st);
+      break;
+    default:
+      d2 ? launch_fwd<256, 2, SH>(A, pers, queue, st) : launch_fwd<256, 1, SH>(A, pers, queue, st);
+      break;
+  }
+}
+
+// variant bit 0: two-deep staging; bit 1: persistent workgroups on a tile
+// queue; bit 2: one wave per tile. With tex_shade set the blend also shades
+// the mesh pixels (their z-buffer is complete); otherwise it reads the mesh
+// colour an earlier shading left in the workspace.
 void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int batch, int variant,
-                          hipStream_t st) {
+                          hipStream_t st, bool shade, const float* tex) {
   if (S.n_tiles == 0) return;
   FwdArgs A{S, w.cams, w.vis_off, w.mat, w.tile_start, w.tile_total, w.tile_order, w.lists,
             w.rec_s, (const unsigned long long*)w.zbuf, w.mesh_rgb, out->image, w.final_T,
             w.n_contrib, out->final_T, out->n_contrib, out->n_blended, out->n_processed,
-            (unsigned long long*)w.tile_np};
-  const bool d2 = (variant & 1) != 0, pers = (variant & 2) != 0;
+            (unsigned long long*)w.tile_np, w.tris, tex,
+            MeshOut{w.mesh_rgb, w.taps, out->mesh_rgb, out->mesh_depth, out->tri_id}};
   uint32_t* queue = w.counters + 14;
-  if (variant & 4) {
-    if (batch >= 128)
-      hipLaunchKernelGGL(k_blend_fwd_w<128>, dim3(A.S.n_tiles), dim3(64), 0, st, A);
-    else
-      hipLaunchKernelGGL(k_blend_fwd_w<64>, dim3(A.S.n_tiles), dim3(64), 0, st, A);
-    return;
-  }
-  switch (batch) {
-    case 32: d2 ? launch_fwd<32, 2>(A, pers, queue, st) : launch_fwd<32, 1>(A, pers, queue, st); break;
-    case 64: d2 ? launch_fwd<64, 2>(A, pers, queue, st) : launch_fwd<64, 1>(A, pers, queue, st); break;
-    case 128: d2 ? launch_fwd<128, 2>(A, pers, queue, st) : launch_fwd<128, 1>(A, pers, queue, st); break;
-    default: d2 ? launch_fwd<256, 2>(A, pers, queue, st) : launch_fwd<256, 1>(A, pers, queue, st); break;
-  }
+  if (shade)
+    launch_variant<true>(A, batch, variant, queue, st);
+  else
+    launch_variant<false>(A, batch, variant, queue, st);
 }
 
 #define HR_BWD(BG)                                                                              \

@@ -103,7 +103,7 @@ void launch_tile_dmax(const SetDev& S, const Work& w, hipStream_t st);
 void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* out,
                  hipStream_t st);
 void launch_blend_forward(const SetDev& S, const Work& w, hr_outputs* out, int batch, int variant,
-                          hipStream_t st);
+                          hipStream_t st, bool shade = false, const float* tex = nullptr);
 void launch_blend_backward(const SetDev& S, const Work& w, const float* grad_image,
                            const float* grad_T, int batch, int variant, hipStream_t st);
 void launch_project_backward(const SetDev& S, const CamDev* cams, const hr_gaussians& g,

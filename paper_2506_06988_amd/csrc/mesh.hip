@@ -9,7 +9,8 @@
 //                  (fp32 depth bits << 32 | triangle index) into the z-buffer.
 //                  Triangle indices increase with face id, so equal depths
 //                  resolve to the lower face whatever the launch order.
-//   k_mesh_resolve per pixel: perspective-correct UV and bilinear texture fetch
+//   the shading of each pixel (perspective-correct UV, bilinear texture fetch,
+//   mesh_math.hpp) runs in the blend's epilogue, beside the composite
 #include "kernels.hpp"
 #include "mesh_math.hpp"
 
@@ -133,61 +134,6 @@ __device__ __forceinline__ int find_cam_by_pix(const CamDev* cams, int n_cams, i
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_mesh_resolve(SetDev S, const CamDev* __restrict__ cams,
-                                                      const unsigned long long* __restrict__ zbuf,
-                                                      const TriRec* __restrict__ tris,
-                                                      const float* __restrict__ tex,
-                                                      float* __restrict__ mesh_rgb_ws,
-                                                      uint4* __restrict__ taps,
-                                                      float* __restrict__ mesh_rgb,
-                                                      float* __restrict__ mesh_depth,
-                                                      int32_t* __restrict__ tri_id) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= S.n_pix) return;
-  const int c = find_cam_by_pix(cams, S.n_cams, p);
-  const CamDev& C = cams[c];
-  const int64_t lp = p - C.pix_off;
-  const int64_t hw = (int64_t)C.W * C.H;
-  const int i = (int)(lp % C.W), j = (int)(lp / C.W);
-  const unsigned long long key = zbuf[p];
-  float rgb[3] = {0.f, 0.f, 0.f};
-  float depth = __int_as_float(0x7f800000);
-  int face = -1;
-  uint4 tq = make_uint4(~0u, 0u, 0u, 0u);
-  if (key != ~0ull) {
-    const TriRec& T = tris[(uint32_t)key];
-    int64_t e[3];
-    tri_cover(T, i, j, e);
-    double uv[2];
-    tri_interp(T, e, uv);
-    const Taps tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
-    tq = pack_taps(T.tex, tp);
-    const float wx = tp.fx, wy = tp.fy;
-    const float w00 = (1.f - wx) * (1.f - wy), w10 = wx * (1.f - wy), w01 = (1.f - wx) * wy,
-                w11 = wx * wy;
-    // one 12-byte load per texel
-    float3 t00, t10, t01, t11;
-    __builtin_memcpy(&t00, tex + tp.o00, 12);
-    __builtin_memcpy(&t10, tex + tp.o10, 12);
-    __builtin_memcpy(&t01, tex + tp.o01, 12);
-    __builtin_memcpy(&t11, tex + tp.o11, 12);
-    rgb[0] = w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x;
-    rgb[1] = w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y;
-    rgb[2] = w00 * t00.z + w10 * t10.z + w01 * t01.z + w11 * t11.z;
-    depth = __uint_as_float((uint32_t)(key >> 32));
-    face = T.face;
-  }
-  const int64_t pl = 3 * C.pix_off;
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    mesh_rgb_ws[pl + ch * hw + lp] = rgb[ch];
-    if (mesh_rgb) mesh_rgb[pl + ch * hw + lp] = rgb[ch];
-  }
-  taps[p] = tq;
-  if (mesh_depth) mesh_depth[p] = depth;
-  if (tri_id) tri_id[p] = face;
-}
-
 __device__ __forceinline__ int find_cam_by_tile_m(const CamDev* cams, int n_cams, int tile) {
   int lo = 0, hi = n_cams - 1;
   while (lo < hi) {
@@ -265,11 +211,9 @@ void launch_mesh(const SetDev& S, const hr_mesh& m, const Work& w, hr_outputs* o
     hipLaunchKernelGGL(k_mesh_raster, dim3(2048), dim3(256), 0, st, S, w.cams, w.tri_off,
                        w.blk_off, w.tris, (unsigned long long*)w.zbuf);
   }
-  const float* tex = MF > 0 ? m.tex : nullptr;
-  hipLaunchKernelGGL(k_mesh_resolve, dim3((unsigned)((S.n_pix + 255) / 256)), dim3(256), 0, st, S,
-                     w.cams, (const unsigned long long*)w.zbuf, w.tris, tex, w.mesh_rgb, w.taps,
-                     out ? out->mesh_rgb : nullptr, out ? out->mesh_depth : nullptr,
-                     out ? out->tri_id : nullptr);
+  // the shading of every pixel (mesh_shade) is done by the blend, once the
+  // z-buffer is complete
+  (void)out;
 }
 
 void launch_tile_dmax(const SetDev& S, const Work& w, hipStream_t st) {

@@ -192,4 +192,63 @@ __device__ __forceinline__ Taps bilinear_taps(int tex, int H, int W, const doubl
   return t;
 }
 
+// Where the shading of a mesh pixel goes: the workspace copies the blend and
+// the backward read (colour, footprint) and the exported outputs (any of
+// colour, depth, face may be null).
+struct MeshOut {
+  float* rgb_ws;
+  uint4* taps;
+  float* rgb;
+  float* depth;
+  int32_t* tri_id;
+};
+
+// Shading of pixel (i, j) of camera C (packed index p) from its z-buffer key:
+// perspective-correct UV, bilinear texture colour, footprint, depth and face;
+// a pixel without a face gets colour 0, depth +inf, face -1 and an empty
+// footprint. Writes all of them and returns the colour.
+__device__ __forceinline__ void mesh_shade(const SetDev& S, const CamDev& C, int i, int j,
+                                           int64_t p, unsigned long long key,
+                                           const TriRec* __restrict__ tris,
+                                           const float* __restrict__ tex, const MeshOut& o,
+                                           float rgb[3]) {
+  rgb[0] = rgb[1] = rgb[2] = 0.f;
+  float depth = __int_as_float(0x7f800000);
+  int face = -1;
+  uint4 tq = make_uint4(~0u, 0u, 0u, 0u);
+  if (key != ~0ull) {
+    const TriRec& T = tris[(uint32_t)key];
+    int64_t e[3];
+    tri_cover(T, i, j, e);
+    double uv[2];
+    tri_interp(T, e, uv);
+    const Taps tp = bilinear_taps(T.tex, S.tex_h, S.tex_w, uv);
+    tq = pack_taps(T.tex, tp);
+    const float wx = tp.fx, wy = tp.fy;
+    const float w00 = (1.f - wx) * (1.f - wy), w10 = wx * (1.f - wy), w01 = (1.f - wx) * wy,
+                w11 = wx * wy;
+    // one 12-byte load per texel
+    float3 t00, t10, t01, t11;
+    __builtin_memcpy(&t00, tex + tp.o00, 12);
+    __builtin_memcpy(&t10, tex + tp.o10, 12);
+    __builtin_memcpy(&t01, tex + tp.o01, 12);
+    __builtin_memcpy(&t11, tex + tp.o11, 12);
+    rgb[0] = w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x;
+    rgb[1] = w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y;
+    rgb[2] = w00 * t00.z + w10 * t10.z + w01 * t01.z + w11 * t11.z;
+    depth = __uint_as_float((uint32_t)(key >> 32));
+    face = T.face;
+  }
+  const int64_t hw = (int64_t)C.W * C.H;
+  const int64_t pl = 3 * C.pix_off + (p - C.pix_off);
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    o.rgb_ws[pl + ch * hw] = rgb[ch];
+    if (o.rgb) o.rgb[pl + ch * hw] = rgb[ch];
+  }
+  o.taps[p] = tq;
+  if (o.depth) o.depth[p] = depth;
+  if (o.tri_id) o.tri_id[p] = face;
+}
+
 }  // namespace hr
