@@ -40,12 +40,12 @@ BLEND_OPS_BLENDED = 7
 # HBM bytes per blend launch over the 32 headline views, by (batch, variant),
 # from the FETCH_SIZE and WRITE_SIZE counter passes of `bench.py --pmc-probe`
 # (scaled by a 256 MiB copy: FETCH x2, WRITE x1), tile-ellipse binning; valid
-# for the blend kernels they were taken with
-BLEND_TRAFFIC = {(32, 0): 165.9e6, (32, 1): 166.2e6, (32, 2): 161.2e6, (32, 3): 161.8e6,
-                 (64, 0): 166.1e6, (64, 1): 166.8e6, (64, 2): 161.6e6, (64, 3): 162.3e6,
-                 (64, 4): 166.4e6, (128, 0): 166.5e6, (128, 1): 167.6e6, (128, 2): 161.8e6,
-                 (128, 3): 162.7e6, (128, 4): 166.9e6, (256, 0): 167.3e6, (256, 1): 168.8e6,
-                 (256, 2): 162.5e6, (256, 3): 163.6e6}
+# for the blend-only kernels (no mesh shading) they were taken with
+BLEND_TRAFFIC = {(32, 0): 165.9e6, (32, 1): 166.2e6, (32, 2): 161.3e6, (32, 3): 161.7e6,
+                 (64, 0): 166.1e6, (64, 1): 166.8e6, (64, 2): 161.5e6, (64, 3): 162.1e6,
+                 (64, 4): 166.4e6, (128, 0): 166.5e6, (128, 1): 167.6e6, (128, 2): 161.9e6,
+                 (128, 3): 162.9e6, (128, 4): 166.9e6, (256, 0): 167.3e6, (256, 1): 168.9e6,
+                 (256, 2): 163.1e6, (256, 3): 163.9e6}
 # every configuration the forward autotuner may choose
 BLEND_CONFIGS = [(b, v) for v in range(4) for b in (32, 64, 128, 256)] + [(64, 4), (128, 4)]
 # pairs outside the alpha >= alpha_min ellipse are skipped by every pixel:
@@ -112,7 +112,7 @@ def pmc_probe_step(torch, hr, scenes, dev):
     s4 = scenes.config4()
     g, m = hr.to_device(s4.gaussians, s4.mesh, device=dev)
     r = hr.Renderer(g, m, s4.cameras, settings=hr.default_settings(flags=PAIR_CULL))
-    r.settings.batch, r.settings.variant, r.settings.batch_bwd = 256, 8, 128
+    r.settings.batch, r.settings.variant, r.settings.batch_bwd = 256, 8, 64
     f = r.render_hybrid(sync_check=True)
     target = torch.cat([torch.as_tensor(t.reshape(-1)) for t in s4.target]).to(dev)
     _, gi, gt, gm = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target, r.sizes)
@@ -149,15 +149,18 @@ def timed_frames(torch, r, frame, views, steps, warmup):
 HBM_BYTES_PER_S = 8.0e12
 
 
-def frame_roofline(stage_ms, counts, blend_stats, n_gauss, sh_degree, faces, blend_ms):
+def frame_roofline(stage_ms, counts, blend_stats, n_gauss, sh_degree, faces, pixels):
     """Per stage of a 1080p frame: the algorithmic bytes (or VALU lane-ops)
     the method must move (or compute), the time that takes at the HBM (VALU)
     peak, and that time as a fraction of the measured stage time; the frame's
     roofline time is their sum (the mesh pass counted although it runs
-    concurrently on its own stream)."""
+    concurrently on its own stream). The blend stage also shades the mesh
+    pixels: its roof is the larger of its lane-ops at the VALU peak and the
+    shading's bytes at the HBM peak."""
     K = (sh_degree + 1) ** 2
     nv, nk = counts["n_visible"], counts["n_keys"]
     ex, bl = blend_stats["pairs_examined_per_view"], blend_stats["pairs_blended_per_view"]
+    valu = VALU_PEAK_TOPS * 1e12
     work = {
         # per Gaussian its 11 geometry and opacity floats in, its visibility and rank
         # out; per visible one its SH coefficients in, depth key, record and
@@ -167,19 +170,26 @@ def frame_roofline(stage_ms, counts, blend_stats, n_gauss, sh_degree, faces, ble
         "depth_sort": ("hbm", nv * 8 * 2 * 4),
         # one 4-byte rank per kept (tile, Gaussian) pair
         "binning": ("hbm", nk * 4),
+        # the pairs' lane-ops; the shading: 4 texels (48 bytes) and 20 bytes of
+        # outputs per mesh pixel
         "blend": ("alu", ex * BLEND_OPS_EXAMINED + bl * BLEND_OPS_BLENDED),
-        # 4 texels (48 bytes) and 20 bytes of outputs per mesh pixel, 80 bytes per face
-        "mesh": ("hbm", counts["mesh_pixels"] * 68 + faces * 80),
+        # the z-buffer cleared (8 bytes per pixel) and one key per mesh pixel, 80 bytes per face
+        "mesh": ("hbm", pixels * 8 + counts["mesh_pixels"] * 8 + faces * 80),
     }
+    shade_bytes = counts["mesh_pixels"] * 68
     out, total_roof = {}, 0.0
     for k, (bound, amount) in work.items():
-        peak = HBM_BYTES_PER_S if bound == "hbm" else VALU_PEAK_TOPS * 1e12
+        peak = HBM_BYTES_PER_S if bound == "hbm" else valu
         roof_ms = amount / peak * 1e3
-        meas = blend_ms if k == "blend" else stage_ms[k]
+        if k == "blend":
+            roof_ms = max(roof_ms, shade_bytes / HBM_BYTES_PER_S * 1e3)
+        meas = stage_ms[k]
         total_roof += roof_ms
         out[k] = {"bound": bound, "work": int(amount), "unit": "bytes" if bound == "hbm" else "lane-ops",
                   "roof_ms": round(roof_ms, 5), "measured_ms": round(meas, 5),
                   "frac": round(roof_ms / meas, 4) if meas > 0 else None}
+        if k == "blend":
+            out[k]["shading_bytes"] = int(shade_bytes)
         if bound == "hbm" and meas > 0:
             out[k]["GB_per_s"] = round(amount / (meas * 1e-3) / 1e9, 1)
     out["frame"] = {"roof_ms": round(total_roof, 5), "measured_ms": round(stage_ms["forward"], 5),
@@ -557,7 +567,7 @@ def main():
         f"; forward without the mesh pass {no_mesh_ms:.4f} ms")
     roof = frame_roofline(stage_sum, counts, hyb_stats, n_gauss=sc.gaussians.n,
                           sh_degree=sc.gaussians.sh_degree, faces=sc.mesh.n_faces,
-                          blend_ms=blend_s / launches * 1e3)
+                          pixels=sc.cameras[0].width * sc.cameras[0].height)
     log("frame roofline: " + json.dumps(roof))
     del r, frame
     torch.cuda.empty_cache()
