@@ -67,7 +67,7 @@ struct alignas(16) TriRec {
   double iz[3];         // 1 / view depth of each vertex
   double uv[3][2];
   int32_t face, tex, cam, pad;
-  int32_t bx0, by0, bx1, by1;  // 8x8 pixel blocks covered by the bbox (inclusive)
+  int32_t bx0, by0, bx1, by1;  // raster blocks (RBLK x RBLK pixels) covered by the bbox (inclusive)
 };
 
 // ----------------------------------------------------------- wave tools --

@@ -1,11 +1,11 @@
 // Z-buffered rasterization of the textured mesh for every camera (Sec. 3.4:
 // the mesh is rendered first, giving I_m and D_m).
 //   k_mesh_count   per (camera, face): clip, snap, count kept triangles and
-//                  8x8 pixel blocks of their bounding boxes
+//                  RBLK x RBLK pixel blocks of their bounding boxes
 //   k_mesh_setup   per (camera, face): write the kept triangles compactly
-//   k_mesh_raster  (triangle, 8x8 block) work items, a contiguous run per wave;
-//                  64 lanes = 64 pixels test integer edge functions and
-//                  atomicMin a 64-bit key
+//   k_mesh_raster  (triangle, block) work items, a contiguous run per group
+//                  of RBLK^2 lanes (one pixel each) that test integer edge
+//                  functions and atomicMin a 64-bit key
 //                  (fp32 depth bits << 32 | triangle index) into the z-buffer.
 //                  Triangle indices increase with face id, so equal depths
 //                  resolve to the lower face whatever the launch order.
@@ -83,12 +83,14 @@ __global__ __launch_bounds__(256) void k_mesh_raster(SetDev S, const CamDev* __r
                                                      unsigned long long* __restrict__ zbuf) {
   const int64_t MF = (int64_t)S.n_faces * S.n_cams;
   const uint32_t nblk = blk_off[MF];
-  const int lane = __lane_id();
-  // each wave rasterizes a contiguous run of blocks: one search, then a walk
-  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const uint32_t per = (nblk + waves - 1) / waves;
-  const uint32_t b0 = wid * per;
+  // a group of RBLK^2 lanes takes one block; each group rasterizes a
+  // contiguous run of blocks: one search, then a walk
+  constexpr int GL = RBLK * RBLK;
+  const int lane = (int)threadIdx.x % GL;
+  const uint32_t groups = gridDim.x * (blockDim.x / GL);
+  const uint32_t gid = blockIdx.x * (blockDim.x / GL) + threadIdx.x / GL;
+  const uint32_t per = (nblk + groups - 1) / groups;
+  const uint32_t b0 = gid * per;
   if (b0 >= nblk) return;
   const uint32_t b1 = b0 + per < nblk ? b0 + per : nblk;
   int64_t lo = 0, hi = MF - 1;
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(256) void k_mesh_raster(SetDev S, const CamDev* __r
     const CamDev& C = cams[T.cam];
     const int nbx = T.bx1 - T.bx0 + 1;
     const int bx = T.bx0 + lb % nbx, by = T.by0 + lb / nbx;
-    const int i = bx * 8 + (lane & 7), j = by * 8 + (lane >> 3);
+    const int i = bx * RBLK + (lane % RBLK), j = by * RBLK + (lane / RBLK);
     int64_t e[3];
     if (i < C.W && j < C.H && tri_cover(T, i, j, e)) {
       const double z = tri_interp(T, e, nullptr);

@@ -75,6 +75,12 @@ __device__ __forceinline__ bool edge_owns(int64_t ax, int64_t ay, int64_t bx, in
   return dy > 0 || (dy == 0 && dx < 0);
 }
 
+// Raster blocks: RBLK x RBLK pixels, one group of RBLK^2 lanes each (the
+// room's triangles cover a few pixels at 1080p, so small blocks keep most
+// lanes on covered pixels).
+constexpr int RBLK_LOG = 2;
+constexpr int RBLK = 1 << RBLK_LOG;
+
 // Sub-triangle `sub` (fan 0, sub+1, sub+2) of a clipped polygon, snapped and
 // oriented; false when degenerate, outside the guard band or off screen.
 __device__ __forceinline__ bool setup_tri(const CamDev& cam, const CV poly[4], int sub, TriRec& T) {
@@ -109,8 +115,8 @@ __device__ __forceinline__ bool setup_tri(const CamDev& cam, const CV poly[4], i
   int j0 = (int)fmax(0.0, ceil((double)(miny - SUBPIX / 2) / SUBPIX));
   int j1 = (int)fmin((double)(cam.H - 1), floor((double)(maxy - SUBPIX / 2) / SUBPIX));
   if (i0 > i1 || j0 > j1) return false;
-  T.bx0 = i0 >> 3; T.bx1 = i1 >> 3;
-  T.by0 = j0 >> 3; T.by1 = j1 >> 3;
+  T.bx0 = i0 >> RBLK_LOG; T.bx1 = i1 >> RBLK_LOG;
+  T.by0 = j0 >> RBLK_LOG; T.by1 = j1 >> RBLK_LOG;
   return true;
 }
 
