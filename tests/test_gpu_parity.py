@@ -101,6 +101,36 @@ def test_small_room_three_uneven_cameras_in_one_call(hr, seed, variant):
     assert st["n_keys"] == key_base
 
 
+def test_many_cameras_grid_barrier_sort_keys_bit_exact(hr):
+    # 700 cameras x 3000 Gaussians = 2.1M possible items, beyond the 2M where
+    # the depth sort switches to the one-dispatch grid-barrier passes; with
+    # more than 256 cameras the sort key has two camera bytes (6 passes)
+    say("case: 700 cameras, grid-barrier depth sort")
+    sc = scenes.small_room(41, n=3000, faces=300, tex=16, n_cams=1)
+    rng = np.random.default_rng(4100)
+    cams = [scenes.random_room_camera(rng, 32, 24) for _ in range(700)]
+    r, f = gpu_render(hr, sc, cams=cams, export_keys=True)
+    st = f.stats_dict()
+    say("stats", st)
+    assert st["wait_limit"] == 0
+    ranges = f.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    keys = f.keys.cpu().numpy().view(np.uint64)
+    vals = f.values.cpu().numpy().view(np.uint32)
+    key_base = tile_base = 0
+    for c, cam in enumerate(cams):
+        k, v, rg = oracle.keys(sc.gaussians, cam)
+        ntl = rg.shape[0]
+        np.testing.assert_array_equal(ranges[tile_base:tile_base + ntl] - key_base, rg)
+        K = len(k)
+        np.testing.assert_array_equal(keys[key_base:key_base + K] - (np.uint64(tile_base) << np.uint64(32)), k)
+        np.testing.assert_array_equal(vals[key_base:key_base + K], v)
+        key_base += K
+        tile_base += ntl
+    assert st["n_keys"] == key_base and st["n_visible"] > 0
+    for c in (0, 349, 699):
+        check_view(f, cams, c, oracle.render(sc.gaussians, sc.mesh, cams[c], alts=True))
+
+
 def test_many_rank_windows_and_pair_slices(hr):
     # > 8192 visible Gaussians per camera: tile lists span several rank
     # windows, and chunks hold more pairs than one binning slice
