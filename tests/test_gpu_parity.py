@@ -131,6 +131,38 @@ def test_many_cameras_grid_barrier_sort_keys_bit_exact(hr):
         check_view(f, cams, c, oracle.render(sc.gaussians, sc.mesh, cams[c], alts=True))
 
 
+def test_mesh_reused_and_blend_only_equal_the_full_forward(hr):
+    # the full forward shades the mesh pixels in its blend; a forward with the
+    # mesh reused and hr_blend_forward read the colour that shading left in the
+    # workspace, give the same image, T and counts, and leave the mesh outputs
+    say("case: mesh reused / blend only")
+    sc = scenes.small_room(17, n=5000, faces=2000, tex=32, width=120, height=90)
+    rng = np.random.default_rng(1700)
+    cams = [sc.cameras[0], scenes.random_room_camera(rng, 70, 50)]
+    r, f = gpu_render(hr, sc, cams=cams)
+    ref = [x.clone() for x in (f.image, f.final_T, f.n_contrib, f.n_blended, f.n_processed)]
+    mesh = [x.clone() for x in (f.mesh_rgb, f.mesh_depth, f.tri_id)]
+    for c in range(len(cams)):
+        check_view(f, cams, c, oracle.render(sc.gaussians, sc.mesh, cams[c], alts=True))
+    for x in (f.image, f.final_T, f.mesh_rgb, f.mesh_depth):
+        x.fill_(-7.0)
+    f.tri_id.fill_(-7)
+    r.render_hybrid_timed(f, mesh_reused=True)
+    torch.cuda.synchronize()
+    for x, y in zip(ref, (f.image, f.final_T, f.n_contrib, f.n_blended, f.n_processed)):
+        assert torch.equal(x, y)
+    assert bool((f.mesh_rgb == -7.0).all()) and bool((f.tri_id == -7).all())
+    f.image.fill_(-7.0)
+    r.blend_forward(f)
+    torch.cuda.synchronize()
+    assert torch.equal(ref[0], f.image)
+    # a full forward again rewrites the mesh outputs as the first one did
+    r.render_hybrid(f)
+    torch.cuda.synchronize()
+    for x, y in zip(mesh, (f.mesh_rgb, f.mesh_depth, f.tri_id)):
+        assert torch.equal(x, y)
+
+
 def test_many_rank_windows_and_pair_slices(hr):
     # > 8192 visible Gaussians per camera: tile lists span several rank
     # windows, and chunks hold more pairs than one binning slice
