@@ -150,15 +150,34 @@ __global__ __launch_bounds__(SB) void k_scan(const uint32_t* in, uint32_t* out, 
 
 // Two-kernel form for long arrays (the single pass would make every
 // workgroup read the totals of all before it): block totals, then a
-// down-sweep in which each block first adds up the totals before it.
+// down-sweep in which each block first adds up the totals before it. Tiles
+// of SB x LI elements (LI per thread, loaded as 16-byte vectors), so that
+// the down-sweep's reads of earlier totals stay few.
+constexpr int LI = 64;
+constexpr int64_t LE = (int64_t)SB * LI;
+
+__device__ __forceinline__ void load_run(const uint32_t* in, int64_t base, int64_t n, uint32_t* v) {
+  if (base + LI <= n) {
+#pragma unroll
+    for (int i = 0; i < LI; i += 4) {
+      const uint4 q = *reinterpret_cast<const uint4*>(in + base + i);
+      v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < LI; ++i) v[i] = base + i < n ? in[base + i] : 0u;
+  }
+}
+
 __global__ __launch_bounds__(SB) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
                                                     uint32_t* __restrict__ partial) {
   __shared__ uint32_t lds[SB / 64];
-  const int64_t base = (int64_t)blockIdx.x * SE + (int64_t)threadIdx.x * SI;
+  const int64_t base = (int64_t)blockIdx.x * LE + (int64_t)threadIdx.x * LI;
+  uint32_t v[LI];
+  load_run(in, base, n, v);
   uint32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < SI; ++i)
-    if (base + i < n) s += in[base + i];
+  for (int i = 0; i < LI; ++i) s += v[i];
   uint32_t total;
   block_excl_scan(s, lds, total);
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
@@ -172,20 +191,30 @@ __global__ __launch_bounds__(SB) void k_scan_down(const uint32_t* in, uint32_t* 
   for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SB) s += partial[b];
   uint32_t pre;
   block_excl_scan(s, lds, pre);
-  const int64_t base = (int64_t)blockIdx.x * SE + (int64_t)threadIdx.x * SI;
-  uint32_t v[SI];
+  const int64_t base = (int64_t)blockIdx.x * LE + (int64_t)threadIdx.x * LI;
+  uint32_t v[LI];
+  load_run(in, base, n, v);
   s = 0;
 #pragma unroll
-  for (int i = 0; i < SI; ++i) {
-    v[i] = base + i < n ? in[base + i] : 0u;
-    s += v[i];
-  }
+  for (int i = 0; i < LI; ++i) s += v[i];
   uint32_t total;
   uint32_t ex = block_excl_scan(s, lds, total) + pre;
+  if (base + LI <= n) {
 #pragma unroll
-  for (int i = 0; i < SI; ++i) {
-    if (base + i < n) out[base + i] = ex;
-    ex += v[i];
+    for (int i = 0; i < LI; i += 4) {
+      uint4 q;
+      q.x = ex; ex += v[i];
+      q.y = ex; ex += v[i + 1];
+      q.z = ex; ex += v[i + 2];
+      q.w = ex; ex += v[i + 3];
+      *reinterpret_cast<uint4*>(out + base + i) = q;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < LI; ++i) {
+      if (base + i < n) out[base + i] = ex;
+      ex += v[i];
+    }
   }
   if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = pre + total;
 }
@@ -212,9 +241,11 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, voi
   if (n <= 0) return;
   const int64_t nb = scan_blocks(n);
   if (nb > ONE_PASS_MAX_BLOCKS) {
+    // fewer, larger tiles: the totals array (sized for nb) has room for them
+    const int64_t nl = (n + LE - 1) / LE;
     uint32_t* partial = (uint32_t*)((char*)scratch + 16 + ONE_PASS_MAX_BLOCKS * 8);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SB), 0, st, in, n, partial);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SB), 0, st, in, out, n,
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nl), dim3(SB), 0, st, in, n, partial);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nl), dim3(SB), 0, st, in, out, n,
                        (const uint32_t*)partial, total);
     return;
   }
