@@ -502,16 +502,18 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t* __restrict__ sva
                                                 uint32_t* __restrict__ item_s,
                                                 int32_t* __restrict__ rank_of, double ln_amin,
                                                 EllP* __restrict__ ell) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= M || r >= (int64_t)counters[0]) return;
-  const uint32_t it = sval[r];
-  const GRec R = rec[it];
-  const uint2 rc = rect[it];
-  rec_s[r] = R;
-  rect_s[r] = rc;
-  item_s[r] = it;
-  rank_of[it] = (int32_t)r;
-  if (ell) ell[r] = ell_params(R, rc, ln_amin);
+  const int64_t nv = std::min<int64_t>(M, (int64_t)counters[0]);
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nv;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t it = sval[r];
+    const GRec R = rec[it];
+    const uint2 rc = rect[it];
+    rec_s[r] = R;
+    rect_s[r] = rc;
+    item_s[r] = it;
+    rank_of[it] = (int32_t)r;
+    if (ell) ell[r] = ell_params(R, rc, ln_amin);
+  }
 }
 
 __device__ __forceinline__ int find_cam_by_row(const CamDev* cams, int n_cams, int64_t row) {
@@ -1048,7 +1050,7 @@ void launch_depth_sort(const SetDev& S, const Work& w, bool ell, hipStream_t st)
                          wait_flag);
   }
   const int cur = passes & 1;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)std::min<int64_t>(4096, (M + 255) / 256)), dim3(256), 0, st,
                      w.sval[cur], w.counters, M, w.rec, w.rect, w.rec_s, w.rect_s,
                      w.item_s, w.rank_of, std::log((double)S.alpha_min),
                      ell ? w.ell_s : nullptr);
@@ -1060,7 +1062,11 @@ void launch_binning(const SetDev& S, const Work& w, int n_cams, bool cull, bool 
   const EllP* ellp = ell ? w.ell_s : nullptr;
   // one workgroup per (chunk, tile row) the cameras could use (the unused ones
   // exit at once): the dispatcher balances the uneven rows, nearest chunks first
-  const unsigned grid = (unsigned)std::max<int64_t>(1, w.bin_items_max);
+  // at most 8192 workgroups, each taking units it, it + grid, ...: the bound
+  // counts every chunk the cameras could fill, and with several cameras most
+  // of those units do not exist, so a workgroup per unit of the bound would
+  // mostly start only to leave
+  const unsigned grid = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, w.bin_items_max));
   if (w.bin_items_max > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(256), 0, st, w.cams, n_cams, w.vis_off,
                        w.item_off, w.rect_s, w.rec_s, tdm, ellp, w.mat, w.counters, w.runs,
