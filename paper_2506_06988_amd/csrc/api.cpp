@@ -1119,7 +1119,7 @@ hr_status hr_autotune_backward(const hr_gaussians* g, const hr_mesh* mesh, const
   uint32_t nvis = 0;
   hipMemcpyAsync(&nvis, w.counters, 4, hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
-  const int cand[4][2] = {{64, 0}, {128, 0}, {64, 8}, {128, 8}};
+  const int cand[5][2] = {{64, 0}, {128, 0}, {32, 8}, {64, 8}, {128, 8}};
   float best = 1e30f;
   int best_b = 64, best_v = 0;
   for (const auto& c : cand) {

@@ -678,10 +678,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
   __shared__ Staged sh[BG];
   __shared__ uint32_t rk[BG];
   __shared__ uint32_t bitmap[WIN_WORDS];
-  // the 9 record gradients of up to RB Gaussians, one row of 64 lane partials
+  // the 9 record gradients of up to RBL Gaussians, one row of 64 lane partials
   // each (padded: the summing lanes read across the banks)
-  __shared__ float part[RB][9][65];
-  __shared__ uint32_t prk[RB];
+  // at batch 32 the staged records leave room for 3 Gaussians' rows in the
+  // LDS that keeps 4 waves per SIMD
+  constexpr int RBL = BG <= 32 ? 3 : RB;
+  __shared__ float part[RBL][9][65];
+  __shared__ uint32_t prk[RBL];
   const int t = (int)tile_order[blockIdx.x];
   const int cam = find_cam_by_tile(cams, S.n_cams, t);
   const CamDev& C = cams[cam];
@@ -737,11 +740,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
   for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o, 64));
   const int64_t last = lmax;
   if (last == 0) return;
-  // RB Gaussians' partials are summed together: row r = 9 gs + q of part
+  // RBL Gaussians' partials are summed together: row r = 9 gs + q of part
   // holds gradient q of Gaussian gs over the 64 lanes; lanes r and r + 32
   // sum its entries [0, 32) and [32, 64), lane r adds the two and the result
   // to the Gaussian's accumulators (one atomic instruction for all rows)
-  static_assert(9 * RB <= 32, "two lanes per row");
+  static_assert(9 * RBL <= 32, "two lanes per row");
   int nb = 0;
   auto flush = [&]() {
     __syncthreads();
@@ -847,7 +850,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 #pragma unroll
           for (int q = 0; q < 9; ++q) part[nb][q][lane] = g[q];
           if (lane == 0) prk[nb] = rk[k];
-          if (++nb == RB) {
+          if (++nb == RBL) {
             flush();
             nb = 0;
           }
@@ -945,7 +948,8 @@ void launch_blend_backward(const SetDev& S, const Work& w, const float* grad_ima
   if (S.n_tiles == 0) return;
   if (variant & 8) {
     if (batch >= 128) HR_BWD_W(128);
-    else HR_BWD_W(64);
+    else if (batch >= 64) HR_BWD_W(64);
+    else HR_BWD_W(32);
     return;
   }
   switch (batch) {

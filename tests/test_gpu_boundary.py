@@ -55,7 +55,7 @@ def test_loss_over_two_uneven_images_matches_oracle_per_image(hr):
     assert not torch.equal(gI1, gI) or abs(L1.item() - L.item()) > 1e-6
 
 
-@pytest.mark.parametrize("variant,batch_bwd", [(0, 0), (8, 128)])
+@pytest.mark.parametrize("variant,batch_bwd", [(0, 0), (8, 128), (8, 32)])
 def test_graph_step_matches_oracle_per_camera(hr, variant, batch_bwd):
     say(f"case: hipGraph step on 2 uneven cameras vs oracle, variant {variant} batch_bwd {batch_bwd}")
     sc, cams, targets = two_camera_room()

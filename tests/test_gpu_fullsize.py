@@ -45,7 +45,7 @@ check_window.by_paths = 0
 # training step, the one-wave backward with 128 per batch
 TILE_ELLIPSE = 1 << 5  # HR_FLAG_TILE_ELLIPSE
 ELLIPSE = dict(flags=TILE_ELLIPSE, batch=256, variant=0)
-STEP = dict(flags=TILE_ELLIPSE, batch=256, variant=8, batch_bwd=128)
+STEP = dict(flags=TILE_ELLIPSE, batch=256, variant=8, batch_bwd=32)
 
 
 def run_frames(hr, sc, cams, n_win, seed, settings=None, params=None):
