@@ -406,7 +406,7 @@ def batched_step(torch, hr, scenes, dev, args, result):
     r.autotune(f, repeats=2)
     L0, gi0, gt0, _ = hr.hybrid_loss(f.image, f.final_T, f.mesh_rgb, f.tri_id, target,
                                       r.sizes)
-    r.autotune_backward(gi0, gt0, repeats=2)
+    r.autotune_backward(gi0, gt0, repeats=5)
     log(f"batched tuning: forward batch {r.settings.batch}, backward batch "
         f"{r.settings.batch_bwd}, variant {r.settings.variant}")
     del L0, gi0, gt0
